@@ -1,0 +1,209 @@
+"""Dense FP64 Sinkhorn (Algorithm 1) with the read-outs of Algorithm 3.
+
+Test infrastructure only (see ``oracle/__init__.py``).
+
+Notation.  The paper writes the Gibbs kernel as k = exp(-lambda d^r) with a
+large lambda meaning weak regularization.  Here ``eps`` is the temperature,
+eps = 1/lambda, so k = exp(-c/eps) with c = |x - y|^r.  Every formula below is
+the paper's with 1/lambda replaced by eps.
+"""
+import numpy as np
+
+
+def cost_matrix(x, y, r):
+    """c_ij = ||x_i - y_j||^r with the Euclidean norm (Definition 2.1, eq. (dist))."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[:, None]
+    if y.ndim == 1:
+        y = y[:, None]
+    diff = x[:, None, :] - y[None, :, :]
+    dist = np.sqrt(np.sum(diff * diff, axis=-1))
+    return dist ** r
+
+
+def gibbs_kernel(x, y, r, eps):
+    """k_ij = exp(-c_ij / eps) (Section 2.2, the Gibbs kernel k = exp(-lambda d^r))."""
+    return np.exp(-cost_matrix(x, y, r) / eps)
+
+
+def xlogy(a, b):
+    """a*log(b) with the convention 0*log(0) = 0 used for zero weights."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    out = np.zeros(np.broadcast(a, b).shape)
+    nz = a != 0
+    out[nz] = a[nz] * np.log(b[nz])
+    return out
+
+
+def entropy(p):
+    """H(P) = -sum p_i log p_i (Lemma 2.1)."""
+    return -float(np.sum(xlogy(p, p)))
+
+
+def kl(a, b):
+    """Kullback-Leibler divergence sum a_i log(a_i/b_i) (Section 2, Notations)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nz = a > 0
+    return float(np.sum(a[nz] * np.log(a[nz] / b[nz])))
+
+
+def dual_value(K, alpha, alpha_t, p, pt, eps):
+    """Dual function of Proposition 2.3, eq. (14), with 1/lambda = eps.
+
+    d = eps + eps*sum p log alpha + eps*sum pt log alpha_t - eps*alpha^T K alpha_t.
+    """
+    return (eps + eps * float(np.sum(xlogy(p, alpha)))
+            + eps * float(np.sum(xlogy(pt, alpha_t)))
+            - eps * float(alpha @ (K @ alpha_t)))
+
+
+def _safe_div(num, den):
+    out = np.zeros_like(num)
+    nz = num != 0
+    out[nz] = num[nz] / den[nz]
+    return out
+
+
+def sinkhorn(K, p, pt, iters, alpha_t0=None, eps=None, record=False):
+    """Algorithm 1 (Sinkhorn's algorithm) for a fixed number of iterations.
+
+    One iteration is the odd half-step (update alpha from alpha_t, eq. (S1)
+    left) followed by the even half-step (update alpha_t from alpha, eq. (S1)
+    right, with the target weights pt).  Both scalings start at one
+    (eq. (MatrixK_sin_div)); ``alpha_t0`` replaces the starting alpha_t (the
+    algorithm's "starting value" input, used for warm restarts).  A point of
+    weight zero gets scaling zero.
+
+    Returns a dict with the final scalings, the last products t = K alpha_t and
+    tt = K^T alpha that produced them, and, when ``record`` is set and ``eps``
+    given, the dual value and the Kullback-Leibler term of every half-step
+    (Lemma 2.4).
+    """
+    K = np.asarray(K, dtype=np.float64)
+    p = np.asarray(p, dtype=np.float64)
+    pt = np.asarray(pt, dtype=np.float64)
+    n, nt = K.shape
+    alpha = np.ones(n)
+    alpha_t = np.ones(nt) if alpha_t0 is None else np.array(alpha_t0, dtype=np.float64)
+    hist = []
+    t = tt = None
+    for _ in range(iters):
+        # odd half-step: row sums of pi = diag(alpha) K diag(alpha_t) before the update
+        t = K @ alpha_t
+        if record:
+            hist.append(dict(kind="row", kl=kl(p, alpha * t),
+                             dual_before=dual_value(K, alpha, alpha_t, p, pt, eps)))
+        alpha = _safe_div(p, t)
+        if record:
+            hist[-1]["dual_after"] = dual_value(K, alpha, alpha_t, p, pt, eps)
+        # even half-step: column sums before the update
+        tt = K.T @ alpha
+        if record:
+            hist.append(dict(kind="col", kl=kl(pt, alpha_t * tt),
+                             dual_before=dual_value(K, alpha, alpha_t, p, pt, eps)))
+        alpha_t = _safe_div(pt, tt)
+        if record:
+            hist[-1]["dual_after"] = dual_value(K, alpha, alpha_t, p, pt, eps)
+    return dict(alpha=alpha, alpha_t=alpha_t, t=t, tt=tt, hist=hist)
+
+
+def sinkhorn_to_tolerance(K, p, pt, tol, max_iter=100000):
+    """Algorithm 1 with its stopping rule ||E|| <= tol (eq. (Error)).
+
+    After each full iteration the column residual is zero, so ||E|| is the row
+    residual ||alpha o (K alpha_t) - p||.
+    """
+    alpha = np.ones(K.shape[0])
+    alpha_t = np.ones(K.shape[1])
+    for it in range(1, max_iter + 1):
+        alpha = _safe_div(p, K @ alpha_t)
+        tt = K.T @ alpha
+        alpha_t = _safe_div(pt, tt)
+        err = float(np.linalg.norm(alpha * (K @ alpha_t) - p))
+        if err <= tol:
+            return dict(alpha=alpha, alpha_t=alpha_t, tt=tt, iters=it, err=err)
+    return dict(alpha=alpha, alpha_t=alpha_t, tt=tt, iters=max_iter, err=err)
+
+
+def cost_readout(alpha, alpha_t, tt, p, pt, eps):
+    """Result of Algorithm 3: s = eps + eps*sum p log alpha + eps*sum pt log alpha_t
+    - eps*sum_j tt_j alpha_t_j, with tt the last product K^T alpha."""
+    return (eps + eps * float(np.sum(xlogy(p, alpha)))
+            + eps * float(np.sum(xlogy(pt, alpha_t)))
+            - eps * float(np.sum(tt * alpha_t)))
+
+
+def cost_upper_bound(s, p, pt, eps):
+    """Upper ERW value of Section 3.2: s + (H(P) + H(Pt))/lambda."""
+    return s + eps * (entropy(p) + entropy(pt))
+
+
+def primal_cost(K, C, alpha, alpha_t):
+    """<pi, C> = sum_ij alpha_i k_ij c_ij alpha_t_j (eq. (15) with pi of eq. (pi*))."""
+    return float(alpha @ ((K * C) @ alpha_t))
+
+
+def marginal_errors(K, alpha, alpha_t, p, pt):
+    """Both terms of the residual of eq. (Error), Euclidean norm."""
+    pi_row = alpha * (K @ alpha_t)
+    pi_col = alpha_t * (K.T @ alpha)
+    return float(np.linalg.norm(pi_row - p)), float(np.linalg.norm(pi_col - pt))
+
+
+def transport_plan(K, alpha, alpha_t):
+    """pi = diag(alpha) k diag(alpha_t) (eq. (pi*)); dense, small problems only."""
+    return alpha[:, None] * K * alpha_t[None, :]
+
+
+def envelope_gradient(x, y, K, alpha, alpha_t, r, eps):
+    """Gradient of s with respect to the source positions and weights.
+
+    Differentiating the dual (eq. (14)) at fixed scalings (envelope theorem):
+      d s / d x_i  = sum_j pi_ij grad_x c(x_i, y_j),
+      d s / d p_i  = eps log alpha_i, projected onto sum = 0 (the weights live
+                     on the probability simplex).
+    For r = 2, grad_x c = 2 (x_i - y_j); for r = 1 it is the unit vector
+    (x_i - y_j)/|x_i - y_j| (zero where the points coincide).
+    """
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[:, None]
+    if y.ndim == 1:
+        y = y[:, None]
+    pi = transport_plan(K, alpha, alpha_t)
+    diff = x[:, None, :] - y[None, :, :]
+    if r == 2:
+        g = 2.0 * diff
+    elif r == 1:
+        nrm = np.sqrt(np.sum(diff * diff, axis=-1, keepdims=True))
+        g = np.where(nrm > 0, diff / np.where(nrm > 0, nrm, 1.0), 0.0)
+    else:
+        raise ValueError("r must be 1 or 2")
+    grad_x = np.einsum("ij,ijc->ic", pi, g)
+    gmu = eps * np.where(alpha > 0, np.log(np.where(alpha > 0, alpha, 1.0)), 0.0)
+    grad_mu = gmu - gmu.mean()
+    return grad_x, grad_mu
+
+
+def solve(x, p, y, pt, r, eps, iters, alpha_t0=None):
+    """Convenience wrapper: Algorithm 1 for ``iters`` iterations plus every read-out.
+
+    Returns the scalings, the cost s (Algorithm 3 result), the upper value,
+    the primal cost <pi, C>, and the residual of eq. (Error) after the last
+    iteration (the row term needs one extra product K alpha_t).
+    """
+    C = cost_matrix(x, y, r)
+    K = np.exp(-C / eps)
+    out = sinkhorn(K, p, pt, iters, alpha_t0=alpha_t0)
+    a, at, tt = out["alpha"], out["alpha_t"], out["tt"]
+    s = cost_readout(a, at, tt, p, pt, eps)
+    e_row, e_col = marginal_errors(K, a, at, p, pt)
+    return dict(alpha=a, alpha_t=at, tt=tt, cost=s,
+                cost_upper=cost_upper_bound(s, p, pt, eps),
+                cost_primal=primal_cost(K, C, a, at),
+                marg_err=e_row + e_col, marg_err_row=e_row, marg_err_col=e_col)
