@@ -1,0 +1,160 @@
+"""Benchmark: NFFT-accelerated Sinkhorn iterations per second on one MI355X.
+
+Workload (default): the 2-D Gaussian-mixture problem, n = nt = 1e6 points,
+Dirichlet weights, squared Euclidean cost, eps = 0.01, N = 512, m = 8,
+sigma = 2, FP32 grids/FFT with FP64 scalings and reductions.  One step is
+one Sinkhorn iteration (alpha update then alpha_t update, each one full fast
+summation plus the fused scaling update), replayed from a captured hipGraph
+with every input resident in HBM.
+
+Prints one JSON line with the throughput, the roofline figure of the dominant
+kernel (device times from HIP events on the solver's stream) and the FP64
+oracle timed on the host cores on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(info, d, which):
+    """Algorithmic HBM bytes per launch: points (FP32 tile-local coordinates,
+    FP64 weights / marginals / scalings) and grid values, each moved once."""
+    n_s = 0.5 * (info["n"] + info["nt"])   # spread and interp alternate between the clouds
+    G = info["grid_cells"]
+    gb = info["grid_value_bytes"]
+    cb = 4 * d if gb == 4 else 8 * d
+    if which == "spread":
+        return n_s * (cb + 8) + G * gb
+    if which == "fft":
+        return 4 * G * gb
+    return G * gb + n_s * (cb + 24)
+
+
+def cpu_baseline(cfg, budget_rows=2048):
+    """Oracle (FP64 matrix-free direct sums in C/OpenMP) timed on a bounded
+    sample: one kernel product K v over all sources for `budget_rows` sampled
+    targets, scaled to the two full products of one iteration."""
+    import numpy as np
+    from oracle import direct
+
+    direct.load()
+    n, nt = cfg["x"].shape[0], cfg["y"].shape[0]
+    rows = np.random.default_rng(5).choice(nt, size=min(budget_rows, nt), replace=False)
+    w = np.ones(n)
+    t0 = time.perf_counter()
+    direct.kv(cfg["y"], cfg["x"], w, cfg["r"], cfg["eps"], rows=rows)
+    dt = time.perf_counter() - t0
+    pairs_sample = len(rows) * n
+    pairs_iter = 2.0 * n * nt
+    sec_per_iter = dt * pairs_iter / pairs_sample
+    return dict(value=1.0 / sec_per_iter, unit="iter/s", cores=direct.num_threads(), kind="oracle",
+                sample=f"one FP64 kernel product on {len(rows)} sampled targets x {n} sources "
+                       f"({dt:.1f} s), scaled to 2 full products per iteration")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-iters", type=int, default=10)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: every box here has a single MI355X; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2201_07524_amd import nfs, workloads
+
+    log("bench: generating the 2-D mixture workload")
+    cfg = workloads.gmm_2d(args.n)
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    x, p, y, pt = T(cfg["x"]), T(cfg["p"]), T(cfg["y"]), T(cfg["pt"])
+    prm = nfs.Params(d=2, eps=cfg["eps"], N=cfg["N"], m=cfg["m"], sigma=cfg["sigma"], precision="fp32")
+    torch.cuda.synchronize()
+    log("bench: planning")
+    t0 = time.perf_counter()
+    solver = nfs.Solver(prm, x, p, y, pt)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    log(f"bench: plan {plan_s * 1e3:.1f} ms; warmup {args.warmup} iterations")
+    solver.iterate(args.warmup)
+    torch.cuda.synchronize()
+
+    log(f"bench: timing {args.steps} iterations")
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    solver.iterate(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_total = ev0.elapsed_time(ev1)
+    ms_per_step = ms_total / args.steps
+    value = args.steps / (ms_total / 1e3)
+    log(f"bench: {ms_per_step:.4f} ms/iteration (wall {wall * 1e3 / args.steps:.4f} ms)")
+
+    res = solver.finish(check=False)
+    log(f"bench: cost={res.cost:.9e} marg_err={res.marg_err:.3e} nonpos={res.n_nonpos}")
+
+    stage_ms, info = solver.profile(args.profile_iters)
+    names = ("spread", "fft", "interp")
+    dom = int(np.argmax(stage_ms[:3]))
+    d = 2
+    achieved = {k: kernel_bytes(info, d, k) / (stage_ms[i] * 1e-3) / 1e9 for i, k in enumerate(names)}
+    log("bench: stage ms/launch " + ", ".join(f"{k}={stage_ms[i]:.4f}" for i, k in enumerate(names))
+        + f", iteration={stage_ms[3]:.4f}")
+    log("bench: algorithmic GB/s " + ", ".join(f"{k}={v:.1f}" for k, v in achieved.items()))
+    fast_pts = 2.0 * (info["n"] + info["nt"]) * value
+
+    out = {
+        "metric": "Sinkhorn iters/s at n=m=1e6 d=2",
+        "value": value,
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"2-D Gaussian mixtures, n=nt={args.n}, Dirichlet weights, |x-y|^2, "
+                               f"eps=0.01, N=512, m=8, sigma=2, FP32 grids + FP64 scalings",
+                   "n": args.n, "d": 2, "N": 512, "m": 8, "eps": 0.01},
+        "fastsum_points_per_s": fast_pts,
+        "plan_ms": plan_s * 1e3,
+        "stage_ms": dict(zip(names + ("iteration",), stage_ms)),
+        "stage_gbs": achieved,
+        "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved[names[dom]],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved[names[dom]] / HBM_PEAK_GBS, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    solver.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

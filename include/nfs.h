@@ -1,0 +1,189 @@
+/*
+ * nfs.h - C ABI of the MI355X (gfx950) NFFT-boosted Sinkhorn library.
+ *
+ * The library solves the entropy-regularized optimal transport problem between
+ * two discrete measures P = sum_i p_i delta_{x_i} and Pt = sum_j pt_j delta_{y_j}
+ * on R^d (Definition 2.2, eqs. (Sinkhorn), (SD1)-(SD2)) with Sinkhorn's scaling
+ * iteration (Algorithm 1), where both Gibbs-kernel products
+ *
+ *     t_i  = sum_j alpha_t_j exp(-|x_i - y_j|^r / eps)      (eq. (matexp))
+ *     tt_j = sum_i alpha_i   exp(-|x_i - y_j|^r / eps)      (eq. (matexpt))
+ *
+ * are evaluated by NFFT fast summation (Section 3.1, eq. (fastsum)), i.e. the
+ * NFFT-accelerated Sinkhorn algorithm (Algorithm 3).
+ *
+ * Notation: the paper writes the kernel as exp(-lambda d^r).  This ABI uses the
+ * temperature eps = 1/lambda, so K = exp(-c/eps).
+ *
+ * Conventions shared by every entry point
+ *   - Arrays named as points, weights, scalings and outputs are DEVICE
+ *     pointers, caller-owned, contiguous, FP64.  Points are point-major:
+ *     x[i*d + c].
+ *   - `workspace` is a caller-allocated device buffer of at least the size
+ *     that nfs_workspace_size() reports for the same call; the library
+ *     allocates no device memory itself.  Its contents on entry are ignored
+ *     and on return are unspecified.
+ *   - All device work is ordered on `stream` (a hipStream_t, 0 = the null
+ *     stream).  Calls return after the plan stage has synchronized `stream`
+ *     once; entry points that return host scalars synchronize it again at
+ *     the end.  Device outputs are complete when the call returns.
+ *   - Return value 0 (NFS_OK) on success, otherwise one of the NFS_E* codes;
+ *     nfs_last_error() then gives a message (thread-local).  Outputs are
+ *     undefined on error.  No exception crosses the ABI.
+ *   - Calls on distinct workspaces may run concurrently on distinct streams.
+ */
+#ifndef NFS_H
+#define NFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+#define NFS_OK 0
+#define NFS_EINVAL 1        /* bad d, r, N, m, sigma, eps, size, null pointer */
+#define NFS_EWEIGHTS 2      /* negative weight or |sum - 1| > 1e-12 * max(n, nt) */
+#define NFS_ENONPOS 3       /* a kernel sum t <= 0 or non-finite during the solve */
+#define NFS_EUNSUPPORTED 4  /* option outside what the library implements */
+#define NFS_EHIP 5          /* HIP runtime error */
+#define NFS_EWORKSPACE 6    /* workspace smaller than nfs_workspace_size() */
+
+/* Grid / FFT / window precision.  Scalings and reductions are always FP64. */
+#define NFS_FP64 0
+#define NFS_FP32 1
+
+/* flags */
+#define NFS_FLAG_NO_GRAPH 1      /* launch the iteration kernels directly, no hipGraph replay */
+#define NFS_FLAG_PRIMAL_COST 2   /* also evaluate <pi, C> (one extra fast summation) */
+
+typedef struct nfs_params {
+  int32_t d;          /* dimension, 1..3 */
+  int32_t r;          /* cost exponent: 2 -> c = |x-y|^2; 1 -> c = |x-y| (needs the near field) */
+  double eps;         /* temperature > 0; K = exp(-c/eps) (the paper's 1/lambda) */
+  int32_t N;          /* bandwidth per dimension: I_N = {-N/2..N/2-1}^d, even, >= 4 */
+  int32_t m;          /* window cutoff: 2m+1 grid taps per dimension, 2 <= m <= 8 */
+  double sigma;       /* oversampling: grid g = sigma*N rounded up to even, g >= N + 2 */
+  int32_t precision;  /* NFS_FP64 or NFS_FP32 */
+  int32_t tile;       /* grid cells per bin side (0 = default for d) */
+  int32_t chunk;      /* max points per workgroup chunk (0 = default) */
+  int32_t flags;      /* NFS_FLAG_* */
+  double eps_I;       /* r = 1: near-field radius in units of the data scale (0 = default) */
+  int32_t p_smooth;   /* r = 1: regularization smoothness (0 = default) */
+  int32_t reserved;
+} nfs_params;
+
+typedef struct nfs_result {
+  double cost;          /* s_{r;lambda;NFFT} (Algorithm 3 result) */
+  double cost_upper;    /* cost + eps*(H(P) + H(Pt)) (Section 3.2) */
+  double cost_primal;   /* <pi, C> = sum alpha_i K_ij c_ij alpha_t_j, if NFS_FLAG_PRIMAL_COST */
+  double marg_err;      /* ||E|| of eq. (Error) after the last iteration (row + column) */
+  double marg_err_row;  /* ||alpha o (K alpha_t) - p||_2 (one extra kernel product) */
+  double marg_err_col;  /* ||alpha_t o (K^T alpha) - pt||_2 */
+  double scale;         /* s: points were mapped to the torus as s*(x - center) */
+  double kernel_err;    /* a-priori bound on the kernel approximation (periodization/truncation) */
+  int32_t iters;        /* iterations done (one = alpha update then alpha_t update) */
+  int32_t precision_used;
+  int64_t n_nonpos;     /* number of kernel sums t <= 0 or non-finite seen */
+} nfs_result;
+
+/* Message for the last error on this thread ("" if none). */
+const char* nfs_last_error(void);
+
+/* CPU-only argument check of params and sizes (no device access). */
+int nfs_validate(const nfs_params* prm, int64_t n, int64_t nt);
+
+/* Workspace bytes needed by fastsum_apply / sinkhorn_solve / sinkhorn_grad for
+ * clouds of n sources and nt targets (or n x-points and nt y-points). */
+int nfs_workspace_size(const nfs_params* prm, int64_t n, int64_t nt, size_t* bytes);
+
+/*
+ * Fast summation (Section 3.1, eq. (fastsum)):
+ *   out_i = sum_j w_j exp(-|tgt_i - src_j|^r / eps),  i < nt.
+ * src: ns x d, w: ns (any sign), tgt: nt x d, out: nt.  ns, nt >= 1.
+ */
+int nfs_fastsum_apply(const nfs_params* prm, const double* src, int64_t ns, const double* w,
+                      const double* tgt, int64_t nt, double* out,
+                      void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Adjoint NFFT, the inner sum of eq. (fastsum) for real weights, on the
+ * period-1 torus: fhat_k = sum_j w_j exp(-2 pi i k.y_j), k in I_N.
+ * pts: n x d with every coordinate in [-1/2, 1/2); fhat: N^d complex values,
+ * interleaved (re, im), row-major with index (k_0 + N/2, ..., k_{d-1} + N/2).
+ */
+int nfs_nfft_adjoint(const nfs_params* prm, const double* pts, int64_t n, const double* w,
+                     double* fhat, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * NFFT, the outer sum of eq. (fastsum): out_i = Re sum_{k in I_N} fhat_k exp(2 pi i k.x_i).
+ * fhat layout as in nfs_nfft_adjoint; pts in [-1/2, 1/2)^d; out: n reals.
+ */
+int nfs_nfft_trafo(const nfs_params* prm, const double* fhat, const double* pts, int64_t n,
+                   double* out, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * NFFT-accelerated Sinkhorn (Algorithm 3).  x: n x d with weights mu (sum 1,
+ * >= 0); y: nt x d with weights nu.  Runs max_iter iterations (alpha update,
+ * then alpha_t update, eq. (S1)); if tol > 0 it stops early once ||E|| <= tol,
+ * checked every 10 iterations with one extra kernel product.
+ *   alpha   (n):  out, final scalings alpha.
+ *   alpha_t (nt): in = starting value when warm_start != 0 (else ones), out = final alpha_t.
+ *   res: host pointer, filled on success.
+ */
+int nfs_sinkhorn_solve(const nfs_params* prm, const double* x, int64_t n, const double* mu,
+                       const double* y, int64_t nt, const double* nu,
+                       int32_t max_iter, double tol, int32_t warm_start,
+                       double* alpha, double* alpha_t, nfs_result* res,
+                       void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Persistent solver handle for the same iteration (Algorithm 3): the plan
+ * (torus scaling, binning, coefficient tables) is done once by create, which
+ * also records one iteration in a hipGraph on an internal stream; iterate
+ * replays it.  Device work of every call is ordered after earlier work on
+ * `stream`, and later work on `stream` waits for it.  The handle keeps
+ * pointers into `workspace`, which must stay allocated and untouched until
+ * destroy.  alpha_t0 (nullable, nt) is the starting value of alpha_t.
+ */
+typedef struct nfs_solver nfs_solver;
+int nfs_solver_create(const nfs_params* prm, const double* x, int64_t n, const double* mu,
+                      const double* y, int64_t nt, const double* nu, const double* alpha_t0,
+                      void* workspace, size_t ws_bytes, void* stream, nfs_solver** out);
+/* Runs `iters` more iterations (alpha update, then alpha_t update). */
+int nfs_solver_iterate(nfs_solver* s, int32_t iters, void* stream);
+/* Row residual ||alpha o (K alpha_t) - p||_2 of the current state (one extra
+ * kernel product); synchronizes and writes the host scalar *err_row. */
+int nfs_solver_residual(nfs_solver* s, double* err_row, void* stream);
+/* Read-out: final scalings in the caller's point order (either may be NULL)
+ * and the result struct, as nfs_sinkhorn_solve.  The solver stays usable. */
+int nfs_solver_finish(nfs_solver* s, double* alpha, double* alpha_t, nfs_result* res, void* stream);
+/* Runs `iters` iterations with direct launches and events between kernels;
+ * stage_ms[4] receives the average device time per launch of spreading, of
+ * the FFT chain, of interpolation with the scaling update, and of one whole
+ * iteration.  info (nullable, 8 doubles): n, nt, d, grid cells, bytes per grid
+ * value, chunks of x, chunks of y, taps per point. */
+int nfs_solver_profile(nfs_solver* s, int32_t iters, double* stage_ms, double* info, void* stream);
+int nfs_solver_destroy(nfs_solver* s);
+
+/*
+ * Gradient of the Sinkhorn cost at given scalings (alpha, alpha_t), by the
+ * envelope theorem applied to the dual (Proposition 2.3, eq. (14)):
+ *   grad_x[i]  = sum_j pi_ij grad_x c(x_i, y_j) = -eps alpha_i (grad K * alpha_t)(x_i)   (n x d)
+ *   grad_mu[i] = eps log alpha_i - mean_k(eps log alpha_k)                               (n)
+ * with the kernel gradient summed by fast summation (coefficients 2 pi i k b_k).
+ * Either output may be NULL.
+ */
+int nfs_sinkhorn_grad(const nfs_params* prm, const double* x, int64_t n, const double* mu,
+                      const double* y, int64_t nt, const double* nu,
+                      const double* alpha, const double* alpha_t,
+                      double* grad_x, double* grad_mu,
+                      void* workspace, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NFS_H */

@@ -1,0 +1,185 @@
+// Kernel argument structs and launcher declarations (host side of the kernels).
+#pragma once
+
+#include "common.h"
+
+namespace nfs {
+
+enum Epilogue : int {
+  EPI_OUT = 0,   // out[perm[q]*stride + comp] = t * scale_vec[q]
+  EPI_SINK = 1,  // alpha[q] = p[q]/t, residual and mass reductions (Algorithm 3 half-step)
+  EPI_EVAL = 2,  // residual sum (alpha[q] t - p[q])^2 only, no update
+};
+
+template <typename R>
+struct SpreadArgs {
+  Geom geo;
+  const R* coords;       // sorted tile-local coordinates, n x d
+  const double* w;       // sorted weights
+  const double* wmul;    // device scalar multiplier of the weights (nullable)
+  double wconst;         // host constant multiplier of the weights
+  const Chunk* chunks;
+  R* grid;               // g^d real grid, must be zero on entry
+  WindowConst win;
+};
+
+template <typename R>
+struct InterpArgs {
+  Geom geo;
+  const R* coords;
+  const Chunk* chunks;
+  const R* grid;
+  WindowConst win;
+  double norm;              // constant factor of the result
+  const double* wmul_src;   // the result is divided by *wmul_src (nullable)
+  int epi;
+  // EPI_OUT
+  const int* perm;
+  double* out;
+  int out_stride;
+  int out_comp;
+  const double* scale_vec;  // sorted per-point factor (nullable)
+  // EPI_SINK / EPI_EVAL
+  const double* p;
+  double* alpha;
+  double* partials;         // 4 doubles per chunk
+  unsigned* counter;        // zero on entry, left zero
+  double* stats;            // 4 doubles: residual^2 sum, mass sum, max alpha, count(t <= 0)
+  double* wmul_next;        // receives 1/max alpha (nullable)
+};
+
+template <typename R>
+hipError_t launch_spread(const SpreadArgs<R>& a, int nchunks, hipStream_t st);
+template <typename R>
+hipError_t launch_interp(const InterpArgs<R>& a, int nchunks, hipStream_t st);
+
+// ----------------------------------------------------------------------------- FFT
+// Spectral multiplier applied inside the axis-0 pass: value(k) = Dtab[|k0|,|k1|,|k2|]
+// (table of extent H = N/2+1 per dimension, row-major), optionally times
+// i 2 pi k_c for the derivative axis c (deriv < 0: none).
+struct Multiplier {
+  const void* tab;   // R table, (N/2+1)^d entries
+  int deriv;         // -1 or derivative axis
+};
+
+enum RowMode : int { ROW_R2C = 0, ROW_C2R = 1, ROW_FUSED1D = 2 };
+enum AxisMode : int { AX_FWD = 0, AX_INV = 1, AX_FUSED = 2 };
+
+template <typename R>
+struct RowArgs {
+  int mode;
+  int L;            // grid size g (FFT length)
+  int N;
+  int nrows;        // number of real rows
+  R* real_io;       // R2C: input rows (zeroed after reading if zero_src); C2R/FUSED1D: output rows
+  const R* real_in; // FUSED1D input row
+  cplx<R>* spec;    // R2C: output [nrows][K0]; C2R: input [nrows][K0]
+  int zero_src;
+  const cplx<R>* tw;
+  Multiplier mul;   // FUSED1D only
+};
+
+template <typename R>
+struct AxisArgs {
+  int mode;
+  int L, N, d;
+  const cplx<R>* in;
+  cplx<R>* out;
+  int nin, in_centered;    // entries along the axis; centered: entry e <-> k = e - N/2
+  int nout, out_centered;
+  long in_stride, out_stride;     // element stride along the axis
+  long in_ostride, out_ostride;   // stride between outer pencil groups
+  int inner;                      // pencils per outer group (contiguous)
+  long npen;                      // total pencils
+  const cplx<R>* tw;
+  Multiplier mul;                 // FUSED: applied between forward and inverse; INV: applied on load
+  int apply_mul;
+};
+
+template <typename R>
+hipError_t launch_rows(const RowArgs<R>& a, hipStream_t st);
+template <typename R>
+hipError_t launch_axis(const AxisArgs<R>& a, hipStream_t st);
+
+// ----------------------------------------------------------------------------- plan / misc
+struct BoxArgs {
+  const double* pts[2];
+  long n[2];
+  const double* w;    // optional weights (for max |w|, min w, sum w)
+  long nw;
+  int d;
+  double* partials;   // per block: 2*d (min,max) + 3
+  unsigned* counter;
+  double* out;        // 2*d + 3 : min_c, max_c, max|w|, min w, sum w
+};
+hipError_t launch_bbox(const BoxArgs& a, hipStream_t st);
+
+struct KeyArgs {
+  const double* pts;
+  long n;
+  int d, g, T;
+  int nt[3];
+  double center[3];
+  double scale;       // torus coordinate = scale*(x - center); scale = 0: points already on the torus
+  int* keys;
+  int* counts;        // histogram per tile
+};
+hipError_t launch_keys(const KeyArgs& a, hipStream_t st);
+
+template <typename R>
+struct ScatterArgs {
+  const double* pts;
+  long n;
+  int d, g, T;
+  int nt[3];
+  double center[3];
+  double scale;
+  const int* keys;
+  const int* offsets;
+  int* cursor;
+  R* coords;          // sorted tile-local coordinates
+  int* perm;          // sorted -> original index
+  const double* w0;   // optional gathered vectors (nullable)
+  double* w0s;
+  const double* w1;
+  double* w1s;
+};
+template <typename R>
+hipError_t launch_scatter(const ScatterArgs<R>& a, hipStream_t st);
+
+hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);
+hipError_t launch_fill_double(double* p, long n, double v, hipStream_t st);
+hipError_t launch_unpermute(const double* src_sorted, const int* perm, long n, double* dst, hipStream_t st);
+
+// readout: over sorted arrays, out[0] += sum a*log(b) (a>0), out[1] += sum a*log(a), out[2] += sum a
+struct ReadoutArgs {
+  const double* a;
+  const double* b;
+  long n;
+  double* partials;
+  unsigned* counter;
+  double* out;
+};
+hipError_t launch_readout(const ReadoutArgs& a, hipStream_t st);
+
+// grad_mu: out[perm[q]] = eps*log(alpha_s[q]) - shift, with shift = eps*mean(log alpha) read from device
+hipError_t launch_gradmu(const double* alpha, long n, double eps, double* partials, unsigned* counter,
+                         double* mean_out, double* grad_mu, hipStream_t st);
+
+// NFFT spectrum conversion between user layout (full I_N, complex FP64) and
+// the internal half spectrum (R), with deconvolution by 1/Phi.
+template <typename R>
+struct SpecArgs {
+  int d, N;
+  const cplx<R>* spec_in;  // internal -> user
+  cplx<R>* spec_out;       // user -> internal
+  const double* user_in;
+  double* user_out;
+  const double* inv_phi;   // N/2+1 entries: 1/Phi(|k|)
+};
+template <typename R>
+hipError_t launch_spec_to_user(const SpecArgs<R>& a, hipStream_t st);
+template <typename R>
+hipError_t launch_user_to_spec(const SpecArgs<R>& a, hipStream_t st);
+
+}  // namespace nfs

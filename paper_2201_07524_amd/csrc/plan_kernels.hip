@@ -1,0 +1,333 @@
+// Plan-stage kernels (bounding box, tile keys, counting-sort scatter) and the
+// small elementwise / reduction kernels around the fast summation.
+#include "common.h"
+#include "kernels.h"
+
+namespace nfs {
+
+// ------------------------------------------------------------------ block helpers
+template <int NV>
+__device__ void block_reduce_arr(double (&v)[NV], const bool (&is_min)[NV], const bool (&is_max)[NV],
+                                 double (*sh)[kBlock]) {
+  for (int k = 0; k < NV; ++k) sh[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      for (int k = 0; k < NV; ++k) {
+        const double a = sh[k][threadIdx.x], b = sh[k][threadIdx.x + s];
+        sh[k][threadIdx.x] = is_min[k] ? fmin(a, b) : (is_max[k] ? fmax(a, b) : a + b);
+      }
+    }
+    __syncthreads();
+  }
+  for (int k = 0; k < NV; ++k) v[k] = sh[k][0];
+  __syncthreads();
+}
+
+// Writes this block's values to partials, and lets the last block reduce all
+// partials into out.  Returns nothing; uses a ticket counter left at zero.
+template <int NV>
+__device__ void grid_reduce_arr(double (&v)[NV], const bool (&is_min)[NV], const bool (&is_max)[NV],
+                                double* partials, unsigned* counter, double* out) {
+  __shared__ double sh[NV][kBlock];
+  __shared__ bool last;
+  block_reduce_arr<NV>(v, is_min, is_max, sh);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NV; ++k) partials[size_t(blockIdx.x) * NV + k] = v[k];
+    __threadfence();
+    last = atomicAdd(counter, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double acc[NV];
+  for (int k = 0; k < NV; ++k) acc[k] = is_min[k] ? 1e308 : (is_max[k] ? -1e308 : 0.0);
+  const volatile double* pv = partials;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
+    for (int k = 0; k < NV; ++k) {
+      const double x = pv[size_t(b) * NV + k];
+      acc[k] = is_min[k] ? fmin(acc[k], x) : (is_max[k] ? fmax(acc[k], x) : acc[k] + x);
+    }
+  block_reduce_arr<NV>(acc, is_min, is_max, sh);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NV; ++k) out[k] = acc[k];
+    *counter = 0u;
+  }
+}
+
+constexpr int kGridBlocks = 1024;
+
+// ------------------------------------------------------------------ bounding box
+// out = {min_0..min_{d-1}, max_0..max_{d-1}} padded to 3 dims, then max|w|, min w, sum w.
+__global__ __launch_bounds__(kBlock) void bbox_kernel(BoxArgs a) {
+  constexpr int NV = 9;
+  double v[NV];
+  bool is_min[NV], is_max[NV];
+  for (int k = 0; k < NV; ++k) {
+    is_min[k] = (k < 3) || k == 7;
+    is_max[k] = (k >= 3 && k < 7);
+    v[k] = is_min[k] ? 1e308 : (is_max[k] ? -1e308 : 0.0);
+  }
+  const long stride = long(gridDim.x) * kBlock;
+  for (int s = 0; s < 2; ++s) {
+    const double* p = a.pts[s];
+    if (!p) continue;
+    for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < a.n[s]; i += stride)
+      for (int c = 0; c < a.d; ++c) {
+        const double x = p[i * a.d + c];
+        v[c] = fmin(v[c], x);
+        v[3 + c] = fmax(v[3 + c], x);
+      }
+  }
+  if (a.w)
+    for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < a.nw; i += stride) {
+      const double w = a.w[i];
+      v[6] = fmax(v[6], fabs(w));
+      v[7] = fmin(v[7], w);
+      v[8] += w;
+    }
+  grid_reduce_arr<NV>(v, is_min, is_max, a.partials, a.counter, a.out);
+}
+
+hipError_t launch_bbox(const BoxArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(bbox_kernel, dim3(kGridBlocks), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ keys + histogram
+__device__ __forceinline__ double grid_coord(double x, double center, double scale, int g) {
+  const double tau = scale > 0.0 ? scale * (x - center) : x;
+  double v = double(g) * tau;
+  v -= double(g) * floor(v / double(g));
+  if (v >= double(g)) v -= double(g);
+  if (v < 0.0) v = 0.0;
+  return v;
+}
+
+__global__ __launch_bounds__(kBlock) void keys_kernel(KeyArgs a) {
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= a.n) return;
+  int key = 0;
+  for (int c = 0; c < a.d; ++c) {
+    const double v = grid_coord(a.pts[i * a.d + c], a.center[c], a.scale, a.g);
+    const int cell = min(int(v), a.g - 1);
+    key = key * a.nt[c] + cell / a.T;
+  }
+  a.keys[i] = key;
+  atomicAdd(&a.counts[key], 1);
+}
+
+hipError_t launch_keys(const KeyArgs& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(keys_kernel, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void scatter_kernel(ScatterArgs<R> a) {
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= a.n) return;
+  const int key = a.keys[i];
+  const int pos = a.offsets[key] + atomicAdd(&a.cursor[key], 1);
+  for (int c = 0; c < a.d; ++c) {
+    const double v = grid_coord(a.pts[i * a.d + c], a.center[c], a.scale, a.g);
+    const int cell = min(int(v), a.g - 1);
+    const double u = v - double((cell / a.T) * a.T);
+    R ur = R(u);
+    if (ur >= R(a.T)) ur = nextafter(R(a.T), R(0));
+    if (ur < R(0)) ur = R(0);
+    a.coords[size_t(pos) * a.d + c] = ur;
+  }
+  a.perm[pos] = int(i);
+  if (a.w0) a.w0s[pos] = a.w0[i];
+  if (a.w1) a.w1s[pos] = a.w1[i];
+}
+
+template <typename R>
+hipError_t launch_scatter(const ScatterArgs<R>& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_kernel<R>, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+template hipError_t launch_scatter<float>(const ScatterArgs<float>&, hipStream_t);
+template hipError_t launch_scatter<double>(const ScatterArgs<double>&, hipStream_t);
+
+// ------------------------------------------------------------------ fills / permutations
+__global__ __launch_bounds__(kBlock) void fill_kernel(uint32_t* p, size_t nwords) {
+  const size_t stride = size_t(gridDim.x) * kBlock;
+  for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < nwords; i += stride) p[i] = 0u;
+}
+
+hipError_t launch_fill(void* p, size_t bytes, hipStream_t st) {
+  const size_t nw = bytes / 4;
+  if (nw == 0) return hipSuccess;
+  const size_t nb = std::min<size_t>((nw + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL(fill_kernel, dim3(nb), dim3(kBlock), 0, st, reinterpret_cast<uint32_t*>(p), nw);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void fill_double_kernel(double* p, long n, double v) {
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_double(double* p, long n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_double_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void unpermute_kernel(const double* src, const int* perm, long n, double* dst) {
+  const long q = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (q < n) dst[perm[q]] = src[q];
+}
+
+hipError_t launch_unpermute(const double* src, const int* perm, long n, double* dst, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(unpermute_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, src, perm, n, dst);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ read-out sums
+__global__ __launch_bounds__(kBlock) void readout_kernel(ReadoutArgs a) {
+  constexpr int NV = 3;
+  double v[NV] = {0.0, 0.0, 0.0};
+  const bool is_min[NV] = {false, false, false}, is_max[NV] = {false, false, false};
+  const long stride = long(gridDim.x) * kBlock;
+  for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < a.n; i += stride) {
+    const double x = a.a[i];
+    if (x > 0.0) {
+      v[0] += x * log(a.b[i]);
+      v[1] += x * log(x);
+    }
+    v[2] += x;
+  }
+  grid_reduce_arr<NV>(v, is_min, is_max, a.partials, a.counter, a.out);
+}
+
+hipError_t launch_readout(const ReadoutArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(readout_kernel, dim3(256), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void logmean_kernel(const double* alpha, long n, double* partials,
+                                                         unsigned* counter, double* out) {
+  constexpr int NV = 1;
+  double v[NV] = {0.0};
+  const bool is_min[NV] = {false}, is_max[NV] = {false};
+  const long stride = long(gridDim.x) * kBlock;
+  for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) v[0] += log(alpha[i]);
+  grid_reduce_arr<NV>(v, is_min, is_max, partials, counter, out);
+}
+
+__global__ __launch_bounds__(kBlock) void gradmu_kernel(const double* alpha, long n, double eps,
+                                                        const double* sumlog, double* g) {
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) g[i] = eps * (log(alpha[i]) - *sumlog / double(n));
+}
+
+hipError_t launch_gradmu(const double* alpha, long n, double eps, double* partials, unsigned* counter,
+                         double* mean_out, double* grad_mu, hipStream_t st) {
+  hipLaunchKernelGGL(logmean_kernel, dim3(256), dim3(kBlock), 0, st, alpha, n, partials, counter, mean_out);
+  hipLaunchKernelGGL(gradmu_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, alpha, n, eps,
+                     (const double*)mean_out, grad_mu);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ NFFT spectrum conversions
+// Internal half spectrum: all axes but the last centered (N+1 entries, k + N/2),
+// the last axis k = 0..N/2 (K0 entries).
+__device__ __forceinline__ long spec_index(int d, int N, const int* k) {
+  const int K0 = N / 2 + 1;
+  long idx = 0;
+  for (int c = 0; c < d - 1; ++c) idx = idx * (N + 1) + (k[c] + N / 2);
+  return idx * K0 + k[d - 1];
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void spec_to_user_kernel(SpecArgs<R> a) {
+  long total = 1;
+  for (int c = 0; c < a.d; ++c) total *= a.N;
+  const long u = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (u >= total) return;
+  int k[3];
+  long rem = u;
+  for (int c = a.d - 1; c >= 0; --c) {
+    k[c] = int(rem % a.N) - a.N / 2;
+    rem /= a.N;
+  }
+  double f = 1.0;
+  for (int c = 0; c < a.d; ++c) f *= a.inv_phi[abs(k[c])];
+  cplx<R> h;
+  if (k[a.d - 1] >= 0) {
+    h = a.spec_in[spec_index(a.d, a.N, k)];
+  } else {
+    int km[3];
+    for (int c = 0; c < a.d; ++c) km[c] = -k[c];
+    h = a.spec_in[spec_index(a.d, a.N, km)];
+    h.y = -h.y;
+  }
+  a.user_out[2 * u] = double(h.x) * f;
+  a.user_out[2 * u + 1] = double(h.y) * f;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void user_to_spec_kernel(SpecArgs<R> a) {
+  const int K0 = a.N / 2 + 1;
+  long total = K0;
+  for (int c = 0; c < a.d - 1; ++c) total *= (a.N + 1);
+  const long s = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (s >= total) return;
+  int k[3];
+  long rem = s;
+  k[a.d - 1] = int(rem % K0);
+  rem /= K0;
+  for (int c = a.d - 2; c >= 0; --c) {
+    k[c] = int(rem % (a.N + 1)) - a.N / 2;
+    rem /= (a.N + 1);
+  }
+  // F(k) and F(-k) from the user array (zero outside I_N = [-N/2, N/2-1]^d)
+  double fr = 0.0, fi = 0.0, gr = 0.0, gi = 0.0;
+  bool in_p = true, in_m = true;
+  long up = 0, um = 0;
+  for (int c = 0; c < a.d; ++c) {
+    in_p = in_p && (k[c] <= a.N / 2 - 1);
+    in_m = in_m && (-k[c] <= a.N / 2 - 1);
+    up = up * a.N + (k[c] + a.N / 2);
+    um = um * a.N + (-k[c] + a.N / 2);
+  }
+  if (in_p) {
+    fr = a.user_in[2 * up];
+    fi = a.user_in[2 * up + 1];
+  }
+  if (in_m) {
+    gr = a.user_in[2 * um];
+    gi = a.user_in[2 * um + 1];
+  }
+  double f = 0.5;
+  for (int c = 0; c < a.d; ++c) f *= a.inv_phi[abs(k[c])];
+  a.spec_out[s] = cplx<R>{R((fr + gr) * f), R((fi - gi) * f)};
+}
+
+template <typename R>
+hipError_t launch_spec_to_user(const SpecArgs<R>& a, hipStream_t st) {
+  long total = 1;
+  for (int c = 0; c < a.d; ++c) total *= a.N;
+  hipLaunchKernelGGL(spec_to_user_kernel<R>, dim3((total + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_user_to_spec(const SpecArgs<R>& a, hipStream_t st) {
+  long total = a.N / 2 + 1;
+  for (int c = 0; c < a.d - 1; ++c) total *= (a.N + 1);
+  hipLaunchKernelGGL(user_to_spec_kernel<R>, dim3((total + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_spec_to_user<float>(const SpecArgs<float>&, hipStream_t);
+template hipError_t launch_spec_to_user<double>(const SpecArgs<double>&, hipStream_t);
+template hipError_t launch_user_to_spec<float>(const SpecArgs<float>&, hipStream_t);
+template hipError_t launch_user_to_spec<double>(const SpecArgs<double>&, hipStream_t);
+
+}  // namespace nfs

@@ -1,0 +1,102 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol that
+include/nfs.h declares, rejects bad arguments with the documented codes
+without touching a device, and the oracle and the HIP path share no code."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2201_07524_amd import nfs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "nfs.h")).read()
+    return sorted(set(re.findall(r"\b(nfs_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = nfs.load_library()
+    syms = header_symbols()
+    assert len(syms) >= 8
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(nfs.EXPORTED)
+
+
+def _p(**kw):
+    base = dict(d=2, eps=0.01, N=64, m=6, r=2, sigma=2.0, precision="fp32")
+    base.update(kw)
+    return nfs.Params(**base)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(d=0), nfs.NFS_EINVAL),
+    (dict(d=4), nfs.NFS_EINVAL),
+    (dict(r=3), nfs.NFS_EUNSUPPORTED),
+    (dict(eps=0.0), nfs.NFS_EINVAL),
+    (dict(eps=-1.0), nfs.NFS_EINVAL),
+    (dict(N=63), nfs.NFS_EINVAL),
+    (dict(N=2), nfs.NFS_EINVAL),
+    (dict(m=1), nfs.NFS_EINVAL),
+    (dict(m=9), nfs.NFS_EINVAL),
+    (dict(sigma=0.5), nfs.NFS_EINVAL),
+    (dict(N=4096), nfs.NFS_EUNSUPPORTED),
+    (dict(d=3, tile=64), nfs.NFS_EINVAL),
+])
+def test_validate_rejects(kw, code):
+    assert nfs.validate(_p(**kw), 100, 100) == code
+
+
+def test_validate_sizes_and_accepts():
+    assert nfs.validate(_p(), 0, 10) == nfs.NFS_EINVAL
+    assert nfs.validate(_p(), 10, 0) == nfs.NFS_EINVAL
+    assert nfs.validate(_p(), 1, 1) == nfs.NFS_OK
+    assert nfs.validate(_p(d=1, N=256, m=8, precision="fp64"), 2048, 2048) == nfs.NFS_OK
+    assert nfs.validate(_p(d=3, N=128, m=8), 10**6, 10**6) == nfs.NFS_OK
+
+
+def test_error_message_and_workspace_size():
+    lib = nfs.load_library()
+    assert nfs.validate(_p(N=63), 10, 10) == nfs.NFS_EINVAL
+    assert b"even" in lib.nfs_last_error()
+    ws32 = nfs.workspace_size(_p(), 1000, 2000)
+    ws64 = nfs.workspace_size(_p(precision="fp64"), 1000, 2000)
+    assert 0 < ws32 < ws64
+    # the 2-D mixture workload at full size fits easily in HBM
+    big = nfs.workspace_size(_p(N=512, m=8), 10**6, 10**6)
+    assert big < 2 * 2**30
+    with pytest.raises(nfs.NfsError):
+        nfs.workspace_size(_p(m=1), 10, 10)
+
+
+def test_null_pointers_rejected_without_device():
+    lib = nfs.load_library()
+    prm = _p().to_c()
+    rc = lib.nfs_fastsum_apply(ctypes.byref(prm), None, 10, None, None, 10, None, None, 0, None)
+    assert rc == nfs.NFS_EINVAL
+    rc = lib.nfs_sinkhorn_solve(ctypes.byref(prm), None, 10, None, None, 10, None, 5, 0.0, 0,
+                                None, None, None, None, 0, None)
+    assert rc == nfs.NFS_EINVAL
+
+
+def _imports(path):
+    mods = set()
+    for dirpath, _, files in os.walk(path):
+        for f in files:
+            if f.endswith(".py"):
+                src = open(os.path.join(dirpath, f)).read()
+                mods |= set(re.findall(r"^\s*(?:from|import)\s+([\w\.]+)", src, re.M))
+    return mods
+
+
+def test_oracle_and_hip_path_share_no_code():
+    pkg = os.path.join(ROOT, "paper_2201_07524_amd")
+    oracle = os.path.join(ROOT, "oracle")
+    assert not any(m.startswith("oracle") for m in _imports(pkg))
+    assert not any(m.startswith("paper_2201_07524_amd") for m in _imports(oracle))
+    for dirpath, _, files in os.walk(os.path.join(pkg, "csrc")):
+        for f in files:
+            assert "oracle" not in open(os.path.join(dirpath, f)).read().lower(), f

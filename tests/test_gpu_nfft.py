@@ -1,0 +1,134 @@
+"""GPU parity of the NFFT sub-steps and of fast summation against the oracle.
+
+Every case calls the HIP path through the C ABI and compares element by
+element with the FP64 oracle (direct trigonometric sums, dense Gibbs kernel).
+Tolerances: FP64 with m = 8 within 1e-10 relative (normwise, relative to the
+largest output), FP32 within 1e-5.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import ndft
+from oracle import sinkhorn_dense as sd
+from paper_2201_07524_amd import nfs, workloads
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def T(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def relerr(got, ref):
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
+@pytest.mark.parametrize("d,N", [(1, 32), (2, 16), (3, 8)])
+def test_nfft_adjoint_matches_direct_sums(d, N, prec, tol):
+    rng = np.random.default_rng(100 + d)
+    n = 300
+    pts = rng.uniform(-0.5, 0.5, size=(n, d))
+    w = rng.uniform(-1.0, 1.0, size=n)
+    prm = nfs.Params(d=d, eps=1.0, N=N, m=8, precision=prec, chunk=37)
+    got = nfs.nfft_adjoint(prm, T(pts), T(w)).cpu().numpy()
+    ref = ndft.ndft_adjoint(pts, w, N)
+    assert got.shape == ref.shape
+    assert np.max(np.abs(got - ref)) <= tol * np.sum(np.abs(w))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
+@pytest.mark.parametrize("d,N", [(1, 32), (2, 16), (3, 8)])
+def test_nfft_trafo_matches_direct_sums(d, N, prec, tol):
+    rng = np.random.default_rng(200 + d)
+    n = 257
+    pts = rng.uniform(-0.5, 0.5, size=(n, d))
+    fhat = rng.standard_normal((N,) * d) + 1j * rng.standard_normal((N,) * d)
+    prm = nfs.Params(d=d, eps=1.0, N=N, m=8, precision=prec, chunk=29)
+    got = nfs.nfft_trafo(prm, torch.as_tensor(fhat, device=DEV), T(pts)).cpu().numpy()
+    ref = np.real(ndft.ndft_trafo(fhat, pts, N))
+    assert np.max(np.abs(got - ref)) <= tol * np.sum(np.abs(fhat))
+
+
+def _clouds(d, ns, nt, seed):
+    x = workloads.gaussian_mixture(nt, d, seed)
+    y = workloads.gaussian_mixture(ns, d, seed + 1)
+    w = np.random.default_rng(seed + 2).uniform(0.0, 1.0, size=ns)
+    return y, w, x
+
+
+@pytest.mark.parametrize("d,N,eps,ns,nt", [
+    (1, 256, 0.05, 2048, 2048),
+    (1, 64, 0.05, 1000, 777),
+    (2, 128, 0.01, 3000, 2500),
+    (2, 64, 0.05, 1500, 1999),
+    (3, 32, 0.05, 1200, 900),
+])
+def test_fastsum_fp64_matches_dense(d, N, eps, ns, nt):
+    src, w, tgt = _clouds(d, ns, nt, 300 + d)
+    prm = nfs.Params(d=d, eps=eps, N=N, m=8, precision="fp64", chunk=257)
+    got = nfs.fastsum(prm, T(src), T(w), T(tgt)).cpu().numpy()
+    ref = sd.gibbs_kernel(tgt, src, 2, eps) @ w
+    assert relerr(got, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("d,N,eps,ns,nt", [
+    (1, 64, 0.05, 1000, 777),
+    (2, 128, 0.01, 3000, 2500),
+    (3, 32, 0.05, 1200, 900),
+])
+def test_fastsum_fp32_matches_dense(d, N, eps, ns, nt):
+    src, w, tgt = _clouds(d, ns, nt, 400 + d)
+    prm = nfs.Params(d=d, eps=eps, N=N, m=8 if d < 3 else 6, precision="fp32", chunk=300)
+    got = nfs.fastsum(prm, T(src), T(w), T(tgt)).cpu().numpy()
+    ref = sd.gibbs_kernel(tgt, src, 2, eps) @ w
+    assert relerr(got, ref) <= 1e-5
+
+
+def test_fastsum_error_decays_with_m():
+    """Window error of the Kaiser-Bessel NFFT decays geometrically in m
+    (about e^{-2 pi m sqrt(1 - 1/sigma)} at sigma = 2) down to rounding."""
+    src, w, tgt = _clouds(2, 800, 700, 500)
+    ref = sd.gibbs_kernel(tgt, src, 2, 0.02) @ w
+    errs = []
+    for m in range(2, 9):
+        prm = nfs.Params(d=2, eps=0.02, N=64, m=m, precision="fp64")
+        errs.append(relerr(nfs.fastsum(prm, T(src), T(w), T(tgt)).cpu().numpy(), ref))
+    for a, b in zip(errs[:-2], errs[2:]):
+        assert b < a / 10 or b < 1e-13
+    assert errs[0] > 1e-5
+    assert errs[-1] < 1e-11
+
+
+@pytest.mark.parametrize("ns,nt,chunk", [(1, 1, 0), (1, 500, 0), (500, 1, 7), (1025, 1023, 1), (4097, 3, 64)])
+def test_fastsum_ragged_and_degenerate_sizes(ns, nt, chunk):
+    src, w, tgt = _clouds(2, ns, nt, 600)
+    prm = nfs.Params(d=2, eps=0.02, N=64, m=8, precision="fp64", chunk=chunk)
+    got = nfs.fastsum(prm, T(src), T(w), T(tgt)).cpu().numpy()
+    ref = sd.gibbs_kernel(tgt, src, 2, 0.02) @ w
+    assert relerr(got, ref) <= 1e-10
+
+
+def test_fastsum_coincident_points_and_signed_weights():
+    """All sources in one point with weights of both signs; targets spread out."""
+    src = np.tile([[0.01, -0.02]], (600, 1))
+    w = np.random.default_rng(7).uniform(-1, 1, 600)
+    tgt = np.random.default_rng(8).uniform(-0.3, 0.3, size=(400, 2))
+    prm = nfs.Params(d=2, eps=0.03, N=64, m=8, precision="fp64")
+    got = nfs.fastsum(prm, T(src), T(w), T(tgt)).cpu().numpy()
+    ref = sd.gibbs_kernel(tgt, src, 2, 0.03) @ w
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.sum(np.abs(w))
+
+
+def test_fastsum_tile_sizes_agree():
+    src, w, tgt = _clouds(2, 2000, 2000, 700)
+    ref = sd.gibbs_kernel(tgt, src, 2, 0.01) @ w
+    for tile in (8, 16, 32, 64):
+        prm = nfs.Params(d=2, eps=0.01, N=128, m=8, precision="fp64", tile=tile, chunk=128)
+        assert relerr(nfs.fastsum(prm, T(src), T(w), T(tgt)).cpu().numpy(), ref) <= 1e-10
