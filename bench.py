@@ -71,6 +71,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-iters", type=int, default=10)
     ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--flags", type=int, default=0, help="nfs_params.flags (library variants)")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every box here has a single MI355X; "
@@ -86,7 +89,8 @@ def main():
     dev = torch.device("cuda:0")
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     x, p, y, pt = T(cfg["x"]), T(cfg["p"]), T(cfg["y"]), T(cfg["pt"])
-    prm = nfs.Params(d=2, eps=cfg["eps"], N=cfg["N"], m=cfg["m"], sigma=cfg["sigma"], precision="fp32")
+    prm = nfs.Params(d=2, eps=cfg["eps"], N=cfg["N"], m=cfg["m"], sigma=cfg["sigma"], precision="fp32",
+                     flags=args.flags, tile=args.tile, chunk=args.chunk)
     torch.cuda.synchronize()
     log("bench: planning")
     t0 = time.perf_counter()

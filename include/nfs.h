@@ -58,6 +58,9 @@ extern "C" {
 /* flags */
 #define NFS_FLAG_NO_GRAPH 1      /* launch the iteration kernels directly, no hipGraph replay */
 #define NFS_FLAG_PRIMAL_COST 2   /* also evaluate <pi, C> (one extra fast summation) */
+#define NFS_FLAG_TILE_REDUCE 4   /* spread: store each chunk's LDS tile and sum the tiles per
+                                    (tile, neighbour) instead of flushing LDS tiles straight
+                                    into the grid with global atomics (the default) */
 
 typedef struct nfs_params {
   int32_t d;          /* dimension, 1..3 */

@@ -19,9 +19,23 @@ struct SpreadArgs {
   const double* wmul;    // device scalar multiplier of the weights (nullable)
   double wconst;         // host constant multiplier of the weights
   const Chunk* chunks;
-  R* grid;               // g^d real grid, must be zero on entry
+  R* grid;               // g^d real grid, must be zero on entry (atomic flush only)
+  R* part;               // non-null: store each chunk's padded tile here instead of flushing
   WindowConst win;
 };
+
+// Sum of the padded chunk tiles into the grid: one workgroup per (tile, neighbour)
+// sums the overlap of that neighbour's chunks and adds it to the grid with
+// at most 3^d atomic adds per cell (the grid must be zero on entry).
+template <typename R>
+struct ReduceArgs {
+  Geom geo;
+  const R* part;           // chunk tiles, E^d values each
+  const int* tile_chunks;  // nbins + 1 offsets into the chunk list (chunks are sorted by tile)
+  R* grid;
+};
+template <typename R>
+hipError_t launch_spread_reduce(const ReduceArgs<R>& a, int nbins, hipStream_t st);
 
 template <typename R>
 struct InterpArgs {
@@ -176,6 +190,7 @@ struct SpecArgs {
   const double* user_in;
   double* user_out;
   const double* inv_phi;   // N/2+1 entries: 1/Phi(|k|)
+  double scale;            // internal -> user: factor applied to the output
 };
 template <typename R>
 hipError_t launch_spec_to_user(const SpecArgs<R>& a, hipStream_t st);

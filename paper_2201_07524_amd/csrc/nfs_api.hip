@@ -63,7 +63,6 @@ static int check_params(const nfs_params* p, int64_t n, int64_t nt) {
   if (p->precision != NFS_FP64 && p->precision != NFS_FP32) return fail(NFS_EINVAL, "precision must be NFS_FP64 or NFS_FP32");
   const int g = grid_size(p);
   if (g > 4096) return fail(NFS_EUNSUPPORTED, "grid size sigma*N above 4096 per dimension");
-  if (2 * p->m + 1 > g) return fail(NFS_EINVAL, "window wider than the grid (2m+1 > g)");
   if (p->tile < 0 || p->tile > 256) return fail(NFS_EINVAL, "tile must be in [0, 256]");
   if (p->chunk < 0 || p->chunk > (1 << 20)) return fail(NFS_EINVAL, "chunk must be in [0, 2^20]");
   if (n < 1 || nt < 1) return fail(NFS_EINVAL, "point counts must be >= 1");
@@ -100,6 +99,7 @@ struct CloudBuf {
   int* offsets = nullptr;
   int* cursor = nullptr;
   Chunk* chunks = nullptr;
+  int* tile_chunks = nullptr;  // nbins + 1: chunks of tile b are [tile_chunks[b], tile_chunks[b+1])
   long max_chunks = 0;
   int nchunks = 0;
   double* w0s = nullptr;  // sorted first vector (weights)
@@ -113,6 +113,9 @@ struct Work {
   int K0 = 0, nbins = 0, chunk = 0;
   long ncell = 0;
   CloudBuf<R> A, B;  // A: x / sources, B: y / targets
+  bool two_level = false;  // chunk tiles + per-tile gather instead of global atomics
+  R* part = nullptr;       // chunk tiles (two_level)
+  long ecell = 0;          // values per chunk tile, E^d
   R* S = nullptr;    // spread grid
   R* U = nullptr;    // interpolation grid
   cplx<R>* W = nullptr;
@@ -169,11 +172,21 @@ static void carve(Work<R>& w, const nfs_params* p, long nA, long nB, char* base,
     cb.cursor = cv.take<int>(nbins);
     cb.max_chunks = n / chunk + std::min<long>(nbins, n) + 1;
     cb.chunks = cv.take<Chunk>(cb.max_chunks);
+    cb.tile_chunks = cv.take<int>(nbins + 1);
     cb.w0s = nvec >= 1 ? cv.take<double>(n) : nullptr;
     cb.w1s = nvec >= 2 ? cv.take<double>(n) : nullptr;
   };
   cloud(w.A, nA, kind_vectors);
   cloud(w.B, nB, kind_vectors);
+  long ecell = 1;
+  for (int c = 0; c < d; ++c) ecell *= w.geo.E;
+  w.ecell = ecell;
+  long tcells = 1;
+  for (int c = 0; c < d; ++c) tcells *= T;
+  bool two = (p->flags & NFS_FLAG_TILE_REDUCE) && T >= p->m + 1 && (g % T) == 0 && tcells <= 2048;
+  for (int c = 0; c < d; ++c) two = two && w.geo.nt[c] >= 3;
+  w.two_level = two;
+  w.part = two ? cv.take<R>(size_t(std::max(w.A.max_chunks, w.B.max_chunks)) * ecell) : nullptr;
   w.S = cv.take<R>(ncell);
   w.U = cv.take<R>(ncell);
   const long rows = ncell / g;
@@ -222,17 +235,21 @@ static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const Scal
   NFS_HIP(hipMemcpyAsync(counts.data(), cb.counts, sizeof(int) * w.nbins, hipMemcpyDeviceToHost, st));
   NFS_HIP(hipStreamSynchronize(st));
   std::vector<Chunk> chunks;
+  std::vector<int> tile_chunks(w.nbins + 1);
   chunks.reserve(cb.max_chunks);
   int acc = 0;
   for (int b = 0; b < w.nbins; ++b) {
     offsets[b] = acc;
+    tile_chunks[b] = int(chunks.size());
     for (int s = 0; s < counts[b]; s += w.chunk) chunks.push_back(Chunk{b, acc + s, std::min(w.chunk, counts[b] - s), 0});
     acc += counts[b];
   }
+  tile_chunks[w.nbins] = int(chunks.size());
   if ((long)chunks.size() > cb.max_chunks) return fail(NFS_EINVAL, "internal: chunk table overflow");
   cb.nchunks = int(chunks.size());
   NFS_HIP(hipMemcpyAsync(cb.offsets, offsets.data(), sizeof(int) * w.nbins, hipMemcpyHostToDevice, st));
   NFS_HIP(hipMemcpyAsync(cb.chunks, chunks.data(), sizeof(Chunk) * chunks.size(), hipMemcpyHostToDevice, st));
+  NFS_HIP(hipMemcpyAsync(cb.tile_chunks, tile_chunks.data(), sizeof(int) * (w.nbins + 1), hipMemcpyHostToDevice, st));
   ScatterArgs<R> sa{};
   sa.pts = pts;
   sa.n = cb.n;
@@ -424,6 +441,26 @@ static SpreadArgs<R> spread_args(Work<R>& w, const CloudBuf<R>& src, const doubl
   return a;
 }
 
+// Spreading into the grid S (zero on entry; the forward FFT pass zeroes it
+// again after reading): either chunk tiles summed per (tile, neighbour) or LDS
+// tiles flushed straight to the grid with global atomics.
+template <typename R>
+static hipError_t spread(Work<R>& w, const CloudBuf<R>& src, const double* weights, const double* wmul,
+                         double wconst, hipStream_t st) {
+  SpreadArgs<R> a = spread_args(w, src, weights, wmul);
+  a.wconst = wconst;
+  if (!w.two_level) return launch_spread(a, src.nchunks, st);
+  a.part = w.part;
+  hipError_t e = launch_spread(a, src.nchunks, st);
+  if (e != hipSuccess) return e;
+  ReduceArgs<R> r{};
+  r.geo = w.geo;
+  r.part = w.part;
+  r.tile_chunks = src.tile_chunks;
+  r.grid = w.S;
+  return launch_spread_reduce(r, w.nbins, st);
+}
+
 template <typename R>
 static InterpArgs<R> interp_args(Work<R>& w, const CloudBuf<R>& tgt, int epi, const double* wmul_src) {
   InterpArgs<R> a{};
@@ -448,7 +485,7 @@ template <typename R>
 static hipError_t half_step(Work<R>& w, CloudBuf<R>& src, CloudBuf<R>& tgt, double* wmul_src, double* wmul_tgt,
                             double* stats, int epi, hipStream_t st) {
   hipError_t e;
-  if ((e = launch_spread(spread_args(w, src, src.w1s, wmul_src), src.nchunks, st)) != hipSuccess) return e;
+  if ((e = spread(w, src, src.w1s, wmul_src, 1.0, st)) != hipSuccess) return e;
   if ((e = fft_chain(w, w.dtab, -1, st)) != hipSuccess) return e;
   InterpArgs<R> ia = interp_args(w, tgt, epi, wmul_src);
   ia.p = tgt.w0s;
@@ -478,9 +515,7 @@ static int do_fastsum(const nfs_params* p, const double* src, int64_t ns, const 
   NFS_TRY(upload_tables(w, p, sc, st));
   NFS_HIP(launch_fill(w.S, sizeof(R) * w.ncell, st));
   const double wmax = box[6] > 0.0 ? box[6] : 1.0;
-  SpreadArgs<R> sa = spread_args(w, w.A, w.A.w0s, nullptr);
-  sa.wconst = 1.0 / wmax;
-  NFS_HIP(launch_spread(sa, w.A.nchunks, st));
+  NFS_HIP(spread(w, w.A, w.A.w0s, nullptr, 1.0 / wmax, st));
   NFS_HIP(fft_chain(w, w.dtab, -1, st));
   InterpArgs<R> ia = interp_args(w, w.B, EPI_OUT, nullptr);
   ia.norm = wmax;
@@ -514,6 +549,7 @@ static int do_nfft(const nfs_params* p, bool adjoint, const double* pts, int64_t
   sp.d = d;
   sp.N = N;
   sp.inv_phi = w.inv_phi;
+  sp.scale = 1.0;
   AxisArgs<R> ax{};
   ax.L = g;
   ax.N = N;
@@ -522,7 +558,10 @@ static int do_nfft(const nfs_params* p, bool adjoint, const double* pts, int64_t
   ax.mul = Multiplier{nullptr, -1};
   if (adjoint) {
     NFS_HIP(launch_fill(w.S, sizeof(R) * w.ncell, st));
-    NFS_HIP(launch_spread(spread_args(w, w.A, w.A.w0s, nullptr), w.A.nchunks, st));
+    // weights normalized by max |w| so every spread contribution is at most one in size
+    const double wmax = box[6] > 0.0 ? box[6] : 1.0;
+    NFS_HIP(spread(w, w.A, w.A.w0s, nullptr, 1.0 / wmax, st));
+    sp.scale = wmax;
     RowArgs<R> ra{};
     ra.mode = ROW_R2C;
     ra.L = g;
@@ -786,7 +825,7 @@ struct Solver : SolverBase {
         CloudBuf<R>& tgt = h == 0 ? w.A : w.B;
         double* ws_ = h == 0 ? wmul_y() : wmul_x();
         double* wt_ = h == 0 ? wmul_x() : wmul_y();
-        NFS_HIP(launch_spread(spread_args(w, src, src.w1s, ws_), src.nchunks, gs));
+        NFS_HIP(spread(w, src, src.w1s, ws_, 1.0, gs));
         NFS_HIP(hipEventRecord(evs[ie++], gs));
         NFS_HIP(fft_chain(w, w.dtab, -1, gs));
         NFS_HIP(hipEventRecord(evs[ie++], gs));
@@ -851,7 +890,7 @@ struct Solver : SolverBase {
     ReadoutArgs rb{w.B.w0s, w.B.w1s, nt, w.partials, w.counters + CT_RD, S + ST_RD_Y};
     NFS_HIP(launch_readout(rb, st));
     if (p.flags & NFS_FLAG_PRIMAL_COST) {
-      NFS_HIP(launch_spread(spread_args(w, w.B, w.B.w1s, wmul_y()), w.B.nchunks, st));
+      NFS_HIP(spread(w, w.B, w.B.w1s, wmul_y(), 1.0, st));
       NFS_HIP(fft_chain(w, w.dtab2, -1, st));
       InterpArgs<R> ia = interp_args(w, w.A, EPI_OUT, wmul_y());
       ia.out = w.tmp;
@@ -955,9 +994,7 @@ static int do_grad(const nfs_params* p, const double* x, int64_t n, const double
     // The spectrum of the spread alpha_t is formed once per derivative axis;
     // each pass applies (2 pi i k_c) b_k / Phi^2 and interpolates at x.
     for (int c = 0; c < p->d; ++c) {
-      SpreadArgs<R> sa = spread_args(w, w.B, w.B.w1s, nullptr);
-      sa.wconst = 1.0 / wmax;
-      NFS_HIP(launch_spread(sa, w.B.nchunks, st));
+      NFS_HIP(spread(w, w.B, w.B.w1s, nullptr, 1.0 / wmax, st));
       NFS_HIP(fft_chain(w, w.dtab, c, st));
       InterpArgs<R> ia = interp_args(w, w.A, EPI_OUT, nullptr);
       // grad_x_i = -eps alpha_i s (dK'/dx'_c * alpha_t)(x'_i), x' = s (x - center)

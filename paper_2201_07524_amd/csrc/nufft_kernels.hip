@@ -42,17 +42,79 @@ __device__ __forceinline__ int wrap(int v, int g) {
 }
 
 // --------------------------------------------------------------------------- spread
-template <typename R, int D, int M>
+// LDS accumulation modes.  Float atomics in LDS (ds_add_f32/f64) are slow on
+// gfx950 (about one lane per three clocks per CU) while 64-bit integer LDS
+// atomics run an order of magnitude faster, so contributions v (|v| <= 1 after
+// the weights are normalized by their maximum) are accumulated in fixed point:
+//   FIX64  (FP32 path): q = round(v 2^32) in one int64 word;
+//   FIX128 (FP64 path): hi = round(v 2^30), lo = round((v 2^30 - hi) 2^30) in
+//                       two int64 words (resolution 2^-60 of the largest weight).
+// Integer sums are exact and order independent, so the spread grid is
+// deterministic.  ACC_FLOAT keeps native float atomics for tiles too large for
+// the fixed-point LDS footprint.
+enum AccMode : int { ACC_FLOAT = 0, ACC_FIX64 = 1, ACC_FIX128 = 2 };
+
+template <typename R, int ACC>
+struct Acc;
+
+template <typename R>
+struct Acc<R, ACC_FLOAT> {
+  static constexpr int kWords = 0;
+  R* t;
+  __device__ Acc(unsigned char* raw, int) : t(reinterpret_cast<R*>(raw)) {}
+  __device__ __forceinline__ void zero(int i) { t[i] = R(0); }
+  __device__ __forceinline__ void add(int i, R v) { atomicAdd(&t[i], v); }
+  __device__ __forceinline__ R get(int i) const { return t[i]; }
+};
+
+template <>
+struct Acc<float, ACC_FIX64> {
+  long long* t;
+  __device__ Acc(unsigned char* raw, int) : t(reinterpret_cast<long long*>(raw)) {}
+  __device__ __forceinline__ void zero(int i) { t[i] = 0; }
+  __device__ __forceinline__ void add(int i, float v) {
+    const float x = v * 65536.0f;                      // exact scaling
+    const float hi = rintf(x);
+    const int lo = __float2int_rn((x - hi) * 65536.0f);  // x - hi is exact, |.| <= 1/2
+    const long long q = (long long)(int)hi * 65536LL + lo;
+    atomicAdd(reinterpret_cast<unsigned long long*>(&t[i]), (unsigned long long)q);
+  }
+  __device__ __forceinline__ float get(int i) const { return float(double(t[i]) * 2.3283064365386963e-10); }
+};
+
+template <>
+struct Acc<double, ACC_FIX128> {
+  long long* hi_;
+  long long* lo_;
+  __device__ Acc(unsigned char* raw, int ncell)
+      : hi_(reinterpret_cast<long long*>(raw)), lo_(reinterpret_cast<long long*>(raw) + ncell) {}
+  __device__ __forceinline__ void zero(int i) {
+    hi_[i] = 0;
+    lo_[i] = 0;
+  }
+  __device__ __forceinline__ void add(int i, double v) {
+    const double x = v * 1073741824.0;  // 2^30, exact
+    const double h = rint(x);
+    const double l = rint((x - h) * 1073741824.0);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&hi_[i]), (unsigned long long)(long long)h);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&lo_[i]), (unsigned long long)(long long)l);
+  }
+  __device__ __forceinline__ double get(int i) const {
+    return double(hi_[i]) * 9.313225746154785e-10 + double(lo_[i]) * 8.673617379884035e-19;
+  }
+};
+
+template <typename R, int D, int M, int ACC>
 __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  R* tile = reinterpret_cast<R*>(smem_raw);
   constexpr int W = 2 * M + 1;
   const Geom geo = a.geo;
   const int E = geo.E;
   const int ncell = D == 1 ? E : (D == 2 ? E * E : E * E * E);
+  Acc<R, ACC> tile(smem_raw, ncell);
   const Chunk ch = a.chunks[blockIdx.x];
 
-  for (int i = threadIdx.x; i < ncell; i += kBlock) tile[i] = R(0);
+  for (int i = threadIdx.x; i < ncell; i += kBlock) tile.zero(i);
   __syncthreads();
 
   const double wm = a.wconst * (a.wmul ? *a.wmul : 1.0);
@@ -66,14 +128,14 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs<R> a) {
     tp.compute(u, a.win);
     if constexpr (D == 1) {
 #pragma unroll
-      for (int j = 0; j < W; ++j) atomicAdd(&tile[tp.off[0] + j], w * tp.psi[0][j]);
+      for (int j = 0; j < W; ++j) tile.add(tp.off[0] + j, w * tp.psi[0][j]);
     } else if constexpr (D == 2) {
 #pragma unroll
       for (int j0 = 0; j0 < W; ++j0) {
         const R v0 = w * tp.psi[0][j0];
-        R* row = tile + (tp.off[0] + j0) * E + tp.off[1];
+        const int row = (tp.off[0] + j0) * E + tp.off[1];
 #pragma unroll
-        for (int j1 = 0; j1 < W; ++j1) atomicAdd(&row[j1], v0 * tp.psi[1][j1]);
+        for (int j1 = 0; j1 < W; ++j1) tile.add(row + j1, v0 * tp.psi[1][j1]);
       }
     } else {
       for (int j0 = 0; j0 < W; ++j0) {
@@ -81,14 +143,20 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs<R> a) {
 #pragma unroll 1
         for (int j1 = 0; j1 < W; ++j1) {
           const R v1 = v0 * tp.psi[1][j1];
-          R* row = tile + ((tp.off[0] + j0) * E + tp.off[1] + j1) * E + tp.off[2];
+          const int row = ((tp.off[0] + j0) * E + tp.off[1] + j1) * E + tp.off[2];
 #pragma unroll
-          for (int j2 = 0; j2 < W; ++j2) atomicAdd(&row[j2], v1 * tp.psi[2][j2]);
+          for (int j2 = 0; j2 < W; ++j2) tile.add(row + j2, v1 * tp.psi[2][j2]);
         }
       }
     }
   }
   __syncthreads();
+
+  if (a.part) {
+    R* dst = a.part + size_t(blockIdx.x) * ncell;
+    for (int i = threadIdx.x; i < ncell; i += kBlock) dst[i] = tile.get(i);
+    return;
+  }
 
   // flush the tile (with halo) into the periodic global grid
   int org[3] = {0, 0, 0};
@@ -101,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs<R> a) {
   }
   const int g = geo.g;
   for (int i = threadIdx.x; i < ncell; i += kBlock) {
-    const R v = tile[i];
+    const R v = tile.get(i);
     if (v == R(0)) continue;
     size_t lin;
     if constexpr (D == 1) {
@@ -116,6 +184,116 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs<R> a) {
     atomicAdd(&a.grid[lin], v);
   }
 }
+
+// --------------------------------------------------------------------------- spread reduction
+// Tile b owns cells [b T, b T + T) per axis.  A chunk of neighbour tile
+// nb = b + delta stores cells [nb T - M, nb T + T + M] (E = T + 2M + 1 values);
+// per axis the overlap with tile b is
+//   delta =  0: cells [0, T)      <-> e = M + l
+//   delta = -1: cells [0, M+1)    <-> e = T + M + l
+//   delta = +1: cells [T-M, T)    <-> e = l - (T - M)
+// One workgroup per (tile, delta) sums that overlap over the chunks of nb in
+// registers (index math hoisted out of the chunk loop) and adds it to the
+// grid, so each grid cell receives at most 3^d atomic adds.  Requires
+// T >= M + 1, T dividing g and at least 3 tiles per axis; the grid must be
+// zero on entry.
+constexpr int kRedPerThread = 8;
+
+template <typename R, int D>
+__global__ __launch_bounds__(kBlock) void spread_reduce_kernel(ReduceArgs<R> a) {
+  const Geom geo = a.geo;
+  const int T = geo.T, M = geo.M, E = geo.E, g = geo.g;
+  constexpr int NNB = D == 1 ? 3 : (D == 2 ? 9 : 27);
+  const int tile = blockIdx.x / NNB;
+  const int k = blockIdx.x - tile * NNB;
+  int bc[3] = {0, 0, 0}, dl[3] = {0, 0, 0};
+  {
+    int t = tile, r = k;
+    for (int c = D - 1; c >= 0; --c) {
+      bc[c] = t % geo.nt[c];
+      t /= geo.nt[c];
+      dl[c] = r % 3 - 1;
+      r /= 3;
+    }
+  }
+  int nb = 0, lb[3] = {0, 0, 0}, len[3] = {1, 1, 1}, e0[3] = {0, 0, 0}, cnt = 1;
+  for (int c = 0; c < D; ++c) {
+    int t = bc[c] + dl[c];
+    t = t < 0 ? t + geo.nt[c] : (t >= geo.nt[c] ? t - geo.nt[c] : t);
+    nb = nb * geo.nt[c] + t;
+    if (dl[c] == 0) {
+      lb[c] = 0;
+      len[c] = T;
+      e0[c] = M;
+    } else if (dl[c] < 0) {
+      lb[c] = 0;
+      len[c] = M + 1;
+      e0[c] = T + M;
+    } else {
+      lb[c] = T - M;
+      len[c] = M;
+      e0[c] = 0;
+    }
+    cnt *= len[c];
+  }
+  const int c0 = a.tile_chunks[nb], c1 = a.tile_chunks[nb + 1];
+  if (c0 == c1) return;
+  int ecell = 1;
+  for (int c = 0; c < D; ++c) ecell *= E;
+  int eidx[kRedPerThread];
+  size_t gidx[kRedPerThread];
+  R acc[kRedPerThread];
+  int nmine = 0;
+#pragma unroll
+  for (int s = 0; s < kRedPerThread; ++s) {
+    const int i = threadIdx.x + s * kBlock;
+    eidx[s] = -1;
+    gidx[s] = 0;
+    acc[s] = R(0);
+    if (i < cnt) {
+      int rem = i, ei = 0;
+      size_t gi = 0;
+      int l[3], e[3];
+      for (int c = D - 1; c >= 0; --c) {
+        const int v = rem % len[c];
+        rem /= len[c];
+        l[c] = lb[c] + v;
+        e[c] = e0[c] + v;
+      }
+      for (int c = 0; c < D; ++c) {
+        ei = ei * E + e[c];
+        gi = gi * g + size_t(bc[c] * T + l[c]);
+      }
+      eidx[s] = ei;
+      gidx[s] = gi;
+      nmine = s + 1;
+    }
+  }
+  for (int ch = c0; ch < c1; ++ch) {
+    const R* src = a.part + size_t(ch) * ecell;
+#pragma unroll
+    for (int s = 0; s < kRedPerThread; ++s)
+      if (s < nmine && eidx[s] >= 0) acc[s] += src[eidx[s]];
+  }
+#pragma unroll
+  for (int s = 0; s < kRedPerThread; ++s)
+    if (s < nmine && eidx[s] >= 0 && acc[s] != R(0)) atomicAdd(&a.grid[gidx[s]], acc[s]);
+}
+
+template <typename R>
+hipError_t launch_spread_reduce(const ReduceArgs<R>& a, int nbins, hipStream_t st) {
+  size_t tc = 1;
+  for (int c = 0; c < a.geo.d; ++c) tc *= a.geo.T;
+  if (tc > size_t(kRedPerThread) * kBlock) return hipErrorInvalidValue;
+  const int nnb = a.geo.d == 1 ? 3 : (a.geo.d == 2 ? 9 : 27);
+  const dim3 grid(nbins * nnb);
+  if (a.geo.d == 1) hipLaunchKernelGGL((spread_reduce_kernel<R, 1>), grid, dim3(kBlock), 0, st, a);
+  else if (a.geo.d == 2) hipLaunchKernelGGL((spread_reduce_kernel<R, 2>), grid, dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL((spread_reduce_kernel<R, 3>), grid, dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+template hipError_t launch_spread_reduce<float>(const ReduceArgs<float>&, int, hipStream_t);
+template hipError_t launch_spread_reduce<double>(const ReduceArgs<double>&, int, hipStream_t);
 
 // --------------------------------------------------------------------------- block reduction
 struct Red4 {
@@ -305,19 +483,60 @@ size_t tile_bytes(const Geom& geo) {
     default: return hipErrorInvalidValue;                                                                 \
   }
 
+// Bytes of LDS per cell of the spread tile for each accumulation mode.
+template <typename R>
+int acc_mode_for(const Geom& geo, size_t* shm) {
+  size_t n = geo.E;
+  for (int c = 1; c < geo.d; ++c) n *= geo.E;
+  const size_t lds_max = 160 * 1024;
+  if (sizeof(R) == 4 && n * 8 <= lds_max) {
+    *shm = n * 8;
+    return ACC_FIX64;
+  }
+  if (sizeof(R) == 8 && n * 16 <= lds_max) {
+    *shm = n * 16;
+    return ACC_FIX128;
+  }
+  *shm = n * sizeof(R);
+  return ACC_FLOAT;
+}
+
+#define NFS_SPREAD_M(D_, R_, ACC_, NBLK, SHM, STREAM)                                                          \
+  switch (geo.M) {                                                                                             \
+    case 2: hipLaunchKernelGGL((spread_kernel<R_, D_, 2, ACC_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, a); break; \
+    case 3: hipLaunchKernelGGL((spread_kernel<R_, D_, 3, ACC_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, a); break; \
+    case 4: hipLaunchKernelGGL((spread_kernel<R_, D_, 4, ACC_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, a); break; \
+    case 5: hipLaunchKernelGGL((spread_kernel<R_, D_, 5, ACC_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, a); break; \
+    case 6: hipLaunchKernelGGL((spread_kernel<R_, D_, 6, ACC_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, a); break; \
+    case 7: hipLaunchKernelGGL((spread_kernel<R_, D_, 7, ACC_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, a); break; \
+    case 8: hipLaunchKernelGGL((spread_kernel<R_, D_, 8, ACC_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, a); break; \
+    default: return hipErrorInvalidValue;                                                                      \
+  }
+
+template <typename R, int ACC>
+hipError_t launch_spread_acc(const SpreadArgs<R>& a, int nchunks, size_t shm, hipStream_t st) {
+  const Geom& geo = a.geo;
+  if (geo.d == 1) {
+    NFS_SPREAD_M(1, R, ACC, nchunks, shm, st)
+  } else if (geo.d == 2) {
+    NFS_SPREAD_M(2, R, ACC, nchunks, shm, st)
+  } else {
+    NFS_SPREAD_M(3, R, ACC, nchunks, shm, st)
+  }
+  return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_spread(const SpreadArgs<R>& a, int nchunks, hipStream_t st) {
   if (nchunks <= 0) return hipSuccess;
-  const Geom& geo = a.geo;
-  const size_t shm = tile_bytes<R>(geo);
-  if (geo.d == 1) {
-    NFS_DISPATCH_M(1, R, spread_kernel, a, nchunks, shm, st)
-  } else if (geo.d == 2) {
-    NFS_DISPATCH_M(2, R, spread_kernel, a, nchunks, shm, st)
+  size_t shm = 0;
+  const int mode = acc_mode_for<R>(a.geo, &shm);
+  if constexpr (sizeof(R) == 4) {
+    if (mode == ACC_FIX64) return launch_spread_acc<R, ACC_FIX64>(a, nchunks, shm, st);
   } else {
-    NFS_DISPATCH_M(3, R, spread_kernel, a, nchunks, shm, st)
+    if (mode == ACC_FIX128) return launch_spread_acc<R, ACC_FIX128>(a, nchunks, shm, st);
   }
-  return hipGetLastError();
+  return launch_spread_acc<R, ACC_FLOAT>(a, nchunks, shm, st);
 }
 
 template <typename R>

@@ -256,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void spec_to_user_kernel(SpecArgs<R> a) {
     k[c] = int(rem % a.N) - a.N / 2;
     rem /= a.N;
   }
-  double f = 1.0;
+  double f = a.scale;
   for (int c = 0; c < a.d; ++c) f *= a.inv_phi[abs(k[c])];
   cplx<R> h;
   if (k[a.d - 1] >= 0) {

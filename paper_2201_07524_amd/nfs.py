@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "lib", "libnfs.so")
 
 NFS_OK, NFS_EINVAL, NFS_EWEIGHTS, NFS_ENONPOS, NFS_EUNSUPPORTED, NFS_EHIP, NFS_EWORKSPACE = range(7)
 NFS_FP64, NFS_FP32 = 0, 1
-FLAG_NO_GRAPH, FLAG_PRIMAL_COST = 1, 2
+FLAG_NO_GRAPH, FLAG_PRIMAL_COST, FLAG_TILE_REDUCE = 1, 2, 4
 
 EXPORTED = ("nfs_last_error", "nfs_validate", "nfs_workspace_size", "nfs_fastsum_apply",
             "nfs_nfft_adjoint", "nfs_nfft_trafo", "nfs_sinkhorn_solve", "nfs_sinkhorn_grad",

@@ -132,3 +132,17 @@ def test_fastsum_tile_sizes_agree():
     for tile in (8, 16, 32, 64):
         prm = nfs.Params(d=2, eps=0.01, N=128, m=8, precision="fp64", tile=tile, chunk=128)
         assert relerr(nfs.fastsum(prm, T(src), T(w), T(tgt)).cpu().numpy(), ref) <= 1e-10
+
+
+@pytest.mark.parametrize("d,N,m,tile", [(1, 256, 8, 32), (2, 128, 8, 16), (3, 32, 6, 8)])
+def test_spread_paths_agree(d, N, m, tile):
+    """LDS tiles flushed with global atomics and chunk tiles summed per
+    (tile, neighbour) give the same fast summation (both against the dense kernel)."""
+    src, w, tgt = _clouds(d, 3000, 2000, 800 + d)
+    ref = sd.gibbs_kernel(tgt, src, 2, 0.03) @ w
+    outs = []
+    for flags in (0, nfs.FLAG_TILE_REDUCE):
+        prm = nfs.Params(d=d, eps=0.03, N=N, m=m, precision="fp64", tile=tile, chunk=200, flags=flags)
+        outs.append(nfs.fastsum(prm, T(src), T(w), T(tgt)).cpu().numpy())
+        assert relerr(outs[-1], ref) <= 1e-10
+    assert relerr(outs[0], outs[1]) <= 1e-13

@@ -63,11 +63,16 @@ def test_2d_mixture_fp32_small_vs_oracle():
     assert rel(res.cost_primal, ref["cost_primal"]) <= 1e-5
     a = res.alpha.cpu().numpy()
     assert np.all(a > 0) and np.all(np.isfinite(a))
-    # scalings agree where they carry mass: compare the row marginals pi 1 = alpha o (K alpha_t)
+    # marginal error of the GPU scalings (evaluated with the exact kernel) within
+    # 10x the oracle's after the same number of iterations, plus the FP32 floor
+    # (the 1e-5 relative tolerance applied to the marginal vector)
     K = sd.gibbs_kernel(cfg["x"], cfg["y"], 2, eps)
+    e_row, e_col = sd.marginal_errors(K, a, res.alpha_t.cpu().numpy(), cfg["p"], cfg["pt"])
+    assert e_row + e_col <= 10 * ref["marg_err"] + 1e-5 * np.linalg.norm(cfg["p"])
+    # and the row marginals of the two states agree to FP32 accuracy amplified by the iteration
     row_gpu = a * (K @ res.alpha_t.cpu().numpy())
     row_ref = ref["alpha"] * (K @ ref["alpha_t"])
-    assert np.max(np.abs(row_gpu - row_ref)) <= 1e-5 * np.max(row_ref)
+    assert np.max(np.abs(row_gpu - row_ref)) <= 1e-4 * np.max(row_ref)
 
 
 def test_2d_fp64_small_vs_oracle():
