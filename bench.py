@@ -41,7 +41,7 @@ def kernel_bytes(info, d, which):
     return G * gb + n_s * (cb + 24)
 
 
-def cpu_baseline(cfg, budget_rows=2048):
+def cpu_baseline(cfg, budget_rows=8192):
     """Oracle (FP64 matrix-free direct sums in C/OpenMP) timed on a bounded
     sample: one kernel product K v over all sources for `budget_rows` sampled
     targets, scaled to the two full products of one iteration."""
