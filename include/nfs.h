@@ -172,6 +172,29 @@ int nfs_solver_profile(nfs_solver* s, int32_t iters, double* stage_ms, double* i
 int nfs_solver_destroy(nfs_solver* s);
 
 /*
+ * Batched form (the project's own): nprob independent problems that share d,
+ * r, N, m, sigma, precision, tile and chunk (prm->eps is ignored; eps[b] is
+ * problem b's temperature).  Points and weights are packed in problem order:
+ * problem b's x points are rows [sum_{c<b} n[c], sum_{c<=b} n[c]) of x (and
+ * of mu and alpha), likewise y, nu, alpha_t with nt.  n, nt, eps: host arrays.
+ * Every stage of an iteration is one kernel launch over all problems and one
+ * iteration of all problems is captured in one hipGraph.  res: host array of
+ * nprob results.  A solver made by nfs_batch_solver_create is driven with the
+ * nfs_solver_* calls above (nfs_solver_finish then fills nprob results and
+ * nfs_solver_residual returns the largest residual over the problems).
+ */
+int nfs_batch_workspace_size(const nfs_params* prm, int32_t nprob, const int64_t* n, const int64_t* nt,
+                             size_t* bytes);
+int nfs_batch_solver_create(const nfs_params* prm, int32_t nprob, const int64_t* n, const int64_t* nt,
+                            const double* eps, const double* x, const double* mu, const double* y,
+                            const double* nu, const double* alpha_t0, void* workspace, size_t ws_bytes,
+                            void* stream, nfs_solver** out);
+int nfs_batch_solve(const nfs_params* prm, int32_t nprob, const int64_t* n, const int64_t* nt,
+                    const double* eps, const double* x, const double* mu, const double* y,
+                    const double* nu, int32_t max_iter, double tol, double* alpha, double* alpha_t,
+                    nfs_result* res, void* workspace, size_t ws_bytes, void* stream);
+
+/*
  * Gradient of the Sinkhorn cost at given scalings (alpha, alpha_t), by the
  * envelope theorem applied to the dual (Proposition 2.3, eq. (14)):
  *   grad_x[i]  = sum_j pi_ij grad_x c(x_i, y_j) = -eps alpha_i (grad K * alpha_t)(x_i)   (n x d)

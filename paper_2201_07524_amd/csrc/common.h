@@ -56,12 +56,13 @@ struct Geom {
   int nt[3];    // tiles per dimension (nt[c] = ceil(g / T)), unused dims = 1
 };
 
-// A chunk is a run of at most `chunk` sorted points that share one tile.
+// A chunk is a run of at most `chunk` sorted points of one problem that share
+// one tile of that problem's grid.
 struct Chunk {
-  int tile;     // linear tile id
-  int start;    // first sorted point
+  int tile;     // linear tile id within the problem's grid
+  int start;    // first sorted point (index into the packed arrays)
   int count;    // points in the chunk
-  int pad;
+  int prob;     // problem index (0 for a single problem)
 };
 
 }  // namespace nfs

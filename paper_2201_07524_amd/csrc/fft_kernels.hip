@@ -98,14 +98,19 @@ __device__ cplx<R>* stockham(cplx<R>* A, cplx<R>* B, int L, int P, const cplx<R>
 }
 
 template <typename R>
-__device__ __forceinline__ cplx<R> apply_multiplier(cplx<R> v, const Multiplier& mu, int d, int N, int k0, int k1,
-                                                   int k2) {
+__device__ __forceinline__ R table_value(const Multiplier& mu, long prob, int d, int N, int k0, int k1, int k2) {
   const int H = N / 2 + 1;
   const int a0 = abs(k0), a1 = abs(k1), a2 = abs(k2);
   long idx = a0;
   if (d >= 2) idx = idx * H + a1;
   if (d >= 3) idx = idx * H + a2;
-  const R m = reinterpret_cast<const R*>(mu.tab)[idx];
+  return reinterpret_cast<const R*>(mu.tab)[prob * mu.tab_stride + idx];
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R> apply_multiplier(cplx<R> v, const Multiplier& mu, long prob, int d, int N, int k0,
+                                                   int k1, int k2) {
+  const R m = table_value<R>(mu, prob, d, N, k0, k1, k2);
   v.x *= m;
   v.y *= m;
   if (mu.deriv >= 0) {
@@ -164,18 +169,34 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(RowArgs<R> a) {
       }
       return;
     }
-    // FUSED1D: multiplier on I_N (symmetric set, boundary weights in the table), zero elsewhere
+    // FUSED1D: each row is one problem; pencil p packs rows a = row0+2p and
+    // b = a+1 as Z = A + iB.  With real even tables Da, Db the product
+    // Da A + i Db B is ((Da+Db)/2) Z_k + ((Da-Db)/2) conj(Z_{-k}) (zero outside
+    // the symmetric set I_N, boundary weights in the tables), times i 2 pi k for
+    // a derivative.
+    cplx<R>* other = res == A ? B : A;
     for (int i = threadIdx.x; i < P * L; i += kBlock) {
+      const int p = i >> lshift;
       const int j = i & (L - 1);
       const int kk = j <= L / 2 ? j : j - L;
-      cplx<R> v = res[i];
-      if (abs(kk) <= a.N / 2) v = apply_multiplier(v, a.mul, 1, a.N, kk, 0, 0);
-      else v = cplx<R>{R(0), R(0)};
-      res[i] = v;
+      cplx<R> v{R(0), R(0)};
+      if (abs(kk) <= a.N / 2) {
+        const long ra = row0 + 2 * p;
+        const R da = ra < a.nrows ? table_value<R>(a.mul, ra, 1, a.N, kk, 0, 0) : R(0);
+        const R db = ra + 1 < a.nrows ? table_value<R>(a.mul, ra + 1, 1, a.N, kk, 0, 0) : R(0);
+        const cplx<R> z = res[i];
+        const cplx<R> zm = cconj(res[p * L + ((L - j) & (L - 1))]);
+        const R sp = R(0.5) * (da + db), sm = R(0.5) * (da - db);
+        v = cplx<R>{sp * z.x + sm * zm.x, sp * z.y + sm * zm.y};
+        if (a.mul.deriv >= 0) {
+          const R f = R(6.283185307179586476925286766559) * R(kk);
+          v = cplx<R>{-v.y * f, v.x * f};
+        }
+      }
+      other[i] = v;
     }
     __syncthreads();
-    cplx<R>* other = res == A ? B : A;
-    cplx<R>* out = stockham(res, other, L, P, a.tw, true);
+    cplx<R>* out = stockham(other, res, L, P, a.tw, true);
     for (int i = threadIdx.x; i < 2 * P * L; i += kBlock) {
       const int r = i >> lshift;
       const int c = i & (L - 1);
@@ -265,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void axis_kernel(AxisArgs<R> a) {
           k1 = int(ii / K0) - half;
           k2 = int(ii % K0);
         }
-        v = apply_multiplier(v, a.mul, a.d, a.N, k, k1, k2);
+        v = apply_multiplier(v, a.mul, o, a.d, a.N, k, k1, k2);
       }
     }
     A[p * L + bin] = v;
@@ -285,7 +306,8 @@ __global__ __launch_bounds__(kBlock) void axis_kernel(AxisArgs<R> a) {
         const long q = q0 + p;
         cplx<R> v{R(0), R(0)};
         if (abs(k0) <= half && q < a.npen) {
-          const long ii = q % a.inner;
+          const long o = q / a.inner;
+          const long ii = q - o * a.inner;
           int k1 = 0, k2 = 0;
           if (a.d == 2) k1 = int(ii);
           else if (a.d == 3) {
@@ -293,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void axis_kernel(AxisArgs<R> a) {
             k1 = int(ii / K0) - half;
             k2 = int(ii % K0);
           }
-          v = apply_multiplier(res[i], a.mul, a.d, a.N, k0, k1, k2);
+          v = apply_multiplier(res[i], a.mul, o, a.d, a.N, k0, k1, k2);
         }
         res[i] = v;
       }

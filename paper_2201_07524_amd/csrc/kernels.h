@@ -16,10 +16,11 @@ struct SpreadArgs {
   Geom geo;
   const R* coords;       // sorted tile-local coordinates, n x d
   const double* w;       // sorted weights
-  const double* wmul;    // device scalar multiplier of the weights (nullable)
+  const double* wmul;    // per-problem multiplier of the weights, indexed by chunk.prob (nullable)
   double wconst;         // host constant multiplier of the weights
   const Chunk* chunks;
-  R* grid;               // g^d real grid, must be zero on entry (atomic flush only)
+  R* grid;               // problem p's g^d real grid at grid + p*grid_stride, zero on entry
+  long grid_stride;
   R* part;               // non-null: store each chunk's padded tile here instead of flushing
   WindowConst win;
 };
@@ -42,10 +43,11 @@ struct InterpArgs {
   Geom geo;
   const R* coords;
   const Chunk* chunks;
-  const R* grid;
+  const R* grid;            // problem p's grid at grid + p*grid_stride
+  long grid_stride;
   WindowConst win;
   double norm;              // constant factor of the result
-  const double* wmul_src;   // the result is divided by *wmul_src (nullable)
+  const double* wmul_src;   // the result is divided by wmul_src[prob] (nullable)
   int epi;
   // EPI_OUT
   const int* perm;
@@ -57,9 +59,11 @@ struct InterpArgs {
   const double* p;
   double* alpha;
   double* partials;         // 4 doubles per chunk
-  unsigned* counter;        // zero on entry, left zero
-  double* stats;            // 4 doubles: residual^2 sum, mass sum, max alpha, count(t <= 0)
-  double* wmul_next;        // receives 1/max alpha (nullable)
+  unsigned* counter;        // per problem, zero on entry, left zero
+  const int* prob_chunks;   // B + 1: chunks of problem p are [prob_chunks[p], prob_chunks[p+1])
+  double* stats;            // per problem (stride 8): residual^2 sum, mass sum, max alpha, count(t <= 0),
+                            // running count
+  double* wmul_next;        // per problem, receives 1/max alpha (nullable)
 };
 
 template <typename R>
@@ -72,8 +76,9 @@ hipError_t launch_interp(const InterpArgs<R>& a, int nchunks, hipStream_t st);
 // (table of extent H = N/2+1 per dimension, row-major), optionally times
 // i 2 pi k_c for the derivative axis c (deriv < 0: none).
 struct Multiplier {
-  const void* tab;   // R table, (N/2+1)^d entries
+  const void* tab;   // R table, (N/2+1)^d entries per problem
   int deriv;         // -1 or derivative axis
+  long tab_stride;   // entries between the tables of consecutive problems
 };
 
 enum RowMode : int { ROW_R2C = 0, ROW_C2R = 1, ROW_FUSED1D = 2 };
@@ -149,10 +154,11 @@ struct ScatterArgs {
   double center[3];
   double scale;
   const int* keys;
-  const int* offsets;
+  const int* offsets;  // per tile: global first position
   int* cursor;
-  R* coords;          // sorted tile-local coordinates
-  int* perm;          // sorted -> original index
+  R* coords;          // sorted tile-local coordinates (global positions)
+  int* perm;          // sorted -> original index (global)
+  int idx_base;       // added to the local point index when writing perm
   const double* w0;   // optional gathered vectors (nullable)
   double* w0s;
   const double* w1;

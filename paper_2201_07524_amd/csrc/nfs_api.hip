@@ -1,7 +1,13 @@
 // C ABI of the NFFT-boosted Sinkhorn library: argument checks, workspace
 // layout, the plan stage (torus scaling, binning), the fast-summation chain
 // and the Sinkhorn iteration (Algorithm 3) with hipGraph replay.
+//
+// Everything is written for a batch of B independent problems that share d,
+// N, m and sigma (so one grid geometry): every stage is one kernel launch
+// over all problems (chunks carry their problem index, grids and diagonal
+// tables are stacked per problem).  A single problem is the batch B = 1.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -89,62 +95,72 @@ struct Carver {
   }
 };
 
+// One point set (x or y) of every problem, packed in problem order.
 template <typename R>
 struct CloudBuf {
-  long n = 0;
-  R* coords = nullptr;
-  int* perm = nullptr;
+  long n = 0;                 // total points
+  std::vector<long> off;      // B + 1 host offsets into the packed arrays
+  R* coords = nullptr;        // sorted tile-local coordinates
+  int* perm = nullptr;        // sorted position -> packed input index
   int* keys = nullptr;
-  int* counts = nullptr;
-  int* offsets = nullptr;
-  int* cursor = nullptr;
+  int* counts = nullptr;      // B x nbins
+  int* offsets = nullptr;     // B x nbins (global positions)
+  int* cursor = nullptr;      // B x nbins
   Chunk* chunks = nullptr;
-  int* tile_chunks = nullptr;  // nbins + 1: chunks of tile b are [tile_chunks[b], tile_chunks[b+1])
   long max_chunks = 0;
   int nchunks = 0;
-  double* w0s = nullptr;  // sorted first vector (weights)
-  double* w1s = nullptr;  // sorted second vector (scalings)
+  int* prob_chunks = nullptr;  // B + 1: chunks of problem b
+  int* tile_chunks = nullptr;  // nbins + 1 (single problem, per-tile reduction only)
+  double* w0s = nullptr;       // sorted weights
+  double* w1s = nullptr;       // sorted scalings
 };
 
 template <typename R>
 struct Work {
+  int B = 1;
   Geom geo{};
   WindowConst win{};
   int K0 = 0, nbins = 0, chunk = 0;
-  long ncell = 0;
-  CloudBuf<R> A, B;  // A: x / sources, B: y / targets
-  bool two_level = false;  // chunk tiles + per-tile gather instead of global atomics
-  R* part = nullptr;       // chunk tiles (two_level)
-  long ecell = 0;          // values per chunk tile, E^d
-  R* S = nullptr;    // spread grid
-  R* U = nullptr;    // interpolation grid
+  long ncell = 0;     // g^d
+  long H = 0;         // diagonal table entries per problem, (N/2+1)^d
+  CloudBuf<R> X, Y;   // X: x / sources, Y: y / targets
+  bool two_level = false;
+  R* part = nullptr;
+  long ecell = 0;
+  R* S = nullptr;     // B spread grids
+  R* U = nullptr;     // B interpolation grids
   cplx<R>* W = nullptr;
   cplx<R>* V = nullptr;
   cplx<R>* spec = nullptr;
   cplx<R>* tw = nullptr;
-  R* dtab = nullptr;
-  R* dtab2 = nullptr;
+  R* dtab = nullptr;   // B kernel tables
+  R* dtab2 = nullptr;  // B cost tables
   double* inv_phi = nullptr;
   double* partials = nullptr;
-  unsigned* counters = nullptr;
-  double* stats = nullptr;
+  unsigned* ct_interp = nullptr;  // B
+  unsigned* ct_misc = nullptr;    // 8
+  double* st_row = nullptr;   // B x 8
+  double* st_col = nullptr;   // B x 8
+  double* st_eval = nullptr;  // B x 8
+  double* st_rdx = nullptr;   // B x 4
+  double* st_rdy = nullptr;   // B x 4
+  double* st_cost = nullptr;  // B x 4
+  double* wmul_x = nullptr;   // B
+  double* wmul_y = nullptr;   // B
+  double* st_box = nullptr;   // B x 20 + 20: per problem, x box at 0, y weight box at 10
   double* tmp = nullptr;
+  std::vector<Scaling> sc;
   size_t bytes = 0;
 };
 
-enum StatSlot : int {
-  ST_ROW = 0, ST_COL = 8, ST_EVAL = 16, ST_RD_X = 24, ST_RD_Y = 28, ST_WMUL_X = 32, ST_WMUL_Y = 33,
-  ST_BOX = 40, ST_BOX2 = 52, ST_LOGMEAN = 64, ST_MISC = 72, ST_TOTAL = 128
-};
-enum CounterSlot : int { CT_INTERP = 0, CT_BOX = 1, CT_RD = 2, CT_TOTAL = 16 };
-
 template <typename R>
-static void carve(Work<R>& w, const nfs_params* p, long nA, long nB, char* base, int kind_vectors) {
+static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char* base, int nvec) {
   Carver cv{base};
   const int d = p->d;
   const int g = grid_size(p);
   const int T = p->tile ? p->tile : default_tile(d, p->precision);
   const int chunk = p->chunk ? p->chunk : 1024;
+  w.B = B;
   w.chunk = chunk;
   w.geo.d = d;
   w.geo.g = g;
@@ -159,154 +175,86 @@ static void carve(Work<R>& w, const nfs_params* p, long nA, long nB, char* base,
   }
   w.nbins = nbins;
   w.K0 = p->N / 2 + 1;
-  long ncell = 1;
-  for (int c = 0; c < d; ++c) ncell *= g;
+  long ncell = 1, H = 1;
+  for (int c = 0; c < d; ++c) {
+    ncell *= g;
+    H *= w.K0;
+  }
   w.ncell = ncell;
-  auto cloud = [&](CloudBuf<R>& cb, long n, int nvec) {
+  w.H = H;
+  auto cloud = [&](CloudBuf<R>& cb, long n) {
     cb.n = n;
     cb.coords = cv.take<R>(size_t(n) * d);
     cb.perm = cv.take<int>(n);
     cb.keys = cv.take<int>(n);
-    cb.counts = cv.take<int>(nbins);
-    cb.offsets = cv.take<int>(nbins);
-    cb.cursor = cv.take<int>(nbins);
-    cb.max_chunks = n / chunk + std::min<long>(nbins, n) + 1;
+    cb.counts = cv.take<int>(size_t(B) * nbins);
+    cb.offsets = cv.take<int>(size_t(B) * nbins);
+    cb.cursor = cv.take<int>(size_t(B) * nbins);
+    cb.max_chunks = n / chunk + std::min<long>(long(B) * nbins, n) + B + 1;
     cb.chunks = cv.take<Chunk>(cb.max_chunks);
+    cb.prob_chunks = cv.take<int>(B + 1);
     cb.tile_chunks = cv.take<int>(nbins + 1);
     cb.w0s = nvec >= 1 ? cv.take<double>(n) : nullptr;
     cb.w1s = nvec >= 2 ? cv.take<double>(n) : nullptr;
   };
-  cloud(w.A, nA, kind_vectors);
-  cloud(w.B, nB, kind_vectors);
-  long ecell = 1;
-  for (int c = 0; c < d; ++c) ecell *= w.geo.E;
+  cloud(w.X, nA);
+  cloud(w.Y, nB);
+  long ecell = 1, tcells = 1;
+  for (int c = 0; c < d; ++c) {
+    ecell *= w.geo.E;
+    tcells *= T;
+  }
   w.ecell = ecell;
-  long tcells = 1;
-  for (int c = 0; c < d; ++c) tcells *= T;
-  bool two = (p->flags & NFS_FLAG_TILE_REDUCE) && T >= p->m + 1 && (g % T) == 0 && tcells <= 2048;
+  bool two = (p->flags & NFS_FLAG_TILE_REDUCE) && B == 1 && T >= p->m + 1 && (g % T) == 0 && tcells <= 2048;
   for (int c = 0; c < d; ++c) two = two && w.geo.nt[c] >= 3;
   w.two_level = two;
-  w.part = two ? cv.take<R>(size_t(std::max(w.A.max_chunks, w.B.max_chunks)) * ecell) : nullptr;
-  w.S = cv.take<R>(ncell);
-  w.U = cv.take<R>(ncell);
+  w.part = two ? cv.take<R>(size_t(std::max(w.X.max_chunks, w.Y.max_chunks)) * ecell) : nullptr;
+  w.S = cv.take<R>(size_t(B) * ncell);
+  w.U = cv.take<R>(size_t(B) * ncell);
   const long rows = ncell / g;
-  w.W = cv.take<cplx<R>>(size_t(rows) * w.K0);
-  w.V = d == 3 ? cv.take<cplx<R>>(size_t(g) * (p->N + 1) * w.K0) : nullptr;
+  w.W = cv.take<cplx<R>>(size_t(B) * rows * w.K0);
+  w.V = d == 3 ? cv.take<cplx<R>>(size_t(B) * g * (p->N + 1) * w.K0) : nullptr;
   long spec_n = w.K0;
   for (int c = 0; c < d - 1; ++c) spec_n *= (p->N + 1);
   w.spec = cv.take<cplx<R>>(spec_n);
   w.tw = cv.take<cplx<R>>(g);
-  long H = 1;
-  for (int c = 0; c < d; ++c) H *= w.K0;
-  w.dtab = cv.take<R>(H);
-  w.dtab2 = cv.take<R>(H);
+  w.dtab = cv.take<R>(size_t(B) * H);
+  w.dtab2 = cv.take<R>(size_t(B) * H);
   w.inv_phi = cv.take<double>(w.K0);
-  const long maxch = std::max(w.A.max_chunks, w.B.max_chunks);
+  const long maxch = std::max(w.X.max_chunks, w.Y.max_chunks);
   w.partials = cv.take<double>(size_t(std::max<long>(maxch, 1024)) * 9);
-  w.counters = cv.take<unsigned>(CT_TOTAL);
-  w.stats = cv.take<double>(ST_TOTAL);
-  w.tmp = cv.take<double>(std::max(nA, nB) * std::max(d, 1));
+  w.ct_interp = cv.take<unsigned>(B);
+  w.ct_misc = cv.take<unsigned>(8);
+  w.st_row = cv.take<double>(size_t(B) * 8);
+  w.st_col = cv.take<double>(size_t(B) * 8);
+  w.st_eval = cv.take<double>(size_t(B) * 8);
+  w.st_rdx = cv.take<double>(size_t(B) * 4);
+  w.st_rdy = cv.take<double>(size_t(B) * 4);
+  w.st_cost = cv.take<double>(size_t(B) * 4);
+  w.wmul_x = cv.take<double>(B);
+  w.wmul_y = cv.take<double>(B);
+  w.st_box = cv.take<double>(size_t(B) * 20 + 20);
+  w.tmp = cv.take<double>(size_t(std::max(nA, nB)) * std::max(d, 1));
   w.bytes = cv.off + 256;
   w.win = make_window(p->m, g, p->N);
 }
 
+// Zero the counters and statistics (fill kernels, so a later graph capture
+// never records a memset).
+template <typename R>
+static int zero_state(Work<R>& w, hipStream_t st) {
+  NFS_HIP(launch_fill(w.ct_interp, sizeof(unsigned) * w.B, st));
+  NFS_HIP(launch_fill(w.ct_misc, sizeof(unsigned) * 8, st));
+  for (double* s : {w.st_row, w.st_col, w.st_eval}) NFS_HIP(launch_fill(s, sizeof(double) * 8 * w.B, st));
+  for (double* s : {w.st_rdx, w.st_rdy, w.st_cost}) NFS_HIP(launch_fill(s, sizeof(double) * 4 * w.B, st));
+  return NFS_OK;
+}
+
 // ----------------------------------------------------------------------------- plan stage
-template <typename R>
-static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const Scaling& sc, const double* v0,
-                      const double* v1, hipStream_t st) {
-  const Geom& geo = w.geo;
-  NFS_HIP(launch_fill(cb.counts, sizeof(int) * w.nbins, st));
-  NFS_HIP(launch_fill(cb.cursor, sizeof(int) * w.nbins, st));
-  KeyArgs ka{};
-  ka.pts = pts;
-  ka.n = cb.n;
-  ka.d = geo.d;
-  ka.g = geo.g;
-  ka.T = geo.T;
-  for (int c = 0; c < 3; ++c) {
-    ka.nt[c] = geo.nt[c];
-    ka.center[c] = sc.center[c];
-  }
-  ka.scale = sc.scale;
-  ka.keys = cb.keys;
-  ka.counts = cb.counts;
-  NFS_HIP(launch_keys(ka, st));
-  std::vector<int> counts(w.nbins), offsets(w.nbins);
-  NFS_HIP(hipMemcpyAsync(counts.data(), cb.counts, sizeof(int) * w.nbins, hipMemcpyDeviceToHost, st));
-  NFS_HIP(hipStreamSynchronize(st));
-  std::vector<Chunk> chunks;
-  std::vector<int> tile_chunks(w.nbins + 1);
-  chunks.reserve(cb.max_chunks);
-  int acc = 0;
-  for (int b = 0; b < w.nbins; ++b) {
-    offsets[b] = acc;
-    tile_chunks[b] = int(chunks.size());
-    for (int s = 0; s < counts[b]; s += w.chunk) chunks.push_back(Chunk{b, acc + s, std::min(w.chunk, counts[b] - s), 0});
-    acc += counts[b];
-  }
-  tile_chunks[w.nbins] = int(chunks.size());
-  if ((long)chunks.size() > cb.max_chunks) return fail(NFS_EINVAL, "internal: chunk table overflow");
-  cb.nchunks = int(chunks.size());
-  NFS_HIP(hipMemcpyAsync(cb.offsets, offsets.data(), sizeof(int) * w.nbins, hipMemcpyHostToDevice, st));
-  NFS_HIP(hipMemcpyAsync(cb.chunks, chunks.data(), sizeof(Chunk) * chunks.size(), hipMemcpyHostToDevice, st));
-  NFS_HIP(hipMemcpyAsync(cb.tile_chunks, tile_chunks.data(), sizeof(int) * (w.nbins + 1), hipMemcpyHostToDevice, st));
-  ScatterArgs<R> sa{};
-  sa.pts = pts;
-  sa.n = cb.n;
-  sa.d = geo.d;
-  sa.g = geo.g;
-  sa.T = geo.T;
-  for (int c = 0; c < 3; ++c) {
-    sa.nt[c] = geo.nt[c];
-    sa.center[c] = sc.center[c];
-  }
-  sa.scale = sc.scale;
-  sa.keys = cb.keys;
-  sa.offsets = cb.offsets;
-  sa.cursor = cb.cursor;
-  sa.coords = cb.coords;
-  sa.perm = cb.perm;
-  sa.w0 = v0;
-  sa.w0s = cb.w0s;
-  sa.w1 = v1;
-  sa.w1s = cb.w1s;
-  NFS_HIP(launch_scatter(sa, st));
-  NFS_HIP(hipStreamSynchronize(st));  // host vectors above must outlive the copies
-  return NFS_OK;
-}
-
-template <typename R>
-static int upload_tables(Work<R>& w, const nfs_params* p, const Scaling& sc, hipStream_t st) {
-  const int g = w.geo.g;
-  std::vector<cplx<R>> tw(g);
-  for (int j = 0; j < g; ++j) {
-    const double a = -2.0 * kPi * double(j) / double(g);
-    tw[j] = cplx<R>{R(std::cos(a)), R(std::sin(a))};
-  }
-  NFS_HIP(hipMemcpyAsync(w.tw, tw.data(), sizeof(cplx<R>) * g, hipMemcpyHostToDevice, st));
-  std::vector<double> iphi(w.K0);
-  for (int k = 0; k < w.K0; ++k) iphi[k] = 1.0 / window_hat(k, p->m, g, w.win);
-  NFS_HIP(hipMemcpyAsync(w.inv_phi, iphi.data(), sizeof(double) * w.K0, hipMemcpyHostToDevice, st));
-  std::vector<R> t1, t2;
-  if (sc.eps_t > 0.0) {
-    const int d = p->d;
-    const double et = sc.eps_t;
-    auto a = diag_table(d, p->N, p->m, g, w.win, [&](double k2) { return gauss_coeff(d, et, k2); });
-    auto b = diag_table(d, p->N, p->m, g, w.win, [&](double k2) { return gauss_cost_coeff(d, et, k2); });
-    t1.assign(a.begin(), a.end());
-    t2.resize(b.size());
-    const double inv_s2 = 1.0 / (sc.scale * sc.scale);
-    for (size_t i = 0; i < b.size(); ++i) t2[i] = R(b[i] * inv_s2);
-    NFS_HIP(hipMemcpyAsync(w.dtab, t1.data(), sizeof(R) * t1.size(), hipMemcpyHostToDevice, st));
-    NFS_HIP(hipMemcpyAsync(w.dtab2, t2.data(), sizeof(R) * t2.size(), hipMemcpyHostToDevice, st));
-  }
-  NFS_HIP(hipStreamSynchronize(st));
-  return NFS_OK;
-}
-
-// Bounding box of up to two clouds plus weight statistics of one vector.
-static int box_stats(double* stats_dev, double* partials, unsigned* counter, int d, const double* p0, long n0,
-                     const double* p1, long n1, const double* w, long nw, double host_out[9], hipStream_t st) {
+// Bounding box of up to two clouds plus the statistics of one weight vector,
+// written to out[0..8] on the device (no synchronization).
+static int box_launch(double* out, double* partials, unsigned* counter, int d, const double* p0, long n0,
+                      const double* p1, long n1, const double* w, long nw, hipStream_t st) {
   BoxArgs b{};
   b.pts[0] = p0;
   b.n[0] = n0;
@@ -317,28 +265,144 @@ static int box_stats(double* stats_dev, double* partials, unsigned* counter, int
   b.d = d;
   b.partials = partials;
   b.counter = counter;
-  b.out = stats_dev;
+  b.out = out;
   NFS_HIP(launch_bbox(b, st));
-  NFS_HIP(hipMemcpyAsync(host_out, stats_dev, sizeof(double) * 9, hipMemcpyDeviceToHost, st));
+  return NFS_OK;
+}
+
+// Counting sort of every problem's points by tile, and the chunk table.
+// `sc` gives each problem's torus mapping (scale 0: points already on the torus).
+template <typename R>
+static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const std::vector<Scaling>& sc,
+                      const double* v0, const double* v1, hipStream_t st) {
+  const Geom& geo = w.geo;
+  const int B = w.B, nb = w.nbins, d = geo.d;
+  NFS_HIP(launch_fill(cb.counts, sizeof(int) * size_t(B) * nb, st));
+  NFS_HIP(launch_fill(cb.cursor, sizeof(int) * size_t(B) * nb, st));
+  for (int b = 0; b < B; ++b) {
+    const long o = cb.off[b], n = cb.off[b + 1] - o;
+    if (n == 0) continue;
+    KeyArgs ka{};
+    ka.pts = pts + o * d;
+    ka.n = n;
+    ka.d = d;
+    ka.g = geo.g;
+    ka.T = geo.T;
+    for (int c = 0; c < 3; ++c) {
+      ka.nt[c] = geo.nt[c];
+      ka.center[c] = sc[b].center[c];
+    }
+    ka.scale = sc[b].scale;
+    ka.keys = cb.keys + o;
+    ka.counts = cb.counts + size_t(b) * nb;
+    NFS_HIP(launch_keys(ka, st));
+  }
+  std::vector<int> counts(size_t(B) * nb), offsets(size_t(B) * nb);
+  NFS_HIP(hipMemcpyAsync(counts.data(), cb.counts, sizeof(int) * counts.size(), hipMemcpyDeviceToHost, st));
+  NFS_HIP(hipStreamSynchronize(st));
+  std::vector<Chunk> chunks;
+  std::vector<int> prob_chunks(B + 1), tile_chunks(nb + 1);
+  chunks.reserve(cb.max_chunks);
+  for (int b = 0; b < B; ++b) {
+    prob_chunks[b] = int(chunks.size());
+    long acc = cb.off[b];
+    for (int t = 0; t < nb; ++t) {
+      const int cnt = counts[size_t(b) * nb + t];
+      offsets[size_t(b) * nb + t] = int(acc);
+      if (B == 1) tile_chunks[t] = int(chunks.size());
+      for (int s = 0; s < cnt; s += w.chunk) chunks.push_back(Chunk{t, int(acc) + s, std::min(w.chunk, cnt - s), b});
+      acc += cnt;
+    }
+    if (acc != cb.off[b + 1]) return fail(NFS_EINVAL, "internal: tile histogram does not match the point count");
+  }
+  prob_chunks[B] = int(chunks.size());
+  tile_chunks[nb] = int(chunks.size());
+  if ((long)chunks.size() > cb.max_chunks) return fail(NFS_EINVAL, "internal: chunk table overflow");
+  cb.nchunks = int(chunks.size());
+  NFS_HIP(hipMemcpyAsync(cb.offsets, offsets.data(), sizeof(int) * offsets.size(), hipMemcpyHostToDevice, st));
+  NFS_HIP(hipMemcpyAsync(cb.chunks, chunks.data(), sizeof(Chunk) * chunks.size(), hipMemcpyHostToDevice, st));
+  NFS_HIP(hipMemcpyAsync(cb.prob_chunks, prob_chunks.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, st));
+  NFS_HIP(hipMemcpyAsync(cb.tile_chunks, tile_chunks.data(), sizeof(int) * (nb + 1), hipMemcpyHostToDevice, st));
+  for (int b = 0; b < B; ++b) {
+    const long o = cb.off[b], n = cb.off[b + 1] - o;
+    if (n == 0) continue;
+    ScatterArgs<R> sa{};
+    sa.pts = pts + o * d;
+    sa.n = n;
+    sa.d = d;
+    sa.g = geo.g;
+    sa.T = geo.T;
+    for (int c = 0; c < 3; ++c) {
+      sa.nt[c] = geo.nt[c];
+      sa.center[c] = sc[b].center[c];
+    }
+    sa.scale = sc[b].scale;
+    sa.keys = cb.keys + o;
+    sa.offsets = cb.offsets + size_t(b) * nb;
+    sa.cursor = cb.cursor + size_t(b) * nb;
+    sa.coords = cb.coords;
+    sa.perm = cb.perm;
+    sa.idx_base = int(o);
+    sa.w0 = v0 ? v0 + o : nullptr;
+    sa.w0s = cb.w0s;
+    sa.w1 = v1 ? v1 + o : nullptr;
+    sa.w1s = cb.w1s;
+    NFS_HIP(launch_scatter(sa, st));
+  }
+  NFS_HIP(hipStreamSynchronize(st));  // host vectors above must outlive the copies
+  return NFS_OK;
+}
+
+template <typename R>
+static int upload_tables(Work<R>& w, const nfs_params* p, hipStream_t st) {
+  const int g = w.geo.g;
+  std::vector<cplx<R>> tw(g);
+  for (int j = 0; j < g; ++j) {
+    const double a = -2.0 * kPi * double(j) / double(g);
+    tw[j] = cplx<R>{R(std::cos(a)), R(std::sin(a))};
+  }
+  NFS_HIP(hipMemcpyAsync(w.tw, tw.data(), sizeof(cplx<R>) * g, hipMemcpyHostToDevice, st));
+  const std::vector<double> phi = window_hat_table(p->N, p->m, g, w.win);
+  std::vector<double> iphi(w.K0);
+  for (int k = 0; k < w.K0; ++k) iphi[k] = 1.0 / phi[k];
+  NFS_HIP(hipMemcpyAsync(w.inv_phi, iphi.data(), sizeof(double) * w.K0, hipMemcpyHostToDevice, st));
+  std::vector<R> t1, t2;
+  bool any = false;
+  for (int b = 0; b < w.B; ++b) any = any || w.sc[b].eps_t > 0.0;
+  if (any) {
+    t1.resize(size_t(w.B) * w.H);
+    t2.resize(size_t(w.B) * w.H);
+    for (int b = 0; b < w.B; ++b) {
+      if (!(w.sc[b].eps_t > 0.0)) continue;
+      const DiagTables tb = gauss_tables(p->d, p->N, w.sc[b].eps_t, w.sc[b].scale, phi);
+      for (long i = 0; i < w.H; ++i) {
+        t1[size_t(b) * w.H + i] = R(tb.kernel[i]);
+        t2[size_t(b) * w.H + i] = R(tb.cost[i]);
+      }
+    }
+    NFS_HIP(hipMemcpyAsync(w.dtab, t1.data(), sizeof(R) * t1.size(), hipMemcpyHostToDevice, st));
+    NFS_HIP(hipMemcpyAsync(w.dtab2, t2.data(), sizeof(R) * t2.size(), hipMemcpyHostToDevice, st));
+  }
   NFS_HIP(hipStreamSynchronize(st));
   return NFS_OK;
 }
 
 // ----------------------------------------------------------------------------- the fast-summation chain
-// grid S (spread, zero on entry) -> U, with the multiplier applied in LDS.
-// S is left zero for the next spread.
+// B stacked grids S (zero on entry) -> U, with the per-problem multiplier
+// applied in LDS between the forward and inverse passes of axis 0.  The
+// forward pass zeroes S again after reading it.
 template <typename R>
 static hipError_t fft_chain(Work<R>& w, const R* table, int deriv, hipStream_t st) {
   const Geom& geo = w.geo;
-  const int g = geo.g, N = geo.N, d = geo.d, K0 = w.K0;
-  Multiplier mu{table, deriv};
+  const int g = geo.g, N = geo.N, d = geo.d, K0 = w.K0, B = w.B;
+  Multiplier mu{table, deriv, w.H};
   hipError_t e;
   if (d == 1) {
     RowArgs<R> ra{};
     ra.mode = ROW_FUSED1D;
     ra.L = g;
     ra.N = N;
-    ra.nrows = 1;
+    ra.nrows = B;
     ra.real_in = w.S;
     ra.real_io = w.U;
     ra.zero_src = 1;
@@ -346,12 +410,12 @@ static hipError_t fft_chain(Work<R>& w, const R* table, int deriv, hipStream_t s
     ra.mul = mu;
     return launch_rows(ra, st);
   }
-  const long rows = w.ncell / g;
+  const long rows = w.ncell / g;  // per problem
   RowArgs<R> ra{};
   ra.mode = ROW_R2C;
   ra.L = g;
   ra.N = N;
-  ra.nrows = int(rows);
+  ra.nrows = int(rows * B);
   ra.real_io = w.S;
   ra.spec = w.W;
   ra.zero_src = 1;
@@ -370,12 +434,12 @@ static hipError_t fft_chain(Work<R>& w, const R* table, int deriv, hipStream_t s
     ax.nin = g;
     ax.nout = g;
     ax.in_stride = ax.out_stride = K0;
-    ax.in_ostride = ax.out_ostride = 0;
+    ax.in_ostride = ax.out_ostride = long(g) * K0;
     ax.inner = K0;
-    ax.npen = K0;
+    ax.npen = long(B) * K0;
     if ((e = launch_axis(ax, st)) != hipSuccess) return e;
   } else {
-    // axis 1 forward: W[l0][l1][k2] -> V[l0][k1'][k2]
+    // axis 1 forward: W[b l0][l1][k2] -> V[b l0][k1'][k2]
     AxisArgs<R> a1 = ax;
     a1.mode = AX_FWD;
     a1.in = w.W;
@@ -388,8 +452,9 @@ static hipError_t fft_chain(Work<R>& w, const R* table, int deriv, hipStream_t s
     a1.in_ostride = long(g) * K0;
     a1.out_ostride = long(N + 1) * K0;
     a1.inner = K0;
-    a1.npen = long(g) * K0;
+    a1.npen = long(B) * g * K0;
     if ((e = launch_axis(a1, st)) != hipSuccess) return e;
+    // axis 0 fused: V[b][l0][k1' k2], one problem per outer group
     AxisArgs<R> a0 = ax;
     a0.mode = AX_FUSED;
     a0.in = w.V;
@@ -397,9 +462,9 @@ static hipError_t fft_chain(Work<R>& w, const R* table, int deriv, hipStream_t s
     a0.nin = g;
     a0.nout = g;
     a0.in_stride = a0.out_stride = long(N + 1) * K0;
-    a0.in_ostride = a0.out_ostride = 0;
+    a0.in_ostride = a0.out_ostride = long(g) * (N + 1) * K0;
     a0.inner = (N + 1) * K0;
-    a0.npen = long(N + 1) * K0;
+    a0.npen = long(B) * (N + 1) * K0;
     if ((e = launch_axis(a0, st)) != hipSuccess) return e;
     AxisArgs<R> a2 = ax;
     a2.mode = AX_INV;
@@ -413,14 +478,14 @@ static hipError_t fft_chain(Work<R>& w, const R* table, int deriv, hipStream_t s
     a2.in_ostride = long(N + 1) * K0;
     a2.out_ostride = long(g) * K0;
     a2.inner = K0;
-    a2.npen = long(g) * K0;
+    a2.npen = long(B) * g * K0;
     if ((e = launch_axis(a2, st)) != hipSuccess) return e;
   }
   RowArgs<R> rb{};
   rb.mode = ROW_C2R;
   rb.L = g;
   rb.N = N;
-  rb.nrows = int(rows);
+  rb.nrows = int(rows * B);
   rb.real_io = w.U;
   rb.spec = w.W;
   rb.tw = w.tw;
@@ -437,13 +502,14 @@ static SpreadArgs<R> spread_args(Work<R>& w, const CloudBuf<R>& src, const doubl
   a.wconst = 1.0;
   a.chunks = src.chunks;
   a.grid = w.S;
+  a.grid_stride = w.ncell;
   a.win = w.win;
   return a;
 }
 
-// Spreading into the grid S (zero on entry; the forward FFT pass zeroes it
-// again after reading): either chunk tiles summed per (tile, neighbour) or LDS
-// tiles flushed straight to the grid with global atomics.
+// Spreading into the grids S (zero on entry): LDS tiles flushed straight to
+// the grid with global atomics, or (single problem, NFS_FLAG_TILE_REDUCE)
+// chunk tiles summed per (tile, neighbour).
 template <typename R>
 static hipError_t spread(Work<R>& w, const CloudBuf<R>& src, const double* weights, const double* wmul,
                          double wconst, hipStream_t st) {
@@ -468,6 +534,7 @@ static InterpArgs<R> interp_args(Work<R>& w, const CloudBuf<R>& tgt, int epi, co
   a.coords = tgt.coords;
   a.chunks = tgt.chunks;
   a.grid = w.U;
+  a.grid_stride = w.ncell;
   a.win = w.win;
   a.norm = 1.0;
   a.wmul_src = wmul_src;
@@ -475,12 +542,14 @@ static InterpArgs<R> interp_args(Work<R>& w, const CloudBuf<R>& tgt, int epi, co
   a.perm = tgt.perm;
   a.out_stride = 1;
   a.partials = w.partials;
-  a.counter = w.counters + CT_INTERP;
+  a.counter = w.ct_interp;
+  a.prob_chunks = tgt.prob_chunks;
   return a;
 }
 
-// One Sinkhorn half-step: spread the scalings of `src`, transform, and update
-// (or evaluate) the scalings of `tgt` (eq. (S1) via eq. (fastsum)).
+// One Sinkhorn half-step for every problem: spread the scalings of `src`,
+// transform, and update (or evaluate) the scalings of `tgt` (eq. (S1) via
+// eq. (fastsum)).
 template <typename R>
 static hipError_t half_step(Work<R>& w, CloudBuf<R>& src, CloudBuf<R>& tgt, double* wmul_src, double* wmul_tgt,
                             double* stats, int epi, hipStream_t st) {
@@ -495,32 +564,35 @@ static hipError_t half_step(Work<R>& w, CloudBuf<R>& src, CloudBuf<R>& tgt, doub
   return launch_interp(ia, tgt.nchunks, st);
 }
 
-// ----------------------------------------------------------------------------- entry point bodies
+// ----------------------------------------------------------------------------- fast summation / NFFT
 template <typename R>
 static int do_fastsum(const nfs_params* p, const double* src, int64_t ns, const double* wv, const double* tgt,
                       int64_t nt, double* out, void* ws, size_t wsb, hipStream_t st) {
   Work<R> w;
-  carve(w, p, ns, nt, nullptr, 1);
+  carve(w, p, 1, ns, nt, nullptr, 1);
   if (wsb < w.bytes) return fail(NFS_EWORKSPACE, "workspace too small");
-  carve(w, p, ns, nt, static_cast<char*>(ws), 1);
-  NFS_HIP(launch_fill(w.counters, sizeof(unsigned) * CT_TOTAL, st));
-  NFS_HIP(launch_fill(w.stats, sizeof(double) * ST_TOTAL, st));
+  carve(w, p, 1, ns, nt, static_cast<char*>(ws), 1);
+  w.X.off = {0, ns};
+  w.Y.off = {0, nt};
+  NFS_TRY(zero_state(w, st));
   double box[9];
-  NFS_TRY(box_stats(w.stats + ST_BOX, w.partials, w.counters + CT_BOX, p->d, src, ns, tgt, nt, wv, ns, box, st));
+  NFS_TRY(box_launch(w.st_box, w.partials, w.ct_misc, p->d, src, ns, tgt, nt, wv, ns, st));
+  NFS_HIP(hipMemcpyAsync(box, w.st_box, sizeof(box), hipMemcpyDeviceToHost, st));
+  NFS_HIP(hipStreamSynchronize(st));
   for (int i = 0; i < 9; ++i)
     if (!std::isfinite(box[i])) return fail(NFS_EINVAL, "non-finite point coordinates or weights");
-  Scaling sc = choose_scaling(p->d, p->r, p->eps, p->N, box, box + 3);
-  NFS_TRY(sort_cloud(w, w.A, src, sc, wv, nullptr, st));
-  NFS_TRY(sort_cloud(w, w.B, tgt, sc, nullptr, nullptr, st));
-  NFS_TRY(upload_tables(w, p, sc, st));
+  w.sc = {choose_scaling(p->d, p->r, p->eps, p->N, box, box + 3)};
+  NFS_TRY(sort_cloud(w, w.X, src, w.sc, wv, nullptr, st));
+  NFS_TRY(sort_cloud(w, w.Y, tgt, w.sc, nullptr, nullptr, st));
+  NFS_TRY(upload_tables(w, p, st));
   NFS_HIP(launch_fill(w.S, sizeof(R) * w.ncell, st));
   const double wmax = box[6] > 0.0 ? box[6] : 1.0;
-  NFS_HIP(spread(w, w.A, w.A.w0s, nullptr, 1.0 / wmax, st));
+  NFS_HIP(spread(w, w.X, w.X.w0s, nullptr, 1.0 / wmax, st));
   NFS_HIP(fft_chain(w, w.dtab, -1, st));
-  InterpArgs<R> ia = interp_args(w, w.B, EPI_OUT, nullptr);
+  InterpArgs<R> ia = interp_args(w, w.Y, EPI_OUT, nullptr);
   ia.norm = wmax;
   ia.out = out;
-  NFS_HIP(launch_interp(ia, w.B.nchunks, st));
+  NFS_HIP(launch_interp(ia, w.Y.nchunks, st));
   NFS_HIP(hipStreamSynchronize(st));
   return NFS_OK;
 }
@@ -529,19 +601,23 @@ template <typename R>
 static int do_nfft(const nfs_params* p, bool adjoint, const double* pts, int64_t n, const double* wv,
                    const double* fhat_in, double* fhat_out, double* out, void* ws, size_t wsb, hipStream_t st) {
   Work<R> w;
-  carve(w, p, n, 1, nullptr, 1);
+  carve(w, p, 1, n, 1, nullptr, 1);
   if (wsb < w.bytes) return fail(NFS_EWORKSPACE, "workspace too small");
-  carve(w, p, n, 1, static_cast<char*>(ws), 1);
-  NFS_HIP(launch_fill(w.counters, sizeof(unsigned) * CT_TOTAL, st));
+  carve(w, p, 1, n, 1, static_cast<char*>(ws), 1);
+  w.X.off = {0, n};
+  w.Y.off = {0, 0};
+  NFS_TRY(zero_state(w, st));
   double box[9];
-  NFS_TRY(box_stats(w.stats + ST_BOX, w.partials, w.counters + CT_BOX, p->d, pts, n, nullptr, 0, wv, wv ? n : 0,
-                    box, st));
+  NFS_TRY(box_launch(w.st_box, w.partials, w.ct_misc, p->d, pts, n, nullptr, 0, wv, wv ? n : 0, st));
+  NFS_HIP(hipMemcpyAsync(box, w.st_box, sizeof(box), hipMemcpyDeviceToHost, st));
+  NFS_HIP(hipStreamSynchronize(st));
   for (int c = 0; c < p->d; ++c)
     if (!(box[c] >= -0.5) || !(box[3 + c] < 0.5)) return fail(NFS_EINVAL, "NFFT points must lie in [-1/2, 1/2)^d");
   Scaling sc{};
   sc.scale = 0.0;  // points are already torus coordinates
-  NFS_TRY(sort_cloud(w, w.A, pts, sc, wv, nullptr, st));
-  NFS_TRY(upload_tables(w, p, sc, st));
+  w.sc = {sc};
+  NFS_TRY(sort_cloud(w, w.X, pts, w.sc, wv, nullptr, st));
+  NFS_TRY(upload_tables(w, p, st));
   const Geom& geo = w.geo;
   const int g = geo.g, N = geo.N, d = geo.d, K0 = w.K0;
   const long rows = w.ncell / g;
@@ -555,12 +631,12 @@ static int do_nfft(const nfs_params* p, bool adjoint, const double* pts, int64_t
   ax.N = N;
   ax.d = d;
   ax.tw = w.tw;
-  ax.mul = Multiplier{nullptr, -1};
+  ax.mul = Multiplier{nullptr, -1, 0};
   if (adjoint) {
     NFS_HIP(launch_fill(w.S, sizeof(R) * w.ncell, st));
     // weights normalized by max |w| so every spread contribution is at most one in size
     const double wmax = box[6] > 0.0 ? box[6] : 1.0;
-    NFS_HIP(spread(w, w.A, w.A.w0s, nullptr, 1.0 / wmax, st));
+    NFS_HIP(spread(w, w.X, w.X.w0s, nullptr, 1.0 / wmax, st));
     sp.scale = wmax;
     RowArgs<R> ra{};
     ra.mode = ROW_R2C;
@@ -649,52 +725,60 @@ static int do_nfft(const nfs_params* p, bool adjoint, const double* pts, int64_t
     rb.spec = const_cast<cplx<R>*>(rows_in);
     rb.tw = w.tw;
     NFS_HIP(launch_rows(rb, st));
-    InterpArgs<R> ia = interp_args(w, w.A, EPI_OUT, nullptr);
+    InterpArgs<R> ia = interp_args(w, w.X, EPI_OUT, nullptr);
     ia.out = out;
-    NFS_HIP(launch_interp(ia, w.A.nchunks, st));
+    NFS_HIP(launch_interp(ia, w.X.nchunks, st));
   }
   NFS_HIP(hipStreamSynchronize(st));
   return NFS_OK;
 }
 
-static int check_weights(const double box[9], long n, long nt_other, const char* name) {
+// ----------------------------------------------------------------------------- Sinkhorn
+static int check_weights(const double box[9], long n, long nt_other, const char* name, int b) {
   const double tol = 1e-12 * double(std::max(n, nt_other));
-  if (box[7] < 0.0) return fail(NFS_EWEIGHTS, std::string(name) + " has a negative weight");
-  if (!(std::fabs(box[8] - 1.0) <= tol)) return fail(NFS_EWEIGHTS, std::string(name) + " does not sum to 1");
+  const std::string who = std::string(name) + (b >= 0 ? " of problem " + std::to_string(b) : "");
+  if (box[7] < 0.0) return fail(NFS_EWEIGHTS, who + " has a negative weight");
+  if (!(std::fabs(box[8] - 1.0) <= tol)) return fail(NFS_EWEIGHTS, who + " does not sum to 1");
   return NFS_OK;
 }
 
-struct SolveCtx {
-  Scaling sc;
-  double box_x[9], box_y[9];
-};
-
-// Plan shared by solve and grad: scaling from both clouds, sorting with the
+// Plan shared by solve and grad: per-problem scaling from both clouds, the
 // weights (and scalings) gathered into sorted order, tables.
 template <typename R>
-static int plan_sinkhorn(Work<R>& w, const nfs_params* p, const double* x, long n, const double* mu, const double* y,
-                         long nt, const double* nu, const double* ax, const double* ay, SolveCtx& ctx,
-                         hipStream_t st) {
-  NFS_HIP(launch_fill(w.counters, sizeof(unsigned) * CT_TOTAL, st));
-  NFS_HIP(launch_fill(w.stats, sizeof(double) * ST_TOTAL, st));
-  NFS_TRY(box_stats(w.stats + ST_BOX, w.partials, w.counters + CT_BOX, p->d, x, n, y, nt, mu, n, ctx.box_x, st));
-  NFS_TRY(box_stats(w.stats + ST_BOX2, w.partials, w.counters + CT_BOX, p->d, nullptr, 0, nullptr, 0, nu, nt,
-                    ctx.box_y, st));
-  for (int i = 0; i < 9; ++i)
-    if (!std::isfinite(ctx.box_x[i]) || !std::isfinite(ctx.box_y[i]))
-      return fail(NFS_EINVAL, "non-finite point coordinates or weights");
-  NFS_TRY(check_weights(ctx.box_x, n, nt, "mu"));
-  NFS_TRY(check_weights(ctx.box_y, nt, n, "nu"));
-  ctx.sc = choose_scaling(p->d, p->r, p->eps, p->N, ctx.box_x, ctx.box_x + 3);
-  NFS_TRY(sort_cloud(w, w.A, x, ctx.sc, mu, ax, st));
-  NFS_TRY(sort_cloud(w, w.B, y, ctx.sc, nu, ay, st));
-  NFS_TRY(upload_tables(w, p, ctx.sc, st));
-  NFS_HIP(launch_fill(w.S, sizeof(R) * w.ncell, st));
+static int plan_sinkhorn(Work<R>& w, const nfs_params* p, const double* eps, const double* x, const double* mu,
+                         const double* y, const double* nu, const double* ax, const double* ay, hipStream_t st) {
+  const int B = w.B, d = p->d;
+  NFS_TRY(zero_state(w, st));
+  for (int b = 0; b < B; ++b) {
+    const long ox = w.X.off[b], nx = w.X.off[b + 1] - ox, oy = w.Y.off[b], ny = w.Y.off[b + 1] - oy;
+    if (nx < 1 || ny < 1) return fail(NFS_EINVAL, "every problem needs at least one point per cloud");
+    NFS_TRY(box_launch(w.st_box + 20 * b, w.partials, w.ct_misc, d, x + ox * d, nx, y + oy * d, ny, mu + ox, nx, st));
+    NFS_TRY(box_launch(w.st_box + 20 * b + 10, w.partials, w.ct_misc, d, nullptr, 0, nullptr, 0, nu + oy, ny, st));
+  }
+  std::vector<double> box(size_t(B) * 20);
+  NFS_HIP(hipMemcpyAsync(box.data(), w.st_box, sizeof(double) * box.size(), hipMemcpyDeviceToHost, st));
+  NFS_HIP(hipStreamSynchronize(st));
+  w.sc.resize(B);
+  for (int b = 0; b < B; ++b) {
+    const double* bx = box.data() + 20 * b;
+    const double* by = bx + 10;
+    for (int i = 0; i < 9; ++i)
+      if (!std::isfinite(bx[i]) || (i >= 6 && !std::isfinite(by[i])))
+        return fail(NFS_EINVAL, "non-finite point coordinates or weights");
+    const long nx = w.X.off[b + 1] - w.X.off[b], ny = w.Y.off[b + 1] - w.Y.off[b];
+    NFS_TRY(check_weights(bx, nx, ny, "mu", B > 1 ? b : -1));
+    NFS_TRY(check_weights(by, ny, nx, "nu", B > 1 ? b : -1));
+    w.sc[b] = choose_scaling(d, p->r, eps[b], p->N, bx, bx + 3);
+  }
+  NFS_TRY(sort_cloud(w, w.X, x, w.sc, mu, ax, st));
+  NFS_TRY(sort_cloud(w, w.Y, y, w.sc, nu, ay, st));
+  NFS_TRY(upload_tables(w, p, st));
+  NFS_HIP(launch_fill(w.S, sizeof(R) * size_t(w.B) * w.ncell, st));
   return NFS_OK;
 }
 
-// Persistent Sinkhorn state: plan done once, one iteration captured in a
-// hipGraph on an internal stream and replayed; read-out on demand.
+// Persistent Sinkhorn state: plan done once, one iteration (10 kernels for
+// all problems) captured in a hipGraph on an internal stream and replayed.
 struct SolverBase {
   virtual ~SolverBase() {}
   virtual int iterate(int k, hipStream_t caller) = 0;
@@ -708,47 +792,55 @@ template <typename R>
 struct Solver : SolverBase {
   nfs_params p{};
   Work<R> w;
-  SolveCtx ctx{};
-  long n = 0, nt = 0;
+  std::vector<double> eps;
   int done = 0;
   hipStream_t gs = nullptr;
   hipEvent_t ev = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
 
-  double* stats() { return w.stats; }
-  double* wmul_x() { return w.stats + ST_WMUL_X; }
-  double* wmul_y() { return w.stats + ST_WMUL_Y; }
-
   hipError_t iteration(hipStream_t s) {
-    hipError_t e = half_step(w, w.B, w.A, wmul_y(), wmul_x(), stats() + ST_ROW, EPI_SINK, s);
+    hipError_t e = half_step(w, w.Y, w.X, w.wmul_y, w.wmul_x, w.st_row, EPI_SINK, s);
     if (e != hipSuccess) return e;
-    return half_step(w, w.A, w.B, wmul_x(), wmul_y(), stats() + ST_COL, EPI_SINK, s);
+    return half_step(w, w.X, w.Y, w.wmul_x, w.wmul_y, w.st_col, EPI_SINK, s);
   }
 
-  int create(const nfs_params* prm, const double* x, long n_, const double* mu, const double* y, long nt_,
-             const double* nu, const double* alpha_t0, void* ws, size_t wsb, hipStream_t caller) {
+  int create(const nfs_params* prm, int B, const int64_t* n, const int64_t* nt, const double* eps_in,
+             const double* x, const double* mu, const double* y, const double* nu, const double* alpha_t0, void* ws,
+             size_t wsb, hipStream_t caller) {
     p = *prm;
-    n = n_;
-    nt = nt_;
-    carve(w, &p, n, nt, nullptr, 2);
-    if (wsb < w.bytes) return fail(NFS_EWORKSPACE, "workspace too small");
-    carve(w, &p, n, nt, static_cast<char*>(ws), 2);
-    hipStream_t st = caller;
-    NFS_TRY(plan_sinkhorn(w, &p, x, n, mu, y, nt, nu, nullptr, alpha_t0, ctx, st));
-    NFS_HIP(launch_fill_double(w.A.w1s, n, 1.0, st));
-    if (!alpha_t0) {
-      NFS_HIP(launch_fill_double(w.B.w1s, nt, 1.0, st));
-      NFS_HIP(launch_fill_double(wmul_y(), 1, 1.0, st));
-    } else {
-      double box[9];
-      NFS_TRY(box_stats(stats() + ST_MISC, w.partials, w.counters + CT_BOX, p.d, nullptr, 0, nullptr, 0, alpha_t0,
-                        nt, box, st));
-      if (!(box[7] > 0.0) || !std::isfinite(box[6]))
-        return fail(NFS_EINVAL, "warm-start alpha_t must be positive and finite");
-      NFS_HIP(launch_fill_double(wmul_y(), 1, 1.0 / box[6], st));
+    eps.assign(eps_in, eps_in + B);
+    std::vector<long> ox(B + 1, 0), oy(B + 1, 0);
+    for (int b = 0; b < B; ++b) {
+      ox[b + 1] = ox[b] + n[b];
+      oy[b + 1] = oy[b] + nt[b];
     }
-    NFS_HIP(launch_fill_double(wmul_x(), 1, 1.0, st));
+    carve(w, &p, B, ox[B], oy[B], nullptr, 2);
+    if (wsb < w.bytes) return fail(NFS_EWORKSPACE, "workspace too small");
+    carve(w, &p, B, ox[B], oy[B], static_cast<char*>(ws), 2);
+    w.X.off = ox;
+    w.Y.off = oy;
+    hipStream_t st = caller;
+    NFS_TRY(plan_sinkhorn(w, &p, eps.data(), x, mu, y, nu, nullptr, alpha_t0, st));
+    NFS_HIP(launch_fill_double(w.X.w1s, w.X.n, 1.0, st));
+    NFS_HIP(launch_fill_double(w.wmul_x, B, 1.0, st));
+    if (!alpha_t0) {
+      NFS_HIP(launch_fill_double(w.Y.w1s, w.Y.n, 1.0, st));
+      NFS_HIP(launch_fill_double(w.wmul_y, B, 1.0, st));
+    } else {
+      for (int b = 0; b < B; ++b)
+        NFS_TRY(box_launch(w.st_box + 20 * b, w.partials, w.ct_misc, p.d, nullptr, 0, nullptr, 0, alpha_t0 + oy[b],
+                           oy[b + 1] - oy[b], st));
+      std::vector<double> box(size_t(B) * 20), wm(B);
+      NFS_HIP(hipMemcpyAsync(box.data(), w.st_box, sizeof(double) * box.size(), hipMemcpyDeviceToHost, st));
+      NFS_HIP(hipStreamSynchronize(st));
+      for (int b = 0; b < B; ++b) {
+        if (!(box[20 * b + 7] > 0.0) || !std::isfinite(box[20 * b + 6]))
+          return fail(NFS_EINVAL, "warm-start alpha_t must be positive and finite");
+        wm[b] = 1.0 / box[20 * b + 6];
+      }
+      NFS_HIP(hipMemcpyAsync(w.wmul_y, wm.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
+    }
     NFS_HIP(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
     NFS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     NFS_HIP(hipStreamSynchronize(st));
@@ -798,33 +890,32 @@ struct Solver : SolverBase {
     return leave(caller);
   }
 
+  // Largest row residual over the problems.
   int residual(double* err_row, hipStream_t caller) override {
     NFS_TRY(enter(caller));
-    NFS_HIP(half_step(w, w.B, w.A, wmul_y(), wmul_x(), stats() + ST_EVAL, EPI_EVAL, gs));
-    double h[4];
-    NFS_HIP(hipMemcpyAsync(h, stats() + ST_EVAL, sizeof(h), hipMemcpyDeviceToHost, gs));
+    NFS_HIP(half_step(w, w.Y, w.X, w.wmul_y, w.wmul_x, w.st_eval, EPI_EVAL, gs));
+    std::vector<double> h(size_t(w.B) * 8);
+    NFS_HIP(hipMemcpyAsync(h.data(), w.st_eval, sizeof(double) * h.size(), hipMemcpyDeviceToHost, gs));
     NFS_HIP(hipStreamSynchronize(gs));
-    *err_row = std::sqrt(h[0]);
+    double e = 0.0;
+    for (int b = 0; b < w.B; ++b) e = std::max(e, std::sqrt(h[8 * b]));
+    *err_row = e;
     return leave(caller);
   }
 
-  // Per-stage device times with events between the kernels of `k` iterations
-  // (direct launches on the internal stream, no graph).  stage_ms receives the
-  // average per launch of: [0] spread, [1] FFT chain, [2] interpolation + update,
-  // [3] whole iteration.
   int profile(int k, double* stage_ms, hipStream_t caller) override {
     if (k <= 0) return fail(NFS_EINVAL, "profile needs k >= 1");
     NFS_TRY(enter(caller));
-    std::vector<hipEvent_t> evs(8 * k + 1);
+    std::vector<hipEvent_t> evs(6 * k + 1);
     for (auto& e : evs) NFS_HIP(hipEventCreate(&e));
     int ie = 0;
     NFS_HIP(hipEventRecord(evs[ie++], gs));
     for (int it = 0; it < k; ++it) {
       for (int h = 0; h < 2; ++h) {
-        CloudBuf<R>& src = h == 0 ? w.B : w.A;
-        CloudBuf<R>& tgt = h == 0 ? w.A : w.B;
-        double* ws_ = h == 0 ? wmul_y() : wmul_x();
-        double* wt_ = h == 0 ? wmul_x() : wmul_y();
+        CloudBuf<R>& src = h == 0 ? w.Y : w.X;
+        CloudBuf<R>& tgt = h == 0 ? w.X : w.Y;
+        double* ws_ = h == 0 ? w.wmul_y : w.wmul_x;
+        double* wt_ = h == 0 ? w.wmul_x : w.wmul_y;
         NFS_HIP(spread(w, src, src.w1s, ws_, 1.0, gs));
         NFS_HIP(hipEventRecord(evs[ie++], gs));
         NFS_HIP(fft_chain(w, w.dtab, -1, gs));
@@ -832,29 +923,20 @@ struct Solver : SolverBase {
         InterpArgs<R> ia = interp_args(w, tgt, EPI_SINK, ws_);
         ia.p = tgt.w0s;
         ia.alpha = tgt.w1s;
-        ia.stats = stats() + (h == 0 ? ST_ROW : ST_COL);
+        ia.stats = h == 0 ? w.st_row : w.st_col;
         ia.wmul_next = wt_;
         NFS_HIP(launch_interp(ia, tgt.nchunks, gs));
         NFS_HIP(hipEventRecord(evs[ie++], gs));
-        ie++;  // keep 4 slots per half-step (last unused)
       }
     }
     NFS_HIP(hipStreamSynchronize(gs));
     double acc[3] = {0, 0, 0};
     float ms;
-    int prev = 0;
-    ie = 1;
-    for (int it = 0; it < k; ++it)
-      for (int h = 0; h < 2; ++h) {
-        for (int s = 0; s < 3; ++s) {
-          NFS_HIP(hipEventElapsedTime(&ms, evs[prev], evs[ie]));
-          acc[s] += ms;
-          prev = ie;
-          ++ie;
-        }
-        ++ie;
-      }
-    NFS_HIP(hipEventElapsedTime(&ms, evs[0], evs[prev]));
+    for (int i = 1; i < ie; ++i) {
+      NFS_HIP(hipEventElapsedTime(&ms, evs[i - 1], evs[i]));
+      acc[(i - 1) % 3] += ms;
+    }
+    NFS_HIP(hipEventElapsedTime(&ms, evs[0], evs[ie - 1]));
     for (int s = 0; s < 3; ++s) stage_ms[s] = acc[s] / (2.0 * k);
     stage_ms[3] = ms / k;
     for (auto& e : evs) hipEventDestroy(e);
@@ -862,78 +944,95 @@ struct Solver : SolverBase {
     return leave(caller);
   }
 
-  // Sizes that set the algorithmic traffic: [0] n, [1] nt, [2] d, [3] grid cells,
-  // [4] bytes per grid cell, [5] chunks of x, [6] chunks of y, [7] taps per point.
   int stage_info(double* info) override {
-    info[0] = double(n);
-    info[1] = double(nt);
+    info[0] = double(w.X.n);
+    info[1] = double(w.Y.n);
     info[2] = p.d;
-    info[3] = double(w.ncell);
+    info[3] = double(w.ncell) * w.B;
     info[4] = double(sizeof(R));
-    info[5] = w.A.nchunks;
-    info[6] = w.B.nchunks;
+    info[5] = w.X.nchunks;
+    info[6] = w.Y.nchunks;
     info[7] = std::pow(2.0 * p.m + 1.0, p.d);
     return NFS_OK;
   }
 
+  // Read-out of every problem (Algorithm 3 result, eq. (Error), Section 3.2
+  // upper value, eq. (15) primal cost); res has B entries.
   int finish(double* alpha, double* alpha_t, nfs_result* res, hipStream_t caller) override {
     NFS_TRY(enter(caller));
     hipStream_t st = gs;
-    double* S = stats();
+    const int B = w.B;
     // row residual of eq. (Error): one extra product K alpha_t
-    NFS_HIP(half_step(w, w.B, w.A, wmul_y(), wmul_x(), S + ST_EVAL, EPI_EVAL, st));
-    double ev_row[8];
-    NFS_HIP(hipMemcpyAsync(ev_row, S + ST_EVAL, sizeof(ev_row), hipMemcpyDeviceToHost, st));
-    NFS_HIP(half_step(w, w.A, w.B, wmul_x(), wmul_y(), S + ST_EVAL, EPI_EVAL, st));
-    ReadoutArgs ra{w.A.w0s, w.A.w1s, n, w.partials, w.counters + CT_RD, S + ST_RD_X};
-    NFS_HIP(launch_readout(ra, st));
-    ReadoutArgs rb{w.B.w0s, w.B.w1s, nt, w.partials, w.counters + CT_RD, S + ST_RD_Y};
-    NFS_HIP(launch_readout(rb, st));
-    if (p.flags & NFS_FLAG_PRIMAL_COST) {
-      NFS_HIP(spread(w, w.B, w.B.w1s, wmul_y(), 1.0, st));
-      NFS_HIP(fft_chain(w, w.dtab2, -1, st));
-      InterpArgs<R> ia = interp_args(w, w.A, EPI_OUT, wmul_y());
-      ia.out = w.tmp;
-      ia.scale_vec = w.A.w1s;
-      NFS_HIP(launch_interp(ia, w.A.nchunks, st));
-      ReadoutArgs rc2{w.tmp, w.tmp, n, w.partials, w.counters + CT_RD, S + ST_MISC + 8};
-      NFS_HIP(launch_readout(rc2, st));
+    NFS_HIP(half_step(w, w.Y, w.X, w.wmul_y, w.wmul_x, w.st_eval, EPI_EVAL, st));
+    std::vector<double> ev_row(size_t(B) * 8), ev_col(size_t(B) * 8);
+    NFS_HIP(hipMemcpyAsync(ev_row.data(), w.st_eval, sizeof(double) * ev_row.size(), hipMemcpyDeviceToHost, st));
+    NFS_HIP(half_step(w, w.X, w.Y, w.wmul_x, w.wmul_y, w.st_eval, EPI_EVAL, st));
+    NFS_HIP(hipMemcpyAsync(ev_col.data(), w.st_eval, sizeof(double) * ev_col.size(), hipMemcpyDeviceToHost, st));
+    for (int b = 0; b < B; ++b) {
+      const long ox = w.X.off[b], oy = w.Y.off[b];
+      ReadoutArgs ra{w.X.w0s + ox, w.X.w1s + ox, w.X.off[b + 1] - ox, w.partials, w.ct_misc + 1, w.st_rdx + 4 * b};
+      NFS_HIP(launch_readout(ra, st));
+      ReadoutArgs rb{w.Y.w0s + oy, w.Y.w1s + oy, w.Y.off[b + 1] - oy, w.partials, w.ct_misc + 1, w.st_rdy + 4 * b};
+      NFS_HIP(launch_readout(rb, st));
     }
-    if (alpha) NFS_HIP(launch_unpermute(w.A.w1s, w.A.perm, n, alpha, st));
-    if (alpha_t) NFS_HIP(launch_unpermute(w.B.w1s, w.B.perm, nt, alpha_t, st));
-    double hs[ST_TOTAL];
-    NFS_HIP(hipMemcpyAsync(hs, S, sizeof(hs), hipMemcpyDeviceToHost, st));
+    const bool primal = p.flags & NFS_FLAG_PRIMAL_COST;
+    if (primal) {
+      NFS_HIP(spread(w, w.Y, w.Y.w1s, w.wmul_y, 1.0, st));
+      NFS_HIP(fft_chain(w, w.dtab2, -1, st));
+      InterpArgs<R> ia = interp_args(w, w.X, EPI_OUT, w.wmul_y);
+      ia.out = w.tmp;
+      ia.scale_vec = w.X.w1s;
+      NFS_HIP(launch_interp(ia, w.X.nchunks, st));
+      for (int b = 0; b < B; ++b) {
+        const long ox = w.X.off[b];
+        ReadoutArgs rc{w.tmp + ox, w.tmp + ox, w.X.off[b + 1] - ox, w.partials, w.ct_misc + 1, w.st_cost + 4 * b};
+        NFS_HIP(launch_readout(rc, st));
+      }
+    }
+    if (alpha) NFS_HIP(launch_unpermute(w.X.w1s, w.X.perm, w.X.n, alpha, st));
+    if (alpha_t) NFS_HIP(launch_unpermute(w.Y.w1s, w.Y.perm, w.Y.n, alpha_t, st));
+    std::vector<double> col(size_t(B) * 8), row(size_t(B) * 8), rdx(size_t(B) * 4), rdy(size_t(B) * 4),
+        cost(size_t(B) * 4);
+    NFS_HIP(hipMemcpyAsync(col.data(), w.st_col, sizeof(double) * col.size(), hipMemcpyDeviceToHost, st));
+    NFS_HIP(hipMemcpyAsync(row.data(), w.st_row, sizeof(double) * row.size(), hipMemcpyDeviceToHost, st));
+    NFS_HIP(hipMemcpyAsync(rdx.data(), w.st_rdx, sizeof(double) * rdx.size(), hipMemcpyDeviceToHost, st));
+    NFS_HIP(hipMemcpyAsync(rdy.data(), w.st_rdy, sizeof(double) * rdy.size(), hipMemcpyDeviceToHost, st));
+    NFS_HIP(hipMemcpyAsync(cost.data(), w.st_cost, sizeof(double) * cost.size(), hipMemcpyDeviceToHost, st));
     NFS_HIP(hipStreamSynchronize(st));
     NFS_TRY(leave(caller));
-    const double eps = p.eps;
-    nfs_result r{};
-    r.iters = done;
-    r.precision_used = p.precision;
-    r.scale = ctx.sc.scale;
-    r.kernel_err = ctx.sc.kernel_err;
-    // s = eps (1 + sum p log a + sum pt log at - sum_j at_j tt_j), tt the last K^T alpha
-    const double mass = done > 0 ? hs[ST_COL + 1] : ev_row[1];
-    r.cost = eps * (1.0 + hs[ST_RD_X + 0] + hs[ST_RD_Y + 0] - mass);
-    r.cost_upper = r.cost - eps * (hs[ST_RD_X + 1] + hs[ST_RD_Y + 1]);
-    r.cost_primal = (p.flags & NFS_FLAG_PRIMAL_COST) ? hs[ST_MISC + 8 + 2] : NAN;
-    r.marg_err_row = std::sqrt(ev_row[0]);
-    r.marg_err_col = std::sqrt(hs[ST_EVAL + 0]);
-    r.marg_err = r.marg_err_row + r.marg_err_col;
-    r.n_nonpos = int64_t(hs[ST_ROW + 4] + hs[ST_COL + 4]);
-    if (res) *res = r;
-    if (r.n_nonpos > 0)
+    int64_t nonpos = 0;
+    for (int b = 0; b < B; ++b) {
+      const double e = eps[b];
+      nfs_result r{};
+      r.iters = done;
+      r.precision_used = p.precision;
+      r.scale = w.sc[b].scale;
+      r.kernel_err = w.sc[b].kernel_err;
+      // s = eps (1 + sum p log a + sum pt log at - sum_j at_j tt_j), tt the last K^T alpha
+      const double mass = done > 0 ? col[8 * b + 1] : ev_row[8 * b + 1];
+      r.cost = e * (1.0 + rdx[4 * b + 0] + rdy[4 * b + 0] - mass);
+      r.cost_upper = r.cost - e * (rdx[4 * b + 1] + rdy[4 * b + 1]);
+      r.cost_primal = primal ? cost[4 * b + 2] : NAN;
+      r.marg_err_row = std::sqrt(ev_row[8 * b + 0]);
+      r.marg_err_col = std::sqrt(ev_col[8 * b + 0]);
+      r.marg_err = r.marg_err_row + r.marg_err_col;
+      r.n_nonpos = int64_t(row[8 * b + 4] + col[8 * b + 4]);
+      nonpos += r.n_nonpos;
+      if (res) res[b] = r;
+    }
+    if (nonpos > 0)
       return fail(NFS_ENONPOS, "fast summation produced kernel sums t <= 0 (normwise error above the dynamic range)");
     return NFS_OK;
   }
 };
 
-static int make_solver(const nfs_params* prm, const double* x, int64_t n, const double* mu, const double* y,
-                       int64_t nt, const double* nu, const double* alpha_t0, void* ws, size_t wsb, hipStream_t st,
-                       SolverBase** out) {
+static int make_solver(const nfs_params* prm, int B, const int64_t* n, const int64_t* nt, const double* eps,
+                       const double* x, const double* mu, const double* y, const double* nu, const double* alpha_t0,
+                       void* ws, size_t wsb, hipStream_t st, SolverBase** out) {
   *out = nullptr;
   if (prm->precision == NFS_FP32) {
     auto* s = new Solver<float>();
-    int rc = s->create(prm, x, n, mu, y, nt, nu, alpha_t0, ws, wsb, st);
+    int rc = s->create(prm, B, n, nt, eps, x, mu, y, nu, alpha_t0, ws, wsb, st);
     if (rc != NFS_OK) {
       delete s;
       return rc;
@@ -941,7 +1040,7 @@ static int make_solver(const nfs_params* prm, const double* x, int64_t n, const 
     *out = s;
   } else {
     auto* s = new Solver<double>();
-    int rc = s->create(prm, x, n, mu, y, nt, nu, alpha_t0, ws, wsb, st);
+    int rc = s->create(prm, B, n, nt, eps, x, mu, y, nu, alpha_t0, ws, wsb, st);
     if (rc != NFS_OK) {
       delete s;
       return rc;
@@ -951,11 +1050,8 @@ static int make_solver(const nfs_params* prm, const double* x, int64_t n, const 
   return NFS_OK;
 }
 
-static int do_solve(const nfs_params* p, const double* x, int64_t n, const double* mu, const double* y, int64_t nt,
-                    const double* nu, int32_t max_iter, double tol, int32_t warm, double* alpha, double* alpha_t,
-                    nfs_result* res, void* ws, size_t wsb, hipStream_t caller) {
-  SolverBase* s = nullptr;
-  NFS_TRY(make_solver(p, x, n, mu, y, nt, nu, warm ? alpha_t : nullptr, ws, wsb, caller, &s));
+static int run_solver(SolverBase* s, int32_t max_iter, double tol, double* alpha, double* alpha_t, nfs_result* res,
+                      hipStream_t caller) {
   int rc = NFS_OK;
   int done = 0;
   const int check_every = 10;
@@ -970,7 +1066,6 @@ static int do_solve(const nfs_params* p, const double* x, int64_t n, const doubl
     }
   }
   if (rc == NFS_OK) rc = s->finish(alpha, alpha_t, res, caller);
-  delete s;
   return rc;
 }
 
@@ -979,34 +1074,66 @@ static int do_grad(const nfs_params* p, const double* x, int64_t n, const double
                    const double* nu, const double* alpha, const double* alpha_t, double* grad_x, double* grad_mu,
                    void* ws, size_t wsb, hipStream_t st) {
   Work<R> w;
-  carve(w, p, n, nt, nullptr, 2);
+  carve(w, p, 1, n, nt, nullptr, 2);
   if (wsb < w.bytes) return fail(NFS_EWORKSPACE, "workspace too small");
-  carve(w, p, n, nt, static_cast<char*>(ws), 2);
-  SolveCtx ctx;
-  NFS_TRY(plan_sinkhorn(w, p, x, n, mu, y, nt, nu, alpha, alpha_t, ctx, st));
-  if (grad_mu) NFS_HIP(launch_gradmu(alpha, n, p->eps, w.partials, w.counters + CT_RD, w.stats + ST_LOGMEAN, grad_mu, st));
+  carve(w, p, 1, n, nt, static_cast<char*>(ws), 2);
+  w.X.off = {0, n};
+  w.Y.off = {0, nt};
+  const double eps = p->eps;
+  NFS_TRY(plan_sinkhorn(w, p, &eps, x, mu, y, nu, alpha, alpha_t, st));
+  if (grad_mu) NFS_HIP(launch_gradmu(alpha, n, p->eps, w.partials, w.ct_misc + 2, w.st_cost, grad_mu, st));
   if (grad_x) {
     double box[9];
-    NFS_TRY(box_stats(w.stats + ST_MISC, w.partials, w.counters + CT_BOX, p->d, nullptr, 0, nullptr, 0, alpha_t, nt,
-                      box, st));
+    NFS_TRY(box_launch(w.st_box, w.partials, w.ct_misc, p->d, nullptr, 0, nullptr, 0, alpha_t, nt, st));
+    NFS_HIP(hipMemcpyAsync(box, w.st_box, sizeof(box), hipMemcpyDeviceToHost, st));
+    NFS_HIP(hipStreamSynchronize(st));
     if (!(box[6] > 0.0) || !std::isfinite(box[6])) return fail(NFS_EINVAL, "alpha_t must be positive and finite");
     const double wmax = box[6];
-    // The spectrum of the spread alpha_t is formed once per derivative axis;
-    // each pass applies (2 pi i k_c) b_k / Phi^2 and interpolates at x.
+    // Each derivative axis applies (2 pi i k_c) b_k / Phi^2 to the spread
+    // alpha_t and interpolates at x.
     for (int c = 0; c < p->d; ++c) {
-      NFS_HIP(spread(w, w.B, w.B.w1s, nullptr, 1.0 / wmax, st));
+      NFS_HIP(spread(w, w.Y, w.Y.w1s, nullptr, 1.0 / wmax, st));
       NFS_HIP(fft_chain(w, w.dtab, c, st));
-      InterpArgs<R> ia = interp_args(w, w.A, EPI_OUT, nullptr);
+      InterpArgs<R> ia = interp_args(w, w.X, EPI_OUT, nullptr);
       // grad_x_i = -eps alpha_i s (dK'/dx'_c * alpha_t)(x'_i), x' = s (x - center)
-      ia.norm = -p->eps * ctx.sc.scale * wmax;
-      ia.scale_vec = w.A.w1s;
+      ia.norm = -p->eps * w.sc[0].scale * wmax;
+      ia.scale_vec = w.X.w1s;
       ia.out = grad_x;
       ia.out_stride = p->d;
       ia.out_comp = c;
-      NFS_HIP(launch_interp(ia, w.A.nchunks, st));
+      NFS_HIP(launch_interp(ia, w.X.nchunks, st));
     }
   }
   NFS_HIP(hipStreamSynchronize(st));
+  return NFS_OK;
+}
+
+// Workspace for a batch: the sum over problems of the points, B grids.
+static int batch_sizes(const nfs_params* prm, int32_t B, const int64_t* n, const int64_t* nt, long* sn, long* snt) {
+  if (B < 1) return fail(NFS_EINVAL, "batch needs at least one problem");
+  if (!n || !nt) return fail(NFS_EINVAL, "NULL size array");
+  long a = 0, b = 0;
+  for (int i = 0; i < B; ++i) {
+    if (n[i] < 1 || nt[i] < 1) return fail(NFS_EINVAL, "every problem needs at least one point per cloud");
+    a += n[i];
+    b += nt[i];
+  }
+  NFS_TRY(check_params(prm, a, b));
+  *sn = a;
+  *snt = b;
+  return NFS_OK;
+}
+
+static int batch_workspace(const nfs_params* prm, int32_t B, long sn, long snt, size_t* bytes) {
+  if (prm->precision == NFS_FP32) {
+    Work<float> w;
+    carve(w, prm, B, sn, snt, nullptr, 2);
+    *bytes = w.bytes;
+  } else {
+    Work<double> w;
+    carve(w, prm, B, sn, snt, nullptr, 2);
+    *bytes = w.bytes;
+  }
   return NFS_OK;
 }
 
@@ -1028,16 +1155,7 @@ int nfs_workspace_size(const nfs_params* prm, int64_t n, int64_t nt, size_t* byt
   g_err.clear();
   NFS_TRY(check_params(prm, n, nt));
   if (!bytes) return fail(NFS_EINVAL, "bytes is NULL");
-  if (prm->precision == NFS_FP32) {
-    Work<float> w;
-    carve(w, prm, n, nt, nullptr, 2);
-    *bytes = w.bytes;
-  } else {
-    Work<double> w;
-    carve(w, prm, n, nt, nullptr, 2);
-    *bytes = w.bytes;
-  }
-  return NFS_OK;
+  return batch_workspace(prm, 1, n, nt, bytes);
 }
 
 int nfs_fastsum_apply(const nfs_params* prm, const double* src, int64_t ns, const double* w, const double* tgt,
@@ -1079,8 +1197,13 @@ int nfs_sinkhorn_solve(const nfs_params* prm, const double* x, int64_t n, const 
   NFS_TRY(check_params(prm, n, nt));
   if (!x || !mu || !y || !nu || !alpha || !alpha_t || !workspace) return fail(NFS_EINVAL, "NULL pointer argument");
   if (max_iter < 0) return fail(NFS_EINVAL, "max_iter must be >= 0");
-  return do_solve(prm, x, n, mu, y, nt, nu, max_iter, tol, warm_start, alpha, alpha_t, res, workspace, ws_bytes,
-                  static_cast<hipStream_t>(stream));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SolverBase* s = nullptr;
+  NFS_TRY(make_solver(prm, 1, &n, &nt, &prm->eps, x, mu, y, nu, warm_start ? alpha_t : nullptr, workspace, ws_bytes,
+                      st, &s));
+  const int rc = run_solver(s, max_iter, tol, alpha, alpha_t, res, st);
+  delete s;
+  return rc;
 }
 
 int nfs_solver_create(const nfs_params* prm, const double* x, int64_t n, const double* mu, const double* y,
@@ -1092,7 +1215,8 @@ int nfs_solver_create(const nfs_params* prm, const double* x, int64_t n, const d
   NFS_TRY(check_params(prm, n, nt));
   if (!x || !mu || !y || !nu || !workspace) return fail(NFS_EINVAL, "NULL pointer argument");
   SolverBase* s = nullptr;
-  NFS_TRY(make_solver(prm, x, n, mu, y, nt, nu, alpha_t0, workspace, ws_bytes, static_cast<hipStream_t>(stream), &s));
+  NFS_TRY(make_solver(prm, 1, &n, &nt, &prm->eps, x, mu, y, nu, alpha_t0, workspace, ws_bytes,
+                      static_cast<hipStream_t>(stream), &s));
   *out = reinterpret_cast<nfs_solver*>(s);
   return NFS_OK;
 }
@@ -1127,6 +1251,50 @@ int nfs_solver_profile(nfs_solver* s, int32_t iters, double* stage_ms, double* i
 int nfs_solver_destroy(nfs_solver* s) {
   delete reinterpret_cast<SolverBase*>(s);
   return NFS_OK;
+}
+
+int nfs_batch_workspace_size(const nfs_params* prm, int32_t nprob, const int64_t* n, const int64_t* nt,
+                             size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(NFS_EINVAL, "bytes is NULL");
+  long sn = 0, snt = 0;
+  NFS_TRY(batch_sizes(prm, nprob, n, nt, &sn, &snt));
+  return batch_workspace(prm, nprob, sn, snt, bytes);
+}
+
+int nfs_batch_solver_create(const nfs_params* prm, int32_t nprob, const int64_t* n, const int64_t* nt,
+                            const double* eps, const double* x, const double* mu, const double* y, const double* nu,
+                            const double* alpha_t0, void* workspace, size_t ws_bytes, void* stream, nfs_solver** out) {
+  g_err.clear();
+  if (!out) return fail(NFS_EINVAL, "out is NULL");
+  *out = nullptr;
+  long sn = 0, snt = 0;
+  NFS_TRY(batch_sizes(prm, nprob, n, nt, &sn, &snt));
+  if (!eps) return fail(NFS_EINVAL, "eps is NULL");
+  for (int b = 0; b < nprob; ++b)
+    if (!(eps[b] > 0.0) || !std::isfinite(eps[b])) return fail(NFS_EINVAL, "every eps must be positive and finite");
+  if (!x || !mu || !y || !nu || !workspace) return fail(NFS_EINVAL, "NULL pointer argument");
+  SolverBase* s = nullptr;
+  NFS_TRY(make_solver(prm, nprob, n, nt, eps, x, mu, y, nu, alpha_t0, workspace, ws_bytes,
+                      static_cast<hipStream_t>(stream), &s));
+  *out = reinterpret_cast<nfs_solver*>(s);
+  return NFS_OK;
+}
+
+int nfs_batch_solve(const nfs_params* prm, int32_t nprob, const int64_t* n, const int64_t* nt, const double* eps,
+                    const double* x, const double* mu, const double* y, const double* nu, int32_t max_iter,
+                    double tol, double* alpha, double* alpha_t, nfs_result* res, void* workspace, size_t ws_bytes,
+                    void* stream) {
+  g_err.clear();
+  if (max_iter < 0) return fail(NFS_EINVAL, "max_iter must be >= 0");
+  if (!alpha || !alpha_t) return fail(NFS_EINVAL, "NULL pointer argument");
+  nfs_solver* h = nullptr;
+  NFS_TRY(nfs_batch_solver_create(prm, nprob, n, nt, eps, x, mu, y, nu, nullptr, workspace, ws_bytes, stream, &h));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto* s = reinterpret_cast<SolverBase*>(h);
+  const int rc = run_solver(s, max_iter, tol, alpha, alpha_t, res, st);
+  delete s;
+  return rc;
 }
 
 int nfs_sinkhorn_grad(const nfs_params* prm, const double* x, int64_t n, const double* mu, const double* y,

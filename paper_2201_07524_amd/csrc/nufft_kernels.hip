@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs<R> a) {
   for (int i = threadIdx.x; i < ncell; i += kBlock) tile.zero(i);
   __syncthreads();
 
-  const double wm = a.wconst * (a.wmul ? *a.wmul : 1.0);
+  const double wm = a.wconst * (a.wmul ? a.wmul[ch.prob] : 1.0);
   for (int q = ch.start + threadIdx.x; q < ch.start + ch.count; q += kBlock) {
     const R w = R(a.w[q] * wm);
     if (w == R(0)) continue;
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs<R> a) {
       const int e0 = i / (E * E), rem = i - e0 * E * E, e1 = rem / E, e2 = rem - e1 * E;
       lin = (size_t(wrap(org[0] + e0, g)) * g + wrap(org[1] + e1, g)) * g + wrap(org[2] + e2, g);
     }
-    atomicAdd(&a.grid[lin], v);
+    atomicAdd(&a.grid[size_t(ch.prob) * a.grid_stride + lin], v);
   }
 }
 
@@ -327,8 +327,10 @@ __device__ Red4 block_reduce(Red4 v, Red4* sh) {
 // Final reduction by the last workgroup to finish (ticket counter).  Writes
 // stats[0..3] = {sum s0, sum s1, max, count}, adds count to stats[4], and, if wmul_next is set,
 // wmul_next = 1/max (the normalization of the next spread's weights).
+// The chunks of one problem are [c0, c1); the last of them to finish reduces
+// that problem's partials.
 __device__ void finish_reduce(Red4 mine, Red4* sh, double* partials, unsigned* counter, double* stats,
-                              double* wmul_next) {
+                              double* wmul_next, int c0, int c1) {
   __shared__ bool last;
   if (threadIdx.x == 0) {
     partials[4 * blockIdx.x + 0] = mine.s0;
@@ -337,14 +339,14 @@ __device__ void finish_reduce(Red4 mine, Red4* sh, double* partials, unsigned* c
     partials[4 * blockIdx.x + 3] = mine.cnt;
     __threadfence();
     const unsigned ticket = atomicAdd(counter, 1u);
-    last = (ticket == gridDim.x - 1);
+    last = (ticket == unsigned(c1 - c0) - 1u);
   }
   __syncthreads();
   if (!last) return;
   __threadfence();
   Red4 v{0.0, 0.0, 0.0, 0.0};
   const volatile double* pv = partials;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) {
+  for (int b = c0 + threadIdx.x; b < c1; b += kBlock) {
     Red4 w{pv[4 * b + 0], pv[4 * b + 1], pv[4 * b + 2], pv[4 * b + 3]};
     v = red_combine(v, w);
   }
@@ -393,11 +395,11 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
       const int e0 = i / (E * E), rem = i - e0 * E * E, e1 = rem / E, e2 = rem - e1 * E;
       lin = (size_t(wrap(org[0] + e0, g)) * g + wrap(org[1] + e1, g)) * g + wrap(org[2] + e2, g);
     }
-    tile[i] = a.grid[lin];
+    tile[i] = a.grid[size_t(ch.prob) * a.grid_stride + lin];
   }
   __syncthreads();
 
-  const double outmul = a.norm / (a.wmul_src ? *a.wmul_src : 1.0);
+  const double outmul = a.norm / (a.wmul_src ? a.wmul_src[ch.prob] : 1.0);
   Red4 acc_red{0.0, 0.0, 0.0, 0.0};
   for (int q = ch.start + threadIdx.x; q < ch.start + ch.count; q += kBlock) {
     R u[D];
@@ -459,7 +461,9 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
   }
   if (a.epi != EPI_OUT) {
     const Red4 r = block_reduce(acc_red, red_sh);
-    finish_reduce(r, red_sh, a.partials, a.counter, a.stats, a.wmul_next);
+    const int pb = ch.prob;
+    finish_reduce(r, red_sh, a.partials, a.counter + pb, a.stats + 8 * pb, a.wmul_next ? a.wmul_next + pb : nullptr,
+                  a.prob_chunks[pb], a.prob_chunks[pb + 1]);
   }
 }
 

@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(ScatterArgs<R> a) {
     if (ur < R(0)) ur = R(0);
     a.coords[size_t(pos) * a.d + c] = ur;
   }
-  a.perm[pos] = int(i);
+  a.perm[pos] = int(i) + a.idx_base;
   if (a.w0) a.w0s[pos] = a.w0[i];
   if (a.w1) a.w1s[pos] = a.w1[i];
 }

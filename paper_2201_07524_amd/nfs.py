@@ -21,7 +21,8 @@ FLAG_NO_GRAPH, FLAG_PRIMAL_COST, FLAG_TILE_REDUCE = 1, 2, 4
 EXPORTED = ("nfs_last_error", "nfs_validate", "nfs_workspace_size", "nfs_fastsum_apply",
             "nfs_nfft_adjoint", "nfs_nfft_trafo", "nfs_sinkhorn_solve", "nfs_sinkhorn_grad",
             "nfs_solver_create", "nfs_solver_iterate", "nfs_solver_residual", "nfs_solver_finish",
-            "nfs_solver_profile", "nfs_solver_destroy")
+            "nfs_solver_profile", "nfs_solver_destroy", "nfs_batch_workspace_size",
+            "nfs_batch_solver_create", "nfs_batch_solve")
 
 
 class NfsError(RuntimeError):
@@ -111,6 +112,15 @@ def load_library():
     lib.nfs_solver_profile.argtypes = [P, ctypes.c_int32, P, P, P]
     lib.nfs_solver_destroy.restype = ctypes.c_int
     lib.nfs_solver_destroy.argtypes = [P]
+    PI64, PD = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
+    lib.nfs_batch_workspace_size.restype = ctypes.c_int
+    lib.nfs_batch_workspace_size.argtypes = [PP, ctypes.c_int32, PI64, PI64, ctypes.POINTER(SZ)]
+    lib.nfs_batch_solver_create.restype = ctypes.c_int
+    lib.nfs_batch_solver_create.argtypes = [PP, ctypes.c_int32, PI64, PI64, PD, P, P, P, P, P, P, SZ, P,
+                                            ctypes.POINTER(P)]
+    lib.nfs_batch_solve.restype = ctypes.c_int
+    lib.nfs_batch_solve.argtypes = [PP, ctypes.c_int32, PI64, PI64, PD, P, P, P, P, ctypes.c_int32,
+                                    ctypes.c_double, P, P, ctypes.POINTER(_Result), P, SZ, P]
     _lib = lib
     return lib
 
@@ -331,6 +341,82 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def _results(arr, alpha, alpha_t, offs_x, offs_y):
+    out = []
+    for b, r in enumerate(arr):
+        out.append(SinkhornResult(alpha[offs_x[b]:offs_x[b + 1]], alpha_t[offs_y[b]:offs_y[b + 1]], r.cost,
+                                  r.cost_upper, r.cost_primal, r.marg_err, r.marg_err_row, r.marg_err_col,
+                                  r.iters, r.n_nonpos, r.scale, r.kernel_err))
+    return out
+
+
+class BatchSolver(Solver):
+    """Many independent problems (same d, N, m, sigma) in one solver.
+
+    ``xs, mus, ys, nus`` are lists of GPU float64 tensors, ``eps`` a list of
+    floats.  ``finish()`` returns one SinkhornResult per problem.
+    """
+
+    def __init__(self, params, xs, mus, ys, nus, eps):
+        lib = load_library()
+        self.params = params
+        self.nprob = len(xs)
+        self.ns = [int(x.shape[0]) for x in xs]
+        self.nts = [int(y.shape[0]) for y in ys]
+        self.offs_x = [0]
+        self.offs_y = [0]
+        for a, b in zip(self.ns, self.nts):
+            self.offs_x.append(self.offs_x[-1] + a)
+            self.offs_y.append(self.offs_y[-1] + b)
+        self.x = torch.cat([_pts(x, params.d, "x").reshape(-1, params.d) for x in xs]).contiguous()
+        self.y = torch.cat([_pts(y, params.d, "y").reshape(-1, params.d) for y in ys]).contiguous()
+        self.mu = torch.cat([_dev(m, "mu") for m in mus]).contiguous()
+        self.nu = torch.cat([_dev(m, "nu") for m in nus]).contiguous()
+        self.n, self.nt = self.x.shape[0], self.y.shape[0]
+        n_arr = (ctypes.c_int64 * self.nprob)(*self.ns)
+        nt_arr = (ctypes.c_int64 * self.nprob)(*self.nts)
+        self.eps = (ctypes.c_double * self.nprob)(*[float(e) for e in eps])
+        nb = ctypes.c_size_t(0)
+        _check(lib.nfs_batch_workspace_size(ctypes.byref(params.to_c()), self.nprob, n_arr, nt_arr,
+                                            ctypes.byref(nb)))
+        self.nb = nb.value
+        self.ws = torch.empty(self.nb, dtype=torch.uint8, device=self.x.device)
+        h = ctypes.c_void_p()
+        _check(lib.nfs_batch_solver_create(ctypes.byref(params.to_c()), self.nprob, n_arr, nt_arr, self.eps,
+                                           self.x.data_ptr(), self.mu.data_ptr(), self.y.data_ptr(),
+                                           self.nu.data_ptr(), None, self.ws.data_ptr(), self.nb, _stream(),
+                                           ctypes.byref(h)))
+        self.h = h
+
+    def finish(self, check=True):
+        lib = load_library()
+        alpha = torch.empty(self.n, dtype=torch.float64, device=self.x.device)
+        alpha_t = torch.empty(self.nt, dtype=torch.float64, device=self.x.device)
+        res = (_Result * self.nprob)()
+        rc = lib.nfs_solver_finish(self.h, alpha.data_ptr(), alpha_t.data_ptr(), res, _stream())
+        if rc != NFS_OK and (check or rc != NFS_ENONPOS):
+            _check(rc)
+        return _results(res, alpha, alpha_t, self.offs_x, self.offs_y)
+
+
+def batch_sinkhorn(params, xs, mus, ys, nus, eps, iters, tol=0.0, check=True):
+    """Solve many problems at once (nfs_batch_solve); returns a list of SinkhornResult."""
+    s = BatchSolver(params, xs, mus, ys, nus, eps)
+    try:
+        s.iterate(iters) if tol <= 0 else None
+        if tol > 0:
+            done = 0
+            while done < iters:
+                k = min(10, iters - done)
+                s.iterate(k)
+                done += k
+                if s.residual() <= tol:
+                    break
+        return s.finish(check=check)
+    finally:
+        s.close()
 
 
 class SinkhornCost(torch.autograd.Function):
