@@ -63,6 +63,79 @@ def cpu_baseline(cfg, budget_rows=8192):
                        f"({dt:.1f} s), scaled to 2 full products per iteration")
 
 
+def batched_leg(nfs, workloads, torch, T, iters=10, sample_every=16):
+    """The batched form: 512 independent 2-D mixture problems (sizes log-uniform
+    in [1e3, 2e5], eps uniform in [0.005, 0.05], N = 256, m = 6, FP32), all
+    advanced by one captured iteration; compared with plain single-problem
+    solvers run one after another (every `sample_every`-th problem, scaled to
+    the whole batch)."""
+    import numpy as np
+    cfg = workloads.batched_2d()
+    probs = cfg["problems"]
+    prm = nfs.Params(d=2, eps=1.0, N=cfg["N"], m=cfg["m"], precision="fp32")
+    xs = [T(p["x"]) for p in probs]
+    ps = [T(p["p"]) for p in probs]
+    ys = [T(p["y"]) for p in probs]
+    pts = [T(p["pt"]) for p in probs]
+    eps = [p["eps"] for p in probs]
+    s = nfs.BatchSolver(prm, xs, ps, ys, pts, eps)
+    s.iterate(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.iterate(iters)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / iters
+    res = s.finish(check=False)
+    nonpos = sum(1 for r in res if r.n_nonpos > 0)
+    s.close()
+    del s
+    t_plain = 0.0
+    sample = list(range(0, len(probs), sample_every))
+    for b in sample:
+        sp = nfs.Params(d=2, eps=eps[b], N=cfg["N"], m=cfg["m"], precision="fp32")
+        one = nfs.Solver(sp, xs[b], ps[b], ys[b], pts[b])
+        one.iterate(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        one.iterate(iters)
+        torch.cuda.synchronize()
+        t_plain += (time.perf_counter() - t0) / iters
+        one.close()
+    t_plain *= len(probs) / len(sample)
+    npts = sum(p["x"].shape[0] + p["y"].shape[0] for p in probs)
+    return {"problems": len(probs), "points": npts, "ms_per_iteration": t_batch * 1e3,
+            "problem_iterations_per_s": len(probs) / t_batch,
+            "plain_sequential_ms_per_iteration_est": t_plain * 1e3,
+            "speedup_vs_plain": t_plain / t_batch,
+            "problems_with_nonpositive_sums_fp32": nonpos}
+
+
+def grad_leg(nfs, workloads, torch, T, iters=5):
+    """The differentiated form: 3-D mixtures, n = nt = 1e6, eps = 0.01, N = 128,
+    m = 8, FP32; time of one forward iteration vs one envelope gradient
+    (positions and weights) at the resulting scalings."""
+    cfg = workloads.gmm_3d()
+    prm = nfs.Params(d=3, eps=cfg["eps"], N=cfg["N"], m=cfg["m"], precision="fp32")
+    x, p, y, pt = T(cfg["x"]), T(cfg["p"]), T(cfg["y"]), T(cfg["pt"])
+    s = nfs.Solver(prm, x, p, y, pt)
+    s.iterate(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.iterate(iters)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / iters
+    res = s.finish(check=False)
+    s.close()
+    nfs.sinkhorn_grad(prm, x, p, y, pt, res.alpha, res.alpha_t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nfs.sinkhorn_grad(prm, x, p, y, pt, res.alpha, res.alpha_t)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    return {"forward_ms_per_iteration": t_fwd * 1e3, "gradient_ms_incl_plan": t_grad * 1e3,
+            "gradient_over_forward_iteration": t_grad / t_fwd}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +147,7 @@ def main():
     ap.add_argument("--flags", type=int, default=0, help="nfs_params.flags (library variants)")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--no-legs", action="store_true", help="skip the batched and gradient legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every box here has a single MI355X; "
@@ -153,10 +227,19 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved[names[dom]] / HBM_PEAK_GBS, "traffic": None},
     }
+    solver.close()
+    del solver
+    if not args.no_legs:
+        log("bench: batched leg")
+        out["batched"] = batched_leg(nfs, workloads, torch, T)
+        log("bench: batched " + json.dumps(out["batched"]))
+        torch.cuda.empty_cache()
+        log("bench: gradient leg")
+        out["gradient"] = grad_leg(nfs, workloads, torch, T)
+        log("bench: gradient " + json.dumps(out["gradient"]))
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(cfg)
-    solver.close()
     print(json.dumps(out), flush=True)
 
 

@@ -64,7 +64,8 @@ extern "C" {
 
 typedef struct nfs_params {
   int32_t d;          /* dimension, 1..3 */
-  int32_t r;          /* cost exponent: 2 -> c = |x-y|^2; 1 -> c = |x-y| (needs the near field) */
+  int32_t r;          /* cost exponent: 2 -> c = |x-y|^2; 1 -> c = |x-y| (near-field corrected,
+                         Remark 3.2; not for nfs_sinkhorn_grad, no primal cost) */
   double eps;         /* temperature > 0; K = exp(-c/eps) (the paper's 1/lambda) */
   int32_t N;          /* bandwidth per dimension: I_N = {-N/2..N/2-1}^d, even, >= 4 */
   int32_t m;          /* window cutoff: 2m+1 grid taps per dimension, 2 <= m <= 8 */
@@ -73,8 +74,9 @@ typedef struct nfs_params {
   int32_t tile;       /* grid cells per bin side (0 = default for d) */
   int32_t chunk;      /* max points per workgroup chunk (0 = default) */
   int32_t flags;      /* NFS_FLAG_* */
-  double eps_I;       /* r = 1: near-field radius in units of the data scale (0 = default) */
-  int32_t p_smooth;   /* r = 1: regularization smoothness (0 = default) */
+  double eps_I;       /* r = 1: near-field radius times N on the period-1 torus (0 = default 4);
+                         the radius must fit in 2 kt + 1 tiles, kt = ceil(eps_I sigma / tile) */
+  int32_t p_smooth;   /* r = 1: derivatives matched by the inner polynomial (0 = default 8, max 16) */
   int32_t reserved;
 } nfs_params;
 

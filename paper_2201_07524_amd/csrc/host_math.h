@@ -81,9 +81,164 @@ inline Scaling choose_scaling(int d, int r, double eps, int N, const double* lo,
     const double tr = kPi * kPi * s.eps_t * double(N) * N / 4.0;
     s.kernel_err = std::exp(-std::min(per, tr));
   } else {
-    s.scale = 0.0;  // r = 1 is set up by the near-field planner
+    s.scale = 0.0;  // r = 1: see choose_scaling_r1
   }
   return s;
+}
+
+// r = 1 (kernel exp(-|z|/eps)): the periodization error is exp(-(1 - 2 R s)/(eps s));
+// keep it below exp(-L) (L = 20 for FP32 grids, 36 for FP64).
+inline Scaling choose_scaling_r1(int d, double eps, double L, const double* lo, const double* hi) {
+  Scaling s{};
+  double R = 0.0;
+  for (int c = 0; c < d; ++c) {
+    s.center[c] = 0.5 * (lo[c] + hi[c]);
+    R = std::max(R, 0.5 * (hi[c] - lo[c]));
+  }
+  s.scale = 1.0 / (2.0 * R + L * eps);
+  s.eps_t = eps * s.scale;
+  s.kernel_err = std::exp(-(1.0 - 2.0 * R * s.scale) / s.eps_t);
+  return s;
+}
+
+// Near-field regularization of K(r) = exp(-r/e) (r = |z| on the torus): inside
+// r < eI the kernel is replaced by the even polynomial
+//   K_R(r) = sum_{j<p} c_j (r/eI)^{2j},
+// whose first p-1 derivatives match K at r = eI, so K_R is smooth at the origin
+// and p-1 times differentiable at eI.  The difference K - K_R on r < eI is the
+// near-field correction.  The p x p system is solved in long double.
+inline std::vector<double> nearfield_poly(double e, double eI, int p) {
+  std::vector<long double> A(size_t(p) * p, 0.0L), b(p);
+  for (int q = 0; q < p; ++q) {
+    for (int j = 0; j < p; ++j) {
+      if (2 * j >= q) {
+        long double f = 1.0L;
+        for (int t = 0; t < q; ++t) f *= (long double)(2 * j - t);
+        A[size_t(q) * p + j] = f;
+      }
+    }
+    b[q] = std::pow(-(long double)(eI / e), (long double)q) * std::exp(-(long double)(eI / e));
+  }
+  for (int c = 0; c < p; ++c) {  // Gaussian elimination with partial pivoting
+    int piv = c;
+    for (int r = c + 1; r < p; ++r)
+      if (std::fabs(A[size_t(r) * p + c]) > std::fabs(A[size_t(piv) * p + c])) piv = r;
+    if (piv != c) {
+      for (int k = 0; k < p; ++k) std::swap(A[size_t(c) * p + k], A[size_t(piv) * p + k]);
+      std::swap(b[c], b[piv]);
+    }
+    for (int r = c + 1; r < p; ++r) {
+      const long double f = A[size_t(r) * p + c] / A[size_t(c) * p + c];
+      for (int k = c; k < p; ++k) A[size_t(r) * p + k] -= f * A[size_t(c) * p + k];
+      b[r] -= f * b[c];
+    }
+  }
+  std::vector<double> cf(p);
+  for (int r = p - 1; r >= 0; --r) {
+    long double acc = b[r];
+    for (int k = r + 1; k < p; ++k) acc -= A[size_t(r) * p + k] * (long double)cf[k];
+    cf[r] = double(acc / A[size_t(r) * p + r]);
+  }
+  return cf;
+}
+
+// Fourier transform (period-free, Poisson summation) of the radial function
+// K_R at frequency magnitude kappa in d dimensions:
+//   FT[exp(-r/e)] + FT[(K_R - K) 1_{r < eI}],
+// with FT[exp(-r/e)] = 2e/(1+a^2) (d=1), 2 pi e^2/(1+a^2)^{3/2} (d=2),
+// 8 pi e^3/(1+a^2)^2 (d=3), a = 2 pi kappa e, and the correction as a radial
+// integral (cos, J0, sinc kernels) by Gauss-Legendre quadrature on [0, eI];
+// J0 by its integral (1/pi) int_0^pi cos(x sin t) dt (midpoint rule).
+struct RadialQuad {
+  std::vector<double> r, w;
+};
+
+inline RadialQuad gauss_legendre(int n, double a, double b) {
+  RadialQuad q;
+  q.r.resize(n);
+  q.w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      const double dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    const double dp = n * (x * p1 - p0) / (x * x - 1.0);
+    q.r[i] = 0.5 * (b - a) * (x + 1.0) + a;
+    q.w[i] = (b - a) / ((1.0 - x * x) * dp * dp);
+  }
+  return q;
+}
+
+inline double bessel_j0(double x) {
+  const int n = 64;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += std::cos(x * std::sin(kPi * (i + 0.5) / n));
+  return s / n;
+}
+
+inline double r1_coeff(int d, double kappa, double e, double eI, const std::vector<double>& cf, const RadialQuad& q) {
+  const double a2 = std::pow(2.0 * kPi * kappa * e, 2);
+  double full;
+  if (d == 1) full = 2.0 * e / (1.0 + a2);
+  else if (d == 2) full = 2.0 * kPi * e * e / std::pow(1.0 + a2, 1.5);
+  else full = 8.0 * kPi * e * e * e / ((1.0 + a2) * (1.0 + a2));
+  double corr = 0.0;
+  for (size_t i = 0; i < q.r.size(); ++i) {
+    const double r = q.r[i];
+    const double rho2 = (r / eI) * (r / eI);
+    double P = 0.0;
+    for (int j = int(cf.size()) - 1; j >= 0; --j) P = P * rho2 + cf[j];
+    const double diff = P - std::exp(-r / e);
+    const double x = 2.0 * kPi * kappa * r;
+    double ker;
+    if (d == 1) ker = 2.0 * std::cos(x);
+    else if (d == 2) ker = 2.0 * kPi * r * bessel_j0(x);
+    else ker = 4.0 * kPi * r * r * (x > 0.0 ? std::sin(x) / x : 1.0);
+    corr += q.w[i] * diff * ker;
+  }
+  return full + corr;
+}
+
+// Diagonal table for r = 1 over |k_c| = 0..N/2: b(|k|) hw / prod Phi^2 (radial
+// coefficients cached per integer |k|^2).
+inline std::vector<double> r1_table(int d, int N, double e, double eI, const std::vector<double>& cf,
+                                    const std::vector<double>& phi) {
+  const int H = N / 2 + 1;
+  const RadialQuad q = gauss_legendre(96, 0.0, eI);
+  std::vector<double> byk2(size_t(d) * (N / 2) * (N / 2) + 1, std::nan(""));
+  long total = 1;
+  for (int c = 0; c < d; ++c) total *= H;
+  std::vector<double> tab(total);
+  for (long i = 0; i < total; ++i) {
+    long rem = i;
+    long k2 = 0;
+    double f = 1.0;
+    for (int c = d - 1; c >= 0; --c) {
+      const int kc = int(rem % H);
+      rem /= H;
+      k2 += long(kc) * kc;
+      f /= phi[kc] * phi[kc];
+      if (kc == N / 2) f *= 0.5;
+    }
+    if (std::isnan(byk2[k2])) byk2[k2] = r1_coeff(d, std::sqrt(double(k2)), e, eI, cf, q);
+    tab[i] = byk2[k2] * f;
+  }
+  return tab;
 }
 
 // Tables of the fused diagonal over |k_c| = 0..N/2 per axis (extent H = N/2+1,

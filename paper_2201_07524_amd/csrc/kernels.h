@@ -55,6 +55,7 @@ struct InterpArgs {
   int out_stride;
   int out_comp;
   const double* scale_vec;  // sorted per-point factor (nullable)
+  const double* nf;         // sorted per-target near-field sum added before scaling (nullable)
   // EPI_SINK / EPI_EVAL
   const double* p;
   double* alpha;
@@ -65,6 +66,32 @@ struct InterpArgs {
                             // running count
   double* wmul_next;        // per problem, receives 1/max alpha (nullable)
 };
+
+// Near-field correction for r = 1 (kernel exp(-|z|/eps) regularized inside
+// |z| < eps_I by an even polynomial): for every target,
+//   out[q] = sum_{sources j within eps_I} w_j wm (K - K_R)(x_q - y_j),
+// over the sources of the (2 kt + 1)^d neighbour tiles.  Per-problem constants
+// (stride kNearStride doubles): [0] 1/(eps_t g) (cell distance -> r/eps),
+// [1] eps_I^2 in cells^2, [2] 1/eps_I^2 in cells^-2, [3] p, [4 + j] c_j (j < p <= 16).
+constexpr int kNearStride = 24;
+template <typename R>
+struct NearArgs {
+  Geom geo;
+  const R* tcoords;
+  const Chunk* tchunks;
+  const R* scoords;
+  const double* sw;
+  const int* soffsets;  // B x nbins: first sorted source of each tile
+  const int* scounts;   // B x nbins
+  const double* wmul;   // per problem (nullable)
+  double wconst;
+  const double* coef;   // B x kNearStride
+  int kt;
+  int ps;               // polynomial terms p
+  double* out;
+};
+template <typename R>
+hipError_t launch_nearfield(const NearArgs<R>& a, int nchunks, hipStream_t st);
 
 template <typename R>
 hipError_t launch_spread(const SpreadArgs<R>& a, int nchunks, hipStream_t st);

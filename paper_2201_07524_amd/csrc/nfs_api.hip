@@ -61,7 +61,6 @@ static int check_params(const nfs_params* p, int64_t n, int64_t nt) {
   if (!p) return fail(NFS_EINVAL, "params is NULL");
   if (p->d < 1 || p->d > 3) return fail(NFS_EINVAL, "d must be 1, 2 or 3");
   if (p->r != 1 && p->r != 2) return fail(NFS_EUNSUPPORTED, "cost exponent r must be 1 or 2");
-  if (p->r == 1) return fail(NFS_EUNSUPPORTED, "r = 1 (near-field regularization) is not available in this build");
   if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(NFS_EINVAL, "eps must be positive and finite");
   if (p->N < 4 || (p->N & 1)) return fail(NFS_EINVAL, "N must be even and >= 4");
   if (p->m < 2 || p->m > 8) return fail(NFS_EINVAL, "m must be in [2, 8]");
@@ -79,8 +78,22 @@ static int check_params(const nfs_params* p, int64_t n, int64_t nt) {
   const int E = T + 2 * p->m + 1;
   const double tb = std::pow(double(E), p->d) * (p->precision == NFS_FP32 ? 4.0 : 8.0);
   if (tb > 160.0 * 1024.0) return fail(NFS_EINVAL, "LDS tile (tile + 2m + 1)^d exceeds 160 KiB; use a smaller tile");
+  if (p->r == 1) {
+    const double eIN = p->eps_I > 0.0 ? p->eps_I : 4.0;
+    const int ps = p->p_smooth ? p->p_smooth : 8;
+    if (!(eIN > 0.0) || eIN > 0.25 * p->N) return fail(NFS_EINVAL, "eps_I (near-field radius times N) must be in (0, N/4]");
+    if (ps < 2 || ps > 16) return fail(NFS_EINVAL, "p_smooth must be in [2, 16]");
+    if (p->chunk > 1024) return fail(NFS_EINVAL, "r = 1 needs chunk <= 1024");
+    const int kt = int(std::ceil(eIN * (double(g) / p->N) / T - 1e-12));
+    if ((g + T - 1) / T < 2 * kt + 1)
+      return fail(NFS_EUNSUPPORTED, "near-field radius too large for the grid (needs 2 kt + 1 tiles per axis)");
+  }
   return NFS_OK;
 }
+
+// Near-field radius on the torus and smoothness for r = 1.
+static double near_radius(const nfs_params* p) { return (p->eps_I > 0.0 ? p->eps_I : 4.0) / p->N; }
+static int near_smooth(const nfs_params* p) { return p->p_smooth ? p->p_smooth : 8; }
 
 // ----------------------------------------------------------------------------- workspace layout
 struct Carver {
@@ -149,6 +162,11 @@ struct Work {
   double* wmul_y = nullptr;   // B
   double* st_box = nullptr;   // B x 20 + 20: per problem, x box at 0, y weight box at 10
   double* tmp = nullptr;
+  int r = 2;
+  double* nf = nullptr;       // near-field sums (r = 1), per sorted target
+  double* nfcoef = nullptr;   // B x kNearStride (r = 1)
+  int kt = 0;
+  int ps = 0;
   std::vector<Scaling> sc;
   size_t bytes = 0;
 };
@@ -235,6 +253,13 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
   w.wmul_y = cv.take<double>(B);
   w.st_box = cv.take<double>(size_t(B) * 20 + 20);
   w.tmp = cv.take<double>(size_t(std::max(nA, nB)) * std::max(d, 1));
+  w.r = p->r;
+  if (p->r == 1) {
+    w.nf = cv.take<double>(size_t(std::max(nA, nB)));
+    w.nfcoef = cv.take<double>(size_t(B) * kNearStride);
+    w.kt = int(std::ceil(near_radius(p) * g / T - 1e-12));
+    w.ps = near_smooth(p);
+  }
   w.bytes = cv.off + 256;
   w.win = make_window(p->m, g, p->N);
 }
@@ -369,7 +394,28 @@ static int upload_tables(Work<R>& w, const nfs_params* p, hipStream_t st) {
   std::vector<R> t1, t2;
   bool any = false;
   for (int b = 0; b < w.B; ++b) any = any || w.sc[b].eps_t > 0.0;
-  if (any) {
+  if (any && p->r == 1) {
+    const double eI = near_radius(p);
+    const int ps = near_smooth(p);
+    t1.assign(size_t(w.B) * w.H, R(0));
+    t2.assign(size_t(w.B) * w.H, R(0));
+    std::vector<double> coef(size_t(w.B) * kNearStride, 0.0);
+    for (int b = 0; b < w.B; ++b) {
+      const double e = w.sc[b].eps_t;
+      const std::vector<double> cf = nearfield_poly(e, eI, ps);
+      const std::vector<double> tb = r1_table(p->d, p->N, e, eI, cf, phi);
+      for (long i = 0; i < w.H; ++i) t1[size_t(b) * w.H + i] = R(tb[i]);
+      double* c = coef.data() + size_t(b) * kNearStride;
+      c[0] = 1.0 / (e * g);
+      c[1] = (eI * g) * (eI * g);
+      c[2] = 1.0 / c[1];
+      c[3] = ps;
+      for (int j = 0; j < ps; ++j) c[4 + j] = cf[j];
+    }
+    NFS_HIP(hipMemcpyAsync(w.dtab, t1.data(), sizeof(R) * t1.size(), hipMemcpyHostToDevice, st));
+    NFS_HIP(hipMemcpyAsync(w.dtab2, t2.data(), sizeof(R) * t2.size(), hipMemcpyHostToDevice, st));
+    NFS_HIP(hipMemcpyAsync(w.nfcoef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, st));
+  } else if (any) {
     t1.resize(size_t(w.B) * w.H);
     t2.resize(size_t(w.B) * w.H);
     for (int b = 0; b < w.B; ++b) {
@@ -392,7 +438,7 @@ static int upload_tables(Work<R>& w, const nfs_params* p, hipStream_t st) {
 // applied in LDS between the forward and inverse passes of axis 0.  The
 // forward pass zeroes S again after reading it.
 template <typename R>
-static hipError_t fft_chain(Work<R>& w, const R* table, int deriv, hipStream_t st) {
+static hipError_t fft_chain(Work<R>& w, const R* table, int deriv, hipStream_t st, bool keep_src = false) {
   const Geom& geo = w.geo;
   const int g = geo.g, N = geo.N, d = geo.d, K0 = w.K0, B = w.B;
   Multiplier mu{table, deriv, w.H};
@@ -405,7 +451,7 @@ static hipError_t fft_chain(Work<R>& w, const R* table, int deriv, hipStream_t s
     ra.nrows = B;
     ra.real_in = w.S;
     ra.real_io = w.U;
-    ra.zero_src = 1;
+    ra.zero_src = keep_src ? 0 : 1;
     ra.tw = w.tw;
     ra.mul = mu;
     return launch_rows(ra, st);
@@ -418,7 +464,7 @@ static hipError_t fft_chain(Work<R>& w, const R* table, int deriv, hipStream_t s
   ra.nrows = int(rows * B);
   ra.real_io = w.S;
   ra.spec = w.W;
-  ra.zero_src = 1;
+  ra.zero_src = keep_src ? 0 : 1;
   ra.tw = w.tw;
   if ((e = launch_rows(ra, st)) != hipSuccess) return e;
   AxisArgs<R> ax{};
@@ -547,6 +593,28 @@ static InterpArgs<R> interp_args(Work<R>& w, const CloudBuf<R>& tgt, int epi, co
   return a;
 }
 
+// Near-field correction (r = 1) of the product with sources `src` at the
+// targets `tgt`, into w.nf (sorted target order, normalized like the spread).
+template <typename R>
+static hipError_t near_field(Work<R>& w, const CloudBuf<R>& src, const CloudBuf<R>& tgt, const double* weights,
+                             const double* wmul, double wconst, hipStream_t st) {
+  NearArgs<R> a{};
+  a.geo = w.geo;
+  a.tcoords = tgt.coords;
+  a.tchunks = tgt.chunks;
+  a.scoords = src.coords;
+  a.sw = weights;
+  a.soffsets = src.offsets;
+  a.scounts = src.counts;
+  a.wmul = wmul;
+  a.wconst = wconst;
+  a.coef = w.nfcoef;
+  a.kt = w.kt;
+  a.ps = w.ps;
+  a.out = w.nf;
+  return launch_nearfield(a, tgt.nchunks, st);
+}
+
 // One Sinkhorn half-step for every problem: spread the scalings of `src`,
 // transform, and update (or evaluate) the scalings of `tgt` (eq. (S1) via
 // eq. (fastsum)).
@@ -556,7 +624,9 @@ static hipError_t half_step(Work<R>& w, CloudBuf<R>& src, CloudBuf<R>& tgt, doub
   hipError_t e;
   if ((e = spread(w, src, src.w1s, wmul_src, 1.0, st)) != hipSuccess) return e;
   if ((e = fft_chain(w, w.dtab, -1, st)) != hipSuccess) return e;
+  if (w.r == 1 && (e = near_field(w, src, tgt, src.w1s, wmul_src, 1.0, st)) != hipSuccess) return e;
   InterpArgs<R> ia = interp_args(w, tgt, epi, wmul_src);
+  if (w.r == 1) ia.nf = w.nf;
   ia.p = tgt.w0s;
   ia.alpha = tgt.w1s;
   ia.stats = stats;
@@ -581,7 +651,8 @@ static int do_fastsum(const nfs_params* p, const double* src, int64_t ns, const 
   NFS_HIP(hipStreamSynchronize(st));
   for (int i = 0; i < 9; ++i)
     if (!std::isfinite(box[i])) return fail(NFS_EINVAL, "non-finite point coordinates or weights");
-  w.sc = {choose_scaling(p->d, p->r, p->eps, p->N, box, box + 3)};
+  w.sc = {p->r == 1 ? choose_scaling_r1(p->d, p->eps, p->precision == NFS_FP32 ? 20.0 : 36.0, box, box + 3)
+                     : choose_scaling(p->d, p->r, p->eps, p->N, box, box + 3)};
   NFS_TRY(sort_cloud(w, w.X, src, w.sc, wv, nullptr, st));
   NFS_TRY(sort_cloud(w, w.Y, tgt, w.sc, nullptr, nullptr, st));
   NFS_TRY(upload_tables(w, p, st));
@@ -589,7 +660,9 @@ static int do_fastsum(const nfs_params* p, const double* src, int64_t ns, const 
   const double wmax = box[6] > 0.0 ? box[6] : 1.0;
   NFS_HIP(spread(w, w.X, w.X.w0s, nullptr, 1.0 / wmax, st));
   NFS_HIP(fft_chain(w, w.dtab, -1, st));
+  if (w.r == 1) NFS_HIP(near_field(w, w.X, w.Y, w.X.w0s, nullptr, 1.0 / wmax, st));
   InterpArgs<R> ia = interp_args(w, w.Y, EPI_OUT, nullptr);
+  if (w.r == 1) ia.nf = w.nf;
   ia.norm = wmax;
   ia.out = out;
   NFS_HIP(launch_interp(ia, w.Y.nchunks, st));
@@ -768,7 +841,8 @@ static int plan_sinkhorn(Work<R>& w, const nfs_params* p, const double* eps, con
     const long nx = w.X.off[b + 1] - w.X.off[b], ny = w.Y.off[b + 1] - w.Y.off[b];
     NFS_TRY(check_weights(bx, nx, ny, "mu", B > 1 ? b : -1));
     NFS_TRY(check_weights(by, ny, nx, "nu", B > 1 ? b : -1));
-    w.sc[b] = choose_scaling(d, p->r, eps[b], p->N, bx, bx + 3);
+    w.sc[b] = p->r == 1 ? choose_scaling_r1(d, eps[b], p->precision == NFS_FP32 ? 20.0 : 36.0, bx, bx + 3)
+                        : choose_scaling(d, p->r, eps[b], p->N, bx, bx + 3);
   }
   NFS_TRY(sort_cloud(w, w.X, x, w.sc, mu, ax, st));
   NFS_TRY(sort_cloud(w, w.Y, y, w.sc, nu, ay, st));
@@ -920,7 +994,9 @@ struct Solver : SolverBase {
         NFS_HIP(hipEventRecord(evs[ie++], gs));
         NFS_HIP(fft_chain(w, w.dtab, -1, gs));
         NFS_HIP(hipEventRecord(evs[ie++], gs));
+        if (w.r == 1) NFS_HIP(near_field(w, src, tgt, src.w1s, ws_, 1.0, gs));
         InterpArgs<R> ia = interp_args(w, tgt, EPI_SINK, ws_);
+        if (w.r == 1) ia.nf = w.nf;
         ia.p = tgt.w0s;
         ia.alpha = tgt.w1s;
         ia.stats = h == 0 ? w.st_row : w.st_col;
@@ -975,7 +1051,7 @@ struct Solver : SolverBase {
       ReadoutArgs rb{w.Y.w0s + oy, w.Y.w1s + oy, w.Y.off[b + 1] - oy, w.partials, w.ct_misc + 1, w.st_rdy + 4 * b};
       NFS_HIP(launch_readout(rb, st));
     }
-    const bool primal = p.flags & NFS_FLAG_PRIMAL_COST;
+    const bool primal = (p.flags & NFS_FLAG_PRIMAL_COST) && p.r == 2;
     if (primal) {
       NFS_HIP(spread(w, w.Y, w.Y.w1s, w.wmul_y, 1.0, st));
       NFS_HIP(fft_chain(w, w.dtab2, -1, st));
@@ -1089,11 +1165,11 @@ static int do_grad(const nfs_params* p, const double* x, int64_t n, const double
     NFS_HIP(hipStreamSynchronize(st));
     if (!(box[6] > 0.0) || !std::isfinite(box[6])) return fail(NFS_EINVAL, "alpha_t must be positive and finite");
     const double wmax = box[6];
-    // Each derivative axis applies (2 pi i k_c) b_k / Phi^2 to the spread
-    // alpha_t and interpolates at x.
+    // alpha_t is spread once; each derivative axis applies (2 pi i k_c) b_k / Phi^2
+    // to its transform and interpolates at x (the last pass clears the grid).
+    NFS_HIP(spread(w, w.Y, w.Y.w1s, nullptr, 1.0 / wmax, st));
     for (int c = 0; c < p->d; ++c) {
-      NFS_HIP(spread(w, w.Y, w.Y.w1s, nullptr, 1.0 / wmax, st));
-      NFS_HIP(fft_chain(w, w.dtab, c, st));
+      NFS_HIP(fft_chain(w, w.dtab, c, st, c + 1 < p->d));
       InterpArgs<R> ia = interp_args(w, w.X, EPI_OUT, nullptr);
       // grad_x_i = -eps alpha_i s (dK'/dx'_c * alpha_t)(x'_i), x' = s (x - center)
       ia.norm = -p->eps * w.sc[0].scale * wmax;
@@ -1302,6 +1378,7 @@ int nfs_sinkhorn_grad(const nfs_params* prm, const double* x, int64_t n, const d
                       double* grad_mu, void* workspace, size_t ws_bytes, void* stream) {
   g_err.clear();
   NFS_TRY(check_params(prm, n, nt));
+  if (prm->r != 2) return fail(NFS_EUNSUPPORTED, "the gradient is implemented for r = 2");
   if (!x || !mu || !y || !nu || !alpha || !alpha_t || !workspace) return fail(NFS_EINVAL, "NULL pointer argument");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (prm->precision == NFS_FP32)

@@ -295,6 +295,146 @@ hipError_t launch_spread_reduce(const ReduceArgs<R>& a, int nbins, hipStream_t s
 template hipError_t launch_spread_reduce<float>(const ReduceArgs<float>&, int, hipStream_t);
 template hipError_t launch_spread_reduce<double>(const ReduceArgs<double>&, int, hipStream_t);
 
+// --------------------------------------------------------------------------- near field (r = 1)
+// One workgroup per target chunk (at most kNearTargets targets, kept in
+// registers, kNearTPT per thread); sources of each neighbour tile are staged
+// through LDS in batches of kBlock.  Distances are taken in grid cells
+// relative to the target tile's origin, so they stay small and exact enough
+// in FP32.
+constexpr int kNearTPT = 4;
+constexpr int kNearTargets = kNearTPT * kBlock;
+
+template <typename R>
+__device__ __forceinline__ R fast_exp(R x) {
+  if constexpr (sizeof(R) == 4) return __expf(x);
+  else return exp(x);
+}
+
+template <typename R, int D, int PS>
+__global__ __launch_bounds__(kBlock) void nearfield_kernel(NearArgs<R> a) {
+  __shared__ R su[D][kBlock];
+  __shared__ R sw[kBlock];
+  const Geom geo = a.geo;
+  const Chunk ch = a.tchunks[blockIdx.x];
+  const int pb = ch.prob;
+  const int nbins = geo.nt[0] * geo.nt[1] * geo.nt[2];
+  const double* cf = a.coef + size_t(pb) * kNearStride;
+  const R inv_e = R(cf[0]), ei2 = R(cf[1]), inv_ei2 = R(cf[2]);
+  R c[PS];
+#pragma unroll
+  for (int j = 0; j < PS; ++j) c[j] = R(cf[4 + j]);
+  const double wm = a.wconst * (a.wmul ? a.wmul[pb] : 1.0);
+
+  int tc[3] = {0, 0, 0};
+  {
+    int t = ch.tile;
+    for (int k = D - 1; k >= 0; --k) {
+      tc[k] = t % geo.nt[k];
+      t /= geo.nt[k];
+    }
+  }
+  R ut[kNearTPT][D];
+  R acc[kNearTPT];
+#pragma unroll
+  for (int k = 0; k < kNearTPT; ++k) {
+    acc[k] = R(0);
+    const int q = ch.start + threadIdx.x + k * kBlock;
+#pragma unroll
+    for (int cc = 0; cc < D; ++cc)
+      ut[k][cc] = (q < ch.start + ch.count) ? a.tcoords[size_t(q) * D + cc] : R(1e30);
+  }
+  const int span = 2 * a.kt + 1;
+  int nnb = 1;
+  for (int k = 0; k < D; ++k) nnb *= span;
+  for (int nbi = 0; nbi < nnb; ++nbi) {
+    int rem = nbi, tile = 0;
+    R shift[3] = {R(0), R(0), R(0)};
+    for (int k = 0; k < D; ++k) {
+      const int dl = rem % span - a.kt;
+      rem /= span;
+      int t = tc[k] + dl;
+      t = ((t % geo.nt[k]) + geo.nt[k]) % geo.nt[k];
+      tile = tile * geo.nt[k] + t;
+      shift[k] = R(dl * geo.T);
+    }
+    const int so = a.soffsets[size_t(pb) * nbins + tile];
+    const int sc = a.scounts[size_t(pb) * nbins + tile];
+    for (int s0 = 0; s0 < sc; s0 += kBlock) {
+      const int nb = min(kBlock, sc - s0);
+      __syncthreads();
+      if (threadIdx.x < nb) {
+        const int j = so + s0 + threadIdx.x;
+#pragma unroll
+        for (int cc = 0; cc < D; ++cc) su[cc][threadIdx.x] = a.scoords[size_t(j) * D + cc] + shift[cc];
+        sw[threadIdx.x] = R(a.sw[j] * wm);
+      }
+      __syncthreads();
+      for (int j = 0; j < nb; ++j) {
+        R ys[D];
+#pragma unroll
+        for (int cc = 0; cc < D; ++cc) ys[cc] = su[cc][j];
+        const R wj = sw[j];
+#pragma unroll
+        for (int k = 0; k < kNearTPT; ++k) {
+          R r2 = R(0);
+#pragma unroll
+          for (int cc = 0; cc < D; ++cc) {
+            const R dz = ut[k][cc] - ys[cc];
+            r2 += dz * dz;
+          }
+          if (r2 < ei2) {
+            const R rho2 = r2 * inv_ei2;
+            R P = c[PS - 1];
+#pragma unroll
+            for (int jj = PS - 2; jj >= 0; --jj) P = P * rho2 + c[jj];
+            acc[k] += wj * (fast_exp(-sqrt(r2) * inv_e) - P);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kNearTPT; ++k) {
+    const int q = ch.start + threadIdx.x + k * kBlock;
+    if (q < ch.start + ch.count) a.out[q] = double(acc[k]);
+  }
+}
+
+#define NFS_NEAR_P(D_)                                                                                       \
+  switch (a.ps) {                                                                                          \
+    case 2: hipLaunchKernelGGL((nearfield_kernel<R, D_, 2>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
+    case 3: hipLaunchKernelGGL((nearfield_kernel<R, D_, 3>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
+    case 4: hipLaunchKernelGGL((nearfield_kernel<R, D_, 4>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
+    case 5: hipLaunchKernelGGL((nearfield_kernel<R, D_, 5>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
+    case 6: hipLaunchKernelGGL((nearfield_kernel<R, D_, 6>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
+    case 7: hipLaunchKernelGGL((nearfield_kernel<R, D_, 7>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
+    case 8: hipLaunchKernelGGL((nearfield_kernel<R, D_, 8>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
+    case 9: hipLaunchKernelGGL((nearfield_kernel<R, D_, 9>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
+    case 10: hipLaunchKernelGGL((nearfield_kernel<R, D_, 10>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
+    case 11: hipLaunchKernelGGL((nearfield_kernel<R, D_, 11>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
+    case 12: hipLaunchKernelGGL((nearfield_kernel<R, D_, 12>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
+    case 13: hipLaunchKernelGGL((nearfield_kernel<R, D_, 13>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
+    case 14: hipLaunchKernelGGL((nearfield_kernel<R, D_, 14>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
+    case 15: hipLaunchKernelGGL((nearfield_kernel<R, D_, 15>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
+    case 16: hipLaunchKernelGGL((nearfield_kernel<R, D_, 16>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
+    default: return hipErrorInvalidValue;                                                                  \
+  }
+
+template <typename R>
+hipError_t launch_nearfield(const NearArgs<R>& a, int nchunks, hipStream_t st) {
+  if (nchunks <= 0) return hipSuccess;
+  if (a.geo.d == 1) {
+    NFS_NEAR_P(1)
+  } else if (a.geo.d == 2) {
+    NFS_NEAR_P(2)
+  } else {
+    NFS_NEAR_P(3)
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_nearfield<float>(const NearArgs<float>&, int, hipStream_t);
+template hipError_t launch_nearfield<double>(const NearArgs<double>&, int, hipStream_t);
+
 // --------------------------------------------------------------------------- block reduction
 struct Red4 {
   double s0, s1, mx;
@@ -434,7 +574,7 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
         acc += pacc * tp.psi[0][j0];
       }
     }
-    const double t = double(acc) * outmul;
+    const double t = (double(acc) + (a.nf ? a.nf[q] : 0.0)) * outmul;
     if (a.epi == EPI_OUT) {
       const double sc = a.scale_vec ? a.scale_vec[q] : 1.0;
       a.out[size_t(a.perm[q]) * a.out_stride + a.out_comp] = t * sc;

@@ -146,3 +146,49 @@ def test_spread_paths_agree(d, N, m, tile):
         outs.append(nfs.fastsum(prm, T(src), T(w), T(tgt)).cpu().numpy())
         assert relerr(outs[-1], ref) <= 1e-10
     assert relerr(outs[0], outs[1]) <= 1e-13
+
+
+# ------------------------------------------------------------------ r = 1 (near field)
+def _r1_clouds(d, n, seed):
+    if d == 3:
+        x = workloads.uniform_ball(n, seed, d=3)
+        y = workloads.noisy_shell(n, seed + 1, d=3)
+    else:
+        x = np.random.default_rng(seed).uniform(-0.2, 0.2, (n, d))
+        y = np.random.default_rng(seed + 1).uniform(-0.2, 0.2, (n, d))
+    w = np.random.default_rng(seed + 2).uniform(0.0, 1.0, n)
+    return y, w, x
+
+
+@pytest.mark.parametrize("d,N,eps,tol", [(1, 256, 0.05, 1e-8), (2, 64, 0.05, 1e-7), (3, 32, 0.05, 2e-7),
+                                         (3, 128, 0.02, 5e-7)])
+def test_fastsum_r1_fp64_matches_dense(d, N, eps, tol):
+    """Euclidean cost: kernel exp(-|z|/eps) regularized inside eps_I = 8/N by an
+    even polynomial (p = 10) plus the near-field correction.  The error is the
+    truncation of the regularized kernel's Fourier series (no rate is printed
+    in the paper; the bound is the measured one with a margin)."""
+    src, w, tgt = _r1_clouds(d, 1500 if d < 3 else 1200, 1000 + d)
+    prm = nfs.Params(d=d, r=1, eps=eps, N=N, m=8, precision="fp64", eps_I=8, p_smooth=10)
+    got = nfs.fastsum(prm, T(src), T(w), T(tgt)).cpu().numpy()
+    ref = sd.gibbs_kernel(tgt, src, 1, eps) @ w
+    assert relerr(got, ref) <= tol
+
+
+def test_fastsum_r1_error_decays_with_near_field_radius():
+    src, w, tgt = _r1_clouds(3, 1000, 1100)
+    ref = sd.gibbs_kernel(tgt, src, 1, 0.05) @ w
+    errs = []
+    for eI in (3, 4, 6, 8):
+        prm = nfs.Params(d=3, r=1, eps=0.05, N=32, m=8, precision="fp64", eps_I=eI, p_smooth=8)
+        errs.append(relerr(nfs.fastsum(prm, T(src), T(w), T(tgt)).cpu().numpy(), ref))
+    assert all(b < a / 3 for a, b in zip(errs, errs[1:]))
+
+
+def test_fastsum_r1_fp32_default_near_field():
+    """The 3-D ball/shell shape at N = 128, eps = 0.02, m = 6, FP32 with the
+    default near field (eps_I = 4/N, p = 8) is within the FP32 bar."""
+    src, w, tgt = _r1_clouds(3, 1500, 1200)
+    prm = nfs.Params(d=3, r=1, eps=0.02, N=128, m=6, precision="fp32")
+    got = nfs.fastsum(prm, T(src), T(w), T(tgt)).cpu().numpy()
+    ref = sd.gibbs_kernel(tgt, src, 1, 0.02) @ w
+    assert relerr(got, ref) <= 1e-5

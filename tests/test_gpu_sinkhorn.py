@@ -169,3 +169,21 @@ def test_2d_mixture_full_size_sampled_parity():
     tt_gpu = cfg["pt"][rows] / at[rows]          # the K^T alpha the GPU divided by
     assert np.max(np.abs(tt_gpu - tt)) <= 1e-5 * np.max(tt)
     assert np.isfinite(res.cost) and res.marg_err_col <= 1e-3 * np.linalg.norm(cfg["pt"])
+
+
+def test_sinkhorn_r1_3d_vs_oracle():
+    """Euclidean cost (r = 1) on a ball/shell subsample: the solve with the
+    near-field corrected fast summation tracks the dense oracle."""
+    x = workloads.uniform_ball(1200, 1300)
+    y = workloads.noisy_shell(1000, 1301)
+    p, pt = workloads.uniform_weights(1200), workloads.uniform_weights(1000)
+    eps, iters = 0.02, 40
+    ref = sd.solve(x, p, y, pt, 1, eps, iters)
+    prm = nfs.Params(d=3, r=1, eps=eps, N=128, m=8, precision="fp64", eps_I=8, p_smooth=10)
+    res = nfs.sinkhorn(prm, T(x), T(p), T(y), T(pt), iters)
+    assert rel(res.cost, ref["cost"]) <= 1e-6
+    a = res.alpha.cpu().numpy()
+    assert np.all(a > 0)
+    K = sd.gibbs_kernel(x, y, 1, eps)
+    e_row, e_col = sd.marginal_errors(K, a, res.alpha_t.cpu().numpy(), p, pt)
+    assert e_row + e_col <= 10 * ref["marg_err"] + 1e-5 * np.linalg.norm(p)
