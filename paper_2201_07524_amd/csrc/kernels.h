@@ -19,6 +19,8 @@ struct SpreadArgs {
   const double* wmul;    // per-problem multiplier of the weights, indexed by chunk.prob (nullable)
   double wconst;         // host constant multiplier of the weights
   const Chunk* chunks;
+  const int* runs;       // run table of each chunk (offsets from the chunk's start)
+  const int* nruns;      // per chunk: full runs, single points
   R* grid;               // problem p's g^d real grid at grid + p*grid_stride, zero on entry
   long grid_stride;
   R* part;               // non-null: store each chunk's padded tile here instead of flushing
@@ -43,6 +45,8 @@ struct InterpArgs {
   Geom geo;
   const R* coords;
   const Chunk* chunks;
+  const int* runs;          // run table of each chunk (offsets from the chunk's start)
+  const int* nruns;         // per chunk: full runs, single points
   const R* grid;            // problem p's grid at grid + p*grid_stride
   long grid_stride;
   WindowConst win;
@@ -193,6 +197,32 @@ struct ScatterArgs {
 };
 template <typename R>
 hipError_t launch_scatter(const ScatterArgs<R>& a, hipStream_t st);
+
+// Per-chunk cell sort and run table.  Chunks of at most kChunkSortMax points
+// in tiles of at most kChunkSortBins cells are reordered in place by cell;
+// every cell's points form full runs of G = run_length(d) and c mod G single
+// points.  For the chunk starting at `start`, runs[start + r] is the offset
+// (from `start`) of the first point of entry r: nruns[2 chunk] full runs come
+// first, then nruns[2 chunk + 1] single points.  Chunks that are not sorted
+// get single points only.
+constexpr int kChunkSortMax = 1024;
+constexpr int kChunkSortBins = 4096;
+template <typename R>
+struct ChunkSortArgs {
+  const Chunk* chunks;
+  int nchunks;
+  int d, T;
+  int sort;     // 0: one run per point, no reordering
+  int G;        // longest run
+  R* coords;
+  int* perm;
+  double* w0s;  // nullable
+  double* w1s;  // nullable
+  int* runs;
+  int* nruns;
+};
+template <typename R>
+hipError_t launch_chunk_sort(const ChunkSortArgs<R>& a, hipStream_t st);
 
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_fill_double(double* p, long n, double v, hipStream_t st);

@@ -126,6 +126,8 @@ struct CloudBuf {
   int* tile_chunks = nullptr;  // nbins + 1 (single problem, per-tile reduction only)
   double* w0s = nullptr;       // sorted weights
   double* w1s = nullptr;       // sorted scalings
+  int* runs = nullptr;         // n: run table of each chunk (offsets from the chunk start)
+  int* nruns = nullptr;        // 2 x max_chunks: full runs and single points per chunk
 };
 
 template <typename R>
@@ -212,6 +214,8 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
     cb.chunks = cv.take<Chunk>(cb.max_chunks);
     cb.prob_chunks = cv.take<int>(B + 1);
     cb.tile_chunks = cv.take<int>(nbins + 1);
+    cb.runs = cv.take<int>(n);
+    cb.nruns = cv.take<int>(2 * cb.max_chunks);
     cb.w0s = nvec >= 1 ? cv.take<double>(n) : nullptr;
     cb.w1s = nvec >= 2 ? cv.take<double>(n) : nullptr;
   };
@@ -374,6 +378,22 @@ static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const std:
     sa.w1s = cb.w1s;
     NFS_HIP(launch_scatter(sa, st));
   }
+  int cells = 1;
+  for (int c = 0; c < d; ++c) cells *= geo.T;
+  ChunkSortArgs<R> ca{};
+  ca.chunks = cb.chunks;
+  ca.nchunks = cb.nchunks;
+  ca.d = d;
+  ca.T = geo.T;
+  ca.sort = w.chunk <= kChunkSortMax && cells <= kChunkSortBins;
+  ca.G = run_length<R>(d);
+  ca.coords = cb.coords;
+  ca.perm = cb.perm;
+  ca.w0s = v0 ? cb.w0s : nullptr;
+  ca.w1s = v1 ? cb.w1s : nullptr;
+  ca.runs = cb.runs;
+  ca.nruns = cb.nruns;
+  NFS_HIP(launch_chunk_sort(ca, st));
   NFS_HIP(hipStreamSynchronize(st));  // host vectors above must outlive the copies
   return NFS_OK;
 }
@@ -547,6 +567,8 @@ static SpreadArgs<R> spread_args(Work<R>& w, const CloudBuf<R>& src, const doubl
   a.wmul = wmul;
   a.wconst = 1.0;
   a.chunks = src.chunks;
+  a.runs = src.runs;
+  a.nruns = src.nruns;
   a.grid = w.S;
   a.grid_stride = w.ncell;
   a.win = w.win;
@@ -579,6 +601,8 @@ static InterpArgs<R> interp_args(Work<R>& w, const CloudBuf<R>& tgt, int epi, co
   a.geo = w.geo;
   a.coords = tgt.coords;
   a.chunks = tgt.chunks;
+  a.runs = tgt.runs;
+  a.nruns = tgt.nruns;
   a.grid = w.U;
   a.grid_stride = w.ncell;
   a.win = w.win;

@@ -17,24 +17,60 @@
 
 namespace nfs {
 
-template <typename R, int D, int M>
+// Window evaluation with the constants converted once per kernel.
+template <typename R>
+struct WinEval {
+  R m2, b, bm, cn, b2, bm2, cn2, e2bm, edge;
+  __device__ __forceinline__ explicit WinEval(const WindowConst& wc)
+      : m2(R(wc.m2)), b(R(wc.b)), bm(R(wc.bm)), cn(R(wc.cnorm)), b2(R(wc.b2)), bm2(R(wc.bm2)), cn2(R(wc.cn2)),
+        e2bm(R(wc.e2bm)), edge(R(wc.edge)) {}
+  __device__ __forceinline__ R operator()(R z) const {
+    if constexpr (sizeof(R) == 4) return kb_psi_fast(z, m2, b2, bm2, cn2, e2bm, edge);
+    else return kb_psi(z, m2, b, bm, cn);
+  }
+};
+
+// Window taps of one point: the first tap offset per axis (off), the distance
+// of the first tap (z0), and the 2m+1 window values of every axis c >= FROM
+// (axes below FROM are evaluated on the fly by the caller, one value per row,
+// so that loops over them can stay rolled with static register indices).
+template <typename R, int D, int M, int FROM>
 struct Taps {
   static constexpr int W = 2 * M + 1;
   R psi[D][W];
+  R z0[D];
   int off[D];
 
-  __device__ __forceinline__ void compute(const R* u, const WindowConst& wc) {
-    const R m2 = R(wc.m2), b = R(wc.b), bm = R(wc.bm), cn = R(wc.cnorm);
+  __device__ __forceinline__ void compute(const R* u, const WinEval<R>& ev) {
 #pragma unroll
     for (int c = 0; c < D; ++c) {
       const R s = ceil(u[c] - R(M));
       off[c] = int(s) + M;
-      const R z0 = s - u[c];
+      z0[c] = s - u[c];
+      if (c >= FROM) {
 #pragma unroll
-      for (int j = 0; j < W; ++j) psi[c][j] = kb_psi(z0 + R(j), m2, b, bm, cn);
+        for (int j = 0; j < W; ++j) psi[c][j] = ev(z0[c] + R(j));
+      }
     }
   }
 };
+
+// a[0..W) <- a[1], ..., a[W-1], a[0] (register moves)
+template <typename R, int W>
+__device__ __forceinline__ void rotate_left(R (&v)[W]) {
+  const R first = v[0];
+#pragma unroll
+  for (int j = 0; j + 1 < W; ++j) v[j] = v[j + 1];
+  v[W - 1] = first;
+}
+
+// Lanes of one wave take runs spread over the whole chunk (lane l of slot row
+// r gets run l * rows + r), so that the 64 lanes of a wave work in different
+// cells of the cell-sorted chunk rather than on the same few LDS words.
+constexpr int kWave = 64;
+__device__ __forceinline__ int run_of_slot(int slot, int rows) {
+  return (slot % kWave) * rows + slot / kWave;
+}
 
 __device__ __forceinline__ int wrap(int v, int g) {
   v %= g;
@@ -104,10 +140,80 @@ struct Acc<double, ACC_FIX128> {
   }
 };
 
+// Spreads GC consecutive sorted points that lie in one cell (so their windows
+// start at the same offsets): per tap the GC contributions are summed in
+// registers, and the tap costs one fixed-point conversion and one LDS atomic
+// for the whole run.
+template <typename R, int D, int M, int ACC, int GC>
+__device__ __forceinline__ void spread_run(Acc<R, ACC>& tile, const SpreadArgs<R>& a, const WinEval<R>& ev, int E,
+                                           int q0, double wm) {
+  constexpr int W = 2 * M + 1;
+  constexpr int FROM = D == 1 ? 0 : 1;
+  Taps<R, D, M, FROM> tp[GC];
+  R w[GC];
+#pragma unroll
+  for (int p = 0; p < GC; ++p) {
+    const int q = q0 + p;
+    w[p] = R(a.w[q] * wm);
+    R u[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) u[c] = a.coords[size_t(q) * D + c];
+    tp[p].compute(u, ev);
+  }
+  if constexpr (D == 1) {
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      R v = R(0);
+#pragma unroll
+      for (int p = 0; p < GC; ++p) v += w[p] * tp[p].psi[0][j];
+      tile.add(tp[0].off[0] + j, v);
+    }
+  } else if constexpr (D == 2) {
+#pragma unroll 1
+    for (int j0 = 0; j0 < W; ++j0) {
+      R a0[GC];
+#pragma unroll
+      for (int p = 0; p < GC; ++p) a0[p] = w[p] * ev(tp[p].z0[0] + R(j0));
+      const int row = (tp[0].off[0] + j0) * E + tp[0].off[1];
+#pragma unroll
+      for (int j1 = 0; j1 < W; ++j1) {
+        R v = R(0);
+#pragma unroll
+        for (int p = 0; p < GC; ++p) v += a0[p] * tp[p].psi[1][j1];
+        tile.add(row + j1, v);
+      }
+    }
+  } else {
+    // the rolled j1 loop reads element 0 of the second-axis windows, which
+    // are rotated by one per iteration (a full cycle restores them)
+#pragma unroll 1
+    for (int j0 = 0; j0 < W; ++j0) {
+      R b0[GC];
+#pragma unroll
+      for (int p = 0; p < GC; ++p) b0[p] = w[p] * ev(tp[p].z0[0] + R(j0));
+#pragma unroll 1
+      for (int j1 = 0; j1 < W; ++j1) {
+        R a1[GC];
+#pragma unroll
+        for (int p = 0; p < GC; ++p) a1[p] = b0[p] * tp[p].psi[1][0];
+        const int row = ((tp[0].off[0] + j0) * E + tp[0].off[1] + j1) * E + tp[0].off[2];
+#pragma unroll
+        for (int j2 = 0; j2 < W; ++j2) {
+          R v = R(0);
+#pragma unroll
+          for (int p = 0; p < GC; ++p) v += a1[p] * tp[p].psi[2][j2];
+          tile.add(row + j2, v);
+        }
+#pragma unroll
+        for (int p = 0; p < GC; ++p) rotate_left(tp[p].psi[1]);
+      }
+    }
+  }
+}
+
 template <typename R, int D, int M, int ACC>
 __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int W = 2 * M + 1;
   const Geom geo = a.geo;
   const int E = geo.E;
   const int ncell = D == 1 ? E : (D == 2 ? E * E : E * E * E);
@@ -117,38 +223,22 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs<R> a) {
   for (int i = threadIdx.x; i < ncell; i += kBlock) tile.zero(i);
   __syncthreads();
 
+  // The chunk's run table lists full runs of G same-cell points, then the
+  // remaining points one by one; each phase is free of lane divergence.
+  constexpr int G = run_length<R>(D);
+  const WinEval<R> ev(a.win);
   const double wm = a.wconst * (a.wmul ? a.wmul[ch.prob] : 1.0);
-  for (int q = ch.start + threadIdx.x; q < ch.start + ch.count; q += kBlock) {
-    const R w = R(a.w[q] * wm);
-    if (w == R(0)) continue;
-    R u[D];
-#pragma unroll
-    for (int c = 0; c < D; ++c) u[c] = a.coords[size_t(q) * D + c];
-    Taps<R, D, M> tp;
-    tp.compute(u, a.win);
-    if constexpr (D == 1) {
-#pragma unroll
-      for (int j = 0; j < W; ++j) tile.add(tp.off[0] + j, w * tp.psi[0][j]);
-    } else if constexpr (D == 2) {
-#pragma unroll
-      for (int j0 = 0; j0 < W; ++j0) {
-        const R v0 = w * tp.psi[0][j0];
-        const int row = (tp.off[0] + j0) * E + tp.off[1];
-#pragma unroll
-        for (int j1 = 0; j1 < W; ++j1) tile.add(row + j1, v0 * tp.psi[1][j1]);
-      }
-    } else {
-      for (int j0 = 0; j0 < W; ++j0) {
-        const R v0 = w * tp.psi[0][j0];
-#pragma unroll 1
-        for (int j1 = 0; j1 < W; ++j1) {
-          const R v1 = v0 * tp.psi[1][j1];
-          const int row = ((tp.off[0] + j0) * E + tp.off[1] + j1) * E + tp.off[2];
-#pragma unroll
-          for (int j2 = 0; j2 < W; ++j2) tile.add(row + j2, v1 * tp.psi[2][j2]);
-        }
-      }
-    }
+  const int* runs = a.runs + ch.start;
+  const int nfull = a.nruns[2 * blockIdx.x], nsingle = a.nruns[2 * blockIdx.x + 1];
+  int rows = (nfull + kWave - 1) / kWave;
+  for (int slot = threadIdx.x; slot < rows * kWave; slot += kBlock) {
+    const int rr = run_of_slot(slot, rows);
+    if (rr < nfull) spread_run<R, D, M, ACC, G>(tile, a, ev, E, ch.start + runs[rr], wm);
+  }
+  rows = (nsingle + kWave - 1) / kWave;
+  for (int slot = threadIdx.x; slot < rows * kWave; slot += kBlock) {
+    const int rr = run_of_slot(slot, rows);
+    if (rr < nsingle) spread_run<R, D, M, ACC, 1>(tile, a, ev, E, ch.start + runs[nfull + rr], wm);
   }
   __syncthreads();
 
@@ -504,12 +594,97 @@ __device__ void finish_reduce(Red4 mine, Red4* sh, double* partials, unsigned* c
 }
 
 // --------------------------------------------------------------------------- interp
+constexpr int kInterpRun = 2;
+
+// Interpolates GC consecutive sorted points that lie in one cell: each row of
+// taps is read from the LDS tile once and dotted with the GC windows.
+template <typename R, int D, int M, int GC>
+__device__ __forceinline__ void interp_run(const R* tile, const InterpArgs<R>& a, const WinEval<R>& ev, int E, int q0,
+                                           R (&acc)[GC]) {
+  constexpr int W = 2 * M + 1;
+  constexpr int FROM = D == 1 ? 0 : 1;
+  Taps<R, D, M, FROM> tp[GC];
+#pragma unroll
+  for (int p = 0; p < GC; ++p) {
+    R u[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) u[c] = a.coords[size_t(q0 + p) * D + c];
+    tp[p].compute(u, ev);
+    acc[p] = R(0);
+  }
+  if constexpr (D == 1) {
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const R gv = tile[tp[0].off[0] + j];
+#pragma unroll
+      for (int p = 0; p < GC; ++p) acc[p] += gv * tp[p].psi[0][j];
+    }
+  } else if constexpr (D == 2) {
+#pragma unroll 1
+    for (int j0 = 0; j0 < W; ++j0) {
+      const R* row = tile + (tp[0].off[0] + j0) * E + tp[0].off[1];
+      R gv[W];
+#pragma unroll
+      for (int j1 = 0; j1 < W; ++j1) gv[j1] = row[j1];
+#pragma unroll
+      for (int p = 0; p < GC; ++p) {
+        R racc = R(0);
+#pragma unroll
+        for (int j1 = 0; j1 < W; ++j1) racc += gv[j1] * tp[p].psi[1][j1];
+        acc[p] += racc * ev(tp[p].z0[0] + R(j0));
+      }
+    }
+  } else {
+#pragma unroll 1
+    for (int j0 = 0; j0 < W; ++j0) {
+      R pacc[GC];
+#pragma unroll
+      for (int p = 0; p < GC; ++p) pacc[p] = R(0);
+      if constexpr (sizeof(R) == 4) {
+#pragma unroll
+        for (int j1 = 0; j1 < W; ++j1) {
+          const R* row = tile + ((tp[0].off[0] + j0) * E + tp[0].off[1] + j1) * E + tp[0].off[2];
+          R gv[W];
+#pragma unroll
+          for (int j2 = 0; j2 < W; ++j2) gv[j2] = row[j2];
+#pragma unroll
+          for (int p = 0; p < GC; ++p) {
+            R racc = R(0);
+#pragma unroll
+            for (int j2 = 0; j2 < W; ++j2) racc += gv[j2] * tp[p].psi[2][j2];
+            pacc[p] += racc * tp[p].psi[1][j1];
+          }
+        }
+      } else {
+        // FP64: a fully unrolled j1 loop does not fit the register file; roll
+        // it and rotate the second-axis windows (a full cycle restores them)
+#pragma unroll 1
+        for (int j1 = 0; j1 < W; ++j1) {
+          const R* row = tile + ((tp[0].off[0] + j0) * E + tp[0].off[1] + j1) * E + tp[0].off[2];
+          R gv[W];
+#pragma unroll
+          for (int j2 = 0; j2 < W; ++j2) gv[j2] = row[j2];
+#pragma unroll
+          for (int p = 0; p < GC; ++p) {
+            R racc = R(0);
+#pragma unroll
+            for (int j2 = 0; j2 < W; ++j2) racc += gv[j2] * tp[p].psi[2][j2];
+            pacc[p] += racc * tp[p].psi[1][0];
+            rotate_left(tp[p].psi[1]);
+          }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < GC; ++p) acc[p] += pacc[p] * ev(tp[p].z0[0] + R(j0));
+    }
+  }
+}
+
 template <typename R, int D, int M>
 __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
   __shared__ Red4 red_sh[kBlock / 64];
-  constexpr int W = 2 * M + 1;
   const Geom geo = a.geo;
   const int E = geo.E;
   const int g = geo.g;
@@ -541,40 +716,11 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
 
   const double outmul = a.norm / (a.wmul_src ? a.wmul_src[ch.prob] : 1.0);
   Red4 acc_red{0.0, 0.0, 0.0, 0.0};
-  for (int q = ch.start + threadIdx.x; q < ch.start + ch.count; q += kBlock) {
-    R u[D];
-#pragma unroll
-    for (int c = 0; c < D; ++c) u[c] = a.coords[size_t(q) * D + c];
-    Taps<R, D, M> tp;
-    tp.compute(u, a.win);
-    R acc = R(0);
-    if constexpr (D == 1) {
-#pragma unroll
-      for (int j = 0; j < W; ++j) acc += tile[tp.off[0] + j] * tp.psi[0][j];
-    } else if constexpr (D == 2) {
-#pragma unroll
-      for (int j0 = 0; j0 < W; ++j0) {
-        const R* row = tile + (tp.off[0] + j0) * E + tp.off[1];
-        R racc = R(0);
-#pragma unroll
-        for (int j1 = 0; j1 < W; ++j1) racc += row[j1] * tp.psi[1][j1];
-        acc += racc * tp.psi[0][j0];
-      }
-    } else {
-      for (int j0 = 0; j0 < W; ++j0) {
-        R pacc = R(0);
-#pragma unroll 1
-        for (int j1 = 0; j1 < W; ++j1) {
-          const R* row = tile + ((tp.off[0] + j0) * E + tp.off[1] + j1) * E + tp.off[2];
-          R racc = R(0);
-#pragma unroll
-          for (int j2 = 0; j2 < W; ++j2) racc += row[j2] * tp.psi[2][j2];
-          pacc += racc * tp.psi[1][j1];
-        }
-        acc += pacc * tp.psi[0][j0];
-      }
-    }
-    const double t = (double(acc) + (a.nf ? a.nf[q] : 0.0)) * outmul;
+  // nfq: the point's near-field sum, loaded by the caller before the
+  // interpolation (a load inside here lets the compiler hoist it above the
+  // tap loop together with the LDS reads, at a large cost in registers)
+  auto epilogue = [&](int q, R acc, double nfq) {
+    const double t = (double(acc) + nfq) * outmul;
     if (a.epi == EPI_OUT) {
       const double sc = a.scale_vec ? a.scale_vec[q] : 1.0;
       a.out[size_t(a.perm[q]) * a.out_stride + a.out_comp] = t * sc;
@@ -598,6 +744,33 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
         a.alpha[q] = 0.0;
       }
     }
+  };
+  // Full runs of G same-cell points first, then the remaining points one by
+  // one (each phase free of lane divergence).  Consecutive lanes take
+  // consecutive runs: global accesses stay coalesced, and lanes in the same
+  // cell read the same LDS words (a broadcast).
+  const WinEval<R> ev(a.win);
+  constexpr int G = run_length<R>(D);
+  constexpr int GI = kInterpRun < G ? kInterpRun : G;  // points per interpolation run, divides G
+  constexpr int SUB = G / GI;
+  const int* runs = a.runs + ch.start;
+  const int nfull = a.nruns[2 * blockIdx.x], nsingle = a.nruns[2 * blockIdx.x + 1];
+  for (int rr = threadIdx.x; rr < nfull * SUB; rr += kBlock) {
+    const int q0 = ch.start + runs[rr / SUB] + (rr % SUB) * GI;
+    double nfq[GI];
+#pragma unroll
+    for (int p = 0; p < GI; ++p) nfq[p] = a.nf ? a.nf[q0 + p] : 0.0;
+    R acc[GI];
+    interp_run<R, D, M, GI>(tile, a, ev, E, q0, acc);
+#pragma unroll
+    for (int p = 0; p < GI; ++p) epilogue(q0 + p, acc[p], nfq[p]);
+  }
+  for (int rr = threadIdx.x; rr < nsingle; rr += kBlock) {
+    const int q0 = ch.start + runs[nfull + rr];
+    const double nfq = a.nf ? a.nf[q0] : 0.0;
+    R acc[1];
+    interp_run<R, D, M, 1>(tile, a, ev, E, q0, acc);
+    epilogue(q0, acc[0], nfq);
   }
   if (a.epi != EPI_OUT) {
     const Red4 r = block_reduce(acc_red, red_sh);

@@ -152,6 +152,119 @@ hipError_t launch_scatter(const ScatterArgs<R>& a, hipStream_t st) {
 template hipError_t launch_scatter<float>(const ScatterArgs<float>&, hipStream_t);
 template hipError_t launch_scatter<double>(const ScatterArgs<double>&, hipStream_t);
 
+// ------------------------------------------------------------------ per-chunk cell sort
+// Exclusive prefix sum over the workgroup; returns this thread's prefix and
+// the total in *total.  `part` holds kBlock ints of LDS.
+__device__ int block_exclusive_scan(int v, int* part, int* total) {
+  part[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int u = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += u;
+    __syncthreads();
+  }
+  const int incl = part[threadIdx.x];
+  *total = part[kBlock - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+// One workgroup per chunk.  Sorting mode: an LDS histogram over the T^d cells
+// of the tile gives every point its slot (cell start + arrival rank), the
+// chunk is rewritten in place in cell order, and each cell's points are cut
+// into full runs of G followed by its c mod G remaining points.  The run table
+// lists all full runs of the chunk, then all remaining points.  Same-cell
+// points then share their window taps in spreading and interpolation.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void chunk_sort_kernel(ChunkSortArgs<R> a) {
+  constexpr int PER = kChunkSortMax / kBlock;
+  __shared__ int start[kChunkSortBins];
+  __shared__ int part[kBlock];
+  const Chunk ch = a.chunks[blockIdx.x];
+  if (!a.sort) {
+    for (int i = threadIdx.x; i < ch.count; i += kBlock) a.runs[ch.start + i] = i;
+    if (threadIdx.x == 0) {
+      a.nruns[2 * blockIdx.x] = 0;
+      a.nruns[2 * blockIdx.x + 1] = ch.count;
+    }
+    return;
+  }
+  const int d = a.d, T = a.T, G = a.G;
+  int nc = 1;
+  for (int c = 0; c < d; ++c) nc *= T;
+  for (int i = threadIdx.x; i < nc; i += kBlock) start[i] = 0;
+  __syncthreads();
+  R co[PER][3];
+  int pm[PER], key[PER], rank[PER];
+  double v0[PER], v1[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    key[k] = -1;
+    if (i < ch.count) {
+      const size_t q = size_t(ch.start) + i;
+      int kk = 0;
+      for (int c = 0; c < d; ++c) {
+        co[k][c] = a.coords[q * d + c];
+        kk = kk * T + min(max(int(co[k][c]), 0), T - 1);
+      }
+      pm[k] = a.perm[q];
+      v0[k] = a.w0s ? a.w0s[q] : 0.0;
+      v1[k] = a.w1s ? a.w1s[q] : 0.0;
+      key[k] = kk;
+      rank[k] = atomicAdd(&start[kk], 1);
+    }
+  }
+  __syncthreads();
+  // each thread owns the contiguous cells [b0, b1)
+  const int per = (nc + kBlock - 1) / kBlock;
+  const int b0 = min(int(threadIdx.x) * per, nc), b1 = min(b0 + per, nc);
+  int npts = 0, nfull = 0, nsing = 0;
+  for (int i = b0; i < b1; ++i) {
+    const int c = start[i];
+    npts += c;
+    nfull += c / G;
+    nsing += c % G;
+  }
+  int total_pts, total_full, total_sing;
+  int pos = block_exclusive_scan(npts, part, &total_pts);
+  int fpos = block_exclusive_scan(nfull, part, &total_full);
+  int spos = total_full + block_exclusive_scan(nsing, part, &total_sing);
+  int* runs = a.runs + ch.start;
+  for (int i = b0; i < b1; ++i) {
+    const int c = start[i];
+    const int f = c / G;
+    for (int o = 0; o < f; ++o) runs[fpos++] = pos + o * G;
+    for (int o = f * G; o < c; ++o) runs[spos++] = pos + o;
+    start[i] = pos;
+    pos += c;
+  }
+  if (threadIdx.x == 0) {
+    a.nruns[2 * blockIdx.x] = total_full;
+    a.nruns[2 * blockIdx.x + 1] = total_sing;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    if (key[k] < 0) continue;
+    const size_t q = size_t(ch.start) + start[key[k]] + rank[k];
+    for (int c = 0; c < d; ++c) a.coords[q * d + c] = co[k][c];
+    a.perm[q] = pm[k];
+    if (a.w0s) a.w0s[q] = v0[k];
+    if (a.w1s) a.w1s[q] = v1[k];
+  }
+}
+
+template <typename R>
+hipError_t launch_chunk_sort(const ChunkSortArgs<R>& a, hipStream_t st) {
+  if (a.nchunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(chunk_sort_kernel<R>, dim3(a.nchunks), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+template hipError_t launch_chunk_sort<float>(const ChunkSortArgs<float>&, hipStream_t);
+template hipError_t launch_chunk_sort<double>(const ChunkSortArgs<double>&, hipStream_t);
+
 // ------------------------------------------------------------------ fills / permutations
 __global__ __launch_bounds__(kBlock) void fill_kernel(uint32_t* p, size_t nwords) {
   const size_t stride = size_t(gridDim.x) * kBlock;
