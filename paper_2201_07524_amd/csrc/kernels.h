@@ -198,31 +198,48 @@ struct ScatterArgs {
 template <typename R>
 hipError_t launch_scatter(const ScatterArgs<R>& a, hipStream_t st);
 
-// Per-chunk cell sort and run table.  Chunks of at most kChunkSortMax points
-// in tiles of at most kChunkSortBins cells are reordered in place by cell;
-// every cell's points form full runs of G = run_length(d) and c mod G single
-// points.  For the chunk starting at `start`, runs[start + r] is the offset
-// (from `start`) of the first point of entry r: nruns[2 chunk] full runs come
-// first, then nruns[2 chunk + 1] single points.  Chunks that are not sorted
-// get single points only.
-constexpr int kChunkSortMax = 1024;
-constexpr int kChunkSortBins = 4096;
+// Cell sort of every tile: one workgroup per (problem, tile) moves the tile's
+// points from the staging arrays (as left by the scatter) to the final arrays
+// in increasing order of their cell inside the tile (T^d <= kSortBins cells).
+constexpr int kSortBins = 4096;
 template <typename R>
-struct ChunkSortArgs {
+struct TileSortArgs {
+  const int* counts;    // B x nbins points per tile
+  const int* offsets;   // B x nbins first position of each tile
+  int ntiles;           // B x nbins
+  int d, T;
+  const R* in_coords;   // staging, n x d
+  const int* in_perm;
+  const double* in_w0;  // nullable
+  const double* in_w1;  // nullable
+  R* coords;
+  int* perm;
+  double* w0s;          // nullable
+  double* w1s;          // nullable
+};
+template <typename R>
+hipError_t launch_tile_sort(const TileSortArgs<R>& a, hipStream_t st);
+
+// Run table of every chunk.  When the points are in cell order (sorted = 1,
+// chunks of at most kChunkRunMax points), each cell's points in the chunk
+// form full runs of G = run_length(d) and c mod G single points; otherwise
+// every point is a single point.  For the chunk starting at `start`,
+// runs[start + r] is the offset (from `start`) of the first point of entry r:
+// nruns[2 chunk] full runs come first, then nruns[2 chunk + 1] single points.
+constexpr int kChunkRunMax = 1024;
+template <typename R>
+struct ChunkRunArgs {
   const Chunk* chunks;
   int nchunks;
   int d, T;
-  int sort;     // 0: one run per point, no reordering
-  int G;        // longest run
-  R* coords;
-  int* perm;
-  double* w0s;  // nullable
-  double* w1s;  // nullable
+  int sorted;
+  int G;
+  const R* coords;
   int* runs;
   int* nruns;
 };
 template <typename R>
-hipError_t launch_chunk_sort(const ChunkSortArgs<R>& a, hipStream_t st);
+hipError_t launch_chunk_runs(const ChunkRunArgs<R>& a, hipStream_t st);
 
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_fill_double(double* p, long n, double v, hipStream_t st);

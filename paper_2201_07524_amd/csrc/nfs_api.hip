@@ -139,6 +139,11 @@ struct Work {
   long ncell = 0;     // g^d
   long H = 0;         // diagonal table entries per problem, (N/2+1)^d
   CloudBuf<R> X, Y;   // X: x / sources, Y: y / targets
+  bool cell_order = false;  // points sorted by cell inside each tile (runs of same-cell points)
+  R* stage_coords = nullptr;  // scatter output before the cell sort (max cloud size)
+  int* stage_perm = nullptr;
+  double* stage_w0 = nullptr;
+  double* stage_w1 = nullptr;
   bool two_level = false;
   R* part = nullptr;
   long ecell = 0;
@@ -227,6 +232,14 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
     tcells *= T;
   }
   w.ecell = ecell;
+  w.cell_order = chunk <= kChunkRunMax && tcells <= kSortBins;
+  if (w.cell_order) {
+    const long ns = std::max(nA, nB);
+    w.stage_coords = cv.take<R>(size_t(ns) * d);
+    w.stage_perm = cv.take<int>(ns);
+    w.stage_w0 = nvec >= 1 ? cv.take<double>(ns) : nullptr;
+    w.stage_w1 = nvec >= 2 ? cv.take<double>(ns) : nullptr;
+  }
   bool two = (p->flags & NFS_FLAG_TILE_REDUCE) && B == 1 && T >= p->m + 1 && (g % T) == 0 && tcells <= 2048;
   for (int c = 0; c < d; ++c) two = two && w.geo.nt[c] >= 3;
   w.two_level = two;
@@ -369,31 +382,45 @@ static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const std:
     sa.keys = cb.keys + o;
     sa.offsets = cb.offsets + size_t(b) * nb;
     sa.cursor = cb.cursor + size_t(b) * nb;
-    sa.coords = cb.coords;
-    sa.perm = cb.perm;
+    // with cell order the scatter fills the staging arrays, which the tile
+    // sort below moves into the final arrays
+    sa.coords = w.cell_order ? w.stage_coords : cb.coords;
+    sa.perm = w.cell_order ? w.stage_perm : cb.perm;
     sa.idx_base = int(o);
     sa.w0 = v0 ? v0 + o : nullptr;
-    sa.w0s = cb.w0s;
+    sa.w0s = w.cell_order ? w.stage_w0 : cb.w0s;
     sa.w1 = v1 ? v1 + o : nullptr;
-    sa.w1s = cb.w1s;
+    sa.w1s = w.cell_order ? w.stage_w1 : cb.w1s;
     NFS_HIP(launch_scatter(sa, st));
   }
-  int cells = 1;
-  for (int c = 0; c < d; ++c) cells *= geo.T;
-  ChunkSortArgs<R> ca{};
+  if (w.cell_order) {
+    TileSortArgs<R> ta{};
+    ta.counts = cb.counts;
+    ta.offsets = cb.offsets;
+    ta.ntiles = B * nb;
+    ta.d = d;
+    ta.T = geo.T;
+    ta.in_coords = w.stage_coords;
+    ta.in_perm = w.stage_perm;
+    ta.in_w0 = v0 ? w.stage_w0 : nullptr;
+    ta.in_w1 = v1 ? w.stage_w1 : nullptr;
+    ta.coords = cb.coords;
+    ta.perm = cb.perm;
+    ta.w0s = v0 ? cb.w0s : nullptr;
+    ta.w1s = v1 ? cb.w1s : nullptr;
+    NFS_HIP(launch_tile_sort(ta, st));
+  }
+  ChunkRunArgs<R> ca{};
   ca.chunks = cb.chunks;
   ca.nchunks = cb.nchunks;
   ca.d = d;
   ca.T = geo.T;
-  ca.sort = w.chunk <= kChunkSortMax && cells <= kChunkSortBins;
+  ca.sorted = w.cell_order;
   ca.G = run_length<R>(d);
   ca.coords = cb.coords;
-  ca.perm = cb.perm;
-  ca.w0s = v0 ? cb.w0s : nullptr;
-  ca.w1s = v1 ? cb.w1s : nullptr;
   ca.runs = cb.runs;
   ca.nruns = cb.nruns;
-  NFS_HIP(launch_chunk_sort(ca, st));
+  NFS_HIP(launch_chunk_runs(ca, st));
   NFS_HIP(hipStreamSynchronize(st));  // host vectors above must outlive the copies
   return NFS_OK;
 }

@@ -152,7 +152,7 @@ hipError_t launch_scatter(const ScatterArgs<R>& a, hipStream_t st) {
 template hipError_t launch_scatter<float>(const ScatterArgs<float>&, hipStream_t);
 template hipError_t launch_scatter<double>(const ScatterArgs<double>&, hipStream_t);
 
-// ------------------------------------------------------------------ per-chunk cell sort
+// ------------------------------------------------------------------ cell order and run tables
 // Exclusive prefix sum over the workgroup; returns this thread's prefix and
 // the total in *total.  `part` holds kBlock ints of LDS.
 __device__ int block_exclusive_scan(int v, int* part, int* total) {
@@ -170,20 +170,80 @@ __device__ int block_exclusive_scan(int v, int* part, int* total) {
   return incl - v;
 }
 
-// One workgroup per chunk.  Sorting mode: an LDS histogram over the T^d cells
-// of the tile gives every point its slot (cell start + arrival rank), the
-// chunk is rewritten in place in cell order, and each cell's points are cut
-// into full runs of G followed by its c mod G remaining points.  The run table
-// lists all full runs of the chunk, then all remaining points.  Same-cell
-// points then share their window taps in spreading and interpolation.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void chunk_sort_kernel(ChunkSortArgs<R> a) {
-  constexpr int PER = kChunkSortMax / kBlock;
-  __shared__ int start[kChunkSortBins];
+__device__ __forceinline__ int cell_key_at(const R* coords, size_t q, int d, int T) {
+  int k = 0;
+  for (int c = 0; c < d; ++c) k = k * T + min(max(int(coords[q * d + c]), 0), T - 1);
+  return k;
+}
+
+// Exclusive scan of hist[0..nc) in place (nc <= kSortBins); each thread owns
+// a contiguous run of bins.  Returns the total.
+__device__ int scan_bins(int* hist, int nc, int* part) {
+  const int per = (nc + kBlock - 1) / kBlock;
+  const int b0 = min(int(threadIdx.x) * per, nc), b1 = min(b0 + per, nc);
+  int s = 0;
+  for (int i = b0; i < b1; ++i) s += hist[i];
+  int total;
+  int run = block_exclusive_scan(s, part, &total);
+  for (int i = b0; i < b1; ++i) {
+    const int c = hist[i];
+    hist[i] = run;
+    run += c;
+  }
+  __syncthreads();
+  return total;
+}
+
+// One workgroup per (problem, tile): LDS histogram of the tile's points over
+// its T^d cells, exclusive scan, then each point goes to its cell's next slot.
+// The order inside a cell is arbitrary.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void tile_sort_kernel(TileSortArgs<R> a) {
+  __shared__ int slot[kSortBins];
+  __shared__ int part[kBlock];
+  const int cnt = a.counts[blockIdx.x];
+  if (cnt == 0) return;
+  const size_t off = size_t(a.offsets[blockIdx.x]);
+  const int d = a.d, T = a.T;
+  int nc = 1;
+  for (int c = 0; c < d; ++c) nc *= T;
+  for (int i = threadIdx.x; i < nc; i += kBlock) slot[i] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < cnt; i += kBlock) atomicAdd(&slot[cell_key_at(a.in_coords, off + i, d, T)], 1);
+  __syncthreads();
+  scan_bins(slot, nc, part);
+  for (int i = threadIdx.x; i < cnt; i += kBlock) {
+    const size_t q = off + i;
+    const size_t pos = off + atomicAdd(&slot[cell_key_at(a.in_coords, q, d, T)], 1);
+    for (int c = 0; c < d; ++c) a.coords[pos * d + c] = a.in_coords[q * d + c];
+    a.perm[pos] = a.in_perm[q];
+    if (a.w0s) a.w0s[pos] = a.in_w0[q];
+    if (a.w1s) a.w1s[pos] = a.in_w1[q];
+  }
+}
+
+template <typename R>
+hipError_t launch_tile_sort(const TileSortArgs<R>& a, hipStream_t st) {
+  if (a.ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tile_sort_kernel<R>, dim3(a.ntiles), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+template hipError_t launch_tile_sort<float>(const TileSortArgs<float>&, hipStream_t);
+template hipError_t launch_tile_sort<double>(const TileSortArgs<double>&, hipStream_t);
+
+// One workgroup per chunk.  With the chunk in cell order, an LDS histogram of
+// its points over the tile's cells and a scan give each cell's first
+// position in the chunk; every cell's c points become c / G full runs and
+// c mod G single points.  The table lists all full runs, then all singles.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void chunk_runs_kernel(ChunkRunArgs<R> a) {
+  __shared__ int start[kSortBins];
   __shared__ int part[kBlock];
   const Chunk ch = a.chunks[blockIdx.x];
-  if (!a.sort) {
-    for (int i = threadIdx.x; i < ch.count; i += kBlock) a.runs[ch.start + i] = i;
+  int* runs = a.runs + ch.start;
+  if (!a.sorted) {
+    for (int i = threadIdx.x; i < ch.count; i += kBlock) runs[i] = i;
     if (threadIdx.x == 0) {
       a.nruns[2 * blockIdx.x] = 0;
       a.nruns[2 * blockIdx.x + 1] = ch.count;
@@ -195,29 +255,10 @@ __global__ __launch_bounds__(kBlock) void chunk_sort_kernel(ChunkSortArgs<R> a) 
   for (int c = 0; c < d; ++c) nc *= T;
   for (int i = threadIdx.x; i < nc; i += kBlock) start[i] = 0;
   __syncthreads();
-  R co[PER][3];
-  int pm[PER], key[PER], rank[PER];
-  double v0[PER], v1[PER];
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int i = threadIdx.x + k * kBlock;
-    key[k] = -1;
-    if (i < ch.count) {
-      const size_t q = size_t(ch.start) + i;
-      int kk = 0;
-      for (int c = 0; c < d; ++c) {
-        co[k][c] = a.coords[q * d + c];
-        kk = kk * T + min(max(int(co[k][c]), 0), T - 1);
-      }
-      pm[k] = a.perm[q];
-      v0[k] = a.w0s ? a.w0s[q] : 0.0;
-      v1[k] = a.w1s ? a.w1s[q] : 0.0;
-      key[k] = kk;
-      rank[k] = atomicAdd(&start[kk], 1);
-    }
-  }
+  for (int i = threadIdx.x; i < ch.count; i += kBlock)
+    atomicAdd(&start[cell_key_at(a.coords, size_t(ch.start) + i, d, T)], 1);
   __syncthreads();
-  // each thread owns the contiguous cells [b0, b1)
+  // per-thread cells [b0, b1): points, full runs and singles, then scans
   const int per = (nc + kBlock - 1) / kBlock;
   const int b0 = min(int(threadIdx.x) * per, nc), b1 = min(b0 + per, nc);
   int npts = 0, nfull = 0, nsing = 0;
@@ -231,39 +272,27 @@ __global__ __launch_bounds__(kBlock) void chunk_sort_kernel(ChunkSortArgs<R> a) 
   int pos = block_exclusive_scan(npts, part, &total_pts);
   int fpos = block_exclusive_scan(nfull, part, &total_full);
   int spos = total_full + block_exclusive_scan(nsing, part, &total_sing);
-  int* runs = a.runs + ch.start;
   for (int i = b0; i < b1; ++i) {
     const int c = start[i];
     const int f = c / G;
     for (int o = 0; o < f; ++o) runs[fpos++] = pos + o * G;
     for (int o = f * G; o < c; ++o) runs[spos++] = pos + o;
-    start[i] = pos;
     pos += c;
   }
   if (threadIdx.x == 0) {
     a.nruns[2 * blockIdx.x] = total_full;
     a.nruns[2 * blockIdx.x + 1] = total_sing;
   }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    if (key[k] < 0) continue;
-    const size_t q = size_t(ch.start) + start[key[k]] + rank[k];
-    for (int c = 0; c < d; ++c) a.coords[q * d + c] = co[k][c];
-    a.perm[q] = pm[k];
-    if (a.w0s) a.w0s[q] = v0[k];
-    if (a.w1s) a.w1s[q] = v1[k];
-  }
 }
 
 template <typename R>
-hipError_t launch_chunk_sort(const ChunkSortArgs<R>& a, hipStream_t st) {
+hipError_t launch_chunk_runs(const ChunkRunArgs<R>& a, hipStream_t st) {
   if (a.nchunks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(chunk_sort_kernel<R>, dim3(a.nchunks), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL(chunk_runs_kernel<R>, dim3(a.nchunks), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
-template hipError_t launch_chunk_sort<float>(const ChunkSortArgs<float>&, hipStream_t);
-template hipError_t launch_chunk_sort<double>(const ChunkSortArgs<double>&, hipStream_t);
+template hipError_t launch_chunk_runs<float>(const ChunkRunArgs<float>&, hipStream_t);
+template hipError_t launch_chunk_runs<double>(const ChunkRunArgs<double>&, hipStream_t);
 
 // ------------------------------------------------------------------ fills / permutations
 __global__ __launch_bounds__(kBlock) void fill_kernel(uint32_t* p, size_t nwords) {
