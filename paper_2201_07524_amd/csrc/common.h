@@ -70,6 +70,18 @@ __device__ __forceinline__ float kb_psi_fast(float z, float m2, float b2, float 
   return t > 0.0f ? r : 0.0f;
 }
 
+// Per-tap polynomial form of the FP32 window.  A point whose first tap lies at
+// distance z0 = t - M (t in [0, 1)) from it has, at tap j, the window value
+//   psi(z0 + j) = sum_k c[j][k] x^k,   x = 2 t - 1,
+// a degree-9 Chebyshev interpolant built on the host (absolute error about
+// 5e-8 for m = 2..8, the FP32 rounding level).  Tap 2M lies outside the
+// support except at t = 0 and is zero.
+constexpr int kMaxM = 8;
+constexpr int kPolyCoef = 10;
+struct WindowPoly {
+  float c[2 * kMaxM + 1][kPolyCoef];
+};
+
 // Longest run of same-cell points that spreading and interpolation handle
 // together (window values of a run stay in registers: G x d x (2m+1)).
 template <typename R>

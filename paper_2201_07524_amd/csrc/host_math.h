@@ -42,6 +42,52 @@ inline WindowConst make_window(int m, int g, int N) {
   return w;
 }
 
+// The window in cell units, FP64 (same normalization as the device forms).
+inline double window_value(double z, const WindowConst& w) {
+  const double t = w.m2 - z * z;
+  if (t <= 0.0) return 0.0;
+  const double a = w.b * std::sqrt(t);
+  if (a < 1e-6) return w.edge;
+  return w.cnorm * (std::exp(a - w.bm) - std::exp(-a - w.bm)) / a;
+}
+
+// Per-tap polynomials of the FP32 window (see WindowPoly): for tap j the
+// function x -> psi(j - m + (x + 1)/2) on [-1, 1] is interpolated at the
+// kPolyCoef Chebyshev points, and the Chebyshev series is converted to
+// monomial coefficients (in double, then rounded to float).
+inline WindowPoly make_window_poly(int m, const WindowConst& w) {
+  WindowPoly P{};
+  const int K = kPolyCoef;
+  for (int j = 0; j < 2 * m; ++j) {
+    double f[kPolyCoef], a[kPolyCoef];
+    for (int i = 0; i < K; ++i) {
+      const double xi = std::cos(kPi * (i + 0.5) / K);
+      f[i] = window_value(double(j - m) + 0.5 * (xi + 1.0), w);
+    }
+    for (int k = 0; k < K; ++k) {  // Chebyshev coefficients
+      double sum = 0.0;
+      for (int i = 0; i < K; ++i) sum += f[i] * std::cos(kPi * k * (i + 0.5) / K);
+      a[k] = (k == 0 ? 1.0 : 2.0) * sum / K;
+    }
+    // monomial coefficients: accumulate a_k T_k(x) with T_{k+1} = 2x T_k - T_{k-1}
+    double mono[kPolyCoef] = {0.0}, tkm1[kPolyCoef] = {0.0}, tk[kPolyCoef] = {0.0}, tkp1[kPolyCoef];
+    tkm1[0] = 1.0;  // T_0
+    tk[1] = 1.0;    // T_1
+    for (int q = 0; q < K; ++q) mono[q] += a[0] * tkm1[q];
+    for (int q = 0; q < K; ++q) mono[q] += a[1] * tk[q];
+    for (int k = 2; k < K; ++k) {
+      for (int q = 0; q < K; ++q) tkp1[q] = (q > 0 ? 2.0 * tk[q - 1] : 0.0) - tkm1[q];
+      for (int q = 0; q < K; ++q) mono[q] += a[k] * tkp1[q];
+      for (int q = 0; q < K; ++q) {
+        tkm1[q] = tk[q];
+        tk[q] = tkp1[q];
+      }
+    }
+    for (int q = 0; q < K; ++q) P.c[j][q] = float(mono[q]);
+  }
+  return P;
+}
+
 // Phi(k) = sum_l psi(l - u) exp(-2 pi i k l / g) exp(2 pi i k u / g) up to aliasing,
 // i.e. the continuous Fourier transform of the cell-unit window psi at frequency k/g:
 //   Phi(k) = pi m I_0(m sqrt(b^2 - (2 pi k / g)^2)) / sinh(b m).

@@ -21,10 +21,12 @@ struct SpreadArgs {
   const Chunk* chunks;
   const int* runs;       // run table of each chunk (offsets from the chunk's start)
   const int* nruns;      // per chunk: full runs, single points
+  int cell_order;        // points sorted by cell inside each tile
   R* grid;               // problem p's g^d real grid at grid + p*grid_stride, zero on entry
   long grid_stride;
   R* part;               // non-null: store each chunk's padded tile here instead of flushing
   WindowConst win;
+  const float* __restrict__ wpoly;  // FP32 window polynomials: WindowPoly::c, row-major
 };
 
 // Sum of the padded chunk tiles into the grid: one workgroup per (tile, neighbour)
@@ -47,9 +49,11 @@ struct InterpArgs {
   const Chunk* chunks;
   const int* runs;          // run table of each chunk (offsets from the chunk's start)
   const int* nruns;         // per chunk: full runs, single points
+  int cell_order;           // points sorted by cell inside each tile
   const R* grid;            // problem p's grid at grid + p*grid_stride
   long grid_stride;
   WindowConst win;
+  const float* __restrict__ wpoly;  // FP32 window polynomials: WindowPoly::c, row-major
   double norm;              // constant factor of the result
   const double* wmul_src;   // the result is divided by wmul_src[prob] (nullable)
   int epi;
@@ -220,13 +224,12 @@ struct TileSortArgs {
 template <typename R>
 hipError_t launch_tile_sort(const TileSortArgs<R>& a, hipStream_t st);
 
-// Run table of every chunk.  When the points are in cell order (sorted = 1,
-// chunks of at most kChunkRunMax points), each cell's points in the chunk
+// Run table of every chunk.  When the points are in cell order (sorted = 1),
+// each cell's points in the chunk
 // form full runs of G = run_length(d) and c mod G single points; otherwise
 // every point is a single point.  For the chunk starting at `start`,
 // runs[start + r] is the offset (from `start`) of the first point of entry r:
 // nruns[2 chunk] full runs come first, then nruns[2 chunk + 1] single points.
-constexpr int kChunkRunMax = 1024;
 template <typename R>
 struct ChunkRunArgs {
   const Chunk* chunks;

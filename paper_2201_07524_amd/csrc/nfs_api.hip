@@ -135,6 +135,7 @@ struct Work {
   int B = 1;
   Geom geo{};
   WindowConst win{};
+  float* wpoly = nullptr;    // WindowPoly coefficients (device)
   int K0 = 0, nbins = 0, chunk = 0;
   long ncell = 0;     // g^d
   long H = 0;         // diagonal table entries per problem, (N/2+1)^d
@@ -232,7 +233,7 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
     tcells *= T;
   }
   w.ecell = ecell;
-  w.cell_order = chunk <= kChunkRunMax && tcells <= kSortBins;
+  w.cell_order = tcells <= kSortBins;
   if (w.cell_order) {
     const long ns = std::max(nA, nB);
     w.stage_coords = cv.take<R>(size_t(ns) * d);
@@ -256,6 +257,7 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
   w.dtab = cv.take<R>(size_t(B) * H);
   w.dtab2 = cv.take<R>(size_t(B) * H);
   w.inv_phi = cv.take<double>(w.K0);
+  w.wpoly = cv.take<float>(sizeof(WindowPoly) / sizeof(float));
   const long maxch = std::max(w.X.max_chunks, w.Y.max_chunks);
   w.partials = cv.take<double>(size_t(std::max<long>(maxch, 1024)) * 9);
   w.ct_interp = cv.take<unsigned>(B);
@@ -438,6 +440,8 @@ static int upload_tables(Work<R>& w, const nfs_params* p, hipStream_t st) {
   std::vector<double> iphi(w.K0);
   for (int k = 0; k < w.K0; ++k) iphi[k] = 1.0 / phi[k];
   NFS_HIP(hipMemcpyAsync(w.inv_phi, iphi.data(), sizeof(double) * w.K0, hipMemcpyHostToDevice, st));
+  const WindowPoly wp = make_window_poly(p->m, w.win);
+  NFS_HIP(hipMemcpyAsync(w.wpoly, &wp, sizeof(WindowPoly), hipMemcpyHostToDevice, st));
   std::vector<R> t1, t2;
   bool any = false;
   for (int b = 0; b < w.B; ++b) any = any || w.sc[b].eps_t > 0.0;
@@ -596,9 +600,11 @@ static SpreadArgs<R> spread_args(Work<R>& w, const CloudBuf<R>& src, const doubl
   a.chunks = src.chunks;
   a.runs = src.runs;
   a.nruns = src.nruns;
+  a.cell_order = w.cell_order;
   a.grid = w.S;
   a.grid_stride = w.ncell;
   a.win = w.win;
+  a.wpoly = w.wpoly;
   return a;
 }
 
@@ -630,9 +636,11 @@ static InterpArgs<R> interp_args(Work<R>& w, const CloudBuf<R>& tgt, int epi, co
   a.chunks = tgt.chunks;
   a.runs = tgt.runs;
   a.nruns = tgt.nruns;
+  a.cell_order = w.cell_order;
   a.grid = w.U;
   a.grid_stride = w.ncell;
   a.win = w.win;
+  a.wpoly = w.wpoly;
   a.norm = 1.0;
   a.wmul_src = wmul_src;
   a.epi = epi;

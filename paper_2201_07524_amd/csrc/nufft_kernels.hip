@@ -17,28 +17,47 @@
 
 namespace nfs {
 
-// Window evaluation with the constants converted once per kernel.
+// Window evaluation.  arg() maps the distance z0 in [-M, -M + 1) from a point
+// to its first tap to the per-point argument, and tap(j, x) is the window
+// at tap j.  FP32 evaluates the per-tap polynomials (Horner, coefficients
+// read from a small workspace table through scalar loads); FP64 evaluates the
+// closed form.
 template <typename R>
-struct WinEval {
-  R m2, b, bm, cn, b2, bm2, cn2, e2bm, edge;
-  __device__ __forceinline__ explicit WinEval(const WindowConst& wc)
-      : m2(R(wc.m2)), b(R(wc.b)), bm(R(wc.bm)), cn(R(wc.cnorm)), b2(R(wc.b2)), bm2(R(wc.bm2)), cn2(R(wc.cn2)),
-        e2bm(R(wc.e2bm)), edge(R(wc.edge)) {}
-  __device__ __forceinline__ R operator()(R z) const {
-    if constexpr (sizeof(R) == 4) return kb_psi_fast(z, m2, b2, bm2, cn2, e2bm, edge);
-    else return kb_psi(z, m2, b, bm, cn);
+struct WinEval;
+
+template <>
+struct WinEval<float> {
+  const float* __restrict__ P;  // (2 kMaxM + 1) x kPolyCoef, uniform across the wave
+  float shift;                  // 2M - 1
+  __device__ __forceinline__ WinEval(const WindowConst&, const float* p, int M) : P(p), shift(float(2 * M - 1)) {}
+  __device__ __forceinline__ float arg(float z0) const { return fmaf(2.0f, z0, shift); }
+  __device__ __forceinline__ float tap(int j, float x) const {
+    const float* c = P + j * kPolyCoef;
+    float v = c[kPolyCoef - 1];
+#pragma unroll
+    for (int k = kPolyCoef - 2; k >= 0; --k) v = fmaf(v, x, c[k]);
+    return v;
   }
 };
 
-// Window taps of one point: the first tap offset per axis (off), the distance
-// of the first tap (z0), and the 2m+1 window values of every axis c >= FROM
+template <>
+struct WinEval<double> {
+  double m2, b, bm, cn;
+  __device__ __forceinline__ WinEval(const WindowConst& wc, const float*, int)
+      : m2(wc.m2), b(wc.b), bm(wc.bm), cn(wc.cnorm) {}
+  __device__ __forceinline__ double arg(double z0) const { return z0; }
+  __device__ __forceinline__ double tap(int j, double z0) const { return kb_psi(z0 + double(j), m2, b, bm, cn); }
+};
+
+// Window taps of one point: the first tap offset per axis (off), the window
+// argument per axis (x), and the 2m+1 window values of every axis c >= FROM
 // (axes below FROM are evaluated on the fly by the caller, one value per row,
 // so that loops over them can stay rolled with static register indices).
 template <typename R, int D, int M, int FROM>
 struct Taps {
   static constexpr int W = 2 * M + 1;
   R psi[D][W];
-  R z0[D];
+  R x[D];
   int off[D];
 
   __device__ __forceinline__ void compute(const R* u, const WinEval<R>& ev) {
@@ -46,14 +65,35 @@ struct Taps {
     for (int c = 0; c < D; ++c) {
       const R s = ceil(u[c] - R(M));
       off[c] = int(s) + M;
-      z0[c] = s - u[c];
+      x[c] = ev.arg(s - u[c]);
       if (c >= FROM) {
 #pragma unroll
-        for (int j = 0; j < W; ++j) psi[c][j] = ev(z0[c] + R(j));
+        for (int j = 0; j < W; ++j) psi[c][j] = ev.tap(j, x[c]);
       }
     }
   }
 };
+
+// Range [lo, hi) of LDS tile cells (linear, axis 0 slowest) that a chunk's
+// taps can touch.  In cell order the first axis is the most significant part
+// of the sort key, so the chunk's first and last points bound its axis-0
+// cells c0; a point in cell c0 has taps on E-rows c0 .. c0 + 2M + 1.
+template <typename R, int D, int M>
+__device__ __forceinline__ void chunk_rows(const R* coords, const Chunk& ch, const Geom& geo, bool cell_order,
+                                           int& lo, int& hi) {
+  const int E = geo.E;
+  const int inner = D == 1 ? 1 : (D == 2 ? E : E * E);
+  if (!cell_order) {
+    lo = 0;
+    hi = E * inner;
+    return;
+  }
+  const int T = geo.T;
+  const int c_first = min(max(int(coords[size_t(ch.start) * D]), 0), T - 1);
+  const int c_last = min(max(int(coords[size_t(ch.start + ch.count - 1) * D]), 0), T - 1);
+  lo = c_first * inner;
+  hi = min(c_last + 2 * M + 2, E) * inner;
+}
 
 // a[0..W) <- a[1], ..., a[W-1], a[0] (register moves)
 template <typename R, int W>
@@ -173,7 +213,7 @@ __device__ __forceinline__ void spread_run(Acc<R, ACC>& tile, const SpreadArgs<R
     for (int j0 = 0; j0 < W; ++j0) {
       R a0[GC];
 #pragma unroll
-      for (int p = 0; p < GC; ++p) a0[p] = w[p] * ev(tp[p].z0[0] + R(j0));
+      for (int p = 0; p < GC; ++p) a0[p] = w[p] * ev.tap(j0, tp[p].x[0]);
       const int row = (tp[0].off[0] + j0) * E + tp[0].off[1];
 #pragma unroll
       for (int j1 = 0; j1 < W; ++j1) {
@@ -190,7 +230,7 @@ __device__ __forceinline__ void spread_run(Acc<R, ACC>& tile, const SpreadArgs<R
     for (int j0 = 0; j0 < W; ++j0) {
       R b0[GC];
 #pragma unroll
-      for (int p = 0; p < GC; ++p) b0[p] = w[p] * ev(tp[p].z0[0] + R(j0));
+      for (int p = 0; p < GC; ++p) b0[p] = w[p] * ev.tap(j0, tp[p].x[0]);
 #pragma unroll 1
       for (int j1 = 0; j1 < W; ++j1) {
         R a1[GC];
@@ -220,13 +260,16 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs<R> a) {
   Acc<R, ACC> tile(smem_raw, ncell);
   const Chunk ch = a.chunks[blockIdx.x];
 
-  for (int i = threadIdx.x; i < ncell; i += kBlock) tile.zero(i);
+  // the part store (per-tile reduction) needs the whole tile
+  int lo, hi;
+  chunk_rows<R, D, M>(a.coords, ch, geo, a.cell_order && !a.part, lo, hi);
+  for (int i = lo + threadIdx.x; i < hi; i += kBlock) tile.zero(i);
   __syncthreads();
 
   // The chunk's run table lists full runs of G same-cell points, then the
   // remaining points one by one; each phase is free of lane divergence.
   constexpr int G = run_length<R>(D);
-  const WinEval<R> ev(a.win);
+  const WinEval<R> ev(a.win, a.wpoly, M);
   const double wm = a.wconst * (a.wmul ? a.wmul[ch.prob] : 1.0);
   const int* runs = a.runs + ch.start;
   const int nfull = a.nruns[2 * blockIdx.x], nsingle = a.nruns[2 * blockIdx.x + 1];
@@ -258,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs<R> a) {
     }
   }
   const int g = geo.g;
-  for (int i = threadIdx.x; i < ncell; i += kBlock) {
+  for (int i = lo + threadIdx.x; i < hi; i += kBlock) {
     const R v = tile.get(i);
     if (v == R(0)) continue;
     size_t lin;
@@ -631,7 +674,7 @@ __device__ __forceinline__ void interp_run(const R* tile, const InterpArgs<R>& a
         R racc = R(0);
 #pragma unroll
         for (int j1 = 0; j1 < W; ++j1) racc += gv[j1] * tp[p].psi[1][j1];
-        acc[p] += racc * ev(tp[p].z0[0] + R(j0));
+        acc[p] += racc * ev.tap(j0, tp[p].x[0]);
       }
     }
   } else {
@@ -675,7 +718,7 @@ __device__ __forceinline__ void interp_run(const R* tile, const InterpArgs<R>& a
         }
       }
 #pragma unroll
-      for (int p = 0; p < GC; ++p) acc[p] += pacc[p] * ev(tp[p].z0[0] + R(j0));
+      for (int p = 0; p < GC; ++p) acc[p] += pacc[p] * ev.tap(j0, tp[p].x[0]);
     }
   }
 }
@@ -699,7 +742,9 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
       t /= geo.nt[c];
     }
   }
-  for (int i = threadIdx.x; i < ncell; i += kBlock) {
+  int lo, hi;
+  chunk_rows<R, D, M>(a.coords, ch, geo, a.cell_order, lo, hi);
+  for (int i = lo + threadIdx.x; i < hi; i += kBlock) {
     size_t lin;
     if constexpr (D == 1) {
       lin = wrap(org[0] + i, g);
@@ -749,7 +794,7 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
   // one (each phase free of lane divergence).  Consecutive lanes take
   // consecutive runs: global accesses stay coalesced, and lanes in the same
   // cell read the same LDS words (a broadcast).
-  const WinEval<R> ev(a.win);
+  const WinEval<R> ev(a.win, a.wpoly, M);
   constexpr int G = run_length<R>(D);
   constexpr int GI = kInterpRun < G ? kInterpRun : G;  // points per interpolation run, divides G
   constexpr int SUB = G / GI;
