@@ -29,7 +29,7 @@ __host__ __device__ inline int ilog2(int v) {
 // result.  Forward uses exp(-2 pi i jk/L), inverse exp(+2 pi i jk/L), both
 // unnormalized.  Must be called by all threads of the block.
 template <typename R>
-__device__ cplx<R>* stockham(cplx<R>* A, cplx<R>* B, int L, int P, const cplx<R>* __restrict__ tw,
+__device__ cplx<R>* stockham(cplx<R>* A, cplx<R>* B, int L, int P, const cplx<R>* tw,
                              bool inverse) {
   const int log2L = ilog2(L);
   cplx<R>* src = A;
@@ -133,6 +133,13 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(RowArgs<R> a) {
   const int P = rows_pencils<R>(L);
   cplx<R>* A = reinterpret_cast<cplx<R>*>(smem_raw);
   cplx<R>* B = A + P * L;
+  // twiddles staged in LDS (read by every pass) when they fit
+  const cplx<R>* tw = a.tw;
+  if (a.tw_lds) {
+    cplx<R>* t = B + P * L;
+    for (int i = threadIdx.x; i < L; i += kBlock) t[i] = a.tw[i];
+    tw = t;
+  }
   const int K0 = a.N / 2 + 1;
   const long row0 = long(blockIdx.x) * 2 * P;
   const int lshift = ilog2(L);
@@ -153,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(RowArgs<R> a) {
       else e->x = v;
     }
     __syncthreads();
-    cplx<R>* res = stockham(A, B, L, P, a.tw, false);
+    cplx<R>* res = stockham(A, B, L, P, tw, false);
     if (a.mode == ROW_R2C) {
       for (int i = threadIdx.x; i < P * K0; i += kBlock) {
         const int p = i / K0;
@@ -196,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(RowArgs<R> a) {
       other[i] = v;
     }
     __syncthreads();
-    cplx<R>* out = stockham(other, res, L, P, a.tw, true);
+    cplx<R>* out = stockham(other, res, L, P, tw, true);
     for (int i = threadIdx.x; i < 2 * P * L; i += kBlock) {
       const int r = i >> lshift;
       const int c = i & (L - 1);
@@ -235,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(RowArgs<R> a) {
     A[i] = Z;
   }
   __syncthreads();
-  cplx<R>* out = stockham(A, B, L, P, a.tw, true);
+  cplx<R>* out = stockham(A, B, L, P, tw, true);
   for (int i = threadIdx.x; i < 2 * P * L; i += kBlock) {
     const int r = i >> lshift;
     const int c = i & (L - 1);
@@ -249,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(RowArgs<R> a) {
 
 template <typename R>
 __host__ __device__ inline int axis_pencils(int L) {
-  return L >= 2048 ? 1 : 2048 / L;
+  return L >= 1024 ? 1 : 1024 / L;
 }
 
 template <typename R>
@@ -259,6 +266,13 @@ __global__ __launch_bounds__(kBlock) void axis_kernel(AxisArgs<R> a) {
   const int P = axis_pencils<R>(L);
   cplx<R>* A = reinterpret_cast<cplx<R>*>(smem_raw);
   cplx<R>* B = A + P * L;
+  // twiddles staged in LDS (read by every pass) when they fit
+  const cplx<R>* tw = a.tw;
+  if (a.tw_lds) {
+    cplx<R>* t = B + P * L;
+    for (int i = threadIdx.x; i < L; i += kBlock) t[i] = a.tw[i];
+    tw = t;
+  }
   const long q0 = long(blockIdx.x) * P;
   const int half = a.N / 2;
 
@@ -295,9 +309,9 @@ __global__ __launch_bounds__(kBlock) void axis_kernel(AxisArgs<R> a) {
 
   cplx<R>* res;
   if (a.mode == AX_INV) {
-    res = stockham(A, B, L, P, a.tw, true);
+    res = stockham(A, B, L, P, tw, true);
   } else {
-    res = stockham(A, B, L, P, a.tw, false);
+    res = stockham(A, B, L, P, tw, false);
     if (a.mode == AX_FUSED) {
       for (int i = threadIdx.x; i < P * L; i += kBlock) {
         const int p = i / L;
@@ -321,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void axis_kernel(AxisArgs<R> a) {
       }
       __syncthreads();
       cplx<R>* other = res == A ? B : A;
-      res = stockham(res, other, L, P, a.tw, true);
+      res = stockham(res, other, L, P, tw, true);
     }
   }
 
@@ -341,20 +355,32 @@ __global__ __launch_bounds__(kBlock) void axis_kernel(AxisArgs<R> a) {
   }
 }
 
+// LDS bytes of a pass with P pencils of length L: two ping-pong buffers, plus
+// the twiddle table when that still fits in 160 KiB.
 template <typename R>
-hipError_t launch_rows(const RowArgs<R>& a, hipStream_t st) {
+static size_t fft_lds(int P, int L, int* tw_lds) {
+  const size_t buf = size_t(2) * P * L * sizeof(cplx<R>);
+  const size_t twb = size_t(L) * sizeof(cplx<R>);
+  *tw_lds = buf + twb <= size_t(160) * 1024;
+  return buf + (*tw_lds ? twb : 0);
+}
+
+template <typename R>
+hipError_t launch_rows(const RowArgs<R>& a_in, hipStream_t st) {
+  RowArgs<R> a = a_in;
   const int P = rows_pencils<R>(a.L);
   const long nblk = (a.nrows + 2 * P - 1) / (2 * P);
-  const size_t shm = size_t(2) * P * a.L * sizeof(cplx<R>);
+  const size_t shm = fft_lds<R>(P, a.L, &a.tw_lds);
   hipLaunchKernelGGL(rows_kernel<R>, dim3(nblk), dim3(kBlock), shm, st, a);
   return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_axis(const AxisArgs<R>& a, hipStream_t st) {
+hipError_t launch_axis(const AxisArgs<R>& a_in, hipStream_t st) {
+  AxisArgs<R> a = a_in;
   const int P = axis_pencils<R>(a.L);
   const long nblk = (a.npen + P - 1) / P;
-  const size_t shm = size_t(2) * P * a.L * sizeof(cplx<R>);
+  const size_t shm = fft_lds<R>(P, a.L, &a.tw_lds);
   hipLaunchKernelGGL(axis_kernel<R>, dim3(nblk), dim3(kBlock), shm, st, a);
   return hipGetLastError();
 }

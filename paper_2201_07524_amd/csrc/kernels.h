@@ -130,6 +130,7 @@ struct RowArgs {
   cplx<R>* spec;    // R2C: output [nrows][K0]; C2R: input [nrows][K0]
   int zero_src;
   const cplx<R>* tw;
+  int tw_lds;       // set by the launcher: twiddles staged in LDS
   Multiplier mul;   // FUSED1D only
 };
 
@@ -146,6 +147,7 @@ struct AxisArgs {
   int inner;                      // pencils per outer group (contiguous)
   long npen;                      // total pencils
   const cplx<R>* tw;
+  int tw_lds;          // set by the launcher: twiddles staged in LDS
   Multiplier mul;                 // FUSED: applied between forward and inverse; INV: applied on load
   int apply_mul;
 };
