@@ -22,6 +22,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# Sources whose change invalidates the measured HBM traffic of the hot kernels.
+TRAFFIC_SOURCES = ("paper_2201_07524_amd/csrc/nufft_kernels.hip", "paper_2201_07524_amd/csrc/plan_kernels.hip",
+                   "paper_2201_07524_amd/csrc/common.h", "paper_2201_07524_amd/csrc/kernels.h")
+CALIB_COPY_BYTES = 256 << 20
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -39,6 +44,38 @@ def kernel_bytes(info, d, which):
     if which == "fft":
         return 4 * G * gb
     return G * gb + n_s * (cb + 24)
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/traffic_<kernel>_gmm2d_1e6_fp32.md: FETCH_SIZE + WRITE_SIZE,
+    each scaled by the same counter's reading for a plain copy of known size),
+    or None when that summary is missing or the kernel sources changed since
+    the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_gmm2d_1e6_fp32.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].strip().split(": ", 1)
+                vals[k.strip("`")] = v.strip().strip("`")
+    if vals.get("source_sha256") != source_digest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(cfg, budget_rows=8192):
@@ -148,6 +185,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-legs", action="store_true", help="skip the batched and gradient legs")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="end with one device copy of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every box here has a single MI355X; "
@@ -225,7 +264,8 @@ def main():
         "stage_gbs": achieved,
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved[names[dom]],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved[names[dom]] / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved[names[dom]] / HBM_PEAK_GBS, "traffic": measured_traffic(names[dom]),
+                     "algorithmic_bytes": kernel_bytes(info, d, names[dom])},
     }
     solver.close()
     del solver
@@ -240,6 +280,13 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(cfg)
+    if args.calib_copy:
+        src = torch.full((CALIB_COPY_BYTES // 4,), 1.0, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: calibration copy of {CALIB_COPY_BYTES} bytes")
     print(json.dumps(out), flush=True)
 
 
