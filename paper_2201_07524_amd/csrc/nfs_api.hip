@@ -69,7 +69,7 @@ static int check_params(const nfs_params* p, int64_t n, int64_t nt) {
   const int g = grid_size(p);
   if (g > 4096) return fail(NFS_EUNSUPPORTED, "grid size sigma*N above 4096 per dimension");
   if (p->tile < 0 || p->tile > 256) return fail(NFS_EINVAL, "tile must be in [0, 256]");
-  if (p->chunk < 0 || p->chunk > (1 << 20)) return fail(NFS_EINVAL, "chunk must be in [0, 2^20]");
+  if (p->chunk < 0 || p->chunk > 32768) return fail(NFS_EINVAL, "chunk must be in [0, 32768]");
   if (n < 1 || nt < 1) return fail(NFS_EINVAL, "point counts must be >= 1");
   if (n > (int64_t(1) << 30) || nt > (int64_t(1) << 30)) return fail(NFS_EUNSUPPORTED, "point counts above 2^30");
   const double gd = std::pow(double(g), p->d);

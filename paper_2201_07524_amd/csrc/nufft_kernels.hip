@@ -120,15 +120,31 @@ __device__ __forceinline__ int wrap(int v, int g) {
 // --------------------------------------------------------------------------- spread
 // LDS accumulation modes.  Float atomics in LDS (ds_add_f32/f64) are slow on
 // gfx950 (about one lane per three clocks per CU) while 64-bit integer LDS
-// atomics run an order of magnitude faster, so contributions v (|v| <= 1 after
+// atomics run an order of magnitude faster, so contributions v (|v| <= G after
 // the weights are normalized by their maximum) are accumulated in fixed point:
 //   FIX64  (FP32 path): q = round(v 2^32) in one int64 word;
 //   FIX128 (FP64 path): hi = round(v 2^30), lo = round((v 2^30 - hi) 2^30) in
 //                       two int64 words (resolution 2^-60 of the largest weight).
-// Integer sums are exact and order independent, so the spread grid is
-// deterministic.  ACC_FLOAT keeps native float atomics for tiles too large for
-// the fixed-point LDS footprint.
+// The integer is formed in two FP64 instructions: with M = 1.5 2^52,
+// fma(v, 2^s, M) rounds v 2^s to an integer q (|q| < 2^51) and its bit pattern
+// is bits(M) + q.  The atomics add these patterns directly.  bits(M) has 48
+// zero low bits, so the low 48 bits of a word hold the exact sum of its q's
+// whatever the number of adds, as long as |sum q| < 2^47; that bounds the sum
+// of |v| landing on one cell of one chunk by 2^15 (FIX64) and 2^17 (FIX128),
+// which chunks of at most 32768 points respect.  Integer sums are exact and
+// order independent, so the spread grid is deterministic.  ACC_FLOAT keeps
+// native float atomics for tiles too large for the fixed-point LDS footprint.
 enum AccMode : int { ACC_FLOAT = 0, ACC_FIX64 = 1, ACC_FIX128 = 2 };
+
+constexpr double kFixMagic = 6755399441055744.0;  // 1.5 * 2^52
+
+__device__ __forceinline__ unsigned long long fix_bits(double y) {
+  return (unsigned long long)__double_as_longlong(y);
+}
+// exact sum of the q's held in a word (low 48 bits, sign-extended)
+__device__ __forceinline__ long long fix_sum(long long a) {
+  return (long long)((unsigned long long)a << 16) >> 16;
+}
 
 template <typename R, int ACC>
 struct Acc;
@@ -149,13 +165,10 @@ struct Acc<float, ACC_FIX64> {
   __device__ Acc(unsigned char* raw, int) : t(reinterpret_cast<long long*>(raw)) {}
   __device__ __forceinline__ void zero(int i) { t[i] = 0; }
   __device__ __forceinline__ void add(int i, float v) {
-    const float x = v * 65536.0f;                      // exact scaling
-    const float hi = rintf(x);
-    const int lo = __float2int_rn((x - hi) * 65536.0f);  // x - hi is exact, |.| <= 1/2
-    const long long q = (long long)(int)hi * 65536LL + lo;
-    atomicAdd(reinterpret_cast<unsigned long long*>(&t[i]), (unsigned long long)q);
+    const double y = fma(double(v), 4294967296.0, kFixMagic);  // M + round(v 2^32)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&t[i]), fix_bits(y));
   }
-  __device__ __forceinline__ float get(int i) const { return float(double(t[i]) * 2.3283064365386963e-10); }
+  __device__ __forceinline__ float get(int i) const { return float(double(fix_sum(t[i])) * 2.3283064365386963e-10); }
 };
 
 template <>
@@ -169,14 +182,15 @@ struct Acc<double, ACC_FIX128> {
     lo_[i] = 0;
   }
   __device__ __forceinline__ void add(int i, double v) {
-    const double x = v * 1073741824.0;  // 2^30, exact
-    const double h = rint(x);
-    const double l = rint((x - h) * 1073741824.0);
-    atomicAdd(reinterpret_cast<unsigned long long*>(&hi_[i]), (unsigned long long)(long long)h);
-    atomicAdd(reinterpret_cast<unsigned long long*>(&lo_[i]), (unsigned long long)(long long)l);
+    const double yh = fma(v, 1073741824.0, kFixMagic);  // M + round(v 2^30)
+    const double h = yh - kFixMagic;                      // exact
+    const double r = fma(v, 1073741824.0, -h);            // exact, |r| <= 1/2
+    const double yl = fma(r, 1073741824.0, kFixMagic);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&hi_[i]), fix_bits(yh));
+    atomicAdd(reinterpret_cast<unsigned long long*>(&lo_[i]), fix_bits(yl));
   }
   __device__ __forceinline__ double get(int i) const {
-    return double(hi_[i]) * 9.313225746154785e-10 + double(lo_[i]) * 8.673617379884035e-19;
+    return double(fix_sum(hi_[i])) * 9.313225746154785e-10 + double(fix_sum(lo_[i])) * 8.673617379884035e-19;
   }
 };
 

@@ -45,6 +45,8 @@ def _p(**kw):
     (dict(sigma=0.5), nfs.NFS_EINVAL),
     (dict(N=4096), nfs.NFS_EUNSUPPORTED),
     (dict(d=3, tile=64), nfs.NFS_EINVAL),
+    (dict(chunk=32769), nfs.NFS_EINVAL),   # fixed-point LDS sums stay exact up to 2^15 points per chunk
+    (dict(chunk=-1), nfs.NFS_EINVAL),
 ])
 def test_validate_rejects(kw, code):
     assert nfs.validate(_p(**kw), 100, 100) == code
