@@ -105,7 +105,9 @@ def batched_leg(nfs, workloads, torch, T, iters=10, sample_every=16):
     in [1e3, 2e5], eps uniform in [0.005, 0.05], N = 256, m = 6, FP32), all
     advanced by one captured iteration; compared with plain single-problem
     solvers run one after another (every `sample_every`-th problem, scaled to
-    the whole batch)."""
+    the whole batch).  Then one complete solve of `iters` iterations with
+    automatic FP64 promotion of the problems FP32 grids cannot resolve (wall
+    time including plan, FP32 batch and the FP64 re-solves)."""
     import numpy as np
     cfg = workloads.batched_2d()
     probs = cfg["problems"]
@@ -140,11 +142,22 @@ def batched_leg(nfs, workloads, torch, T, iters=10, sample_every=16):
         one.close()
     t_plain *= len(probs) / len(sample)
     npts = sum(p["x"].shape[0] + p["y"].shape[0] for p in probs)
+    # one-shot solve with automatic promotion of the problems whose FP32 sums
+    # hit t <= 0 (each re-solved alone with FP64 grids)
+    aprm = nfs.Params(d=2, eps=1.0, N=cfg["N"], m=cfg["m"], precision="auto")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ares = nfs.batch_sinkhorn(aprm, xs, ps, ys, pts, eps, iters, check=False)
+    torch.cuda.synchronize()
+    t_auto = time.perf_counter() - t0
     return {"problems": len(probs), "points": npts, "ms_per_iteration": t_batch * 1e3,
             "problem_iterations_per_s": len(probs) / t_batch,
             "plain_sequential_ms_per_iteration_est": t_plain * 1e3,
             "speedup_vs_plain": t_plain / t_batch,
-            "problems_with_nonpositive_sums_fp32": nonpos}
+            "problems_with_nonpositive_sums_fp32": nonpos,
+            "auto_solve_ms": t_auto * 1e3, "auto_iterations": iters,
+            "auto_promoted_to_fp64": sum(1 for r in ares if r.precision_used == "fp64"),
+            "auto_nonpositive_after_promotion": sum(1 for r in ares if r.n_nonpos > 0)}
 
 
 def grad_leg(nfs, workloads, torch, T, iters=5):

@@ -51,9 +51,16 @@ extern "C" {
 #define NFS_EHIP 5          /* HIP runtime error */
 #define NFS_EWORKSPACE 6    /* workspace smaller than nfs_workspace_size() */
 
-/* Grid / FFT / window precision.  Scalings and reductions are always FP64. */
+/* Grid / FFT / window precision.  Scalings and reductions are always FP64.
+ * NFS_AUTO is accepted by the solve calls only (nfs_sinkhorn_solve,
+ * nfs_batch_solve, and the workspace sizes for them): the problem is solved
+ * with FP32 grids, and every problem whose solve met a kernel sum t <= 0 or a
+ * non-finite one (the FP32 dynamic-range floor of fast summation) is solved
+ * again from its starting value with FP64 grids.  nfs_result.precision_used
+ * reports the grid precision of the returned result. */
 #define NFS_FP64 0
 #define NFS_FP32 1
+#define NFS_AUTO 2
 
 /* flags */
 #define NFS_FLAG_NO_GRAPH 1      /* launch the iteration kernels directly, no hipGraph replay */
@@ -70,7 +77,7 @@ typedef struct nfs_params {
   int32_t N;          /* bandwidth per dimension: I_N = {-N/2..N/2-1}^d, even, >= 4 */
   int32_t m;          /* window cutoff: 2m+1 grid taps per dimension, 2 <= m <= 8 */
   double sigma;       /* oversampling: grid g = sigma*N rounded up to even, g >= N + 2 */
-  int32_t precision;  /* NFS_FP64 or NFS_FP32 */
+  int32_t precision;  /* NFS_FP64, NFS_FP32, or NFS_AUTO (solve calls only) */
   int32_t tile;       /* grid cells per bin side (0 = default for d) */
   int32_t chunk;      /* max points per workgroup chunk, 0..32768 (0 = default 1024) */
   int32_t flags;      /* NFS_FLAG_* */

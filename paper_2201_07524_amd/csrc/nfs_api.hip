@@ -65,7 +65,8 @@ static int check_params(const nfs_params* p, int64_t n, int64_t nt) {
   if (p->N < 4 || (p->N & 1)) return fail(NFS_EINVAL, "N must be even and >= 4");
   if (p->m < 2 || p->m > 8) return fail(NFS_EINVAL, "m must be in [2, 8]");
   if (!(p->sigma >= 1.0) || p->sigma > 16.0) return fail(NFS_EINVAL, "sigma must be in [1, 16]");
-  if (p->precision != NFS_FP64 && p->precision != NFS_FP32) return fail(NFS_EINVAL, "precision must be NFS_FP64 or NFS_FP32");
+  if (p->precision != NFS_FP64 && p->precision != NFS_FP32)
+    return fail(NFS_EINVAL, "precision must be NFS_FP64 or NFS_FP32 (NFS_AUTO: solve calls only)");
   const int g = grid_size(p);
   if (g > 4096) return fail(NFS_EUNSUPPORTED, "grid size sigma*N above 4096 per dimension");
   if (p->tile < 0 || p->tile > 256) return fail(NFS_EINVAL, "tile must be in [0, 256]");
@@ -1272,6 +1273,47 @@ static int batch_workspace(const nfs_params* prm, int32_t B, long sn, long snt, 
   return NFS_OK;
 }
 
+// ----------------------------------------------------------------------------- NFS_AUTO
+static nfs_params with_precision(const nfs_params* p, int precision) {
+  nfs_params q = *p;
+  q.precision = precision;
+  return q;
+}
+
+static size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Single problem: [0, S) solver workspace (S = the larger of the FP32 and FP64
+// needs), then nt doubles keeping the caller's starting alpha_t.
+static int auto_workspace(const nfs_params* p, int64_t n, int64_t nt, size_t* S, size_t* total) {
+  const nfs_params p32 = with_precision(p, NFS_FP32), p64 = with_precision(p, NFS_FP64);
+  NFS_TRY(check_params(&p32, n, nt));
+  NFS_TRY(check_params(&p64, n, nt));
+  size_t b32 = 0, b64 = 0;
+  NFS_TRY(batch_workspace(&p32, 1, n, nt, &b32));
+  NFS_TRY(batch_workspace(&p64, 1, n, nt, &b64));
+  *S = align_up(std::max(b32, b64));
+  *total = *S + sizeof(double) * size_t(nt);
+  return NFS_OK;
+}
+
+// Batch: the FP32 batch, or the FP64 single-problem solve of the largest
+// problem, whichever needs more.
+static int auto_batch_workspace(const nfs_params* p, int32_t B, const int64_t* n, const int64_t* nt, size_t* bytes) {
+  const nfs_params p32 = with_precision(p, NFS_FP32), p64 = with_precision(p, NFS_FP64);
+  long sn = 0, snt = 0;
+  NFS_TRY(batch_sizes(&p32, B, n, nt, &sn, &snt));
+  NFS_TRY(batch_sizes(&p64, B, n, nt, &sn, &snt));
+  size_t need = 0;
+  NFS_TRY(batch_workspace(&p32, B, sn, snt, &need));
+  for (int b = 0; b < B; ++b) {
+    size_t one = 0;
+    NFS_TRY(batch_workspace(&p64, 1, n[b], nt[b], &one));
+    need = std::max(need, one);
+  }
+  *bytes = need;
+  return NFS_OK;
+}
+
 }  // namespace nfs
 
 // ============================================================================= C ABI
@@ -1288,8 +1330,12 @@ int nfs_validate(const nfs_params* prm, int64_t n, int64_t nt) {
 
 int nfs_workspace_size(const nfs_params* prm, int64_t n, int64_t nt, size_t* bytes) {
   g_err.clear();
-  NFS_TRY(check_params(prm, n, nt));
   if (!bytes) return fail(NFS_EINVAL, "bytes is NULL");
+  if (prm && prm->precision == NFS_AUTO) {
+    size_t S = 0;
+    return auto_workspace(prm, n, nt, &S, bytes);
+  }
+  NFS_TRY(check_params(prm, n, nt));
   return batch_workspace(prm, 1, n, nt, bytes);
 }
 
@@ -1329,6 +1375,26 @@ int nfs_sinkhorn_solve(const nfs_params* prm, const double* x, int64_t n, const 
                        int64_t nt, const double* nu, int32_t max_iter, double tol, int32_t warm_start, double* alpha,
                        double* alpha_t, nfs_result* res, void* workspace, size_t ws_bytes, void* stream) {
   g_err.clear();
+  if (prm && prm->precision == NFS_AUTO) {
+    size_t S = 0, total = 0;
+    NFS_TRY(auto_workspace(prm, n, nt, &S, &total));
+    if (!x || !mu || !y || !nu || !alpha || !alpha_t || !workspace) return fail(NFS_EINVAL, "NULL pointer argument");
+    if (ws_bytes < total) return fail(NFS_EWORKSPACE, "workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double* start = reinterpret_cast<double*>(static_cast<char*>(workspace) + S);
+    if (warm_start) NFS_HIP(hipMemcpyAsync(start, alpha_t, sizeof(double) * nt, hipMemcpyDeviceToDevice, st));
+    const nfs_params p32 = with_precision(prm, NFS_FP32), p64 = with_precision(prm, NFS_FP64);
+    nfs_result r{};
+    int rc = nfs_sinkhorn_solve(&p32, x, n, mu, y, nt, nu, max_iter, tol, warm_start, alpha, alpha_t, &r, workspace,
+                                S, stream);
+    if (rc == NFS_ENONPOS) {  // again from the caller's starting value, with FP64 grids
+      if (warm_start) NFS_HIP(hipMemcpyAsync(alpha_t, start, sizeof(double) * nt, hipMemcpyDeviceToDevice, st));
+      rc = nfs_sinkhorn_solve(&p64, x, n, mu, y, nt, nu, max_iter, tol, warm_start, alpha, alpha_t, &r, workspace,
+                              S, stream);
+    }
+    if (res) *res = r;
+    return rc;
+  }
   NFS_TRY(check_params(prm, n, nt));
   if (!x || !mu || !y || !nu || !alpha || !alpha_t || !workspace) return fail(NFS_EINVAL, "NULL pointer argument");
   if (max_iter < 0) return fail(NFS_EINVAL, "max_iter must be >= 0");
@@ -1392,6 +1458,7 @@ int nfs_batch_workspace_size(const nfs_params* prm, int32_t nprob, const int64_t
                              size_t* bytes) {
   g_err.clear();
   if (!bytes) return fail(NFS_EINVAL, "bytes is NULL");
+  if (prm && prm->precision == NFS_AUTO) return auto_batch_workspace(prm, nprob, n, nt, bytes);
   long sn = 0, snt = 0;
   NFS_TRY(batch_sizes(prm, nprob, n, nt, &sn, &snt));
   return batch_workspace(prm, nprob, sn, snt, bytes);
@@ -1423,6 +1490,37 @@ int nfs_batch_solve(const nfs_params* prm, int32_t nprob, const int64_t* n, cons
   g_err.clear();
   if (max_iter < 0) return fail(NFS_EINVAL, "max_iter must be >= 0");
   if (!alpha || !alpha_t) return fail(NFS_EINVAL, "NULL pointer argument");
+  if (prm && prm->precision == NFS_AUTO) {
+    size_t need = 0;
+    NFS_TRY(auto_batch_workspace(prm, nprob, n, nt, &need));
+    if (!eps || !x || !mu || !y || !nu || !res || !workspace) return fail(NFS_EINVAL, "NULL pointer argument");
+    if (ws_bytes < need) return fail(NFS_EWORKSPACE, "workspace too small");
+    const nfs_params p32 = with_precision(prm, NFS_FP32), p64 = with_precision(prm, NFS_FP64);
+    int rc = nfs_batch_solve(&p32, nprob, n, nt, eps, x, mu, y, nu, max_iter, tol, alpha, alpha_t, res, workspace,
+                             ws_bytes, stream);
+    if (rc != NFS_ENONPOS) return rc;
+    // each problem with kernel sums t <= 0 again, alone, with FP64 grids
+    const int d = prm->d;
+    int64_t ox = 0, oy = 0;
+    rc = NFS_OK;
+    for (int b = 0; b < nprob; ++b) {
+      if (res[b].n_nonpos > 0) {
+        nfs_params pb = p64;
+        pb.eps = eps[b];
+        nfs_result r{};
+        const int rb = nfs_sinkhorn_solve(&pb, x + ox * d, n[b], mu + ox, y + oy * d, nt[b], nu + oy, max_iter, tol,
+                                          0, alpha + ox, alpha_t + oy, &r, workspace, ws_bytes, stream);
+        if (rb != NFS_OK && rb != NFS_ENONPOS) return rb;
+        res[b] = r;
+        if (rb == NFS_ENONPOS) rc = NFS_ENONPOS;
+      }
+      ox += n[b];
+      oy += nt[b];
+    }
+    if (rc != NFS_OK) return fail(rc, "FP64 grids also produced kernel sums t <= 0");
+    g_err.clear();
+    return NFS_OK;
+  }
   nfs_solver* h = nullptr;
   NFS_TRY(nfs_batch_solver_create(prm, nprob, n, nt, eps, x, mu, y, nu, nullptr, workspace, ws_bytes, stream, &h));
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libnfs.so")
 
 NFS_OK, NFS_EINVAL, NFS_EWEIGHTS, NFS_ENONPOS, NFS_EUNSUPPORTED, NFS_EHIP, NFS_EWORKSPACE = range(7)
-NFS_FP64, NFS_FP32 = 0, 1
+NFS_FP64, NFS_FP32, NFS_AUTO = 0, 1, 2
 FLAG_NO_GRAPH, FLAG_PRIMAL_COST, FLAG_TILE_REDUCE = 1, 2, 4
 
 EXPORTED = ("nfs_last_error", "nfs_validate", "nfs_workspace_size", "nfs_fastsum_apply",
@@ -65,7 +65,7 @@ class Params:
     p_smooth: int = 0
 
     def to_c(self):
-        prec = {"fp64": NFS_FP64, "fp32": NFS_FP32}[self.precision]
+        prec = {"fp64": NFS_FP64, "fp32": NFS_FP32, "auto": NFS_AUTO}[self.precision]
         return _Params(self.d, self.r, self.eps, self.N, self.m, self.sigma, prec, self.tile,
                        self.chunk, self.flags, self.eps_I, self.p_smooth, 0)
 
@@ -213,6 +213,9 @@ def nfft_trafo(params, fhat, pts):
     return out
 
 
+_PREC_NAME = {NFS_FP64: "fp64", NFS_FP32: "fp32"}
+
+
 @dataclass
 class SinkhornResult:
     alpha: torch.Tensor
@@ -227,6 +230,7 @@ class SinkhornResult:
     n_nonpos: int
     scale: float
     kernel_err: float
+    precision_used: str = ""
     extra: dict = field(default_factory=dict)
 
 
@@ -256,7 +260,7 @@ def sinkhorn(params, x, mu, y, nu, iters, tol=0.0, alpha_t0=None, workspace=None
         _check(rc)
     return SinkhornResult(alpha, alpha_t, res.cost, res.cost_upper, res.cost_primal, res.marg_err,
                           res.marg_err_row, res.marg_err_col, res.iters, res.n_nonpos, res.scale,
-                          res.kernel_err)
+                          res.kernel_err, _PREC_NAME.get(res.precision_used, ""))
 
 
 def sinkhorn_grad(params, x, mu, y, nu, alpha, alpha_t, want_x=True, want_mu=True):
@@ -348,7 +352,7 @@ def _results(arr, alpha, alpha_t, offs_x, offs_y):
     for b, r in enumerate(arr):
         out.append(SinkhornResult(alpha[offs_x[b]:offs_x[b + 1]], alpha_t[offs_y[b]:offs_y[b + 1]], r.cost,
                                   r.cost_upper, r.cost_primal, r.marg_err, r.marg_err_row, r.marg_err_col,
-                                  r.iters, r.n_nonpos, r.scale, r.kernel_err))
+                                  r.iters, r.n_nonpos, r.scale, r.kernel_err, _PREC_NAME.get(r.precision_used, "")))
     return out
 
 
@@ -402,21 +406,37 @@ class BatchSolver(Solver):
 
 
 def batch_sinkhorn(params, xs, mus, ys, nus, eps, iters, tol=0.0, check=True):
-    """Solve many problems at once (nfs_batch_solve); returns a list of SinkhornResult."""
-    s = BatchSolver(params, xs, mus, ys, nus, eps)
-    try:
-        s.iterate(iters) if tol <= 0 else None
-        if tol > 0:
-            done = 0
-            while done < iters:
-                k = min(10, iters - done)
-                s.iterate(k)
-                done += k
-                if s.residual() <= tol:
-                    break
-        return s.finish(check=check)
-    finally:
-        s.close()
+    """Solve many problems at once (nfs_batch_solve; precision "auto" promotes
+    the problems whose FP32 sums hit t <= 0 to FP64 grids); returns a list of
+    SinkhornResult."""
+    lib = load_library()
+    nprob = len(xs)
+    ns = [int(x.shape[0]) for x in xs]
+    nts = [int(y.shape[0]) for y in ys]
+    offs_x, offs_y = [0], [0]
+    for a, b in zip(ns, nts):
+        offs_x.append(offs_x[-1] + a)
+        offs_y.append(offs_y[-1] + b)
+    x = torch.cat([_pts(v, params.d, "x").reshape(-1, params.d) for v in xs]).contiguous()
+    y = torch.cat([_pts(v, params.d, "y").reshape(-1, params.d) for v in ys]).contiguous()
+    mu = torch.cat([_dev(v, "mu") for v in mus]).contiguous()
+    nu = torch.cat([_dev(v, "nu") for v in nus]).contiguous()
+    n_arr = (ctypes.c_int64 * nprob)(*ns)
+    nt_arr = (ctypes.c_int64 * nprob)(*nts)
+    eps_arr = (ctypes.c_double * nprob)(*[float(e) for e in eps])
+    prm = params.to_c()
+    nb = ctypes.c_size_t(0)
+    _check(lib.nfs_batch_workspace_size(ctypes.byref(prm), nprob, n_arr, nt_arr, ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=x.device)
+    alpha = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+    alpha_t = torch.empty(y.shape[0], dtype=torch.float64, device=x.device)
+    res = (_Result * nprob)()
+    rc = lib.nfs_batch_solve(ctypes.byref(prm), nprob, n_arr, nt_arr, eps_arr, x.data_ptr(), mu.data_ptr(),
+                             y.data_ptr(), nu.data_ptr(), int(iters), float(tol), alpha.data_ptr(),
+                             alpha_t.data_ptr(), res, ws.data_ptr(), nb.value, _stream())
+    if rc != NFS_OK and (check or rc != NFS_ENONPOS):
+        _check(rc)
+    return _results(res, alpha, alpha_t, offs_x, offs_y)
 
 
 class SinkhornCost(torch.autograd.Function):

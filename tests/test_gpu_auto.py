@@ -1,0 +1,107 @@
+"""NFS_AUTO: FP32 grids, with every problem whose FP32 sums hit t <= 0 (the
+FP32 dynamic-range floor of fast summation) solved again with FP64 grids.
+
+The failing shape is two well separated clusters: targets far from every
+source have kernel sums of about 1e-10 of the largest one, below the FP32
+floor (about 1e-7 of the largest sum) and well above the FP64 floor.
+
+Two solves of one problem are compared within rounding: the spread flush into
+the global grid uses float atomics, whose order varies between runs.  For the
+separated problems, FP64 rounding relative to the largest sum (1.1e-16) is
+about 1e-6 relative to the far cluster's sums (1e-10 of the largest), so
+their scalings agree to about 1e-6 relative, and the cost, through
+eps * sum p log alpha, to about eps * 1e-6 (1e-6 relative here); the bounds
+below leave a factor of ten or more over that.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2201_07524_amd import nfs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def T(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def separated(n, seed):
+    """x: half near -0.2, half near +0.2; y: all near +0.2 (1-D, sigma 0.01)."""
+    rng = np.random.default_rng(seed)
+    x = np.concatenate([rng.normal(-0.2, 0.01, n // 2), rng.normal(0.2, 0.01, n - n // 2)])[:, None]
+    y = rng.normal(0.2, 0.01, n)[:, None]
+    return x, np.full(n, 1.0 / n), y, np.full(n, 1.0 / n)
+
+
+def easy(n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-0.2, 0.2, (n, 1))
+    y = rng.uniform(-0.2, 0.2, (n, 1))
+    return x, np.full(n, 1.0 / n), y, np.full(n, 1.0 / n)
+
+
+def same(a, b, cost_tol, alpha_tol):
+    assert abs(a.cost - b.cost) <= cost_tol * abs(b.cost)
+    for u, v in ((a.alpha, b.alpha), (a.alpha_t, b.alpha_t)):
+        assert torch.all(torch.isfinite(u)) and torch.all(u > 0)
+        assert torch.max(torch.abs(u - v) / v).item() <= alpha_tol
+
+
+def solve(prec, prob, eps, iters=20):
+    x, p, y, pt = prob
+    prm = nfs.Params(d=1, eps=eps, N=256, m=8, precision=prec)
+    return nfs.sinkhorn(prm, T(x), T(p), T(y), T(pt), iters, check=False)
+
+
+def test_auto_promotes_failing_problem_to_fp64():
+    prob, eps = separated(600, 11), 0.007
+    r32 = solve("fp32", prob, eps)
+    assert r32.n_nonpos > 0
+    r64 = solve("fp64", prob, eps)
+    assert r64.n_nonpos == 0
+    ra = solve("auto", prob, eps)
+    assert ra.precision_used == "fp64" and ra.n_nonpos == 0
+    same(ra, r64, 1e-5, 1e-3)
+
+
+def test_auto_keeps_fp32_when_it_suffices():
+    prob, eps = easy(500, 12), 0.02
+    r32 = solve("fp32", prob, eps)
+    ra = solve("auto", prob, eps)
+    assert r32.n_nonpos == 0 and ra.precision_used == "fp32"
+    same(ra, r32, 1e-6, 1e-4)
+
+
+def test_auto_warm_start_reaches_the_fp64_result():
+    prob, eps = separated(400, 13), 0.007
+    x, p, y, pt = prob
+    start = T(np.random.default_rng(3).uniform(0.5, 2.0, y.shape[0]))
+    prm64 = nfs.Params(d=1, eps=eps, N=256, m=8, precision="fp64")
+    prma = nfs.Params(d=1, eps=eps, N=256, m=8, precision="auto")
+    r64 = nfs.sinkhorn(prm64, T(x), T(p), T(y), T(pt), 15, alpha_t0=start)
+    ra = nfs.sinkhorn(prma, T(x), T(p), T(y), T(pt), 15, alpha_t0=start)
+    assert ra.precision_used == "fp64" and ra.n_nonpos == 0
+    same(ra, r64, 1e-5, 1e-3)
+
+
+def test_batch_auto_promotes_only_the_failing_problems():
+    probs = [easy(300, 21), separated(500, 22), easy(700, 23), separated(350, 24)]
+    eps = [0.02, 0.007, 0.03, 0.0065]
+
+    def batch(prec):
+        prm = nfs.Params(d=1, eps=1.0, N=256, m=8, precision=prec)
+        return nfs.batch_sinkhorn(prm, [T(q[0]) for q in probs], [T(q[1]) for q in probs],
+                                  [T(q[2]) for q in probs], [T(q[3]) for q in probs], eps, 20, check=False)
+
+    r32 = batch("fp32")
+    assert [r.n_nonpos > 0 for r in r32] == [False, True, False, True]
+    ra = batch("auto")
+    assert [r.precision_used for r in ra] == ["fp32", "fp64", "fp32", "fp64"]
+    for b in (0, 2):
+        same(ra[b], r32[b], 1e-6, 1e-4)
+    for b in (1, 3):
+        assert ra[b].n_nonpos == 0
+        same(ra[b], solve("fp64", probs[b], eps[b]), 1e-5, 1e-3)
