@@ -207,3 +207,14 @@ def solve(x, p, y, pt, r, eps, iters, alpha_t0=None):
                 cost_upper=cost_upper_bound(s, p, pt, eps),
                 cost_primal=primal_cost(K, C, a, at),
                 marg_err=e_row + e_col, marg_err_row=e_row, marg_err_col=e_col)
+
+
+def sinkhorn_divergence(x, p, y, pt, r, eps, iters):
+    """Sinkhorn divergence sd(P, Pt) = s(P, Pt) - s(P, P)/2 - s(Pt, Pt)/2
+    (Remark on entropy bias and Sinkhorn divergence, Section 2.2; its NFFT form
+    in Section 3.2), each s the Algorithm 3 result after ``iters`` iterations
+    of Algorithm 1 from the default start.  Returns sd and the three costs."""
+    s_xy = solve(x, p, y, pt, r, eps, iters)["cost"]
+    s_xx = solve(x, p, x, p, r, eps, iters)["cost"]
+    s_yy = solve(y, pt, y, pt, r, eps, iters)["cost"]
+    return dict(sd=s_xy - 0.5 * s_xx - 0.5 * s_yy, cost_xy=s_xy, cost_xx=s_xx, cost_yy=s_yy)

@@ -308,3 +308,46 @@ def test_planted_mistakes_are_caught():
     expect = 2.0 * (p @ x - pt @ y)
     assert np.allclose(gx.sum(0), expect, atol=1e-13)
     assert not np.allclose((0.5 * gx).sum(0), expect, atol=1e-6)
+
+    # (e) Sinkhorn divergence without the factors 1/2 is not zero on identical
+    # measures (the pin of property 3 rejects it)
+    out = sd.sinkhorn_divergence(x, p, x, p, 2, eps, 200)
+    assert abs(out["cost_xy"] - out["cost_xx"] - out["cost_yy"]) > 1e-3
+
+
+# ---------------------------------------------------------------- Sinkhorn divergence
+def test_sinkhorn_divergence_vanishes_on_identical_measures():
+    """sd(P, P) = 0 for every eps (property 3 of the Sinkhorn divergence)."""
+    x = _cloud(30, 2, 41)
+    p = np.random.default_rng(42).dirichlet(np.ones(30))
+    for eps in (0.01, 0.1):
+        out = sd.sinkhorn_divergence(x, p, x, p, 2, eps, 200)
+        assert abs(out["sd"]) <= 1e-15 * abs(out["cost_xy"])
+
+
+@pytest.mark.parametrize("r", [1, 2])
+def test_sinkhorn_divergence_nonnegative(r):
+    """sd(P, Pt) >= 0 at convergence (property 1; the Gaussian and Laplace
+    kernels are positive definite), and sd is symmetric."""
+    for seed in range(4):
+        x, y = _cloud(40, 2, 100 + seed), _cloud(35, 2, 200 + seed) + 0.05 * seed
+        p = np.random.default_rng(300 + seed).dirichlet(np.ones(40))
+        pt = np.random.default_rng(400 + seed).dirichlet(np.ones(35))
+        a = sd.sinkhorn_divergence(x, p, y, pt, r, 0.05, 3000)
+        b = sd.sinkhorn_divergence(y, pt, x, p, r, 0.05, 3000)
+        assert a["sd"] >= -1e-12
+        assert abs(a["sd"] - b["sd"]) <= 1e-12
+
+
+def test_sinkhorn_divergence_tends_to_wasserstein_1d():
+    """sd -> w_2 as eps -> 0 (property 2), with the exact 1-D w_2 from sorting
+    (equal uniform weights): the gap shrinks with eps and is within 2% of w_2
+    at the smallest eps."""
+    rng = np.random.default_rng(7)
+    n = 48
+    x, y = rng.uniform(-0.25, 0.25, (n, 1)), rng.uniform(-0.1, 0.3, (n, 1))
+    p = np.full(n, 1.0 / n)
+    w2 = float(np.mean((np.sort(x[:, 0]) - np.sort(y[:, 0])) ** 2))
+    gaps = [abs(sd.sinkhorn_divergence(x, p, y, p, 2, eps, 20000)["sd"] - w2) for eps in (0.02, 0.005, 0.0015)]
+    assert gaps[0] > gaps[1] > gaps[2]
+    assert gaps[2] <= 0.02 * w2
