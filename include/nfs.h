@@ -204,6 +204,22 @@ int nfs_batch_solve(const nfs_params* prm, int32_t nprob, const int64_t* n, cons
                     nfs_result* res, void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * Sinkhorn divergence (Remark on entropy bias and Sinkhorn divergence,
+ * Section 2.2; its NFFT form in Section 3.2):
+ *   sd = s(P, Pt) - s(P, P)/2 - s(Pt, Pt)/2,
+ * each s the Algorithm 3 result after max_iter iterations from the default
+ * start (tol > 0: stop early per problem as in nfs_sinkhorn_solve).  The three
+ * problems run as one batch (batched form) from inputs packed into the
+ * workspace; prm->precision may be NFS_AUTO.  *sd: host scalar.  res
+ * (nullable, host array of 3): results of (P, Pt), (P, P), (Pt, Pt).  Returns
+ * NFS_ENONPOS (with *sd set) when a kernel sum t <= 0 remains.
+ */
+int nfs_divergence_workspace_size(const nfs_params* prm, int64_t n, int64_t nt, size_t* bytes);
+int nfs_sinkhorn_divergence(const nfs_params* prm, const double* x, int64_t n, const double* mu,
+                            const double* y, int64_t nt, const double* nu, int32_t max_iter, double tol,
+                            double* sd, nfs_result* res, void* workspace, size_t ws_bytes, void* stream);
+
+/*
  * Gradient of the Sinkhorn cost at given scalings (alpha, alpha_t), by the
  * envelope theorem applied to the dual (Proposition 2.3, eq. (14)):
  *   grad_x[i]  = sum_j pi_ij grad_x c(x_i, y_j) = -eps alpha_i (grad K * alpha_t)(x_i)   (n x d)

@@ -1314,6 +1314,32 @@ static int auto_batch_workspace(const nfs_params* p, int32_t B, const int64_t* n
   return NFS_OK;
 }
 
+// ----------------------------------------------------------------------------- Sinkhorn divergence
+// Workspace: packed inputs of the three problems (P, Pt), (P, P), (Pt, Pt) and
+// their scalings, then the batch workspace.
+struct DivLayout {
+  int64_t n3[3], nt3[3];
+  size_t packed = 0;  // bytes before the batch workspace
+  size_t batch = 0;
+};
+
+static int divergence_layout(const nfs_params* p, int64_t n, int64_t nt, DivLayout* L) {
+  if (!p) return fail(NFS_EINVAL, "params is NULL");
+  if (n < 1 || nt < 1) return fail(NFS_EINVAL, "every cloud needs at least one point");
+  L->n3[0] = n, L->n3[1] = n, L->n3[2] = nt;
+  L->nt3[0] = nt, L->nt3[1] = n, L->nt3[2] = nt;
+  if (p->precision == NFS_AUTO) {
+    NFS_TRY(auto_batch_workspace(p, 3, L->n3, L->nt3, &L->batch));
+  } else {
+    long sn = 0, snt = 0;
+    NFS_TRY(batch_sizes(p, 3, L->n3, L->nt3, &sn, &snt));
+    NFS_TRY(batch_workspace(p, 3, sn, snt, &L->batch));
+  }
+  const size_t nx = size_t(2 * n + nt), ny = size_t(n + 2 * nt);
+  L->packed = align_up(sizeof(double) * ((nx + ny) * size_t(p->d) + 2 * (nx + ny)));
+  return NFS_OK;
+}
+
 }  // namespace nfs
 
 // ============================================================================= C ABI
@@ -1527,6 +1553,58 @@ int nfs_batch_solve(const nfs_params* prm, int32_t nprob, const int64_t* n, cons
   auto* s = reinterpret_cast<SolverBase*>(h);
   const int rc = run_solver(s, max_iter, tol, alpha, alpha_t, res, st);
   delete s;
+  return rc;
+}
+
+int nfs_divergence_workspace_size(const nfs_params* prm, int64_t n, int64_t nt, size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(NFS_EINVAL, "bytes is NULL");
+  DivLayout L;
+  NFS_TRY(divergence_layout(prm, n, nt, &L));
+  *bytes = L.packed + L.batch;
+  return NFS_OK;
+}
+
+int nfs_sinkhorn_divergence(const nfs_params* prm, const double* x, int64_t n, const double* mu, const double* y,
+                            int64_t nt, const double* nu, int32_t max_iter, double tol, double* sd, nfs_result* res,
+                            void* workspace, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  DivLayout L;
+  NFS_TRY(divergence_layout(prm, n, nt, &L));
+  if (!x || !mu || !y || !nu || !sd || !workspace) return fail(NFS_EINVAL, "NULL pointer argument");
+  if (ws_bytes < L.packed + L.batch) return fail(NFS_EWORKSPACE, "workspace too small");
+  if (max_iter < 0) return fail(NFS_EINVAL, "max_iter must be >= 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int d = prm->d;
+  const size_t nx = size_t(2 * n + nt), ny = size_t(n + 2 * nt);
+  double* X = static_cast<double*>(workspace);
+  double* Y = X + nx * d;
+  double* MU = Y + ny * d;
+  double* NU = MU + nx;
+  double* A = NU + ny;
+  double* AT = A + nx;
+  const size_t bx = sizeof(double) * size_t(n) * d, by = sizeof(double) * size_t(nt) * d;
+  // x rows: x | x | y ; y rows: y | x | y (problems (P, Pt), (P, P), (Pt, Pt))
+  NFS_HIP(hipMemcpyAsync(X, x, bx, hipMemcpyDeviceToDevice, st));
+  NFS_HIP(hipMemcpyAsync(X + size_t(n) * d, x, bx, hipMemcpyDeviceToDevice, st));
+  NFS_HIP(hipMemcpyAsync(X + size_t(2 * n) * d, y, by, hipMemcpyDeviceToDevice, st));
+  NFS_HIP(hipMemcpyAsync(Y, y, by, hipMemcpyDeviceToDevice, st));
+  NFS_HIP(hipMemcpyAsync(Y + size_t(nt) * d, x, bx, hipMemcpyDeviceToDevice, st));
+  NFS_HIP(hipMemcpyAsync(Y + size_t(nt + n) * d, y, by, hipMemcpyDeviceToDevice, st));
+  NFS_HIP(hipMemcpyAsync(MU, mu, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  NFS_HIP(hipMemcpyAsync(MU + n, mu, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  NFS_HIP(hipMemcpyAsync(MU + 2 * n, nu, sizeof(double) * nt, hipMemcpyDeviceToDevice, st));
+  NFS_HIP(hipMemcpyAsync(NU, nu, sizeof(double) * nt, hipMemcpyDeviceToDevice, st));
+  NFS_HIP(hipMemcpyAsync(NU + nt, mu, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  NFS_HIP(hipMemcpyAsync(NU + nt + n, nu, sizeof(double) * nt, hipMemcpyDeviceToDevice, st));
+  const double eps3[3] = {prm->eps, prm->eps, prm->eps};
+  nfs_result r3[3] = {};
+  const int rc = nfs_batch_solve(prm, 3, L.n3, L.nt3, eps3, X, MU, Y, NU, max_iter, tol, A, AT, r3,
+                                 static_cast<char*>(workspace) + L.packed, ws_bytes - L.packed, stream);
+  if (rc != NFS_OK && rc != NFS_ENONPOS) return rc;
+  *sd = r3[0].cost - 0.5 * r3[1].cost - 0.5 * r3[2].cost;
+  if (res)
+    for (int k = 0; k < 3; ++k) res[k] = r3[k];
   return rc;
 }
 

@@ -22,7 +22,8 @@ EXPORTED = ("nfs_last_error", "nfs_validate", "nfs_workspace_size", "nfs_fastsum
             "nfs_nfft_adjoint", "nfs_nfft_trafo", "nfs_sinkhorn_solve", "nfs_sinkhorn_grad",
             "nfs_solver_create", "nfs_solver_iterate", "nfs_solver_residual", "nfs_solver_finish",
             "nfs_solver_profile", "nfs_solver_destroy", "nfs_batch_workspace_size",
-            "nfs_batch_solver_create", "nfs_batch_solve")
+            "nfs_batch_solver_create", "nfs_batch_solve", "nfs_divergence_workspace_size",
+            "nfs_sinkhorn_divergence")
 
 
 class NfsError(RuntimeError):
@@ -121,6 +122,11 @@ def load_library():
     lib.nfs_batch_solve.restype = ctypes.c_int
     lib.nfs_batch_solve.argtypes = [PP, ctypes.c_int32, PI64, PI64, PD, P, P, P, P, ctypes.c_int32,
                                     ctypes.c_double, P, P, ctypes.POINTER(_Result), P, SZ, P]
+    lib.nfs_divergence_workspace_size.restype = ctypes.c_int
+    lib.nfs_divergence_workspace_size.argtypes = [PP, I64, I64, ctypes.POINTER(SZ)]
+    lib.nfs_sinkhorn_divergence.restype = ctypes.c_int
+    lib.nfs_sinkhorn_divergence.argtypes = [PP, P, I64, P, P, I64, P, ctypes.c_int32, ctypes.c_double,
+                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_Result), P, SZ, P]
     _lib = lib
     return lib
 
@@ -437,6 +443,29 @@ def batch_sinkhorn(params, xs, mus, ys, nus, eps, iters, tol=0.0, check=True):
     if rc != NFS_OK and (check or rc != NFS_ENONPOS):
         _check(rc)
     return _results(res, alpha, alpha_t, offs_x, offs_y)
+
+
+def sinkhorn_divergence(params, x, mu, y, nu, iters, tol=0.0, check=True):
+    """Sinkhorn divergence s(P, Pt) - s(P, P)/2 - s(Pt, Pt)/2 (nfs_sinkhorn_divergence);
+    returns (sd, [cost(P, Pt), cost(P, P), cost(Pt, Pt)], [n_nonpos of each])."""
+    lib = load_library()
+    x = _pts(x, params.d, "x")
+    y = _pts(y, params.d, "y")
+    _dev(mu, "mu")
+    _dev(nu, "nu")
+    n, nt = x.shape[0], y.shape[0]
+    prm = params.to_c()
+    nb = ctypes.c_size_t(0)
+    _check(lib.nfs_divergence_workspace_size(ctypes.byref(prm), n, nt, ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=x.device)
+    out = ctypes.c_double(0.0)
+    res = (_Result * 3)()
+    rc = lib.nfs_sinkhorn_divergence(ctypes.byref(prm), x.data_ptr(), n, mu.data_ptr(), y.data_ptr(), nt,
+                                     nu.data_ptr(), int(iters), float(tol), ctypes.byref(out), res,
+                                     ws.data_ptr(), nb.value, _stream())
+    if rc != NFS_OK and (check or rc != NFS_ENONPOS):
+        _check(rc)
+    return out.value, [r.cost for r in res], [r.n_nonpos for r in res]
 
 
 class SinkhornCost(torch.autograd.Function):
