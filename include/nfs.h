@@ -79,7 +79,8 @@ typedef struct nfs_params {
   double sigma;       /* oversampling: grid g = sigma*N rounded up to even, g >= N + 2 */
   int32_t precision;  /* NFS_FP64, NFS_FP32, or NFS_AUTO (solve calls only) */
   int32_t tile;       /* grid cells per bin side (0 = default for d) */
-  int32_t chunk;      /* max points per workgroup chunk, 0..32768 (0 = default 1024) */
+  int32_t chunk;      /* max points per workgroup chunk, 0..32768 (0 = default: 1536 for FP32,
+                         d = 2, r = 2; else 1024) */
   int32_t flags;      /* NFS_FLAG_* */
   double eps_I;       /* r = 1: near-field radius times N on the period-1 torus (0 = default 4);
                          the radius must fit in 2 kt + 1 tiles, kt = ceil(eps_I sigma / tile) */

@@ -85,8 +85,8 @@ struct WindowPoly {
 // Longest run of same-cell points that spreading and interpolation handle
 // together (window values of a run stay in registers: G x d x (2m+1)).
 template <typename R>
-__host__ __device__ constexpr int run_length(int d) {
-  return (sizeof(R) == 8 || d == 3) ? 2 : 4;
+__host__ __device__ constexpr int run_length(int) {
+  return sizeof(R) == 8 ? 2 : 4;
 }
 
 // Geometry of the oversampled grid and its bins (tiles).

@@ -238,28 +238,46 @@ __device__ __forceinline__ void spread_run(Acc<R, ACC>& tile, const SpreadArgs<R
       }
     }
   } else {
-    // the rolled j1 loop reads element 0 of the second-axis windows, which
-    // are rotated by one per iteration (a full cycle restores them)
 #pragma unroll 1
     for (int j0 = 0; j0 < W; ++j0) {
       R b0[GC];
 #pragma unroll
       for (int p = 0; p < GC; ++p) b0[p] = w[p] * ev.tap(j0, tp[p].x[0]);
-#pragma unroll 1
-      for (int j1 = 0; j1 < W; ++j1) {
-        R a1[GC];
+      if constexpr (sizeof(R) == 4) {
+        // FP32: j1 unrolled, every window index static
 #pragma unroll
-        for (int p = 0; p < GC; ++p) a1[p] = b0[p] * tp[p].psi[1][0];
-        const int row = ((tp[0].off[0] + j0) * E + tp[0].off[1] + j1) * E + tp[0].off[2];
+        for (int j1 = 0; j1 < W; ++j1) {
+          R a1[GC];
 #pragma unroll
-        for (int j2 = 0; j2 < W; ++j2) {
-          R v = R(0);
+          for (int p = 0; p < GC; ++p) a1[p] = b0[p] * tp[p].psi[1][j1];
+          const int row = ((tp[0].off[0] + j0) * E + tp[0].off[1] + j1) * E + tp[0].off[2];
 #pragma unroll
-          for (int p = 0; p < GC; ++p) v += a1[p] * tp[p].psi[2][j2];
-          tile.add(row + j2, v);
+          for (int j2 = 0; j2 < W; ++j2) {
+            R v = R(0);
+#pragma unroll
+            for (int p = 0; p < GC; ++p) v += a1[p] * tp[p].psi[2][j2];
+            tile.add(row + j2, v);
+          }
         }
+      } else {
+        // FP64: the rolled j1 loop reads element 0 of the second-axis windows,
+        // which are rotated by one per iteration (a full cycle restores them)
+#pragma unroll 1
+        for (int j1 = 0; j1 < W; ++j1) {
+          R a1[GC];
 #pragma unroll
-        for (int p = 0; p < GC; ++p) rotate_left(tp[p].psi[1]);
+          for (int p = 0; p < GC; ++p) a1[p] = b0[p] * tp[p].psi[1][0];
+          const int row = ((tp[0].off[0] + j0) * E + tp[0].off[1] + j1) * E + tp[0].off[2];
+#pragma unroll
+          for (int j2 = 0; j2 < W; ++j2) {
+            R v = R(0);
+#pragma unroll
+            for (int p = 0; p < GC; ++p) v += a1[p] * tp[p].psi[2][j2];
+            tile.add(row + j2, v);
+          }
+#pragma unroll
+          for (int p = 0; p < GC; ++p) rotate_left(tp[p].psi[1]);
+        }
       }
     }
   }
