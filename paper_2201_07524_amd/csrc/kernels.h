@@ -70,7 +70,8 @@ struct InterpArgs {
   double* partials;         // 4 doubles per chunk
   unsigned* counter;        // per problem, zero on entry, left zero
   const int* prob_chunks;   // B + 1: chunks of problem p are [prob_chunks[p], prob_chunks[p+1])
-  double* stats;            // per problem (stride 8): residual^2 sum, mass sum, max alpha, count(t <= 0),
+  double* stats;            // per problem (stride 8): residual^2 sum (EPI_EVAL only), mass sum, max alpha,
+                            // count(t <= 0),
                             // running count
   double* wmul_next;        // per problem, receives 1/max alpha (nullable)
 };

@@ -283,8 +283,14 @@ __device__ __forceinline__ void spread_run(Acc<R, ACC>& tile, const SpreadArgs<R
   }
 }
 
+// Threads per spreading workgroup: in 3-D the fixed-point LDS tile is large
+// (25^3 words at tile 8, m = 8), one workgroup fills a CU's LDS, and 512
+// threads give two waves per SIMD instead of one.
+__host__ __device__ constexpr int spread_block(int d) { return d == 3 ? 512 : kBlock; }
+
 template <typename R, int D, int M, int ACC>
-__global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs<R> a) {
+__global__ __launch_bounds__(spread_block(D)) void spread_kernel(SpreadArgs<R> a) {
+  constexpr int BS = spread_block(D);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Geom geo = a.geo;
   const int E = geo.E;
@@ -295,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs<R> a) {
   // the part store (per-tile reduction) needs the whole tile
   int lo, hi;
   chunk_rows<R, D, M>(a.coords, ch, geo, a.cell_order && !a.part, lo, hi);
-  for (int i = lo + threadIdx.x; i < hi; i += kBlock) tile.zero(i);
+  for (int i = lo + threadIdx.x; i < hi; i += BS) tile.zero(i);
   __syncthreads();
 
   // The chunk's run table lists full runs of G same-cell points, then the
@@ -306,12 +312,12 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs<R> a) {
   const int* runs = a.runs + ch.start;
   const int nfull = a.nruns[2 * blockIdx.x], nsingle = a.nruns[2 * blockIdx.x + 1];
   int rows = (nfull + kWave - 1) / kWave;
-  for (int slot = threadIdx.x; slot < rows * kWave; slot += kBlock) {
+  for (int slot = threadIdx.x; slot < rows * kWave; slot += BS) {
     const int rr = run_of_slot(slot, rows);
     if (rr < nfull) spread_run<R, D, M, ACC, G>(tile, a, ev, E, ch.start + runs[rr], wm);
   }
   rows = (nsingle + kWave - 1) / kWave;
-  for (int slot = threadIdx.x; slot < rows * kWave; slot += kBlock) {
+  for (int slot = threadIdx.x; slot < rows * kWave; slot += BS) {
     const int rr = run_of_slot(slot, rows);
     if (rr < nsingle) spread_run<R, D, M, ACC, 1>(tile, a, ev, E, ch.start + runs[nfull + rr], wm);
   }
@@ -319,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs<R> a) {
 
   if (a.part) {
     R* dst = a.part + size_t(blockIdx.x) * ncell;
-    for (int i = threadIdx.x; i < ncell; i += kBlock) dst[i] = tile.get(i);
+    for (int i = threadIdx.x; i < ncell; i += BS) dst[i] = tile.get(i);
     return;
   }
 
@@ -333,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs<R> a) {
     }
   }
   const int g = geo.g;
-  for (int i = lo + threadIdx.x; i < hi; i += kBlock) {
+  for (int i = lo + threadIdx.x; i < hi; i += BS) {
     const R v = tile.get(i);
     if (v == R(0)) continue;
     size_t lin;
@@ -801,6 +807,19 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
     if (a.epi == EPI_OUT) {
       const double sc = a.scale_vec ? a.scale_vec[q] : 1.0;
       a.out[size_t(a.perm[q]) * a.out_stride + a.out_comp] = t * sc;
+    } else if (a.epi == EPI_SINK) {
+      // the update reads no old scaling: the row residual of eq. (Error) is
+      // evaluated by EPI_EVAL when it is wanted
+      const double p = a.p[q];
+      if (p > 0.0) {
+        if (!(t > 0.0) || !isfinite(t)) acc_red.cnt += 1.0;
+        const double anew = p / t;
+        a.alpha[q] = anew;
+        acc_red.s1 += anew * t;
+        acc_red.mx = fmax(acc_red.mx, anew);
+      } else {
+        a.alpha[q] = 0.0;
+      }
     } else {
       const double p = a.p[q];
       const double aold = a.alpha[q];
@@ -808,17 +827,8 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
       acc_red.s0 += res * res;
       if (p > 0.0) {
         if (!(t > 0.0) || !isfinite(t)) acc_red.cnt += 1.0;
-        if (a.epi == EPI_SINK) {
-          const double anew = p / t;
-          a.alpha[q] = anew;
-          acc_red.s1 += anew * t;
-          acc_red.mx = fmax(acc_red.mx, anew);
-        } else {
-          acc_red.s1 += aold * t;
-          acc_red.mx = fmax(acc_red.mx, aold);
-        }
-      } else if (a.epi == EPI_SINK) {
-        a.alpha[q] = 0.0;
+        acc_red.s1 += aold * t;
+        acc_red.mx = fmax(acc_red.mx, aold);
       }
     }
   };
@@ -897,13 +907,13 @@ int acc_mode_for(const Geom& geo, size_t* shm) {
 
 #define NFS_SPREAD_M(D_, R_, ACC_, NBLK, SHM, STREAM)                                                          \
   switch (geo.M) {                                                                                             \
-    case 2: hipLaunchKernelGGL((spread_kernel<R_, D_, 2, ACC_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, a); break; \
-    case 3: hipLaunchKernelGGL((spread_kernel<R_, D_, 3, ACC_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, a); break; \
-    case 4: hipLaunchKernelGGL((spread_kernel<R_, D_, 4, ACC_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, a); break; \
-    case 5: hipLaunchKernelGGL((spread_kernel<R_, D_, 5, ACC_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, a); break; \
-    case 6: hipLaunchKernelGGL((spread_kernel<R_, D_, 6, ACC_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, a); break; \
-    case 7: hipLaunchKernelGGL((spread_kernel<R_, D_, 7, ACC_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, a); break; \
-    case 8: hipLaunchKernelGGL((spread_kernel<R_, D_, 8, ACC_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, a); break; \
+    case 2: hipLaunchKernelGGL((spread_kernel<R_, D_, 2, ACC_>), dim3(NBLK), dim3(spread_block(D_)), SHM, STREAM, a); break; \
+    case 3: hipLaunchKernelGGL((spread_kernel<R_, D_, 3, ACC_>), dim3(NBLK), dim3(spread_block(D_)), SHM, STREAM, a); break; \
+    case 4: hipLaunchKernelGGL((spread_kernel<R_, D_, 4, ACC_>), dim3(NBLK), dim3(spread_block(D_)), SHM, STREAM, a); break; \
+    case 5: hipLaunchKernelGGL((spread_kernel<R_, D_, 5, ACC_>), dim3(NBLK), dim3(spread_block(D_)), SHM, STREAM, a); break; \
+    case 6: hipLaunchKernelGGL((spread_kernel<R_, D_, 6, ACC_>), dim3(NBLK), dim3(spread_block(D_)), SHM, STREAM, a); break; \
+    case 7: hipLaunchKernelGGL((spread_kernel<R_, D_, 7, ACC_>), dim3(NBLK), dim3(spread_block(D_)), SHM, STREAM, a); break; \
+    case 8: hipLaunchKernelGGL((spread_kernel<R_, D_, 8, ACC_>), dim3(NBLK), dim3(spread_block(D_)), SHM, STREAM, a); break; \
     default: return hipErrorInvalidValue;                                                                      \
   }
 
