@@ -117,9 +117,51 @@ __global__ __launch_bounds__(kBlock) void keys_kernel(KeyArgs a) {
   atomicAdd(&a.counts[key], 1);
 }
 
+// Clustered clouds put most points into a few tiles, so per-point global
+// atomics on the tile counters serialize.  With at most kPlanBins tiles, each
+// workgroup histograms kPlanPerThread * kBlock points in LDS first and adds
+// one count per (workgroup, tile) to the global counters.
+constexpr int kPlanBins = 8192;
+constexpr int kPlanPerThread = 16;
+constexpr int kPlanPerBlock = kPlanPerThread * kBlock;
+
+__device__ __forceinline__ int tile_key(const double* pts, long i, int d, const double* center, double scale, int g,
+                                        int T, const int* nt) {
+  int key = 0;
+  for (int c = 0; c < d; ++c) {
+    const double v = grid_coord(pts[i * d + c], center[c], scale, g);
+    const int cell = min(int(v), g - 1);
+    key = key * nt[c] + cell / T;
+  }
+  return key;
+}
+
+__global__ __launch_bounds__(kBlock) void keys_lds_kernel(KeyArgs a) {
+  extern __shared__ int hist[];
+  const int nbins = a.nt[0] * a.nt[1] * a.nt[2];
+  for (int b = threadIdx.x; b < nbins; b += kBlock) hist[b] = 0;
+  __syncthreads();
+  const long base = long(blockIdx.x) * kPlanPerBlock;
+  const long end = min(base + kPlanPerBlock, a.n);
+  for (long i = base + threadIdx.x; i < end; i += kBlock) {
+    const int key = tile_key(a.pts, i, a.d, a.center, a.scale, a.g, a.T, a.nt);
+    a.keys[i] = key;
+    atomicAdd(&hist[key], 1);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nbins; b += kBlock)
+    if (hist[b]) atomicAdd(&a.counts[b], hist[b]);
+}
+
 hipError_t launch_keys(const KeyArgs& a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(keys_kernel, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
+  const int nbins = a.nt[0] * a.nt[1] * a.nt[2];
+  if (nbins <= kPlanBins) {
+    const long nblk = (a.n + kPlanPerBlock - 1) / kPlanPerBlock;
+    hipLaunchKernelGGL(keys_lds_kernel, dim3(nblk), dim3(kBlock), sizeof(int) * nbins, st, a);
+  } else {
+    hipLaunchKernelGGL(keys_kernel, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -144,9 +186,61 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(ScatterArgs<R> a) {
 }
 
 template <typename R>
+__device__ __forceinline__ void scatter_point(const ScatterArgs<R>& a, long i, int pos) {
+  for (int c = 0; c < a.d; ++c) {
+    const double v = grid_coord(a.pts[i * a.d + c], a.center[c], a.scale, a.g);
+    const int cell = min(int(v), a.g - 1);
+    const double u = v - double((cell / a.T) * a.T);
+    R ur = R(u);
+    if (ur >= R(a.T)) ur = nextafter(R(a.T), R(0));
+    if (ur < R(0)) ur = R(0);
+    a.coords[size_t(pos) * a.d + c] = ur;
+  }
+  a.perm[pos] = int(i) + a.idx_base;
+  if (a.w0) a.w0s[pos] = a.w0[i];
+  if (a.w1) a.w1s[pos] = a.w1[i];
+}
+
+// Workgroup-local counting: each point's rank among the workgroup's points of
+// its tile (LDS atomics), one global atomic per (workgroup, tile) to reserve
+// the workgroup's slots, then the writes.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void scatter_lds_kernel(ScatterArgs<R> a, int nbins) {
+  extern __shared__ int sh[];
+  int* hist = sh;
+  int* slot = sh + nbins;
+  for (int b = threadIdx.x; b < nbins; b += kBlock) hist[b] = 0;
+  __syncthreads();
+  const long base = long(blockIdx.x) * kPlanPerBlock;
+  int key[kPlanPerThread], rank[kPlanPerThread];
+#pragma unroll
+  for (int k = 0; k < kPlanPerThread; ++k) {
+    const long i = base + threadIdx.x + long(k) * kBlock;
+    key[k] = -1;
+    if (i < a.n) {
+      key[k] = a.keys[i];
+      rank[k] = atomicAdd(&hist[key[k]], 1);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nbins; b += kBlock)
+    if (hist[b]) slot[b] = a.offsets[b] + atomicAdd(&a.cursor[b], hist[b]);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPlanPerThread; ++k)
+    if (key[k] >= 0) scatter_point(a, base + threadIdx.x + long(k) * kBlock, slot[key[k]] + rank[k]);
+}
+
+template <typename R>
 hipError_t launch_scatter(const ScatterArgs<R>& a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(scatter_kernel<R>, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
+  const int nbins = a.nt[0] * a.nt[1] * a.nt[2];
+  if (nbins <= kPlanBins) {
+    const long nblk = (a.n + kPlanPerBlock - 1) / kPlanPerBlock;
+    hipLaunchKernelGGL(scatter_lds_kernel<R>, dim3(nblk), dim3(kBlock), sizeof(int) * 2 * nbins, st, a, nbins);
+  } else {
+    hipLaunchKernelGGL(scatter_kernel<R>, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
+  }
   return hipGetLastError();
 }
 template hipError_t launch_scatter<float>(const ScatterArgs<float>&, hipStream_t);
