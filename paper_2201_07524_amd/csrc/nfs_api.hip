@@ -371,6 +371,14 @@ static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const std:
       acc += cnt;
     }
     if (acc != cb.off[b + 1]) return fail(NFS_EINVAL, "internal: tile histogram does not match the point count");
+    // 3-D: largest chunks first inside the problem's range.  Workgroups are
+    // handed out in launch order, so the heavy chunks start first and the
+    // light ones fill in behind them (3-D mixture: spreading 1.65 -> 1.45 ms).
+    // In 2-D tile order is as fast (its neighbouring halos share L2), and the
+    // per-tile reduction needs each tile's chunks adjacent.
+    if (!w.two_level && d == 3)
+      std::stable_sort(chunks.begin() + prob_chunks[b], chunks.end(),
+                       [](const Chunk& u, const Chunk& v) { return u.count > v.count; });
   }
   prob_chunks[B] = int(chunks.size());
   tile_chunks[nb] = int(chunks.size());
