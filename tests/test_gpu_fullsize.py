@@ -1,0 +1,103 @@
+"""Full-size parity on sampled outputs, in the launch configuration the
+benchmark uses (default tile and chunk): the 3-D mixtures with the gradient,
+the 3-D ball/shell with the Euclidean cost, and the 512-problem batch.
+
+Each test runs a few iterations at full size and checks the last half-step
+alpha_t = nu / (K^T alpha) on sampled targets against the oracle's FP64
+matrix-free sums with the GPU's own alpha (the K^T alpha the GPU divided by),
+normwise within the FP32 tolerance 1e-5 (relative to the largest output, as
+for the fast summation's own tests).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import direct
+from paper_2201_07524_amd import nfs, workloads
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def T(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def check_last_half_step(x, y, pt, a, at, r, eps, rows):
+    """The norm is relative to the largest sum over all targets: the sampled
+    rows get the row where the GPU's sum is largest, and the oracle's value
+    there (checked like the others) sets the scale."""
+    assert np.all(a > 0) and np.all(np.isfinite(a)) and np.all(at > 0) and np.all(np.isfinite(at))
+    rows = np.union1d(rows, [np.argmax(pt / at)])
+    tt = direct.kv(y, x, a, r, eps, rows=rows)
+    tt_gpu = pt[rows] / at[rows]
+    assert np.max(np.abs(tt_gpu - tt)) <= 1e-5 * np.max(tt)
+
+
+def test_3d_mixture_full_size_sampled_parity_and_gradient():
+    """3-D mixtures, 1e6 points per cloud, N = 128, m = 8, eps = 0.01, FP32:
+    10 iterations, then the envelope gradient on 128 sampled points against the
+    oracle's FP64 gradient sums with the FP32 solve's scalings.
+
+    FP64 grids: normwise 1e-10.  FP32 grids: the gradient applies the spectral
+    multiplier 2 pi i k_c s (s the torus scaling) to the spread grid, whose FP32
+    rounding is spread over all frequencies; the gain on that noise is at most
+    pi N s <= pi N / (2 R) (|k_c| <= N/2, s < 1/(2R) with R the half extent of
+    the points).  The bound is that gain times the FP32 kernel-sum tolerance
+    1e-5 of the largest a_i (K alpha_t)_i."""
+    cfg = workloads.gmm_3d()
+    prm = nfs.Params(d=3, eps=cfg["eps"], N=cfg["N"], m=cfg["m"], precision="fp32")
+    x, p, y, pt = T(cfg["x"]), T(cfg["p"]), T(cfg["y"]), T(cfg["pt"])
+    res = nfs.sinkhorn(prm, x, p, y, pt, 10)
+    a, at = res.alpha.cpu().numpy(), res.alpha_t.cpu().numpy()
+    rows = np.random.default_rng(12).choice(cfg["y"].shape[0], size=256, replace=False)
+    check_last_half_step(cfg["x"], cfg["y"], cfg["pt"], a, at, 2, cfg["eps"], rows)
+    xr = np.random.default_rng(13).choice(cfg["x"].shape[0], size=128, replace=False)
+    ref = a[xr, None] * direct.grad_rows(cfg["x"], cfg["y"], at, 2, cfg["eps"], rows=xr)
+    size = np.max(a[xr] * direct.kv(cfg["x"], cfg["y"], at, 2, cfg["eps"], rows=xr))
+    both = np.concatenate([cfg["x"], cfg["y"]])
+    R = 0.5 * np.max(both.max(axis=0) - both.min(axis=0))
+    gain = np.pi * cfg["N"] / (2.0 * R)
+    gx32, _ = nfs.sinkhorn_grad(prm, x, p, y, pt, res.alpha, res.alpha_t, want_mu=False)
+    assert np.max(np.abs(gx32.cpu().numpy()[xr] - ref)) <= 1e-5 * gain * size
+    prm64 = nfs.Params(d=3, eps=cfg["eps"], N=cfg["N"], m=cfg["m"], precision="fp64")
+    gx64, _ = nfs.sinkhorn_grad(prm64, x, p, y, pt, res.alpha, res.alpha_t, want_mu=False)
+    assert np.max(np.abs(gx64.cpu().numpy()[xr] - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_ball_shell_r1_full_size_sampled_parity():
+    """Ball against shell, 4e6 points per cloud, Euclidean cost (r = 1),
+    N = 128, m = 6, eps = 0.02, FP32 with the default near field: 3 iterations."""
+    cfg = workloads.ball_shell_3d()
+    prm = nfs.Params(d=3, r=1, eps=cfg["eps"], N=cfg["N"], m=cfg["m"], precision="fp32")
+    res = nfs.sinkhorn(prm, T(cfg["x"]), T(cfg["p"]), T(cfg["y"]), T(cfg["pt"]), 3)
+    rows = np.random.default_rng(14).choice(cfg["y"].shape[0], size=128, replace=False)
+    check_last_half_step(cfg["x"], cfg["y"], cfg["pt"], res.alpha.cpu().numpy(), res.alpha_t.cpu().numpy(),
+                         1, cfg["eps"], rows)
+
+
+def test_batched_full_size_sampled_parity():
+    """512 problems (sizes 1e3..2e5, eps 0.005..0.05, N = 256, m = 6), FP32
+    batch, 10 iterations; 12 problems with positive sums checked on 64 sampled
+    targets each.  Problems whose FP32 sums hit t <= 0 report it in n_nonpos
+    (they are the ones NFS_AUTO promotes); every other problem must end with
+    positive, finite scalings."""
+    cfg = workloads.batched_2d()
+    probs = cfg["problems"]
+    prm = nfs.Params(d=2, eps=1.0, N=cfg["N"], m=cfg["m"], precision="fp32")
+    res = nfs.batch_sinkhorn(prm, [T(q["x"]) for q in probs], [T(q["p"]) for q in probs],
+                             [T(q["y"]) for q in probs], [T(q["pt"]) for q in probs],
+                             [q["eps"] for q in probs], 10, check=False)
+    ok = [b for b, r in enumerate(res) if r.n_nonpos == 0]
+    assert len(ok) >= 480
+    for b, r in enumerate(res):
+        at = r.alpha_t.cpu().numpy()
+        if r.n_nonpos == 0:
+            assert np.all(at > 0) and np.all(np.isfinite(at))
+    rng = np.random.default_rng(15)
+    for b in rng.choice(ok, size=12, replace=False):
+        q, r = probs[b], res[b]
+        rows = rng.choice(q["y"].shape[0], size=64, replace=False)
+        check_last_half_step(q["x"], q["y"], q["pt"], r.alpha.cpu().numpy(), r.alpha_t.cpu().numpy(), 2,
+                             q["eps"], rows)
