@@ -218,3 +218,114 @@ def sinkhorn_divergence(x, p, y, pt, r, eps, iters):
     s_xx = solve(x, p, x, p, r, eps, iters)["cost"]
     s_yy = solve(y, pt, y, pt, r, eps, iters)["cost"]
     return dict(sd=s_xy - 0.5 * s_xx - 0.5 * s_yy, cost_xy=s_xy, cost_xx=s_xx, cost_yy=s_yy)
+
+
+# ---------------------------------------------------------------------------
+# Log-domain Sinkhorn (Algorithm 2, dense; Algorithm 4 computes the same sums
+# by fast summation).
+#
+# Reading.  Both algorithms enter the potentials into the sums through
+# exp(gamma_j/eps - 1/2) and exp(beta_i/eps - 1/2), and their result is the
+# dual of eq. (14) in potentials,
+#   s = sum p beta + sum pt gamma - eps sum_ij exp((beta_i + gamma_j - c_ij)/eps - 1).
+# That dual is maximized over beta_i exactly when
+#   exp(beta_i/eps - 1/2) sum_j k_ij exp(gamma_j/eps - 1/2) = p_i,
+# i.e. beta_i = eps (log p_i - log t_i) + eps/2.  The printed updates omit the
+# eps/2; with it, alpha = exp(beta/eps - 1/2) and alpha_t = exp(gamma/eps - 1/2)
+# are exactly the scalings of Algorithm 1 and the printed result equals the
+# Algorithm 3 result.  Without it, the iterates reach a plan of mass e^{-1/2}
+# and the result formula is off by a multiple of eps.
+# ---------------------------------------------------------------------------
+def _logsumexp(z, axis):
+    """log sum exp(z) along ``axis``, shifted by the maximum (the log-sum-exp
+    step the log-domain algorithm relies on); -inf where every entry is -inf."""
+    m = np.max(z, axis=axis, keepdims=True)
+    m = np.where(np.isfinite(m), m, 0.0)
+    with np.errstate(divide="ignore"):
+        return np.squeeze(m, axis=axis) + np.log(np.sum(np.exp(z - m), axis=axis))
+
+
+def _log_or_neg_inf(p):
+    with np.errstate(divide="ignore"):
+        return np.where(p > 0, np.log(np.where(p > 0, p, 1.0)), -np.inf)
+
+
+def log_dual_value(C, beta, gamma, p, pt, eps):
+    """Dual of eq. (14) in potentials (the result of Algorithm 2):
+    sum p beta + sum pt gamma - eps sum_ij exp((beta_i + gamma_j - c_ij)/eps - 1)."""
+    z = (beta[:, None] + gamma[None, :] - C) / eps - 1.0
+    mass = float(np.exp(_logsumexp(z.ravel(), axis=0)))
+    return (float(np.sum(p[p > 0] * beta[p > 0])) + float(np.sum(pt[pt > 0] * gamma[pt > 0]))
+            - eps * mass)
+
+
+def log_plan_marginals(C, beta, gamma, eps):
+    """Row and column sums of pi_ij = exp((beta_i + gamma_j - c_ij)/eps - 1)."""
+    z = (beta[:, None] + gamma[None, :] - C) / eps - 1.0
+    return np.exp(_logsumexp(z, axis=1)), np.exp(_logsumexp(z, axis=0))
+
+
+def sinkhorn_log(C, p, pt, eps, iters, gamma0=None, record=False):
+    """Algorithm 2 (log-domain stabilized Sinkhorn) for a fixed number of
+    iterations, with the reading above for the update.
+
+    Potentials start at zero (gamma0 replaces the starting gamma).  One
+    iteration is the odd half-step
+        log t_i = LSE_j (gamma_j/eps - 1/2 - c_ij/eps),
+        beta_i  = eps (log p_i - log t_i) + eps/2,
+    then the even half-step with the roles of (beta, p) and (gamma, pt)
+    swapped.  A zero weight gives the potential -inf.  Returns the potentials,
+    log tt of the last even half-step and, with ``record``, the dual before
+    and after every half-step with the Kullback-Leibler term of Lemma 2.4.
+    """
+    C = np.asarray(C, dtype=np.float64)
+    p = np.asarray(p, dtype=np.float64)
+    pt = np.asarray(pt, dtype=np.float64)
+    n, nt = C.shape
+    beta = np.zeros(n)
+    gamma = np.zeros(nt) if gamma0 is None else np.array(gamma0, dtype=np.float64)
+    logp, logpt = _log_or_neg_inf(p), _log_or_neg_inf(pt)
+    hist = []
+    logt = logtt = None
+    for _ in range(iters):
+        logt = _logsumexp((gamma[None, :] - C) / eps - 0.5, axis=1)
+        if record:
+            rows, _ = log_plan_marginals(C, beta, gamma, eps)
+            hist.append(dict(kind="row", kl=kl(p, rows), dual_before=log_dual_value(C, beta, gamma, p, pt, eps)))
+        beta = eps * (logp - logt) + 0.5 * eps
+        if record:
+            hist[-1]["dual_after"] = log_dual_value(C, beta, gamma, p, pt, eps)
+        logtt = _logsumexp((beta[:, None] - C) / eps - 0.5, axis=0)
+        if record:
+            _, cols = log_plan_marginals(C, beta, gamma, eps)
+            hist.append(dict(kind="col", kl=kl(pt, cols), dual_before=log_dual_value(C, beta, gamma, p, pt, eps)))
+        gamma = eps * (logpt - logtt) + 0.5 * eps
+        if record:
+            hist[-1]["dual_after"] = log_dual_value(C, beta, gamma, p, pt, eps)
+    return dict(beta=beta, gamma=gamma, logt=logt, logtt=logtt, hist=hist)
+
+
+def solve_log(x, p, y, pt, r, eps, iters, gamma0=None):
+    """Algorithm 2 for ``iters`` iterations plus its read-outs.
+
+    cost: sum p beta + sum pt gamma - eps sum_j tt_j exp(gamma_j/eps - 1/2)
+    with tt the last even half-step's sums (the result of Algorithm 4);
+    cost_upper: cost + eps (H(p) + H(pt)) (Section 3.2);
+    marg_err_row / marg_err_col: the two norms of eq. (Error) for the plan
+    exp((beta_i + gamma_j - c_ij)/eps - 1).
+    """
+    p = np.asarray(p, dtype=np.float64)
+    pt = np.asarray(pt, dtype=np.float64)
+    C = cost_matrix(x, y, r)
+    out = sinkhorn_log(C, p, pt, eps, iters, gamma0=gamma0)
+    beta, gamma = out["beta"], out["gamma"]
+    if iters > 0:
+        mass = float(np.sum(np.exp(out["logtt"] + gamma / eps - 0.5)))
+    else:
+        mass = float(np.sum(log_plan_marginals(C, beta, gamma, eps)[0]))
+    s = float(np.sum(p[p > 0] * beta[p > 0])) + float(np.sum(pt[pt > 0] * gamma[pt > 0])) - eps * mass
+    rows, cols = log_plan_marginals(C, beta, gamma, eps)
+    e_row = float(np.linalg.norm(rows - p))
+    e_col = float(np.linalg.norm(cols - pt))
+    return dict(beta=beta, gamma=gamma, cost=s, cost_upper=cost_upper_bound(s, p, pt, eps),
+                marg_err_row=e_row, marg_err_col=e_col, marg_err=e_row + e_col)

@@ -351,3 +351,93 @@ def test_sinkhorn_divergence_tends_to_wasserstein_1d():
     gaps = [abs(sd.sinkhorn_divergence(x, p, y, p, 2, eps, 20000)["sd"] - w2) for eps in (0.02, 0.005, 0.0015)]
     assert gaps[0] > gaps[1] > gaps[2]
     assert gaps[2] <= 0.02 * w2
+
+
+# ---------------------------------------------------------------- log-domain (Algorithms 2 and 4)
+def test_log_domain_single_point_at_underflowing_eps():
+    """n = nt = 1 with c/eps near 950: the Gibbs kernel underflows to zero in
+    FP64 (Algorithm 1 divides by zero), while the log-domain result is c."""
+    x = np.array([[0.1, -0.2]])
+    y = np.array([[-0.05, 0.07]])
+    c = float(np.sum((x - y) ** 2))
+    eps = 1e-4
+    assert sd.gibbs_kernel(x, y, 2, eps)[0, 0] == 0.0
+    out = sd.solve_log(x, np.ones(1), y, np.ones(1), 2, eps, iters=3)
+    assert abs(out["cost"] - c) <= 1e-14 * max(1.0, c)
+    # the plan exp((beta + gamma - c)/eps - 1) carries the rounding of an
+    # exponent of size c/eps
+    assert out["marg_err"] <= 10 * 2.0 ** -52 * (c / eps)
+
+
+@pytest.mark.parametrize("r", [1, 2])
+def test_log_domain_equals_algorithm_1(r):
+    """With alpha_t0 = exp(gamma0/eps - 1/2) Algorithm 1 produces the same
+    couplings: beta = eps (log alpha + 1/2), gamma = eps (log alpha_t + 1/2),
+    and the two results (Algorithm 3 read-out, Algorithm 4 result) agree."""
+    n, nt, eps, iters = 40, 33, 0.05, 7
+    x, y = _cloud(n, 2, 3), _cloud(nt, 2, 4)
+    p, pt = workloads.dirichlet_weights(n, 5), workloads.dirichlet_weights(nt, 6)
+    g0 = np.random.default_rng(9).normal(0.0, 0.02, nt)
+    lg = sd.solve_log(x, p, y, pt, r, eps, iters, gamma0=g0)
+    a1 = sd.solve(x, p, y, pt, r, eps, iters, alpha_t0=np.exp(g0 / eps - 0.5))
+    assert np.max(np.abs(lg["beta"] - eps * (np.log(a1["alpha"]) + 0.5))) <= 1e-14
+    assert np.max(np.abs(lg["gamma"] - eps * (np.log(a1["alpha_t"]) + 0.5))) <= 1e-14
+    assert abs(lg["cost"] - a1["cost"]) <= 1e-14
+    assert abs(lg["marg_err_row"] - a1["marg_err_row"]) <= 1e-13
+    assert abs(lg["cost_upper"] - a1["cost_upper"]) <= 1e-14
+
+
+def test_log_domain_dual_ascent_equals_kl():
+    """Lemma 2.4 in potentials: from the second half-step on, each half-step
+    raises the dual of eq. (14) by exactly eps*KL(target | current marginal)."""
+    n, nt, eps = 40, 33, 0.05
+    x, y = _cloud(n, 2, 3), _cloud(nt, 2, 4)
+    p, pt = workloads.dirichlet_weights(n, 5), workloads.dirichlet_weights(nt, 6)
+    out = sd.sinkhorn_log(sd.cost_matrix(x, y, 2), p, pt, eps, 6, record=True)
+    for step in out["hist"][1:]:
+        gain = step["dual_after"] - step["dual_before"]
+        assert abs(gain - eps * step["kl"]) <= 1e-13 + 1e-10 * abs(gain)
+        assert gain >= -1e-15
+
+
+def test_log_domain_lemma_2_1_chain_where_the_kernel_underflows():
+    """Lemma 2.1, s <= w_2 <= <pi, C> <= s + eps (H(P) + H(Pt)), on two 1-D
+    clusters a distance 1 apart at eps = 1e-3: every entry of the Gibbs
+    kernel underflows to zero in FP64 (c/eps >= 810), while the part of the
+    cost that decides the coupling, -2 (x - mean x)(y - mean y)/eps, spans
+    only a few units, so the iteration converges in tens of steps.  w_2 is the
+    exact 1-D value from sorting."""
+    rng = np.random.default_rng(17)
+    n, eps = 24, 1e-3
+    x, y = rng.uniform(0.0, 0.1, (n, 1)), rng.uniform(1.0, 1.1, (n, 1))
+    p = np.full(n, 1.0 / n)
+    C = sd.cost_matrix(x, y, 2)
+    assert np.all(np.exp(-C / eps) == 0.0)
+    out = sd.solve_log(x, p, y, p, 2, eps, 200)
+    assert out["marg_err"] <= 10 * 2.0 ** -52 * np.max(C) / eps
+    pi = np.exp((out["beta"][:, None] + out["gamma"][None, :] - C) / eps - 1.0)
+    primal = float(np.sum(pi * C))
+    w2 = float(np.mean((np.sort(x[:, 0]) - np.sort(y[:, 0])) ** 2))
+    assert out["cost"] <= w2 <= primal <= out["cost_upper"]
+
+
+def test_log_domain_planted_mistake_is_caught():
+    """The printed update without the eps/2 reaches a coupling of mass
+    e^(-1/2): the equivalence and Lemma 2.4 pins above reject it."""
+    n, nt, eps = 40, 33, 0.05
+    x, y = _cloud(n, 2, 3), _cloud(nt, 2, 4)
+    p, pt = workloads.dirichlet_weights(n, 5), workloads.dirichlet_weights(nt, 6)
+    C = sd.cost_matrix(x, y, 2)
+    beta, gamma = np.zeros(n), np.zeros(nt)
+    gains = []
+    for _ in range(5):
+        beta = eps * (np.log(p) - sd._logsumexp((gamma[None, :] - C) / eps - 0.5, axis=1))   # planted: no eps/2
+        before = sd.log_dual_value(C, beta, gamma, p, pt, eps)
+        _, cols = sd.log_plan_marginals(C, beta, gamma, eps)
+        logtt = sd._logsumexp((beta[:, None] - C) / eps - 0.5, axis=0)
+        gamma = eps * (np.log(pt) - logtt)
+        gains.append((sd.log_dual_value(C, beta, gamma, p, pt, eps) - before, eps * sd.kl(pt, cols)))
+    assert any(abs(g - e) > 1e-6 for g, e in gains)
+    s_bad = float(p @ beta + pt @ gamma) - eps * float(np.sum(np.exp(logtt + gamma / eps - 0.5)))
+    ref = sd.solve(x, p, y, pt, 2, eps, 5)["cost"]
+    assert abs(s_bad - ref) > 0.1 * eps
