@@ -68,6 +68,10 @@ extern "C" {
 #define NFS_FLAG_TILE_REDUCE 4   /* spread: store each chunk's LDS tile and sum the tiles per
                                     (tile, neighbour) instead of flushing LDS tiles straight
                                     into the grid with global atomics (the default) */
+#define NFS_FLAG_LOG_DOMAIN 8    /* solve in potentials (Algorithm 4): the alpha / alpha_t arguments
+                                    of the solve, batch and solver calls hold beta / gamma instead,
+                                    with alpha = exp(beta/eps - 1/2), alpha_t = exp(gamma/eps - 1/2);
+                                    NFS_FLAG_PRIMAL_COST is ignored (cost_primal = NaN) */
 
 typedef struct nfs_params {
   int32_t d;          /* dimension, 1..3 */
@@ -151,6 +155,30 @@ int nfs_sinkhorn_solve(const nfs_params* prm, const double* x, int64_t n, const 
                        int32_t max_iter, double tol, int32_t warm_start,
                        double* alpha, double* alpha_t, nfs_result* res,
                        void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * NFFT-accelerated log-domain Sinkhorn (Algorithm 4): the same iteration in
+ * the dual potentials, which stay finite where the scalings over- or
+ * underflow.  Equals nfs_sinkhorn_solve with NFS_FLAG_LOG_DOMAIN set.
+ * Potentials enter the fast sums as exp(gamma_j/eps - 1/2) and the update is
+ * beta_i = eps (log mu_i - log t_i) + eps/2.  The printed update lacks the
+ * eps/2; with it the iterates are those of Algorithm 3, and the Algorithm 4
+ * result s = sum mu beta + sum nu gamma - eps sum_j t_j exp(gamma_j/eps - 1/2)
+ * equals the Algorithm 3 result.  Each half-step spreads exp((gamma - max
+ * gamma)/eps) in [0, 1] and returns max beta for the next one.
+ *   beta  (n):  out, final potentials beta (-inf where mu_i = 0).
+ *   gamma (nt): in = starting value when warm_start != 0 (finite; else
+ *               zeros, as in the paper), out = final gamma.
+ *   res: as nfs_sinkhorn_solve, with cost the Algorithm 4 result; cost_primal
+ *        is NaN.
+ * Same workspace size, precision (NFS_AUTO included) and errors as
+ * nfs_sinkhorn_solve; NFS_EINVAL for a non-finite gamma start.
+ */
+int nfs_sinkhorn_solve_log(const nfs_params* prm, const double* x, int64_t n, const double* mu,
+                           const double* y, int64_t nt, const double* nu,
+                           int32_t max_iter, double tol, int32_t warm_start,
+                           double* beta, double* gamma, nfs_result* res,
+                           void* workspace, size_t ws_bytes, void* stream);
 
 /*
  * Persistent solver handle for the same iteration (Algorithm 3): the plan

@@ -9,7 +9,15 @@ enum Epilogue : int {
   EPI_OUT = 0,   // out[perm[q]*stride + comp] = t * scale_vec[q]
   EPI_SINK = 1,  // alpha[q] = p[q]/t, residual and mass reductions (Algorithm 3 half-step)
   EPI_EVAL = 2,  // residual sum (alpha[q] t - p[q])^2 only, no update
+  // Log domain (Algorithm 4): alpha[] holds potentials beta, the source side's
+  // weights were exp((gamma - shift)/eps) with shift = wmul_src[prob], so the
+  // kernel sum is t = exp(shift/eps - 1/2) S with S the interpolated value.
+  EPI_LOGSINK = 3,  // beta[q] = eps (log p[q] - log S + 1) - shift, mass and max reductions
+  EPI_LOGEVAL = 4,  // residual sum (exp((beta[q] + shift)/eps - 1) S - p[q])^2 only, no update
 };
+
+// Per-problem constants of the log domain: leps[2 b] = 1/eps_b, leps[2 b + 1] = eps_b.
+constexpr int kLepsStride = 2;
 
 template <typename R>
 struct SpreadArgs {
@@ -55,7 +63,9 @@ struct InterpArgs {
   WindowConst win;
   const float* __restrict__ wpoly;  // FP32 window polynomials: WindowPoly::c, row-major
   double norm;              // constant factor of the result
-  const double* wmul_src;   // the result is divided by wmul_src[prob] (nullable)
+  const double* wmul_src;   // the result is divided by wmul_src[prob] (nullable); log domain:
+                            // the source potentials' shift
+  const double* leps;       // log domain constants (EPI_LOGSINK / EPI_LOGEVAL)
   int epi;
   // EPI_OUT
   const int* perm;
@@ -73,7 +83,7 @@ struct InterpArgs {
   double* stats;            // per problem (stride 8): residual^2 sum (EPI_EVAL only), mass sum, max alpha,
                             // count(t <= 0),
                             // running count
-  double* wmul_next;        // per problem, receives 1/max alpha (nullable)
+  double* wmul_next;        // per problem, receives 1/max alpha (log domain: max beta) (nullable)
 };
 
 // Near-field correction for r = 1 (kernel exp(-|z|/eps) regularized inside
@@ -256,11 +266,21 @@ struct ReadoutArgs {
   const double* a;
   const double* b;
   long n;
+  int logv;  // b holds potentials: sum a b instead of sum a log b
   double* partials;
   unsigned* counter;
   double* out;
 };
 hipError_t launch_readout(const ReadoutArgs& a, hipStream_t st);
+
+// Log-domain weights of a sorted cloud, one workgroup per chunk:
+//   out[q] = exp((pot[q] - shift[prob]) / eps_prob), prob = chunks[blockIdx].prob,
+// in [0, 1] when shift is the problem's largest potential (-inf gives 0).
+hipError_t launch_logweights(const Chunk* chunks, int nchunks, const double* pot, const double* shift,
+                             const double* leps, double* out, hipStream_t st);
+
+// out[0] = max v, out[1] = sum v (non-finite if any entry is), over n values.
+hipError_t launch_maxsum(const double* v, long n, double* partials, unsigned* counter, double* out, hipStream_t st);
 
 // grad_mu: out[perm[q]] = eps*log(alpha_s[q]) - shift, with shift = eps*mean(log alpha) read from device
 hipError_t launch_gradmu(const double* alpha, long n, double eps, double* partials, unsigned* counter,

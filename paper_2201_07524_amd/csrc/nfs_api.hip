@@ -176,6 +176,7 @@ struct Work {
   double* st_cost = nullptr;  // B x 4
   double* wmul_x = nullptr;   // B
   double* wmul_y = nullptr;   // B
+  double* leps = nullptr;     // B x kLepsStride: log-domain constants {1/eps, eps}
   double* st_box = nullptr;   // B x 20 + 20: per problem, x box at 0, y weight box at 10
   double* tmp = nullptr;
   int r = 2;
@@ -278,6 +279,7 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
   w.st_cost = cv.take<double>(size_t(B) * 4);
   w.wmul_x = cv.take<double>(B);
   w.wmul_y = cv.take<double>(B);
+  w.leps = cv.take<double>(size_t(B) * kLepsStride);
   w.st_box = cv.take<double>(size_t(B) * 20 + 20);
   w.tmp = cv.take<double>(size_t(std::max(nA, nB)) * std::max(d, 1));
   w.r = p->r;
@@ -697,20 +699,32 @@ static hipError_t near_field(Work<R>& w, const CloudBuf<R>& src, const CloudBuf<
 
 // One Sinkhorn half-step for every problem: spread the scalings of `src`,
 // transform, and update (or evaluate) the scalings of `tgt` (eq. (S1) via
-// eq. (fastsum)).
+// eq. (fastsum)).  In the log domain (EPI_LOGSINK / EPI_LOGEVAL, Algorithm 4)
+// src.w1s and tgt.w1s hold potentials, wmul_* their per-problem maxima, and
+// the spread weights exp((gamma - max gamma)/eps) go through w.tmp.
 template <typename R>
 static hipError_t half_step(Work<R>& w, CloudBuf<R>& src, CloudBuf<R>& tgt, double* wmul_src, double* wmul_tgt,
                             double* stats, int epi, hipStream_t st) {
+  const bool logd = epi == EPI_LOGSINK || epi == EPI_LOGEVAL;
+  const double* wv = src.w1s;
+  const double* wm = wmul_src;
   hipError_t e;
-  if ((e = spread(w, src, src.w1s, wmul_src, 1.0, st)) != hipSuccess) return e;
+  if (logd) {
+    if ((e = launch_logweights(src.chunks, src.nchunks, src.w1s, wmul_src, w.leps, w.tmp, st)) != hipSuccess)
+      return e;
+    wv = w.tmp;
+    wm = nullptr;
+  }
+  if ((e = spread(w, src, wv, wm, 1.0, st)) != hipSuccess) return e;
   if ((e = fft_chain(w, w.dtab, -1, st)) != hipSuccess) return e;
-  if (w.r == 1 && (e = near_field(w, src, tgt, src.w1s, wmul_src, 1.0, st)) != hipSuccess) return e;
+  if (w.r == 1 && (e = near_field(w, src, tgt, wv, wm, 1.0, st)) != hipSuccess) return e;
   InterpArgs<R> ia = interp_args(w, tgt, epi, wmul_src);
   if (w.r == 1) ia.nf = w.nf;
+  ia.leps = w.leps;
   ia.p = tgt.w0s;
   ia.alpha = tgt.w1s;
   ia.stats = stats;
-  ia.wmul_next = epi == EPI_SINK ? wmul_tgt : nullptr;
+  ia.wmul_next = (epi == EPI_SINK || epi == EPI_LOGSINK) ? wmul_tgt : nullptr;
   return launch_interp(ia, tgt.nchunks, st);
 }
 
@@ -952,17 +966,81 @@ struct Solver : SolverBase {
   hipEvent_t ev = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  bool logd = false;  // log domain (Algorithm 4): w1s holds potentials, wmul_* their maxima
+
+  int sink() const { return logd ? EPI_LOGSINK : EPI_SINK; }
+  int eval() const { return logd ? EPI_LOGEVAL : EPI_EVAL; }
 
   hipError_t iteration(hipStream_t s) {
-    hipError_t e = half_step(w, w.Y, w.X, w.wmul_y, w.wmul_x, w.st_row, EPI_SINK, s);
+    hipError_t e = half_step(w, w.Y, w.X, w.wmul_y, w.wmul_x, w.st_row, sink(), s);
     if (e != hipSuccess) return e;
-    return half_step(w, w.X, w.Y, w.wmul_x, w.wmul_y, w.st_col, EPI_SINK, s);
+    return half_step(w, w.X, w.Y, w.wmul_x, w.wmul_y, w.st_col, sink(), s);
+  }
+
+  // Starting scalings (Algorithm 3): alpha = 1; alpha_t = 1, or the caller's
+  // positive starting value (already sorted into Y.w1s by the plan); wmul_*
+  // normalize the spread weights by their maximum.
+  int start_scalings(int B, const std::vector<long>& oy, const double* alpha_t0, hipStream_t st) {
+    NFS_HIP(launch_fill_double(w.X.w1s, w.X.n, 1.0, st));
+    NFS_HIP(launch_fill_double(w.wmul_x, B, 1.0, st));
+    if (!alpha_t0) {
+      NFS_HIP(launch_fill_double(w.Y.w1s, w.Y.n, 1.0, st));
+      NFS_HIP(launch_fill_double(w.wmul_y, B, 1.0, st));
+      return NFS_OK;
+    }
+    for (int b = 0; b < B; ++b)
+      NFS_TRY(box_launch(w.st_box + 20 * b, w.partials, w.ct_misc, p.d, nullptr, 0, nullptr, 0, alpha_t0 + oy[b],
+                         oy[b + 1] - oy[b], st));
+    std::vector<double> box(size_t(B) * 20), wm(B);
+    NFS_HIP(hipMemcpyAsync(box.data(), w.st_box, sizeof(double) * box.size(), hipMemcpyDeviceToHost, st));
+    NFS_HIP(hipStreamSynchronize(st));
+    for (int b = 0; b < B; ++b) {
+      if (!(box[20 * b + 7] > 0.0) || !std::isfinite(box[20 * b + 6]))
+        return fail(NFS_EINVAL, "warm-start alpha_t must be positive and finite");
+      wm[b] = 1.0 / box[20 * b + 6];
+    }
+    NFS_HIP(hipMemcpyAsync(w.wmul_y, wm.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
+    NFS_HIP(hipStreamSynchronize(st));  // wm is read by the copy
+    return NFS_OK;
+  }
+
+  // Starting potentials (Algorithm 4): beta = 0; gamma = 0, or the caller's
+  // finite starting value (sorted into Y.w1s by the plan); wmul_* hold each
+  // problem's largest potential, the shift of the spread weights.
+  int start_log(int B, const std::vector<long>& oy, const double* gamma0, hipStream_t st) {
+    std::vector<double> le(size_t(B) * kLepsStride), shift(B, 0.0);
+    for (int b = 0; b < B; ++b) {
+      le[kLepsStride * b] = 1.0 / eps[b];
+      le[kLepsStride * b + 1] = eps[b];
+    }
+    NFS_HIP(launch_fill_double(w.X.w1s, w.X.n, 0.0, st));
+    NFS_HIP(launch_fill_double(w.wmul_x, B, 0.0, st));
+    if (!gamma0) {
+      NFS_HIP(launch_fill_double(w.Y.w1s, w.Y.n, 0.0, st));
+    } else {
+      std::vector<double> ms(size_t(B) * 2);
+      for (int b = 0; b < B; ++b)
+        NFS_HIP(launch_maxsum(gamma0 + oy[b], oy[b + 1] - oy[b], w.partials, w.ct_misc, w.st_box + 2 * b, st));
+      NFS_HIP(hipMemcpyAsync(ms.data(), w.st_box, sizeof(double) * ms.size(), hipMemcpyDeviceToHost, st));
+      NFS_HIP(hipStreamSynchronize(st));
+      for (int b = 0; b < B; ++b) {
+        if (!std::isfinite(ms[2 * b]) || !std::isfinite(ms[2 * b + 1]))
+          return fail(NFS_EINVAL, "warm-start gamma must be finite");
+        shift[b] = ms[2 * b];
+      }
+    }
+    NFS_HIP(hipMemcpyAsync(w.wmul_y, shift.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
+    NFS_HIP(hipMemcpyAsync(w.leps, le.data(), sizeof(double) * le.size(), hipMemcpyHostToDevice, st));
+    // the host vectors above are read by the copies: wait before they go
+    NFS_HIP(hipStreamSynchronize(st));
+    return NFS_OK;
   }
 
   int create(const nfs_params* prm, int B, const int64_t* n, const int64_t* nt, const double* eps_in,
              const double* x, const double* mu, const double* y, const double* nu, const double* alpha_t0, void* ws,
              size_t wsb, hipStream_t caller) {
     p = *prm;
+    logd = (p.flags & NFS_FLAG_LOG_DOMAIN) != 0;
     eps.assign(eps_in, eps_in + B);
     std::vector<long> ox(B + 1, 0), oy(B + 1, 0);
     for (int b = 0; b < B; ++b) {
@@ -976,24 +1054,10 @@ struct Solver : SolverBase {
     w.Y.off = oy;
     hipStream_t st = caller;
     NFS_TRY(plan_sinkhorn(w, &p, eps.data(), x, mu, y, nu, nullptr, alpha_t0, st));
-    NFS_HIP(launch_fill_double(w.X.w1s, w.X.n, 1.0, st));
-    NFS_HIP(launch_fill_double(w.wmul_x, B, 1.0, st));
-    if (!alpha_t0) {
-      NFS_HIP(launch_fill_double(w.Y.w1s, w.Y.n, 1.0, st));
-      NFS_HIP(launch_fill_double(w.wmul_y, B, 1.0, st));
+    if (logd) {
+      NFS_TRY(start_log(B, oy, alpha_t0, st));
     } else {
-      for (int b = 0; b < B; ++b)
-        NFS_TRY(box_launch(w.st_box + 20 * b, w.partials, w.ct_misc, p.d, nullptr, 0, nullptr, 0, alpha_t0 + oy[b],
-                           oy[b + 1] - oy[b], st));
-      std::vector<double> box(size_t(B) * 20), wm(B);
-      NFS_HIP(hipMemcpyAsync(box.data(), w.st_box, sizeof(double) * box.size(), hipMemcpyDeviceToHost, st));
-      NFS_HIP(hipStreamSynchronize(st));
-      for (int b = 0; b < B; ++b) {
-        if (!(box[20 * b + 7] > 0.0) || !std::isfinite(box[20 * b + 6]))
-          return fail(NFS_EINVAL, "warm-start alpha_t must be positive and finite");
-        wm[b] = 1.0 / box[20 * b + 6];
-      }
-      NFS_HIP(hipMemcpyAsync(w.wmul_y, wm.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
+      NFS_TRY(start_scalings(B, oy, alpha_t0, st));
     }
     NFS_HIP(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
     NFS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -1047,7 +1111,7 @@ struct Solver : SolverBase {
   // Largest row residual over the problems.
   int residual(double* err_row, hipStream_t caller) override {
     NFS_TRY(enter(caller));
-    NFS_HIP(half_step(w, w.Y, w.X, w.wmul_y, w.wmul_x, w.st_eval, EPI_EVAL, gs));
+    NFS_HIP(half_step(w, w.Y, w.X, w.wmul_y, w.wmul_x, w.st_eval, eval(), gs));
     std::vector<double> h(size_t(w.B) * 8);
     NFS_HIP(hipMemcpyAsync(h.data(), w.st_eval, sizeof(double) * h.size(), hipMemcpyDeviceToHost, gs));
     NFS_HIP(hipStreamSynchronize(gs));
@@ -1070,12 +1134,21 @@ struct Solver : SolverBase {
         CloudBuf<R>& tgt = h == 0 ? w.X : w.Y;
         double* ws_ = h == 0 ? w.wmul_y : w.wmul_x;
         double* wt_ = h == 0 ? w.wmul_x : w.wmul_y;
-        NFS_HIP(spread(w, src, src.w1s, ws_, 1.0, gs));
+        // log domain: the weight pass is timed with the spread
+        const double* wv = src.w1s;
+        const double* wm = ws_;
+        if (logd) {
+          NFS_HIP(launch_logweights(src.chunks, src.nchunks, src.w1s, ws_, w.leps, w.tmp, gs));
+          wv = w.tmp;
+          wm = nullptr;
+        }
+        NFS_HIP(spread(w, src, wv, wm, 1.0, gs));
         NFS_HIP(hipEventRecord(evs[ie++], gs));
         NFS_HIP(fft_chain(w, w.dtab, -1, gs));
         NFS_HIP(hipEventRecord(evs[ie++], gs));
-        if (w.r == 1) NFS_HIP(near_field(w, src, tgt, src.w1s, ws_, 1.0, gs));
-        InterpArgs<R> ia = interp_args(w, tgt, EPI_SINK, ws_);
+        if (w.r == 1) NFS_HIP(near_field(w, src, tgt, wv, wm, 1.0, gs));
+        InterpArgs<R> ia = interp_args(w, tgt, sink(), ws_);
+        ia.leps = w.leps;
         if (w.r == 1) ia.nf = w.nf;
         ia.p = tgt.w0s;
         ia.alpha = tgt.w1s;
@@ -1119,19 +1192,21 @@ struct Solver : SolverBase {
     hipStream_t st = gs;
     const int B = w.B;
     // row residual of eq. (Error): one extra product K alpha_t
-    NFS_HIP(half_step(w, w.Y, w.X, w.wmul_y, w.wmul_x, w.st_eval, EPI_EVAL, st));
+    NFS_HIP(half_step(w, w.Y, w.X, w.wmul_y, w.wmul_x, w.st_eval, eval(), st));
     std::vector<double> ev_row(size_t(B) * 8), ev_col(size_t(B) * 8);
     NFS_HIP(hipMemcpyAsync(ev_row.data(), w.st_eval, sizeof(double) * ev_row.size(), hipMemcpyDeviceToHost, st));
-    NFS_HIP(half_step(w, w.X, w.Y, w.wmul_x, w.wmul_y, w.st_eval, EPI_EVAL, st));
+    NFS_HIP(half_step(w, w.X, w.Y, w.wmul_x, w.wmul_y, w.st_eval, eval(), st));
     NFS_HIP(hipMemcpyAsync(ev_col.data(), w.st_eval, sizeof(double) * ev_col.size(), hipMemcpyDeviceToHost, st));
     for (int b = 0; b < B; ++b) {
       const long ox = w.X.off[b], oy = w.Y.off[b];
-      ReadoutArgs ra{w.X.w0s + ox, w.X.w1s + ox, w.X.off[b + 1] - ox, w.partials, w.ct_misc + 1, w.st_rdx + 4 * b};
+      ReadoutArgs ra{w.X.w0s + ox, w.X.w1s + ox, w.X.off[b + 1] - ox, int(logd), w.partials, w.ct_misc + 1,
+                     w.st_rdx + 4 * b};
       NFS_HIP(launch_readout(ra, st));
-      ReadoutArgs rb{w.Y.w0s + oy, w.Y.w1s + oy, w.Y.off[b + 1] - oy, w.partials, w.ct_misc + 1, w.st_rdy + 4 * b};
+      ReadoutArgs rb{w.Y.w0s + oy, w.Y.w1s + oy, w.Y.off[b + 1] - oy, int(logd), w.partials, w.ct_misc + 1,
+                     w.st_rdy + 4 * b};
       NFS_HIP(launch_readout(rb, st));
     }
-    const bool primal = (p.flags & NFS_FLAG_PRIMAL_COST) && p.r == 2;
+    const bool primal = (p.flags & NFS_FLAG_PRIMAL_COST) && p.r == 2 && !logd;
     if (primal) {
       NFS_HIP(spread(w, w.Y, w.Y.w1s, w.wmul_y, 1.0, st));
       NFS_HIP(fft_chain(w, w.dtab2, -1, st));
@@ -1141,7 +1216,8 @@ struct Solver : SolverBase {
       NFS_HIP(launch_interp(ia, w.X.nchunks, st));
       for (int b = 0; b < B; ++b) {
         const long ox = w.X.off[b];
-        ReadoutArgs rc{w.tmp + ox, w.tmp + ox, w.X.off[b + 1] - ox, w.partials, w.ct_misc + 1, w.st_cost + 4 * b};
+        ReadoutArgs rc{w.tmp + ox, w.tmp + ox, w.X.off[b + 1] - ox, 0, w.partials, w.ct_misc + 1,
+                       w.st_cost + 4 * b};
         NFS_HIP(launch_readout(rc, st));
       }
     }
@@ -1164,9 +1240,10 @@ struct Solver : SolverBase {
       r.precision_used = p.precision;
       r.scale = w.sc[b].scale;
       r.kernel_err = w.sc[b].kernel_err;
-      // s = eps (1 + sum p log a + sum pt log at - sum_j at_j tt_j), tt the last K^T alpha
+      // s = eps (1 + sum p log a + sum pt log at - sum_j at_j tt_j), tt the last K^T alpha;
+      // log domain (Algorithm 4 result): s = sum p beta + sum pt gamma - eps sum_j at_j tt_j
       const double mass = done > 0 ? col[8 * b + 1] : ev_row[8 * b + 1];
-      r.cost = e * (1.0 + rdx[4 * b + 0] + rdy[4 * b + 0] - mass);
+      r.cost = logd ? rdx[4 * b + 0] + rdy[4 * b + 0] - e * mass : e * (1.0 + rdx[4 * b + 0] + rdy[4 * b + 0] - mass);
       r.cost_upper = r.cost - e * (rdx[4 * b + 1] + rdy[4 * b + 1]);
       r.cost_primal = primal ? cost[4 * b + 2] : NAN;
       r.marg_err_row = std::sqrt(ev_row[8 * b + 0]);
@@ -1451,6 +1528,18 @@ int nfs_sinkhorn_solve(const nfs_params* prm, const double* x, int64_t n, const 
   const int rc = run_solver(s, max_iter, tol, alpha, alpha_t, res, st);
   delete s;
   return rc;
+}
+
+int nfs_sinkhorn_solve_log(const nfs_params* prm, const double* x, int64_t n, const double* mu, const double* y,
+                           int64_t nt, const double* nu, int32_t max_iter, double tol, int32_t warm_start,
+                           double* beta, double* gamma, nfs_result* res, void* workspace, size_t ws_bytes,
+                           void* stream) {
+  g_err.clear();
+  if (!prm) return fail(NFS_EINVAL, "params is NULL");
+  nfs_params q = *prm;
+  q.flags |= NFS_FLAG_LOG_DOMAIN;
+  return nfs_sinkhorn_solve(&q, x, n, mu, y, nt, nu, max_iter, tol, warm_start, beta, gamma, res, workspace,
+                            ws_bytes, stream);
 }
 
 int nfs_solver_create(const nfs_params* prm, const double* x, int64_t n, const double* mu, const double* y,

@@ -637,11 +637,12 @@ __device__ Red4 block_reduce(Red4 v, Red4* sh) {
 
 // Final reduction by the last workgroup to finish (ticket counter).  Writes
 // stats[0..3] = {sum s0, sum s1, max, count}, adds count to stats[4], and, if wmul_next is set,
-// wmul_next = 1/max (the normalization of the next spread's weights).
+// wmul_next = 1/max (the normalization of the next spread's weights), or in the
+// log domain the max itself (the shift of the next spread's potentials).
 // The chunks of one problem are [c0, c1); the last of them to finish reduces
 // that problem's partials.
 __device__ void finish_reduce(Red4 mine, Red4* sh, double* partials, unsigned* counter, double* stats,
-                              double* wmul_next, int c0, int c1) {
+                              double* wmul_next, int c0, int c1, bool logd) {
   __shared__ bool last;
   if (threadIdx.x == 0) {
     partials[4 * blockIdx.x + 0] = mine.s0;
@@ -655,7 +656,7 @@ __device__ void finish_reduce(Red4 mine, Red4* sh, double* partials, unsigned* c
   __syncthreads();
   if (!last) return;
   __threadfence();
-  Red4 v{0.0, 0.0, 0.0, 0.0};
+  Red4 v{0.0, 0.0, logd ? -INFINITY : 0.0, 0.0};
   const volatile double* pv = partials;
   for (int b = c0 + threadIdx.x; b < c1; b += kBlock) {
     Red4 w{pv[4 * b + 0], pv[4 * b + 1], pv[4 * b + 2], pv[4 * b + 3]};
@@ -669,7 +670,12 @@ __device__ void finish_reduce(Red4 mine, Red4* sh, double* partials, unsigned* c
     stats[2] = r.mx;
     stats[3] = r.cnt;
     stats[4] += r.cnt;  // running count over all launches into this slot
-    if (wmul_next) *wmul_next = (r.mx > 0.0 && r.mx < 1e300) ? 1.0 / r.mx : 1.0;
+    if (wmul_next) {
+      if (logd)
+        *wmul_next = isfinite(r.mx) ? r.mx : 0.0;
+      else
+        *wmul_next = (r.mx > 0.0 && r.mx < 1e300) ? 1.0 / r.mx : 1.0;
+    }
     *counter = 0u;
   }
 }
@@ -761,7 +767,10 @@ __device__ __forceinline__ void interp_run(const R* tile, const InterpArgs<R>& a
   }
 }
 
-template <typename R, int D, int M>
+// LOG: the log-domain epilogues (EPI_LOGSINK / EPI_LOGEVAL), instantiated
+// apart so that their log and exp do not raise the register count of the
+// others.
+template <typename R, int D, int M, bool LOG>
 __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
@@ -797,14 +806,47 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
   }
   __syncthreads();
 
-  const double outmul = a.norm / (a.wmul_src ? a.wmul_src[ch.prob] : 1.0);
-  Red4 acc_red{0.0, 0.0, 0.0, 0.0};
+  constexpr bool logd = LOG;
+  const double outmul = logd ? a.norm : a.norm / (a.wmul_src ? a.wmul_src[ch.prob] : 1.0);
+  // log domain: t = exp(shift/eps - 1/2) S, alpha = exp(beta/eps - 1/2)
+  const double shift = logd ? a.wmul_src[ch.prob] : 0.0;
+  const double linv = logd ? a.leps[kLepsStride * ch.prob] : 0.0;
+  const double leps = logd ? a.leps[kLepsStride * ch.prob + 1] : 0.0;
+  Red4 acc_red{0.0, 0.0, logd ? -INFINITY : 0.0, 0.0};
   // nfq: the point's near-field sum, loaded by the caller before the
   // interpolation (a load inside here lets the compiler hoist it above the
   // tap loop together with the LDS reads, at a large cost in registers)
   auto epilogue = [&](int q, R acc, double nfq) {
     const double t = (double(acc) + nfq) * outmul;
-    if (a.epi == EPI_OUT) {
+    if constexpr (LOG) {
+      if (a.epi == EPI_LOGSINK) {
+        // beta = eps (log p - log t) + eps/2 with log t = shift/eps - 1/2 + log S;
+        // a zero weight, or a sum t <= 0 (counted), gives the potential -inf
+        const double p = a.p[q];
+        double b = -INFINITY;
+        if (p > 0.0) {
+          if (t > 0.0 && isfinite(t)) {
+            b = leps * (log(p) - log(t) + 1.0) - shift;
+            acc_red.mx = fmax(acc_red.mx, b);
+          } else {
+            acc_red.cnt += 1.0;
+          }
+          acc_red.s1 += p;
+        }
+        a.alpha[q] = b;
+      } else {
+        const double p = a.p[q];
+        const double bold = a.alpha[q];
+        const double m = p > 0.0 ? exp((bold + shift) * linv - 1.0) * t : 0.0;
+        const double res = m - p;
+        acc_red.s0 += res * res;
+        if (p > 0.0) {
+          if (!(t > 0.0) || !isfinite(t)) acc_red.cnt += 1.0;
+          acc_red.s1 += m;
+          acc_red.mx = fmax(acc_red.mx, bold);
+        }
+      }
+    } else if (a.epi == EPI_OUT) {
       const double sc = a.scale_vec ? a.scale_vec[q] : 1.0;
       a.out[size_t(a.perm[q]) * a.out_stride + a.out_comp] = t * sc;
     } else if (a.epi == EPI_SINK) {
@@ -820,7 +862,7 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
       } else {
         a.alpha[q] = 0.0;
       }
-    } else {
+    } else if (a.epi == EPI_EVAL) {
       const double p = a.p[q];
       const double aold = a.alpha[q];
       const double res = aold * t - p;
@@ -863,7 +905,7 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
     const Red4 r = block_reduce(acc_red, red_sh);
     const int pb = ch.prob;
     finish_reduce(r, red_sh, a.partials, a.counter + pb, a.stats + 8 * pb, a.wmul_next ? a.wmul_next + pb : nullptr,
-                  a.prob_chunks[pb], a.prob_chunks[pb + 1]);
+                  a.prob_chunks[pb], a.prob_chunks[pb + 1], logd);
   }
 }
 
@@ -874,6 +916,18 @@ size_t tile_bytes(const Geom& geo) {
   for (int c = 1; c < geo.d; ++c) n *= geo.E;
   return n * sizeof(R);
 }
+
+#define NFS_DISPATCH_M_X(D_, R_, KERNEL, X_, ARGS, NBLK, SHM, STREAM)                                        \
+  switch (geo.M) {                                                                                          \
+    case 2: hipLaunchKernelGGL((KERNEL<R_, D_, 2, X_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, ARGS); break; \
+    case 3: hipLaunchKernelGGL((KERNEL<R_, D_, 3, X_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, ARGS); break; \
+    case 4: hipLaunchKernelGGL((KERNEL<R_, D_, 4, X_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, ARGS); break; \
+    case 5: hipLaunchKernelGGL((KERNEL<R_, D_, 5, X_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, ARGS); break; \
+    case 6: hipLaunchKernelGGL((KERNEL<R_, D_, 6, X_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, ARGS); break; \
+    case 7: hipLaunchKernelGGL((KERNEL<R_, D_, 7, X_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, ARGS); break; \
+    case 8: hipLaunchKernelGGL((KERNEL<R_, D_, 8, X_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, ARGS); break; \
+    default: return hipErrorInvalidValue;                                                                   \
+  }
 
 #define NFS_DISPATCH_M(D_, R_, KERNEL, ARGS, NBLK, SHM, STREAM)                                          \
   switch (geo.M) {                                                                                        \
@@ -948,12 +1002,26 @@ hipError_t launch_interp(const InterpArgs<R>& a, int nchunks, hipStream_t st) {
   if (nchunks <= 0) return hipSuccess;
   const Geom& geo = a.geo;
   const size_t shm = tile_bytes<R>(geo);
+  const bool log_epi = a.epi == EPI_LOGSINK || a.epi == EPI_LOGEVAL;
+  if (log_epi && (!a.wmul_src || !a.leps)) return hipErrorInvalidValue;
   if (geo.d == 1) {
-    NFS_DISPATCH_M(1, R, interp_kernel, a, nchunks, shm, st)
+    if (log_epi) {
+      NFS_DISPATCH_M_X(1, R, interp_kernel, true, a, nchunks, shm, st)
+    } else {
+      NFS_DISPATCH_M_X(1, R, interp_kernel, false, a, nchunks, shm, st)
+    }
   } else if (geo.d == 2) {
-    NFS_DISPATCH_M(2, R, interp_kernel, a, nchunks, shm, st)
+    if (log_epi) {
+      NFS_DISPATCH_M_X(2, R, interp_kernel, true, a, nchunks, shm, st)
+    } else {
+      NFS_DISPATCH_M_X(2, R, interp_kernel, false, a, nchunks, shm, st)
+    }
   } else {
-    NFS_DISPATCH_M(3, R, interp_kernel, a, nchunks, shm, st)
+    if (log_epi) {
+      NFS_DISPATCH_M_X(3, R, interp_kernel, true, a, nchunks, shm, st)
+    } else {
+      NFS_DISPATCH_M_X(3, R, interp_kernel, false, a, nchunks, shm, st)
+    }
   }
   return hipGetLastError();
 }

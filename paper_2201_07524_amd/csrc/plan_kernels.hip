@@ -433,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void readout_kernel(ReadoutArgs a) {
   for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < a.n; i += stride) {
     const double x = a.a[i];
     if (x > 0.0) {
-      v[0] += x * log(a.b[i]);
+      v[0] += x * (a.logv ? a.b[i] : log(a.b[i]));
       v[1] += x * log(x);
     }
     v[2] += x;
@@ -443,6 +443,42 @@ __global__ __launch_bounds__(kBlock) void readout_kernel(ReadoutArgs a) {
 
 hipError_t launch_readout(const ReadoutArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(readout_kernel, dim3(256), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+// Log domain: the spread weights exp((pot - shift)/eps) of one chunk per workgroup.
+__global__ __launch_bounds__(kBlock) void logweights_kernel(const Chunk* chunks, const double* pot,
+                                                            const double* shift, const double* leps, double* out) {
+  const Chunk ch = chunks[blockIdx.x];
+  const double sh = shift[ch.prob], inv = leps[kLepsStride * ch.prob];
+  for (int i = threadIdx.x; i < ch.count; i += kBlock) {
+    const int q = ch.start + i;
+    out[q] = exp((pot[q] - sh) * inv);
+  }
+}
+
+hipError_t launch_logweights(const Chunk* chunks, int nchunks, const double* pot, const double* shift,
+                             const double* leps, double* out, hipStream_t st) {
+  if (nchunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(logweights_kernel, dim3(nchunks), dim3(kBlock), 0, st, chunks, pot, shift, leps, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void maxsum_kernel(const double* vals, long n, double* partials,
+                                                        unsigned* counter, double* out) {
+  constexpr int NV = 2;
+  double v[NV] = {-INFINITY, 0.0};
+  const bool is_min[NV] = {false, false}, is_max[NV] = {true, false};
+  const long stride = long(gridDim.x) * kBlock;
+  for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+    v[0] = fmax(v[0], vals[i]);
+    v[1] += vals[i];
+  }
+  grid_reduce_arr<NV>(v, is_min, is_max, partials, counter, out);
+}
+
+hipError_t launch_maxsum(const double* v, long n, double* partials, unsigned* counter, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(maxsum_kernel, dim3(256), dim3(kBlock), 0, st, v, n, partials, counter, out);
   return hipGetLastError();
 }
 

@@ -16,10 +16,11 @@ LIB_PATH = os.path.join(HERE, "lib", "libnfs.so")
 
 NFS_OK, NFS_EINVAL, NFS_EWEIGHTS, NFS_ENONPOS, NFS_EUNSUPPORTED, NFS_EHIP, NFS_EWORKSPACE = range(7)
 NFS_FP64, NFS_FP32, NFS_AUTO = 0, 1, 2
-FLAG_NO_GRAPH, FLAG_PRIMAL_COST, FLAG_TILE_REDUCE = 1, 2, 4
+FLAG_NO_GRAPH, FLAG_PRIMAL_COST, FLAG_TILE_REDUCE, FLAG_LOG_DOMAIN = 1, 2, 4, 8
 
 EXPORTED = ("nfs_last_error", "nfs_validate", "nfs_workspace_size", "nfs_fastsum_apply",
-            "nfs_nfft_adjoint", "nfs_nfft_trafo", "nfs_sinkhorn_solve", "nfs_sinkhorn_grad",
+            "nfs_nfft_adjoint", "nfs_nfft_trafo", "nfs_sinkhorn_solve", "nfs_sinkhorn_solve_log",
+            "nfs_sinkhorn_grad",
             "nfs_solver_create", "nfs_solver_iterate", "nfs_solver_residual", "nfs_solver_finish",
             "nfs_solver_profile", "nfs_solver_destroy", "nfs_batch_workspace_size",
             "nfs_batch_solver_create", "nfs_batch_solve", "nfs_divergence_workspace_size",
@@ -99,6 +100,8 @@ def load_library():
     lib.nfs_sinkhorn_solve.restype = ctypes.c_int
     lib.nfs_sinkhorn_solve.argtypes = [PP, P, I64, P, P, I64, P, ctypes.c_int32, ctypes.c_double,
                                        ctypes.c_int32, P, P, ctypes.POINTER(_Result), P, SZ, P]
+    lib.nfs_sinkhorn_solve_log.restype = ctypes.c_int
+    lib.nfs_sinkhorn_solve_log.argtypes = lib.nfs_sinkhorn_solve.argtypes
     lib.nfs_sinkhorn_grad.restype = ctypes.c_int
     lib.nfs_sinkhorn_grad.argtypes = [PP, P, I64, P, P, I64, P, P, P, P, P, P, SZ, P]
     lib.nfs_solver_create.restype = ctypes.c_int
@@ -267,6 +270,55 @@ def sinkhorn(params, x, mu, y, nu, iters, tol=0.0, alpha_t0=None, workspace=None
     return SinkhornResult(alpha, alpha_t, res.cost, res.cost_upper, res.cost_primal, res.marg_err,
                           res.marg_err_row, res.marg_err_col, res.iters, res.n_nonpos, res.scale,
                           res.kernel_err, _PREC_NAME.get(res.precision_used, ""))
+
+
+@dataclass
+class LogSinkhornResult:
+    """Result of the log-domain solve: potentials beta (n) and gamma (nt),
+    alpha = exp(beta/eps - 1/2), alpha_t = exp(gamma/eps - 1/2)."""
+    beta: torch.Tensor
+    gamma: torch.Tensor
+    cost: float
+    cost_upper: float
+    marg_err: float
+    marg_err_row: float
+    marg_err_col: float
+    iters: int
+    n_nonpos: int
+    scale: float
+    kernel_err: float
+    precision_used: str = ""
+
+
+def sinkhorn_log(params, x, mu, y, nu, iters, tol=0.0, gamma0=None, workspace=None, check=True):
+    """NFFT-accelerated log-domain Sinkhorn (Algorithm 4) on the GPU; returns a
+    LogSinkhornResult.  gamma0 (nt, finite) is the starting value of gamma
+    (zeros when None)."""
+    lib = load_library()
+    x = _pts(x, params.d, "x")
+    y = _pts(y, params.d, "y")
+    _dev(mu, "mu")
+    _dev(nu, "nu")
+    n, nt = x.shape[0], y.shape[0]
+    beta = torch.empty(n, dtype=torch.float64, device=x.device)
+    if gamma0 is not None:
+        gamma = _dev(gamma0, "gamma0").clone()
+    else:
+        gamma = torch.empty(nt, dtype=torch.float64, device=x.device)
+    if workspace is None:
+        ws, nb = _workspace(params, n, nt, x.device)
+    else:
+        ws, nb = workspace, workspace.numel()
+    res = _Result()
+    rc = lib.nfs_sinkhorn_solve_log(ctypes.byref(params.to_c()), x.data_ptr(), n, mu.data_ptr(),
+                                    y.data_ptr(), nt, nu.data_ptr(), int(iters), float(tol),
+                                    1 if gamma0 is not None else 0, beta.data_ptr(), gamma.data_ptr(),
+                                    ctypes.byref(res), ws.data_ptr(), nb, _stream())
+    if rc != NFS_OK and (check or rc != NFS_ENONPOS):
+        _check(rc)
+    return LogSinkhornResult(beta, gamma, res.cost, res.cost_upper, res.marg_err, res.marg_err_row,
+                             res.marg_err_col, res.iters, res.n_nonpos, res.scale, res.kernel_err,
+                             _PREC_NAME.get(res.precision_used, ""))
 
 
 def sinkhorn_grad(params, x, mu, y, nu, alpha, alpha_t, want_x=True, want_mu=True):

@@ -1,0 +1,185 @@
+"""GPU parity of the NFFT-accelerated log-domain Sinkhorn (Algorithm 4)
+against the FP64 oracle (dense Algorithm 2 with log-sum-exp).
+
+Tolerances: FP64 with m = 8 within 1e-10 relative on the cost and, for the
+potentials, within 1e-10 * eps absolute (a relative error r of a scaling is
+an absolute error eps * r of its potential); FP32 within 1e-5 relative on
+the cost.  At full size (the 2-D mixture workload, 1e6 points per cloud)
+the last half-step is checked on sampled targets with the oracle's
+matrix-free FP64 sums.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import direct
+from oracle import sinkhorn_dense as sd
+from paper_2201_07524_amd import nfs, workloads
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def T(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def same_potentials(got, ref, tol):
+    """Equal -inf positions (zero weights) and |got - ref| <= tol elsewhere."""
+    got = got.cpu().numpy() if hasattr(got, "cpu") else got
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(got), fin)
+    assert np.all(got[~fin] == -np.inf) and np.all(ref[~fin] == -np.inf)
+    assert np.max(np.abs(got[fin] - ref[fin])) <= tol
+
+
+def solve_log(cfg, iters, prec, N, m, eps, gamma0=None, tol=0.0, **kw):
+    prm = nfs.Params(d=cfg["x"].shape[1], eps=eps, N=N, m=m, precision=prec, **kw)
+    return nfs.sinkhorn_log(prm, T(cfg["x"]), T(cfg["p"]), T(cfg["y"]), T(cfg["pt"]), iters, tol=tol,
+                            gamma0=None if gamma0 is None else T(gamma0))
+
+
+def test_plain_1d_full_config_fp64():
+    """d = 1, n = nt = 2048, eps = 0.05, N = 256, m = 8, 200 iterations, FP64."""
+    cfg = workloads.plain_1d()
+    eps = cfg["eps"]
+    ref = sd.solve_log(cfg["x"], cfg["p"], cfg["y"], cfg["pt"], 2, eps, cfg["iters"])
+    res = solve_log(cfg, cfg["iters"], "fp64", cfg["N"], cfg["m"], eps)
+    assert res.iters == 200 and res.n_nonpos == 0
+    same_potentials(res.beta, ref["beta"], 1e-10 * eps)
+    same_potentials(res.gamma, ref["gamma"], 1e-10 * eps)
+    assert rel(res.cost, ref["cost"]) <= 1e-10
+    assert rel(res.cost_upper, ref["cost_upper"]) <= 1e-10
+    assert abs(res.marg_err_row - ref["marg_err_row"]) <= 1e-10 * max(ref["marg_err_row"], 1e-6)
+    assert res.marg_err_col <= 1e-12
+
+
+@pytest.mark.parametrize("d,N", [(2, 64), (3, 32)])
+def test_fp64_2d_3d_vs_oracle(d, N):
+    """Mixture clouds with Dirichlet weights (a few zero), eps = 0.05, 30 iterations."""
+    n, nt, eps, iters = 900, 700, 0.05, 30
+    x = workloads.gaussian_mixture(n, d, 61)
+    y = workloads.gaussian_mixture(nt, d, 62)
+    p = workloads.dirichlet_weights(n, 63)
+    pt = workloads.dirichlet_weights(nt, 64)
+    p[[3, 400]] = 0.0
+    p /= p.sum()
+    pt[[10]] = 0.0
+    pt /= pt.sum()
+    cfg = dict(x=x, p=p, y=y, pt=pt)
+    ref = sd.solve_log(x, p, y, pt, 2, eps, iters)
+    res = solve_log(cfg, iters, "fp64", N, 8, eps)
+    same_potentials(res.beta, ref["beta"], 1e-10 * eps)
+    same_potentials(res.gamma, ref["gamma"], 1e-10 * eps)
+    assert rel(res.cost, ref["cost"]) <= 1e-10
+    assert rel(res.cost_upper, ref["cost_upper"]) <= 1e-10
+
+
+def test_start_beyond_the_scalings_range():
+    """A starting gamma shifted by C = 900 eps: exp(gamma/eps) overflows FP64,
+    so Algorithm 3 cannot take the start (its solver rejects the infinite
+    alpha_t).  The shift moves every beta by -C and every gamma by +C and
+    leaves the coupling and the cost unchanged; the log-domain solve follows
+    the oracle's iterates from that start."""
+    cfg = workloads.plain_1d(1024)
+    eps, iters = 0.02, 25
+    g0 = np.random.default_rng(5).normal(0.0, 0.01, cfg["y"].shape[0]) + 900 * eps
+    assert not np.all(np.isfinite(np.exp(g0 / eps - 0.5)))
+    ref = sd.solve_log(cfg["x"], cfg["p"], cfg["y"], cfg["pt"], 2, eps, iters, gamma0=g0)
+    res = solve_log(cfg, iters, "fp64", 256, 8, eps, gamma0=g0)
+    same_potentials(res.beta, ref["beta"], 1e-10 * eps)
+    same_potentials(res.gamma, ref["gamma"], 1e-10 * eps)
+    assert rel(res.cost, ref["cost"]) <= 1e-10
+    prm = nfs.Params(d=1, eps=eps, N=256, m=8, precision="fp64")
+    with pytest.raises(nfs.NfsError) as err:
+        nfs.sinkhorn(prm, T(cfg["x"]), T(cfg["p"]), T(cfg["y"]), T(cfg["pt"]), iters,
+                     alpha_t0=T(np.exp(g0 / eps - 0.5)))
+    assert err.value.code == nfs.NFS_EINVAL
+
+
+def test_matches_algorithm_3_on_the_device():
+    """The log-domain and scaling solves give the same coupling:
+    beta = eps (log alpha + 1/2) and gamma = eps (log alpha_t + 1/2) when
+    Algorithm 3 starts from alpha_t = exp(-1/2) (the image of gamma = 0)."""
+    cfg = workloads.subsample(workloads.gmm_2d(20000), 4000, seed=8)
+    eps, iters = 0.02, 40
+    lg = solve_log(cfg, iters, "fp64", 128, 8, eps)
+    prm = nfs.Params(d=2, eps=eps, N=128, m=8, precision="fp64")
+    a3 = nfs.sinkhorn(prm, T(cfg["x"]), T(cfg["p"]), T(cfg["y"]), T(cfg["pt"]), iters,
+                      alpha_t0=T(np.full(cfg["y"].shape[0], np.exp(-0.5))))
+    b = eps * (np.log(a3.alpha.cpu().numpy()) + 0.5)
+    g = eps * (np.log(a3.alpha_t.cpu().numpy()) + 0.5)
+    assert np.max(np.abs(lg.beta.cpu().numpy() - b)) <= 1e-11 * eps
+    assert np.max(np.abs(lg.gamma.cpu().numpy() - g)) <= 1e-11 * eps
+    assert rel(lg.cost, a3.cost) <= 1e-12
+
+
+def test_fp32_2d_vs_oracle():
+    """3000-point subsample of the 2-D mixture workload, eps = 0.01, N = 128,
+    m = 8, FP32 grids, 100 iterations: cost within 1e-5."""
+    cfg = workloads.subsample(workloads.gmm_2d(20000), 3000, seed=3)
+    eps, iters = 0.01, 100
+    ref = sd.solve_log(cfg["x"], cfg["p"], cfg["y"], cfg["pt"], 2, eps, iters)
+    res = solve_log(cfg, iters, "fp32", 128, 8, eps)
+    assert res.n_nonpos == 0
+    assert rel(res.cost, ref["cost"]) <= 1e-5
+    assert np.all(np.isfinite(res.beta.cpu().numpy())) and np.all(np.isfinite(res.gamma.cpu().numpy()))
+
+
+def test_batched_log_domain_vs_oracle():
+    """Five ragged 2-D problems with their own eps in one batch (flag
+    NFS_FLAG_LOG_DOMAIN): each matches the oracle within 1e-10."""
+    sizes, eps_list = [150, 900, 37, 1500, 400], [0.05, 0.03, 0.08, 0.04, 0.06]
+    probs = []
+    for b, (n, e) in enumerate(zip(sizes, eps_list)):
+        x = workloads.gaussian_mixture(n, 2, 700 + 2 * b)
+        y = workloads.gaussian_mixture(n + 7 * b, 2, 701 + 2 * b)
+        probs.append(dict(x=x, p=workloads.uniform_weights(n), y=y,
+                          pt=workloads.dirichlet_weights(n + 7 * b, 800 + b)))
+    prm = nfs.Params(d=2, eps=1.0, N=64, m=8, precision="fp64", flags=nfs.FLAG_LOG_DOMAIN)
+    iters = 25
+    res = nfs.batch_sinkhorn(prm, [T(q["x"]) for q in probs], [T(q["p"]) for q in probs],
+                             [T(q["y"]) for q in probs], [T(q["pt"]) for q in probs], eps_list, iters)
+    for q, r, e in zip(probs, res, eps_list):
+        ref = sd.solve_log(q["x"], q["p"], q["y"], q["pt"], 2, e, iters)
+        same_potentials(r.alpha, ref["beta"], 1e-10 * e)
+        same_potentials(r.alpha_t, ref["gamma"], 1e-10 * e)
+        assert rel(r.cost, ref["cost"]) <= 1e-10
+
+
+def test_tolerance_stop_and_rejected_start():
+    """Early stop on ||E|| <= tol as in Algorithm 4's loop condition, and a
+    non-finite starting gamma is rejected with NFS_EINVAL."""
+    cfg = workloads.plain_1d(512)
+    eps = 0.05
+    res = solve_log(cfg, 1000, "fp64", 256, 8, eps, tol=1e-9)
+    assert res.iters < 1000 and res.iters % 10 == 0
+    assert res.marg_err <= 1e-9
+    g0 = np.zeros(cfg["y"].shape[0])
+    g0[7] = np.inf
+    with pytest.raises(nfs.NfsError) as err:
+        solve_log(cfg, 5, "fp64", 256, 8, eps, gamma0=g0)
+    assert err.value.code == nfs.NFS_EINVAL
+
+
+def test_full_size_2d_mixture_sampled():
+    """The benchmarked 2-D mixture (1e6 points per cloud, N = 512, m = 8,
+    eps = 0.01, FP32 grids), 10 log-domain iterations: the last half-step
+    t_j = nu_j exp(1/2 - gamma_j/eps) (from gamma = eps (log nu - log t) + eps/2) against the oracle's FP64 sums
+    sum_i k_ij exp(beta_i/eps - 1/2) on 256 sampled targets (plus the one
+    with the largest sum), normwise within 1e-5 of the largest."""
+    cfg = workloads.gmm_2d()
+    eps = cfg["eps"]
+    res = solve_log(cfg, 10, "fp32", cfg["N"], cfg["m"], eps)
+    b, g = res.beta.cpu().numpy(), res.gamma.cpu().numpy()
+    assert res.n_nonpos == 0 and np.all(np.isfinite(b)) and np.all(np.isfinite(g))
+    tt_gpu = cfg["pt"] * np.exp(0.5 - g / eps)
+    rows = np.random.default_rng(21).choice(cfg["y"].shape[0], size=256, replace=False)
+    rows = np.union1d(rows, [np.argmax(tt_gpu)])
+    tt = direct.kv(cfg["y"], cfg["x"], np.exp(b / eps - 0.5), 2, eps, rows=rows)
+    assert np.max(np.abs(tt_gpu[rows] - tt)) <= 1e-5 * np.max(tt)
