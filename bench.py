@@ -186,6 +186,26 @@ def grad_leg(nfs, workloads, torch, T, iters=5):
             "gradient_over_forward_iteration": t_grad / t_fwd}
 
 
+def log_leg(nfs, prm, x, p, y, pt, torch, iters=20):
+    """The log-domain form (Algorithm 4) on the benchmarked 2-D mixture
+    workload: ms per iteration of the potentials solve, same parameters."""
+    from dataclasses import replace
+    lp = replace(prm, flags=prm.flags | nfs.FLAG_LOG_DOMAIN)
+    s = nfs.Solver(lp, x, p, y, pt)
+    s.iterate(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.iterate(iters)
+    torch.cuda.synchronize()
+    t_it = (time.perf_counter() - t0) / iters
+    stage_ms, _ = s.profile(5)
+    res = s.finish(check=False)
+    s.close()
+    return {"ms_per_iteration": t_it * 1e3, "iterations": iters + 2 + 5, "cost": res.cost,
+            "n_nonpos": res.n_nonpos,
+            "stage_ms": dict(zip(("spread_incl_weights", "fft", "interp", "iteration"), stage_ms))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,7 +217,7 @@ def main():
     ap.add_argument("--flags", type=int, default=0, help="nfs_params.flags (library variants)")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--no-legs", action="store_true", help="skip the batched and gradient legs")
+    ap.add_argument("--no-legs", action="store_true", help="skip the log-domain, batched and gradient legs")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with one device copy of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -283,6 +303,10 @@ def main():
     solver.close()
     del solver
     if not args.no_legs:
+        log("bench: log-domain leg")
+        out["log_domain"] = log_leg(nfs, prm, x, p, y, pt, torch)
+        out["log_domain"]["over_scaling_iteration"] = out["log_domain"]["ms_per_iteration"] / ms_per_step
+        log("bench: log-domain " + json.dumps(out["log_domain"]))
         log("bench: batched leg")
         out["batched"] = batched_leg(nfs, workloads, torch, T)
         log("bench: batched " + json.dumps(out["batched"]))
