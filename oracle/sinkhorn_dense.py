@@ -190,6 +190,41 @@ def envelope_gradient(x, y, K, alpha, alpha_t, r, eps):
     return grad_x, grad_mu
 
 
+def envelope_gradient_targets(x, y, K, alpha, alpha_t, r, eps):
+    """Gradient of s with respect to the target positions and weights, by the
+    same envelope argument on eq. (14):
+      d s / d y_j  = sum_i pi_ij grad_y c(x_i, y_j),
+      d s / d pt_j = eps log alpha_t_j, projected onto sum = 0.
+    For r = 2, grad_y c = 2 (y_j - x_i); for r = 1, (y_j - x_i)/|y_j - x_i|.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[:, None]
+    if y.ndim == 1:
+        y = y[:, None]
+    pi = transport_plan(K, alpha, alpha_t)
+    diff = y[None, :, :] - x[:, None, :]
+    if r == 2:
+        g = 2.0 * diff
+    elif r == 1:
+        nrm = np.sqrt(np.sum(diff * diff, axis=-1, keepdims=True))
+        g = np.where(nrm > 0, diff / np.where(nrm > 0, nrm, 1.0), 0.0)
+    else:
+        raise ValueError("r must be 1 or 2")
+    grad_y = np.einsum("ij,ijc->jc", pi, g)
+    gnu = eps * np.where(alpha_t > 0, np.log(np.where(alpha_t > 0, alpha_t, 1.0)), 0.0)
+    grad_nu = gnu - gnu.mean()
+    return grad_y, grad_nu
+
+
+def plan_apply(K, alpha, alpha_t, v, transpose=False):
+    """Product of the coupling pi = diag(alpha) k diag(alpha_t) (eq. (pi*))
+    with a vector: pi v (n values), or pi^T v (nt values) when ``transpose``."""
+    pi = transport_plan(K, alpha, alpha_t)
+    return pi.T @ v if transpose else pi @ v
+
+
 def solve(x, p, y, pt, r, eps, iters, alpha_t0=None):
     """Convenience wrapper: Algorithm 1 for ``iters`` iterations plus every read-out.
 

@@ -261,6 +261,63 @@ def test_gradient_central_differences(r):
         assert abs(fd - (gmu[i] - gmu[k])) <= 1e-6 * max(1.0, abs(fd))
 
 
+@pytest.mark.parametrize("r", [1, 2])
+def test_target_gradient_central_differences_and_translation(r):
+    """Target-side envelope gradient vs central differences of the converged
+    cost (positions h = 1e-4, weights along e_j - e_k), and translation
+    invariance: moving both clouds together leaves s unchanged, so the
+    position gradients of both sides sum to zero."""
+    n, nt, eps = 22, 24, 0.05
+    x, y = _cloud(n, 2, 34), _cloud(nt, 2, 35)
+    p, pt = workloads.dirichlet_weights(n, 36), workloads.dirichlet_weights(nt, 37)
+
+    def cost(yy, qq):
+        K = sd.gibbs_kernel(x, yy, r, eps)
+        res = sd.sinkhorn_to_tolerance(K, p, qq, tol=1e-15)
+        return sd.cost_readout(res["alpha"], res["alpha_t"], res["tt"], p, qq, eps), res
+
+    s0, res = cost(y, pt)
+    K = sd.gibbs_kernel(x, y, r, eps)
+    gy, gnu = sd.envelope_gradient_targets(x, y, K, res["alpha"], res["alpha_t"], r, eps)
+    gx, _ = sd.envelope_gradient(x, y, K, res["alpha"], res["alpha_t"], r, eps)
+    assert np.allclose(gx.sum(axis=0) + gy.sum(axis=0), 0.0, atol=1e-14)
+    assert abs(gnu.sum()) <= 1e-14
+    h = 1e-4
+    for j, c in [(0, 1), (9, 0), (23, 1)]:
+        yp, ym = y.copy(), y.copy()
+        yp[j, c] += h
+        ym[j, c] -= h
+        fd = (cost(yp, pt)[0] - cost(ym, pt)[0]) / (2 * h)
+        assert abs(fd - gy[j, c]) <= 1e-6 * max(1.0, abs(fd)) + 1e-8
+    for j, k in [(2, 7), (13, 20)]:
+        hh = 1e-3 * min(pt[j], pt[k])
+        qp, qm = pt.copy(), pt.copy()
+        qp[j] += hh
+        qp[k] -= hh
+        qm[j] -= hh
+        qm[k] += hh
+        fd = (cost(y, qp)[0] - cost(y, qm)[0]) / (2 * hh)
+        assert abs(fd - (gnu[j] - gnu[k])) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_plan_apply_marginals_and_bilinearity():
+    """pi 1 is the row marginal alpha o (K alpha_t), and after an even
+    half-step pi^T 1 = pt exactly (eq. (S1)); u^T (pi v) = (pi^T u)^T v."""
+    n, nt, eps = 30, 26, 0.05
+    x, y = _cloud(n, 2, 40), _cloud(nt, 2, 41)
+    p, pt = workloads.dirichlet_weights(n, 42), workloads.dirichlet_weights(nt, 43)
+    K = sd.gibbs_kernel(x, y, 2, eps)
+    out = sd.sinkhorn(K, p, pt, 5)
+    a, at = out["alpha"], out["alpha_t"]
+    assert np.allclose(sd.plan_apply(K, a, at, np.ones(nt)), a * (K @ at), rtol=1e-14, atol=0)
+    assert np.allclose(sd.plan_apply(K, a, at, np.ones(n), transpose=True), pt, rtol=1e-13, atol=0)
+    rng = np.random.default_rng(44)
+    u, v = rng.normal(size=n), rng.normal(size=nt)
+    lhs = u @ sd.plan_apply(K, a, at, v)
+    rhs = sd.plan_apply(K, a, at, u, transpose=True) @ v
+    assert abs(lhs - rhs) <= 1e-14 * max(1.0, abs(lhs))
+
+
 # ---------------------------------------------------------------- the pins bite
 def test_planted_mistakes_are_caught():
     """Plant plausible mistakes in copies of the oracle's formulas (on the
