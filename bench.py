@@ -206,6 +206,30 @@ def log_leg(nfs, prm, x, p, y, pt, torch, iters=20):
             "stage_ms": dict(zip(("spread_incl_weights", "fft", "interp", "iteration"), stage_ms))}
 
 
+def ball_shell_leg(nfs, workloads, torch, T, iters=3):
+    """The Euclidean-cost form (r = 1, with the near field): ball against
+    shell, 4e6 points per cloud, eps = 0.02, N = 128, m = 6, FP32; ms per
+    iteration and per-stage device times."""
+    cfg = workloads.ball_shell_3d()
+    prm = nfs.Params(d=3, r=1, eps=cfg["eps"], N=cfg["N"], m=cfg["m"], precision="fp32")
+    t0 = time.perf_counter()
+    s = nfs.Solver(prm, T(cfg["x"]), T(cfg["p"]), T(cfg["y"]), T(cfg["pt"]))
+    torch.cuda.synchronize()
+    plan = time.perf_counter() - t0
+    s.iterate(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.iterate(iters)
+    torch.cuda.synchronize()
+    t_it = (time.perf_counter() - t0) / iters
+    stage_ms, _ = s.profile(1)
+    res = s.finish(check=False)
+    s.close()
+    return {"points": int(cfg["x"].shape[0]), "ms_per_iteration": t_it * 1e3, "plan_ms": plan * 1e3,
+            "stage_ms": dict(zip(("spread", "fft", "interp", "iteration", "near_field"), stage_ms)),
+            "near_field_share": 2.0 * stage_ms[4] / stage_ms[3], "cost": res.cost, "n_nonpos": res.n_nonpos}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,7 +241,7 @@ def main():
     ap.add_argument("--flags", type=int, default=0, help="nfs_params.flags (library variants)")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--no-legs", action="store_true", help="skip the log-domain, batched and gradient legs")
+    ap.add_argument("--no-legs", action="store_true", help="skip the log-domain, batched, gradient and ball/shell legs")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with one device copy of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -314,6 +338,10 @@ def main():
         log("bench: gradient leg")
         out["gradient"] = grad_leg(nfs, workloads, torch, T)
         log("bench: gradient " + json.dumps(out["gradient"]))
+        torch.cuda.empty_cache()
+        log("bench: ball/shell (r = 1) leg")
+        out["ball_shell_r1"] = ball_shell_leg(nfs, workloads, torch, T)
+        log("bench: ball/shell " + json.dumps(out["ball_shell_r1"]))
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(cfg)

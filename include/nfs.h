@@ -202,9 +202,9 @@ int nfs_solver_residual(nfs_solver* s, double* err_row, void* stream);
  * and the result struct, as nfs_sinkhorn_solve.  The solver stays usable. */
 int nfs_solver_finish(nfs_solver* s, double* alpha, double* alpha_t, nfs_result* res, void* stream);
 /* Runs `iters` iterations with direct launches and events between kernels;
- * stage_ms[4] receives the average device time per launch of spreading, of
- * the FFT chain, of interpolation with the scaling update, and of one whole
- * iteration.  info (nullable, 8 doubles): n, nt, d, grid cells, bytes per grid
+ * stage_ms[5] receives the average device time per launch of spreading, of
+ * the FFT chain, of interpolation with the scaling update, of one whole
+ * iteration, and of the near-field sum (r = 1; about 0 for r = 2).  info (nullable, 8 doubles): n, nt, d, grid cells, bytes per grid
  * value, chunks of x, chunks of y, taps per point. */
 int nfs_solver_profile(nfs_solver* s, int32_t iters, double* stage_ms, double* info, void* stream);
 int nfs_solver_destroy(nfs_solver* s);
@@ -261,6 +261,34 @@ int nfs_sinkhorn_grad(const nfs_params* prm, const double* x, int64_t n, const d
                       const double* alpha, const double* alpha_t,
                       double* grad_x, double* grad_mu,
                       void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Target side of the same gradient (the kernel is even, so this is the
+ * computation above with the roles of the two clouds exchanged):
+ *   grad_y[j]  = sum_i pi_ij grad_y c(x_i, y_j) = -eps alpha_t_j (grad K * alpha)(y_j)   (nt x d)
+ *   grad_nu[j] = eps log alpha_t_j - mean_k(eps log alpha_t_k)                            (nt)
+ * Same arguments, workspace size and errors as nfs_sinkhorn_grad (r = 2
+ * only).  Either output may be NULL.
+ */
+int nfs_sinkhorn_grad_targets(const nfs_params* prm, const double* x, int64_t n, const double* mu,
+                              const double* y, int64_t nt, const double* nu,
+                              const double* alpha, const double* alpha_t,
+                              double* grad_y, double* grad_nu,
+                              void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Product of the coupling pi = diag(alpha) K diag(alpha_t) (eq. (pi*)) with a
+ * vector, by one fast summation, without forming pi (the product the paper's
+ * remark on the optimal transition matrix leaves out):
+ *   transpose = 0: v (nt) -> out (n),  out = alpha o K (alpha_t o v);
+ *   transpose = 1: v (n)  -> out (nt), out = alpha_t o K^T (alpha o v).
+ * alpha, alpha_t: scalings as returned by nfs_sinkhorn_solve (not potentials).
+ * Workspace: nfs_workspace_size(prm, n, nt).  NFS_EINVAL for a NULL pointer or
+ * transpose not in {0, 1}.  r = 1 includes the near field.
+ */
+int nfs_plan_apply(const nfs_params* prm, const double* x, int64_t n, const double* y, int64_t nt,
+                   const double* alpha, const double* alpha_t, const double* v, int32_t transpose,
+                   double* out, void* workspace, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

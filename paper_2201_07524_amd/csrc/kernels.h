@@ -279,6 +279,9 @@ hipError_t launch_readout(const ReadoutArgs& a, hipStream_t st);
 hipError_t launch_logweights(const Chunk* chunks, int nchunks, const double* pot, const double* shift,
                              const double* leps, double* out, hipStream_t st);
 
+// out[i] = a[i] * b[i], i < n.
+hipError_t launch_mul(const double* a, const double* b, long n, double* out, hipStream_t st);
+
 // out[0] = max v, out[1] = sum v (non-finite if any entry is), over n values.
 hipError_t launch_maxsum(const double* v, long n, double* partials, unsigned* counter, double* out, hipStream_t st);
 

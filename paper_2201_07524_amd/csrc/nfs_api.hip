@@ -729,9 +729,12 @@ static hipError_t half_step(Work<R>& w, CloudBuf<R>& src, CloudBuf<R>& tgt, doub
 }
 
 // ----------------------------------------------------------------------------- fast summation / NFFT
+// out_i = tscale_i sum_j wv_j wv2_j K(tgt_i - src_j); wv2 and tscale are optional
+// (the coupling-vector product passes the scalings there).
 template <typename R>
 static int do_fastsum(const nfs_params* p, const double* src, int64_t ns, const double* wv, const double* tgt,
-                      int64_t nt, double* out, void* ws, size_t wsb, hipStream_t st) {
+                      int64_t nt, double* out, void* ws, size_t wsb, hipStream_t st, const double* wv2 = nullptr,
+                      const double* tscale = nullptr) {
   Work<R> w;
   carve(w, p, 1, ns, nt, nullptr, 1);
   if (wsb < w.bytes) return fail(NFS_EWORKSPACE, "workspace too small");
@@ -739,6 +742,10 @@ static int do_fastsum(const nfs_params* p, const double* src, int64_t ns, const 
   w.X.off = {0, ns};
   w.Y.off = {0, nt};
   NFS_TRY(zero_state(w, st));
+  if (wv2) {
+    NFS_HIP(launch_mul(wv, wv2, ns, w.tmp, st));
+    wv = w.tmp;
+  }
   double box[9];
   NFS_TRY(box_launch(w.st_box, w.partials, w.ct_misc, p->d, src, ns, tgt, nt, wv, ns, st));
   NFS_HIP(hipMemcpyAsync(box, w.st_box, sizeof(box), hipMemcpyDeviceToHost, st));
@@ -748,7 +755,7 @@ static int do_fastsum(const nfs_params* p, const double* src, int64_t ns, const 
   w.sc = {p->r == 1 ? choose_scaling_r1(p->d, p->eps, p->precision == NFS_FP32 ? 20.0 : 36.0, box, box + 3)
                      : choose_scaling(p->d, p->r, p->eps, p->N, box, box + 3)};
   NFS_TRY(sort_cloud(w, w.X, src, w.sc, wv, nullptr, st));
-  NFS_TRY(sort_cloud(w, w.Y, tgt, w.sc, nullptr, nullptr, st));
+  NFS_TRY(sort_cloud(w, w.Y, tgt, w.sc, tscale, nullptr, st));
   NFS_TRY(upload_tables(w, p, st));
   NFS_HIP(launch_fill(w.S, sizeof(R) * w.ncell, st));
   const double wmax = box[6] > 0.0 ? box[6] : 1.0;
@@ -759,6 +766,7 @@ static int do_fastsum(const nfs_params* p, const double* src, int64_t ns, const 
   if (w.r == 1) ia.nf = w.nf;
   ia.norm = wmax;
   ia.out = out;
+  if (tscale) ia.scale_vec = w.Y.w0s;
   NFS_HIP(launch_interp(ia, w.Y.nchunks, st));
   NFS_HIP(hipStreamSynchronize(st));
   return NFS_OK;
@@ -1124,7 +1132,7 @@ struct Solver : SolverBase {
   int profile(int k, double* stage_ms, hipStream_t caller) override {
     if (k <= 0) return fail(NFS_EINVAL, "profile needs k >= 1");
     NFS_TRY(enter(caller));
-    std::vector<hipEvent_t> evs(6 * k + 1);
+    std::vector<hipEvent_t> evs(8 * k + 1);
     for (auto& e : evs) NFS_HIP(hipEventCreate(&e));
     int ie = 0;
     NFS_HIP(hipEventRecord(evs[ie++], gs));
@@ -1147,6 +1155,7 @@ struct Solver : SolverBase {
         NFS_HIP(fft_chain(w, w.dtab, -1, gs));
         NFS_HIP(hipEventRecord(evs[ie++], gs));
         if (w.r == 1) NFS_HIP(near_field(w, src, tgt, wv, wm, 1.0, gs));
+        NFS_HIP(hipEventRecord(evs[ie++], gs));
         InterpArgs<R> ia = interp_args(w, tgt, sink(), ws_);
         ia.leps = w.leps;
         if (w.r == 1) ia.nf = w.nf;
@@ -1159,15 +1168,19 @@ struct Solver : SolverBase {
       }
     }
     NFS_HIP(hipStreamSynchronize(gs));
-    double acc[3] = {0, 0, 0};
+    // per half-step: spread | FFT chain | near field | interpolation + update
+    double acc[4] = {0, 0, 0, 0};
     float ms;
     for (int i = 1; i < ie; ++i) {
       NFS_HIP(hipEventElapsedTime(&ms, evs[i - 1], evs[i]));
-      acc[(i - 1) % 3] += ms;
+      acc[(i - 1) % 4] += ms;
     }
     NFS_HIP(hipEventElapsedTime(&ms, evs[0], evs[ie - 1]));
-    for (int s = 0; s < 3; ++s) stage_ms[s] = acc[s] / (2.0 * k);
+    stage_ms[0] = acc[0] / (2.0 * k);
+    stage_ms[1] = acc[1] / (2.0 * k);
+    stage_ms[2] = acc[3] / (2.0 * k);
     stage_ms[3] = ms / k;
+    stage_ms[4] = acc[2] / (2.0 * k);
     for (auto& e : evs) hipEventDestroy(e);
     done += k;
     return leave(caller);
@@ -1472,6 +1485,25 @@ int nfs_fastsum_apply(const nfs_params* prm, const double* src, int64_t ns, cons
   return do_fastsum<double>(prm, src, ns, w, tgt, nt, out, workspace, ws_bytes, st);
 }
 
+int nfs_plan_apply(const nfs_params* prm, const double* x, int64_t n, const double* y, int64_t nt,
+                   const double* alpha, const double* alpha_t, const double* v, int32_t transpose, double* out,
+                   void* workspace, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  NFS_TRY(check_params(prm, n, nt));
+  if (!x || !y || !alpha || !alpha_t || !v || !out || !workspace) return fail(NFS_EINVAL, "NULL pointer argument");
+  if (transpose != 0 && transpose != 1) return fail(NFS_EINVAL, "transpose must be 0 or 1");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // pi v = alpha o K (alpha_t o v): sources y, targets x; pi^T v with the roles swapped
+  const double* src = transpose ? x : y;
+  const double* tgt = transpose ? y : x;
+  const int64_t ns = transpose ? n : nt, ntg = transpose ? nt : n;
+  const double* ws_ = transpose ? alpha : alpha_t;
+  const double* wt_ = transpose ? alpha_t : alpha;
+  if (prm->precision == NFS_FP32)
+    return do_fastsum<float>(prm, src, ns, ws_, tgt, ntg, out, workspace, ws_bytes, st, v, wt_);
+  return do_fastsum<double>(prm, src, ns, ws_, tgt, ntg, out, workspace, ws_bytes, st, v, wt_);
+}
+
 int nfs_nfft_adjoint(const nfs_params* prm, const double* pts, int64_t n, const double* w, double* fhat,
                      void* workspace, size_t ws_bytes, void* stream) {
   g_err.clear();
@@ -1728,6 +1760,20 @@ int nfs_sinkhorn_grad(const nfs_params* prm, const double* x, int64_t n, const d
   if (prm->precision == NFS_FP32)
     return do_grad<float>(prm, x, n, mu, y, nt, nu, alpha, alpha_t, grad_x, grad_mu, workspace, ws_bytes, st);
   return do_grad<double>(prm, x, n, mu, y, nt, nu, alpha, alpha_t, grad_x, grad_mu, workspace, ws_bytes, st);
+}
+
+int nfs_sinkhorn_grad_targets(const nfs_params* prm, const double* x, int64_t n, const double* mu, const double* y,
+                              int64_t nt, const double* nu, const double* alpha, const double* alpha_t,
+                              double* grad_y, double* grad_nu, void* workspace, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  NFS_TRY(check_params(prm, n, nt));
+  if (prm->r != 2) return fail(NFS_EUNSUPPORTED, "the gradient is implemented for r = 2");
+  if (!x || !mu || !y || !nu || !alpha || !alpha_t || !workspace) return fail(NFS_EINVAL, "NULL pointer argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // the kernel is even: the target-side gradient is the source-side one with the roles swapped
+  if (prm->precision == NFS_FP32)
+    return do_grad<float>(prm, y, nt, nu, x, n, mu, alpha_t, alpha, grad_y, grad_nu, workspace, ws_bytes, st);
+  return do_grad<double>(prm, y, nt, nu, x, n, mu, alpha_t, alpha, grad_y, grad_nu, workspace, ws_bytes, st);
 }
 
 }  // extern "C"

@@ -464,6 +464,17 @@ hipError_t launch_logweights(const Chunk* chunks, int nchunks, const double* pot
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(kBlock) void mul_kernel(const double* a, const double* b, long n, double* out) {
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) out[i] = a[i] * b[i];
+}
+
+hipError_t launch_mul(const double* a, const double* b, long n, double* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mul_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a, b, n, out);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kBlock) void maxsum_kernel(const double* vals, long n, double* partials,
                                                         unsigned* counter, double* out) {
   constexpr int NV = 2;

@@ -20,7 +20,7 @@ FLAG_NO_GRAPH, FLAG_PRIMAL_COST, FLAG_TILE_REDUCE, FLAG_LOG_DOMAIN = 1, 2, 4, 8
 
 EXPORTED = ("nfs_last_error", "nfs_validate", "nfs_workspace_size", "nfs_fastsum_apply",
             "nfs_nfft_adjoint", "nfs_nfft_trafo", "nfs_sinkhorn_solve", "nfs_sinkhorn_solve_log",
-            "nfs_sinkhorn_grad",
+            "nfs_sinkhorn_grad", "nfs_sinkhorn_grad_targets", "nfs_plan_apply",
             "nfs_solver_create", "nfs_solver_iterate", "nfs_solver_residual", "nfs_solver_finish",
             "nfs_solver_profile", "nfs_solver_destroy", "nfs_batch_workspace_size",
             "nfs_batch_solver_create", "nfs_batch_solve", "nfs_divergence_workspace_size",
@@ -104,6 +104,10 @@ def load_library():
     lib.nfs_sinkhorn_solve_log.argtypes = lib.nfs_sinkhorn_solve.argtypes
     lib.nfs_sinkhorn_grad.restype = ctypes.c_int
     lib.nfs_sinkhorn_grad.argtypes = [PP, P, I64, P, P, I64, P, P, P, P, P, P, SZ, P]
+    lib.nfs_sinkhorn_grad_targets.restype = ctypes.c_int
+    lib.nfs_sinkhorn_grad_targets.argtypes = lib.nfs_sinkhorn_grad.argtypes
+    lib.nfs_plan_apply.restype = ctypes.c_int
+    lib.nfs_plan_apply.argtypes = [PP, P, I64, P, I64, P, P, P, ctypes.c_int32, P, P, SZ, P]
     lib.nfs_solver_create.restype = ctypes.c_int
     lib.nfs_solver_create.argtypes = [PP, P, I64, P, P, I64, P, P, P, SZ, P, ctypes.POINTER(P)]
     lib.nfs_solver_iterate.restype = ctypes.c_int
@@ -340,6 +344,43 @@ def sinkhorn_grad(params, x, mu, y, nu, alpha, alpha_t, want_x=True, want_mu=Tru
     return gx, gm
 
 
+def sinkhorn_grad_targets(params, x, mu, y, nu, alpha, alpha_t, want_y=True, want_nu=True):
+    """Target side of the envelope gradient: (grad_y (nt, d), grad_nu (nt,))."""
+    lib = load_library()
+    x = _pts(x, params.d, "x")
+    y = _pts(y, params.d, "y")
+    for t, nm in ((mu, "mu"), (nu, "nu"), (alpha, "alpha"), (alpha_t, "alpha_t")):
+        _dev(t, nm)
+    n, nt = x.shape[0], y.shape[0]
+    gy = torch.empty((nt, params.d), dtype=torch.float64, device=x.device) if want_y else None
+    gn = torch.empty(nt, dtype=torch.float64, device=x.device) if want_nu else None
+    ws, nb = _workspace(params, n, nt, x.device)
+    _check(lib.nfs_sinkhorn_grad_targets(ctypes.byref(params.to_c()), x.data_ptr(), n, mu.data_ptr(),
+                                         y.data_ptr(), nt, nu.data_ptr(), alpha.data_ptr(), alpha_t.data_ptr(),
+                                         gy.data_ptr() if gy is not None else None,
+                                         gn.data_ptr() if gn is not None else None,
+                                         ws.data_ptr(), nb, _stream()))
+    return gy, gn
+
+
+def plan_apply(params, x, y, alpha, alpha_t, v, transpose=False):
+    """pi v (n values) or, with transpose, pi^T v (nt values), pi = diag(alpha) K diag(alpha_t)."""
+    lib = load_library()
+    x = _pts(x, params.d, "x")
+    y = _pts(y, params.d, "y")
+    for t, nm in ((alpha, "alpha"), (alpha_t, "alpha_t"), (v, "v")):
+        _dev(t, nm)
+    n, nt = x.shape[0], y.shape[0]
+    if v.shape[0] != (n if transpose else nt):
+        raise ValueError("v has the wrong length")
+    out = torch.empty(nt if transpose else n, dtype=torch.float64, device=x.device)
+    ws, nb = _workspace(params, n, nt, x.device)
+    _check(lib.nfs_plan_apply(ctypes.byref(params.to_c()), x.data_ptr(), n, y.data_ptr(), nt, alpha.data_ptr(),
+                              alpha_t.data_ptr(), v.data_ptr(), 1 if transpose else 0, out.data_ptr(),
+                              ws.data_ptr(), nb, _stream()))
+    return out
+
+
 class Solver:
     """Persistent Sinkhorn state on the GPU (nfs_solver_* entry points).
 
@@ -386,8 +427,9 @@ class Solver:
                               res.kernel_err)
 
     def profile(self, k):
-        """Average device ms per launch of (spread, fft chain, interp+update, iteration) and sizes."""
-        st = (ctypes.c_double * 4)()
+        """Average device ms per launch of (spread, fft chain, interp+update, iteration, near field)
+        and sizes."""
+        st = (ctypes.c_double * 5)()
         info = (ctypes.c_double * 8)()
         _check(load_library().nfs_solver_profile(self.h, int(k), st, info, _stream()))
         keys = ("n", "nt", "d", "grid_cells", "grid_value_bytes", "chunks_x", "chunks_y", "taps_per_point")
@@ -521,7 +563,7 @@ def sinkhorn_divergence(params, x, mu, y, nu, iters, tol=0.0, check=True):
 
 
 class SinkhornCost(torch.autograd.Function):
-    """Sinkhorn cost s(x, mu; y, nu) with gradients w.r.t. x and mu.
+    """Sinkhorn cost s(x, mu; y, nu) with gradients w.r.t. x, mu, y and nu.
 
     Forward runs the NFFT-accelerated Sinkhorn solve and saves the scalings;
     backward evaluates the envelope gradient with the adjoint fast summation.
@@ -537,8 +579,12 @@ class SinkhornCost(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_out):
         x, mu, y, nu, a, at = ctx.saved_tensors
-        gx, gm = sinkhorn_grad(ctx.params, x, mu, y, nu, a, at,
-                               want_x=ctx.needs_input_grad[0], want_mu=ctx.needs_input_grad[1])
+        need = ctx.needs_input_grad
+        gx = gm = gy = gn = None
+        if need[0] or need[1]:
+            gx, gm = sinkhorn_grad(ctx.params, x, mu, y, nu, a, at, want_x=need[0], want_mu=need[1])
+        if need[2] or need[3]:
+            gy, gn = sinkhorn_grad_targets(ctx.params, x, mu, y, nu, a, at, want_y=need[2], want_nu=need[3])
         g = grad_out.to(torch.float64)
-        return (gx * g if gx is not None else None, gm * g if gm is not None else None,
-                None, None, None, None, None)
+        scale = lambda t: t * g if t is not None else None
+        return scale(gx), scale(gm), scale(gy), scale(gn), None, None, None
