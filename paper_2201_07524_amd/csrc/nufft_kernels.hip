@@ -475,12 +475,6 @@ template hipError_t launch_spread_reduce<double>(const ReduceArgs<double>&, int,
 constexpr int kNearTPT = 4;
 constexpr int kNearTargets = kNearTPT * kBlock;
 
-template <typename R>
-__device__ __forceinline__ R fast_exp(R x) {
-  if constexpr (sizeof(R) == 4) return __expf(x);
-  else return exp(x);
-}
-
 template <typename R, int D, int PS>
 __global__ __launch_bounds__(kBlock) void nearfield_kernel(NearArgs<R> a) {
   __shared__ R su[D][kBlock];
@@ -491,6 +485,10 @@ __global__ __launch_bounds__(kBlock) void nearfield_kernel(NearArgs<R> a) {
   const int nbins = geo.nt[0] * geo.nt[1] * geo.nt[2];
   const double* cf = a.coef + size_t(pb) * kNearStride;
   const R inv_e = R(cf[0]), ei2 = R(cf[1]), inv_ei2 = R(cf[2]);
+  // FP32: exp(-r/eps) = exp2(r * (-log2(e)/eps)) on the hardware exp2 and
+  // square root (about 1 ulp each; the correctly rounded sqrtf costs a dozen
+  // more instructions per pair)
+  const float nle = float(-cf[0] * 1.4426950408889634);
   R c[PS];
 #pragma unroll
   for (int j = 0; j < PS; ++j) c[j] = R(cf[4 + j]);
@@ -558,7 +556,10 @@ __global__ __launch_bounds__(kBlock) void nearfield_kernel(NearArgs<R> a) {
             R P = c[PS - 1];
 #pragma unroll
             for (int jj = PS - 2; jj >= 0; --jj) P = P * rho2 + c[jj];
-            acc[k] += wj * (fast_exp(-sqrt(r2) * inv_e) - P);
+            if constexpr (sizeof(R) == 4)
+              acc[k] += wj * (__builtin_amdgcn_exp2f(__builtin_amdgcn_sqrtf(r2) * nle) - P);
+            else
+              acc[k] += wj * (exp(-sqrt(r2) * inv_e) - P);
           }
         }
       }
