@@ -230,6 +230,38 @@ def ball_shell_leg(nfs, workloads, torch, T, iters=3):
             "near_field_share": 2.0 * stage_ms[4] / stage_ms[3], "cost": res.cost, "n_nonpos": res.n_nonpos}
 
 
+def paper_shapes_leg(nfs, workloads, torch, T, iters=10):
+    """The paper's standing workload shapes, FP64 grids, N = 64, m = 8,
+    eps = 0.05 (lambda = 20), r = 2: two images on one k x k pixel grid
+    (k = 32 ... 512) and uniform samples on [0,1]^2 (n = 1e3 ... 1e7).  Plan
+    time and ms per iteration; solve_100_s = plan + 100 iterations."""
+    out = {}
+    cases = [("grid%d" % k, lambda k=k: workloads.pixel_grid_pair(k)) for k in (32, 64, 128, 256, 512)]
+    cases += [("uniform%d" % n, lambda n=n: workloads.uniform_square(n)) for n in (10**3, 10**4, 10**5, 10**6, 10**7)]
+    for name, make in cases:
+        cfg = make()
+        prm = nfs.Params(d=2, eps=cfg["eps"], N=64, m=8, precision="fp64")
+        x, p, y, pt = T(cfg["x"]), T(cfg["p"]), T(cfg["y"]), T(cfg["pt"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = nfs.Solver(prm, x, p, y, pt)
+        torch.cuda.synchronize()
+        plan = time.perf_counter() - t0
+        s.iterate(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.iterate(iters)
+        torch.cuda.synchronize()
+        t_it = (time.perf_counter() - t0) / iters
+        res = s.finish(check=False)
+        s.close()
+        out[name] = {"n": int(cfg["x"].shape[0]), "plan_ms": plan * 1e3, "ms_per_iteration": t_it * 1e3,
+                     "solve_100_s": plan + 100 * t_it, "marg_err": res.marg_err, "n_nonpos": res.n_nonpos}
+        del x, p, y, pt, s
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,7 +273,7 @@ def main():
     ap.add_argument("--flags", type=int, default=0, help="nfs_params.flags (library variants)")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--no-legs", action="store_true", help="skip the log-domain, batched, gradient and ball/shell legs")
+    ap.add_argument("--no-legs", action="store_true", help="skip the log-domain, batched, gradient, ball/shell and paper-shape legs")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with one device copy of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -342,6 +374,10 @@ def main():
         log("bench: ball/shell (r = 1) leg")
         out["ball_shell_r1"] = ball_shell_leg(nfs, workloads, torch, T)
         log("bench: ball/shell " + json.dumps(out["ball_shell_r1"]))
+        torch.cuda.empty_cache()
+        log("bench: paper-shaped workloads leg")
+        out["paper_shapes"] = paper_shapes_leg(nfs, workloads, torch, T)
+        log("bench: paper shapes " + json.dumps(out["paper_shapes"]))
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(cfg)

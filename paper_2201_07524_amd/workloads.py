@@ -17,6 +17,10 @@ Workloads (the paper's data sets are replaced by these stand-ins):
   * ``gmm_3d``       d = 3 mixtures for the differentiated form.
   * ``uniform_square`` uniform on [0,1]^2 (the two-dimensional experiment of
                      Section 4.1.2).
+  * ``pixel_grid_pair`` two k x k images on one pixel grid in [0,1]^2 with
+                     smoothed Gaussian random-field intensities: the shape of
+                     the benchmark-image experiments of Section 4.2 (32^2 to
+                     512^2 pixels).  It is not that data set's images.
 """
 import numpy as np
 
@@ -116,6 +120,30 @@ def uniform_square(n, seed=600):
     x = rng.uniform(0.0, 1.0, size=(n, 2))
     y = rng.uniform(0.0, 1.0, size=(n, 2))
     return dict(x=x, p=uniform_weights(n), y=y, pt=uniform_weights(n), d=2, r=2, eps=0.05)
+
+
+def smoothed_field(k, seed, length=0.08):
+    """Gaussian random field on a k x k periodic pixel grid: white noise
+    filtered by a Gaussian of standard deviation ``length`` (in units of the
+    unit square) through the FFT, then shifted by one standard deviation and
+    clipped at zero (about one pixel in six is zero) and normalized to sum one."""
+    rng = np.random.default_rng(seed)
+    noise = rng.standard_normal((k, k))
+    f = np.fft.fftfreq(k)
+    filt = np.exp(-2.0 * (np.pi * length * k) ** 2 * (f[:, None] ** 2 + f[None, :] ** 2))
+    field = np.real(np.fft.ifft2(np.fft.fft2(noise) * filt))
+    field = (field - field.mean()) / field.std() + 1.0
+    w = np.clip(field, 0.0, None).ravel()
+    return w / w.sum()
+
+
+def pixel_grid_pair(k, seed=800):
+    """Two images on the same k x k grid of pixel centers ((i + 1/2)/k, (j + 1/2)/k),
+    intensities from independent smoothed fields (seeds ``seed``, ``seed + 1``);
+    eps = 0.05 (the paper's lambda = 20), squared Euclidean cost."""
+    c = (np.arange(k) + 0.5) / k
+    g = np.stack(np.meshgrid(c, c, indexing="ij"), axis=-1).reshape(-1, 2)
+    return dict(x=g, p=smoothed_field(k, seed), y=g.copy(), pt=smoothed_field(k, seed + 1), d=2, r=2, eps=0.05)
 
 
 def subsample(cfg, n, seed=7):
