@@ -108,6 +108,8 @@ struct NearArgs {
   int kt;
   int ps;               // polynomial terms p
   double* out;
+  const int* scell;     // nullable: per source tile the cell starts (TileSortArgs::cellstart);
+                        // with it only the source cells within eps_I of each wave's targets are read
 };
 template <typename R>
 hipError_t launch_nearfield(const NearArgs<R>& a, int nchunks, hipStream_t st);
@@ -233,6 +235,8 @@ struct TileSortArgs {
   int* perm;
   double* w0s;          // nullable
   double* w1s;          // nullable
+  int* cellstart;       // nullable: B x nbins x (T^d + 1) first position of each cell,
+                        // relative to the tile's first point (the last entry is the count)
 };
 template <typename R>
 hipError_t launch_tile_sort(const TileSortArgs<R>& a, hipStream_t st);

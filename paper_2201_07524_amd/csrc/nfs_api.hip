@@ -135,6 +135,7 @@ struct CloudBuf {
   double* w0s = nullptr;       // sorted weights
   double* w1s = nullptr;       // sorted scalings
   int* runs = nullptr;         // n: run table of each chunk (offsets from the chunk start)
+  int* cellstart = nullptr;    // r = 1 with cell order: B x nbins x (T^d + 1) cell starts per tile
   int* nruns = nullptr;        // 2 x max_chunks: full runs and single points per chunk
 };
 
@@ -256,6 +257,10 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
   }
   w.ecell = ecell;
   w.cell_order = tcells <= kSortBins;
+  if (w.cell_order && p->r == 1) {
+    w.X.cellstart = cv.take<int>(size_t(B) * nbins * (tcells + 1));
+    w.Y.cellstart = cv.take<int>(size_t(B) * nbins * (tcells + 1));
+  }
   if (w.cell_order) {
     const long ns = std::max(nA, nB);
     w.stage_coords = cv.take<R>(size_t(ns) * d);
@@ -446,6 +451,7 @@ static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const std:
     ta.perm = cb.perm;
     ta.w0s = v0 ? cb.w0s : nullptr;
     ta.w1s = v1 ? cb.w1s : nullptr;
+    ta.cellstart = cb.cellstart;
     NFS_HIP(launch_tile_sort(ta, st));
   }
   ChunkRunArgs<R> ca{};
@@ -707,6 +713,7 @@ static hipError_t near_field(Work<R>& w, const CloudBuf<R>& src, const CloudBuf<
   a.kt = w.kt;
   a.ps = w.ps;
   a.out = w.nf;
+  a.scell = src.cellstart;
   return launch_nearfield(a, tgt.nchunks, st);
 }
 

@@ -297,16 +297,26 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(TileSortArgs<R> a) {
   __shared__ int slot[kSortBins];
   __shared__ int part[kBlock];
   const int cnt = a.counts[blockIdx.x];
-  if (cnt == 0) return;
-  const size_t off = size_t(a.offsets[blockIdx.x]);
   const int d = a.d, T = a.T;
   int nc = 1;
   for (int c = 0; c < d; ++c) nc *= T;
+  int* cs = a.cellstart ? a.cellstart + size_t(blockIdx.x) * (nc + 1) : nullptr;
+  if (cnt == 0) {
+    if (cs)
+      for (int i = threadIdx.x; i <= nc; i += kBlock) cs[i] = 0;
+    return;
+  }
+  const size_t off = size_t(a.offsets[blockIdx.x]);
   for (int i = threadIdx.x; i < nc; i += kBlock) slot[i] = 0;
   __syncthreads();
   for (int i = threadIdx.x; i < cnt; i += kBlock) atomicAdd(&slot[cell_key_at(a.in_coords, off + i, d, T)], 1);
   __syncthreads();
   scan_bins(slot, nc, part);
+  if (cs) {
+    for (int i = threadIdx.x; i < nc; i += kBlock) cs[i] = slot[i];
+    if (threadIdx.x == 0) cs[nc] = cnt;
+  }
+  __syncthreads();
   for (int i = threadIdx.x; i < cnt; i += kBlock) {
     const size_t q = off + i;
     const size_t pos = off + atomicAdd(&slot[cell_key_at(a.in_coords, q, d, T)], 1);
