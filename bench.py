@@ -274,6 +274,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-legs", action="store_true", help="skip the log-domain, batched, gradient, ball/shell and paper-shape legs")
+    ap.add_argument("--only-leg", choices=("batched", "gradient", "ball_shell", "paper_shapes"),
+                    help="run one secondary leg alone and print its JSON (for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with one device copy of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -285,6 +287,14 @@ def main():
     import numpy as np
     import torch
     from paper_2201_07524_amd import nfs, workloads
+
+    if args.only_leg:
+        dev = torch.device("cuda:0")
+        T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+        leg = {"batched": batched_leg, "gradient": grad_leg, "ball_shell": ball_shell_leg,
+               "paper_shapes": paper_shapes_leg}[args.only_leg]
+        print(json.dumps({args.only_leg: leg(nfs, workloads, torch, T)}), flush=True)
+        return
 
     log("bench: generating the 2-D mixture workload")
     cfg = workloads.gmm_2d(args.n)
