@@ -34,11 +34,7 @@ struct WindowConst {
   double b;      // pi (2 - 1/sigma)
   double bm;     // b m
   double cnorm;  // bm / (1 - exp(-2 bm))
-  double e2bm;   // exp(-2 bm)
   double edge;   // 2 cnorm exp(-bm): psi at the support edge
-  double b2;     // b log2(e)
-  double bm2;    // bm log2(e)
-  double cn2;    // cnorm log2(e)
 };
 
 template <typename R>
@@ -48,26 +44,6 @@ __device__ __forceinline__ R kb_psi(R z, R m2, R b, R bm, R cnorm) {
   const R a = b * sqrt(t);
   if (a < R(1e-4)) return cnorm * R(2) * exp(-bm);
   return cnorm * (exp(a - bm) - exp(-a - bm)) / a;
-}
-
-// FP32 form with the hardware transcendentals (v_sqrt_f32, v_exp_f32 = 2^x,
-// v_rcp_f32) and one exponential.  All constants are pre-scaled by log2(e) on
-// the host (b2 = b log2 e, bm2 = b m log2 e, cn2 = cnorm log2 e), so with
-// a2 = b2 sqrt(m^2 - z^2) and E = 2^(a2 - bm2)
-//   psi = cn2 (E - exp(-2 b m)/E) / a2.
-// The exponent is then formed exactly as in the accurate form (one rounding of
-// a2, one subtraction), and the instructions add about 1 ulp each.
-// edge = 2 cnorm exp(-b m) is the limit at the support edge (a2 -> 0).
-__device__ __forceinline__ float kb_psi_fast(float z, float m2, float b2, float bm2, float cn2, float e2bm,
-                                             float edge) {
-  // branch-free: out-of-support and edge cases are selected at the end, so
-  // the 2 d (2m+1) evaluations of a point compile to straight-line code
-  const float t = fmaf(-z, z, m2);
-  const float a2 = b2 * __builtin_amdgcn_sqrtf(fmaxf(t, 0.0f));
-  const float E = __builtin_amdgcn_exp2f(a2 - bm2);
-  const float v = cn2 * (E - e2bm * __builtin_amdgcn_rcpf(E)) * __builtin_amdgcn_rcpf(a2);
-  const float r = a2 < 1.5e-3f ? edge : v;
-  return t > 0.0f ? r : 0.0f;
 }
 
 // Per-tap polynomial form of the FP32 window.  A point whose first tap lies at

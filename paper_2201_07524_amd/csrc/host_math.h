@@ -33,12 +33,7 @@ inline WindowConst make_window(int m, int g, int N) {
   w.m2 = double(m) * double(m);
   w.bm = w.b * m;
   w.cnorm = w.bm / (1.0 - std::exp(-2.0 * w.bm));
-  w.e2bm = std::exp(-2.0 * w.bm);
   w.edge = 2.0 * w.cnorm * std::exp(-w.bm);
-  const double log2e = 1.4426950408889634;
-  w.b2 = w.b * log2e;
-  w.bm2 = w.bm * log2e;
-  w.cn2 = w.cnorm * log2e;
   return w;
 }
 

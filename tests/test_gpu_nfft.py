@@ -174,6 +174,22 @@ def test_fastsum_r1_fp64_matches_dense(d, N, eps, tol):
     assert relerr(got, ref) <= tol
 
 
+def test_fastsum_r1_cell_culled_and_tile_scan_near_fields_agree():
+    """The near field reads only the source cells within eps_I of each wave's
+    targets when the plan leaves per-cell starts (tiles of at most 4096
+    cells), and scans whole neighbour tiles otherwise (here 128^2-cell tiles).
+    Both are the same sum in another order: FP64 agreement to rounding, and
+    both within the r = 1 bound against the dense kernel."""
+    src, w, tgt = _r1_clouds(2, 3000, 1300)
+    ref = sd.gibbs_kernel(tgt, src, 1, 0.03) @ w
+    got = []
+    for tile in (0, 128):
+        prm = nfs.Params(d=2, r=1, eps=0.03, N=256, m=4, precision="fp64", eps_I=8, p_smooth=10, tile=tile)
+        got.append(nfs.fastsum(prm, T(src), T(w), T(tgt)).cpu().numpy())
+    assert relerr(got[0], got[1]) <= 1e-12
+    assert relerr(got[0], ref) <= 1e-5 and relerr(got[1], ref) <= 1e-5
+
+
 def test_fastsum_r1_error_decays_with_near_field_radius():
     src, w, tgt = _r1_clouds(3, 1000, 1100)
     ref = sd.gibbs_kernel(tgt, src, 1, 0.05) @ w
