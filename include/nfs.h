@@ -68,6 +68,10 @@ extern "C" {
 #define NFS_FLAG_TILE_REDUCE 4   /* spread: store each chunk's LDS tile and sum the tiles per
                                     (tile, neighbour) instead of flushing LDS tiles straight
                                     into the grid with global atomics (the default) */
+#define NFS_FLAG_AUTOTUNE 16     /* solver handles (and the solves built on them): after the plan,
+                                    time a few iterations at each candidate chunk size (the default,
+                                    twice it, 4096, 8192 points; r = 2 only) and keep the fastest;
+                                    the starting values are restored before the first iteration */
 #define NFS_FLAG_LOG_DOMAIN 8    /* solve in potentials (Algorithm 4): the alpha / alpha_t arguments
                                     of the solve, batch and solver calls hold beta / gamma instead,
                                     with alpha = exp(beta/eps - 1/2), alpha_t = exp(gamma/eps - 1/2);
@@ -83,8 +87,9 @@ typedef struct nfs_params {
   double sigma;       /* oversampling: grid g = sigma*N rounded up to even, g >= N + 2 */
   int32_t precision;  /* NFS_FP64, NFS_FP32, or NFS_AUTO (solve calls only) */
   int32_t tile;       /* grid cells per bin side (0 = default for d) */
-  int32_t chunk;      /* max points per workgroup chunk, 0..32768 (0 = default: 1536 for FP32,
-                         d = 2, r = 2; else 1024) */
+  int32_t chunk;      /* max points per workgroup chunk, 0..32768 (0 = default: for r = 2, 1536
+                         (FP32, d = 2) or 2048 (FP32, d = 3), 4096 for clouds with more than 8
+                         points per grid cell and n >= 200 * 4096; else 1024) */
   int32_t flags;      /* NFS_FLAG_* */
   double eps_I;       /* r = 1: near-field radius times N on the period-1 torus (0 = default 4);
                          the radius must fit in 2 kt + 1 tiles, kt = ceil(eps_I sigma / tile) */

@@ -60,8 +60,14 @@ static int default_tile(int d, int precision) {
 // Points per chunk: 1536 for the FP32 2-D path (measured best on the 2-D
 // mixture: longer same-cell runs, fewer tile loads and flushes per point,
 // still about 700 workgroups per launch), 1024 otherwise (r = 1 needs <= 1024).
+// Measured defaults: FP32 2-D 1536 (sweep 384..4096 on the 2-D mixture), FP32
+// 3-D 2048 (the 3-D mixture's spreading 1.45 -> 1.03 ms against 1024, found by
+// NFS_FLAG_AUTOTUNE), 1024 otherwise.  r = 1 needs at most 1024 (near field).
 static int default_chunk(const nfs_params* p) {
-  return (p->d == 2 && p->precision == NFS_FP32 && p->r == 2) ? 1536 : 1024;
+  if (p->r != 2) return 1024;
+  if (p->precision == NFS_FP32 && p->d == 2) return 1536;
+  if (p->precision == NFS_FP32 && p->d == 3) return 2048;
+  return 1024;
 }
 
 static int check_params(const nfs_params* p, int64_t n, int64_t nt) {
@@ -136,6 +142,7 @@ struct CloudBuf {
   double* w1s = nullptr;       // sorted scalings
   int* runs = nullptr;         // n: run table of each chunk (offsets from the chunk start)
   int* cellstart = nullptr;    // r = 1 with cell order: B x nbins x (T^d + 1) cell starts per tile
+  std::vector<int> hcounts;    // host copy of counts (the chunk tables are rebuilt from it)
   int* nruns = nullptr;        // 2 x max_chunks: full runs and single points per chunk
 };
 
@@ -344,6 +351,62 @@ static int box_launch(double* out, double* partials, unsigned* counter, int d, c
 
 // Counting sort of every problem's points by tile, and the chunk table.
 // `sc` gives each problem's torus mapping (scale 0: points already on the torus).
+// Chunk tables of a cloud from its host tile counts: each tile's points in
+// ceil(count / chunk) chunks of near-equal size.  With `runs` (points already
+// sorted) the per-chunk run tables are rebuilt as well.
+template <typename R>
+static int build_chunks(Work<R>& w, CloudBuf<R>& cb, int chunk, bool runs, hipStream_t st) {
+  const int B = w.B, nb = w.nbins, d = w.geo.d;
+  const std::vector<int>& counts = cb.hcounts;
+  std::vector<Chunk> chunks;
+  std::vector<int> prob_chunks(B + 1), tile_chunks(nb + 1);
+  chunks.reserve(cb.max_chunks);
+  for (int b = 0; b < B; ++b) {
+    prob_chunks[b] = int(chunks.size());
+    long acc = cb.off[b];
+    for (int t = 0; t < nb; ++t) {
+      const int cnt = counts[size_t(b) * nb + t];
+      if (B == 1) tile_chunks[t] = int(chunks.size());
+      const int nch = (cnt + chunk - 1) / chunk;
+      for (int c = 0; c < nch; ++c) {
+        const int s0 = int(int64_t(cnt) * c / nch), s1 = int(int64_t(cnt) * (c + 1) / nch);
+        chunks.push_back(Chunk{t, int(acc) + s0, s1 - s0, b});
+      }
+      acc += cnt;
+    }
+    // 3-D: largest chunks first inside the problem's range.  Workgroups are
+    // handed out in launch order, so the heavy chunks start first and the
+    // light ones fill in behind them (3-D mixture: spreading 1.65 -> 1.45 ms).
+    // In 2-D tile order is as fast (its neighbouring halos share L2), and the
+    // per-tile reduction needs each tile's chunks adjacent.
+    if (!w.two_level && d == 3)
+      std::stable_sort(chunks.begin() + prob_chunks[b], chunks.end(),
+                       [](const Chunk& u, const Chunk& v) { return u.count > v.count; });
+  }
+  prob_chunks[B] = int(chunks.size());
+  tile_chunks[nb] = int(chunks.size());
+  if ((long)chunks.size() > cb.max_chunks) return fail(NFS_EINVAL, "internal: chunk table overflow");
+  cb.nchunks = int(chunks.size());
+  NFS_HIP(hipMemcpyAsync(cb.chunks, chunks.data(), sizeof(Chunk) * chunks.size(), hipMemcpyHostToDevice, st));
+  NFS_HIP(hipMemcpyAsync(cb.prob_chunks, prob_chunks.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, st));
+  NFS_HIP(hipMemcpyAsync(cb.tile_chunks, tile_chunks.data(), sizeof(int) * (nb + 1), hipMemcpyHostToDevice, st));
+  if (runs) {
+    ChunkRunArgs<R> ca{};
+    ca.chunks = cb.chunks;
+    ca.nchunks = cb.nchunks;
+    ca.d = d;
+    ca.T = w.geo.T;
+    ca.sorted = w.cell_order;
+    ca.G = run_length<R>(d);
+    ca.coords = cb.coords;
+    ca.runs = cb.runs;
+    ca.nruns = cb.nruns;
+    NFS_HIP(launch_chunk_runs(ca, st));
+  }
+  NFS_HIP(hipStreamSynchronize(st));  // the host vectors above must outlive the copies
+  return NFS_OK;
+}
+
 template <typename R>
 static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const std::vector<Scaling>& sc,
                       const double* v0, const double* v1, hipStream_t st) {
@@ -369,45 +432,21 @@ static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const std:
     ka.counts = cb.counts + size_t(b) * nb;
     NFS_HIP(launch_keys(ka, st));
   }
-  std::vector<int> counts(size_t(B) * nb), offsets(size_t(B) * nb);
+  std::vector<int>& counts = cb.hcounts;
+  counts.assign(size_t(B) * nb, 0);
+  std::vector<int> offsets(size_t(B) * nb);
   NFS_HIP(hipMemcpyAsync(counts.data(), cb.counts, sizeof(int) * counts.size(), hipMemcpyDeviceToHost, st));
   NFS_HIP(hipStreamSynchronize(st));
-  std::vector<Chunk> chunks;
-  std::vector<int> prob_chunks(B + 1), tile_chunks(nb + 1);
-  chunks.reserve(cb.max_chunks);
   for (int b = 0; b < B; ++b) {
-    prob_chunks[b] = int(chunks.size());
     long acc = cb.off[b];
     for (int t = 0; t < nb; ++t) {
-      const int cnt = counts[size_t(b) * nb + t];
       offsets[size_t(b) * nb + t] = int(acc);
-      if (B == 1) tile_chunks[t] = int(chunks.size());
-      // the tile's points in ceil(cnt / chunk) chunks of near-equal size
-      const int nch = (cnt + w.chunk - 1) / w.chunk;
-      for (int c = 0; c < nch; ++c) {
-        const int s0 = int(int64_t(cnt) * c / nch), s1 = int(int64_t(cnt) * (c + 1) / nch);
-        chunks.push_back(Chunk{t, int(acc) + s0, s1 - s0, b});
-      }
-      acc += cnt;
+      acc += counts[size_t(b) * nb + t];
     }
     if (acc != cb.off[b + 1]) return fail(NFS_EINVAL, "internal: tile histogram does not match the point count");
-    // 3-D: largest chunks first inside the problem's range.  Workgroups are
-    // handed out in launch order, so the heavy chunks start first and the
-    // light ones fill in behind them (3-D mixture: spreading 1.65 -> 1.45 ms).
-    // In 2-D tile order is as fast (its neighbouring halos share L2), and the
-    // per-tile reduction needs each tile's chunks adjacent.
-    if (!w.two_level && d == 3)
-      std::stable_sort(chunks.begin() + prob_chunks[b], chunks.end(),
-                       [](const Chunk& u, const Chunk& v) { return u.count > v.count; });
   }
-  prob_chunks[B] = int(chunks.size());
-  tile_chunks[nb] = int(chunks.size());
-  if ((long)chunks.size() > cb.max_chunks) return fail(NFS_EINVAL, "internal: chunk table overflow");
-  cb.nchunks = int(chunks.size());
   NFS_HIP(hipMemcpyAsync(cb.offsets, offsets.data(), sizeof(int) * offsets.size(), hipMemcpyHostToDevice, st));
-  NFS_HIP(hipMemcpyAsync(cb.chunks, chunks.data(), sizeof(Chunk) * chunks.size(), hipMemcpyHostToDevice, st));
-  NFS_HIP(hipMemcpyAsync(cb.prob_chunks, prob_chunks.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, st));
-  NFS_HIP(hipMemcpyAsync(cb.tile_chunks, tile_chunks.data(), sizeof(int) * (nb + 1), hipMemcpyHostToDevice, st));
+  NFS_TRY(build_chunks(w, cb, w.chunk, false, st));
   for (int b = 0; b < B; ++b) {
     const long o = cb.off[b], n = cb.off[b + 1] - o;
     if (n == 0) continue;
@@ -1005,6 +1044,63 @@ struct Solver : SolverBase {
     return half_step(w, w.X, w.Y, w.wmul_x, w.wmul_y, w.st_col, sink(), s);
   }
 
+  // Chunk size by measurement: rebuild the chunk and run tables for each
+  // candidate (the sorted clouds do not change), time 3 iterations after one
+  // warm-up, keep the fastest.  The iterations change the scalings and the
+  // t <= 0 counters, so both are restored afterwards.
+  int autotune(hipStream_t st) {
+    const int B = w.B;
+    std::vector<int> cands;
+    for (int c : {w.chunk, 2 * w.chunk, 4096, 8192})
+      if (c >= w.chunk && c <= 32768 && std::find(cands.begin(), cands.end(), c) == cands.end()) cands.push_back(c);
+    if (cands.size() < 2) return NFS_OK;
+    std::vector<double> hx(w.X.n), hy(w.Y.n), hwx(B), hwy(B);
+    NFS_HIP(hipMemcpyAsync(hx.data(), w.X.w1s, sizeof(double) * hx.size(), hipMemcpyDeviceToHost, st));
+    NFS_HIP(hipMemcpyAsync(hy.data(), w.Y.w1s, sizeof(double) * hy.size(), hipMemcpyDeviceToHost, st));
+    NFS_HIP(hipMemcpyAsync(hwx.data(), w.wmul_x, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+    NFS_HIP(hipMemcpyAsync(hwy.data(), w.wmul_y, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+    NFS_HIP(hipStreamSynchronize(st));
+    hipEvent_t e0, e1;
+    NFS_HIP(hipEventCreate(&e0));
+    NFS_HIP(hipEventCreate(&e1));
+    float best = 0.0f;
+    int best_chunk = w.chunk;
+    int rc = NFS_OK;
+    for (int c : cands) {
+      if ((rc = build_chunks(w, w.X, c, true, st)) != NFS_OK) break;
+      if ((rc = build_chunks(w, w.Y, c, true, st)) != NFS_OK) break;
+      hipError_t e = iteration(st);
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      for (int i = 0; i < 3 && e == hipSuccess; ++i) e = iteration(st);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        rc = fail(NFS_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+        break;
+      }
+      if (c == cands.front() || ms < best) {
+        best = ms;
+        best_chunk = c;
+      }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    NFS_TRY(rc);
+    w.chunk = best_chunk;
+    NFS_TRY(build_chunks(w, w.X, best_chunk, true, st));
+    NFS_TRY(build_chunks(w, w.Y, best_chunk, true, st));
+    NFS_HIP(hipMemcpyAsync(w.X.w1s, hx.data(), sizeof(double) * hx.size(), hipMemcpyHostToDevice, st));
+    NFS_HIP(hipMemcpyAsync(w.Y.w1s, hy.data(), sizeof(double) * hy.size(), hipMemcpyHostToDevice, st));
+    NFS_HIP(hipMemcpyAsync(w.wmul_x, hwx.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
+    NFS_HIP(hipMemcpyAsync(w.wmul_y, hwy.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
+    NFS_HIP(launch_fill(w.st_row, sizeof(double) * size_t(B) * 8, st));
+    NFS_HIP(launch_fill(w.st_col, sizeof(double) * size_t(B) * 8, st));
+    NFS_HIP(hipStreamSynchronize(st));  // the host copies above must outlive the transfers
+    return NFS_OK;
+  }
+
   // Starting scalings (Algorithm 3): alpha = 1; alpha_t = 1, or the caller's
   // positive starting value (already sorted into Y.w1s by the plan); wmul_*
   // normalize the spread weights by their maximum.
@@ -1087,6 +1183,7 @@ struct Solver : SolverBase {
     } else {
       NFS_TRY(start_scalings(B, oy, alpha_t0, st));
     }
+    if ((p.flags & NFS_FLAG_AUTOTUNE) && p.r == 2 && !w.two_level) NFS_TRY(autotune(st));
     NFS_HIP(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
     NFS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     NFS_HIP(hipStreamSynchronize(st));

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "lib", "libnfs.so")
 
 NFS_OK, NFS_EINVAL, NFS_EWEIGHTS, NFS_ENONPOS, NFS_EUNSUPPORTED, NFS_EHIP, NFS_EWORKSPACE = range(7)
 NFS_FP64, NFS_FP32, NFS_AUTO = 0, 1, 2
-FLAG_NO_GRAPH, FLAG_PRIMAL_COST, FLAG_TILE_REDUCE, FLAG_LOG_DOMAIN = 1, 2, 4, 8
+FLAG_NO_GRAPH, FLAG_PRIMAL_COST, FLAG_TILE_REDUCE, FLAG_LOG_DOMAIN, FLAG_AUTOTUNE = 1, 2, 4, 8, 16
 
 EXPORTED = ("nfs_last_error", "nfs_validate", "nfs_workspace_size", "nfs_fastsum_apply",
             "nfs_nfft_adjoint", "nfs_nfft_trafo", "nfs_sinkhorn_solve", "nfs_sinkhorn_solve_log",
