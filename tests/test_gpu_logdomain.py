@@ -183,3 +183,41 @@ def test_full_size_2d_mixture_sampled():
     rows = np.union1d(rows, [np.argmax(tt_gpu)])
     tt = direct.kv(cfg["y"], cfg["x"], np.exp(b / eps - 0.5), 2, eps, rows=rows)
     assert np.max(np.abs(tt_gpu[rows] - tt)) <= 1e-5 * np.max(tt)
+
+
+def test_r1_log_domain_vs_oracle():
+    """Euclidean cost (r = 1) in the log domain: the near field takes the same
+    exp((gamma - max gamma)/eps) weights as the spread.  FP64 with eps_I = 8/N,
+    p = 10: the cost within the r = 1 truncation bound (5e-7 relative); the
+    potentials within 1e-5 * eps (a potential carries the relative error of
+    its own sum, which for the smallest sums exceeds the normwise bound)."""
+    x = workloads.uniform_ball(1200, 71, d=3)
+    y = workloads.noisy_shell(1100, 72, d=3)
+    p, pt = workloads.uniform_weights(1200), workloads.dirichlet_weights(1100, 73)
+    eps, iters = 0.05, 20
+    cfg = dict(x=x, p=p, y=y, pt=pt)
+    ref = sd.solve_log(x, p, y, pt, 1, eps, iters)
+    res = solve_log(cfg, iters, "fp64", 32, 8, eps, r=1, eps_I=8, p_smooth=10)
+    same_potentials(res.beta, ref["beta"], 1e-5 * eps)
+    same_potentials(res.gamma, ref["gamma"], 1e-5 * eps)
+    assert rel(res.cost, ref["cost"]) <= 5e-7
+
+
+def test_auto_promotion_in_the_log_domain():
+    """NFS_AUTO with the log-domain solve: the separated problem whose FP32
+    sums hit t <= 0 is solved again with FP64 grids and matches the FP64
+    log-domain solve to rounding."""
+    rng = np.random.default_rng(11)
+    n = 600
+    x = np.concatenate([rng.normal(-0.2, 0.01, n // 2), rng.normal(0.2, 0.01, n - n // 2)])[:, None]
+    y = rng.normal(0.2, 0.01, n)[:, None]
+    cfg = dict(x=x, p=np.full(n, 1.0 / n), y=y, pt=np.full(n, 1.0 / n))
+    eps = 0.0085
+    prm32 = nfs.Params(d=1, eps=eps, N=256, m=8, precision="fp32")
+    r32 = nfs.sinkhorn_log(prm32, T(x), T(cfg["p"]), T(y), T(cfg["pt"]), 20, check=False)
+    assert r32.n_nonpos > 0
+    ra = solve_log(cfg, 20, "auto", 256, 8, eps)
+    r64 = solve_log(cfg, 20, "fp64", 256, 8, eps)
+    assert ra.precision_used == "fp64" and ra.n_nonpos == 0
+    assert abs(ra.cost - r64.cost) <= 1e-6 * abs(r64.cost)
+    assert np.max(np.abs(ra.gamma.cpu().numpy() - r64.gamma.cpu().numpy())) <= 1e-5 * eps
