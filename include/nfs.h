@@ -88,7 +88,7 @@ typedef struct nfs_params {
   int32_t precision;  /* NFS_FP64, NFS_FP32, or NFS_AUTO (solve calls only) */
   int32_t tile;       /* grid cells per bin side (0 = default for d) */
   int32_t chunk;      /* max points per workgroup chunk, 0..32768 (0 = default: for r = 2, 1536
-                         (FP32, d = 2) or 2048 (FP32, d = 3), 4096 for clouds with more than 8
+                         (FP32, d = 2) or 4096 (FP32, d = 3), 4096 for clouds with more than 8
                          points per grid cell and n >= 200 * 4096; else 1024) */
   int32_t flags;      /* NFS_FLAG_* */
   double eps_I;       /* r = 1: near-field radius times N on the period-1 torus (0 = default 4);

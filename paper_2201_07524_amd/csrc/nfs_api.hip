@@ -61,12 +61,13 @@ static int default_tile(int d, int precision) {
 // mixture: longer same-cell runs, fewer tile loads and flushes per point,
 // still about 700 workgroups per launch), 1024 otherwise (r = 1 needs <= 1024).
 // Measured defaults: FP32 2-D 1536 (sweep 384..4096 on the 2-D mixture), FP32
-// 3-D 2048 (the 3-D mixture's spreading 1.45 -> 1.03 ms against 1024, found by
-// NFS_FLAG_AUTOTUNE), 1024 otherwise.  r = 1 needs at most 1024 (near field).
+// 3-D 4096 (picked by NFS_FLAG_AUTOTUNE on the 3-D mixture: iteration 3.25 ms
+// against 3.41 at 2048 and 4.2 at 1024), 1024 otherwise.  r = 1 needs at most
+// 1024 (near field).
 static int default_chunk(const nfs_params* p) {
   if (p->r != 2) return 1024;
   if (p->precision == NFS_FP32 && p->d == 2) return 1536;
-  if (p->precision == NFS_FP32 && p->d == 3) return 2048;
+  if (p->precision == NFS_FP32 && p->d == 3) return 4096;
   return 1024;
 }
 
@@ -144,6 +145,8 @@ struct CloudBuf {
   int* cellstart = nullptr;    // r = 1 with cell order: B x nbins x (T^d + 1) cell starts per tile
   std::vector<int> hcounts;    // host copy of counts (the chunk tables are rebuilt from it)
   int* nruns = nullptr;        // 2 x max_chunks: full runs and single points per chunk
+  int* srun = nullptr;         // n: spreading's run table (cell order only)
+  int* nsrun = nullptr;        // 2 x max_chunks: its pair entries and solo runs per chunk
 };
 
 template <typename R>
@@ -252,6 +255,8 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
     cb.tile_chunks = cv.take<int>(nbins + 1);
     cb.runs = cv.take<int>(n);
     cb.nruns = cv.take<int>(2 * cb.max_chunks);
+    cb.srun = cv.take<int>(n);
+    cb.nsrun = cv.take<int>(2 * cb.max_chunks);
     cb.w0s = nvec >= 1 ? cv.take<double>(n) : nullptr;
     cb.w1s = nvec >= 2 ? cv.take<double>(n) : nullptr;
   };
@@ -401,6 +406,8 @@ static int build_chunks(Work<R>& w, CloudBuf<R>& cb, int chunk, bool runs, hipSt
     ca.coords = cb.coords;
     ca.runs = cb.runs;
     ca.nruns = cb.nruns;
+    ca.srun = w.cell_order ? cb.srun : nullptr;
+    ca.nsrun = cb.nsrun;
     NFS_HIP(launch_chunk_runs(ca, st));
   }
   NFS_HIP(hipStreamSynchronize(st));  // the host vectors above must outlive the copies
@@ -503,6 +510,8 @@ static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const std:
   ca.coords = cb.coords;
   ca.runs = cb.runs;
   ca.nruns = cb.nruns;
+  ca.srun = w.cell_order ? cb.srun : nullptr;
+  ca.nsrun = cb.nsrun;
   NFS_HIP(launch_chunk_runs(ca, st));
   NFS_HIP(hipStreamSynchronize(st));  // host vectors above must outlive the copies
   return NFS_OK;
@@ -681,6 +690,8 @@ static SpreadArgs<R> spread_args(Work<R>& w, const CloudBuf<R>& src, const doubl
   a.chunks = src.chunks;
   a.runs = src.runs;
   a.nruns = src.nruns;
+  a.srun = w.cell_order ? src.srun : nullptr;
+  a.nsrun = src.nsrun;
   a.cell_order = w.cell_order;
   a.grid = w.S;
   a.grid_stride = w.ncell;

@@ -194,34 +194,71 @@ struct Acc<double, ACC_FIX128> {
   }
 };
 
+// The value of the partner lane (lane ^ 1) by a DPP quad permutation [1,0,3,2].
+__device__ __forceinline__ float pair_partner(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double pair_partner(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffLL), 0xB1, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0xB1, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Adds the W taps of one tile row.  tap(j) gives this lane's value of tap j.
+// PAIR: lanes 2i and 2i+1 hold two runs of the same cell (same tap offsets);
+// each pair of taps is summed across the two lanes by DPP, and the even lane
+// adds tap j while the odd lane adds tap j + 1, so one atomic instruction
+// with every lane active does the work of two (the last, odd tap is added by
+// the even lane alone).
+template <bool PAIR, int W, typename R, typename ACCT, typename F>
+__device__ __forceinline__ void add_row(ACCT& tile, int row, int member, F tap) {
+  if constexpr (!PAIR) {
+#pragma unroll
+    for (int j = 0; j < W; ++j) tile.add(row + j, tap(j));
+  } else {
+#pragma unroll
+    for (int j = 0; j + 1 < W; j += 2) {
+      R v0 = tap(j), v1 = tap(j + 1);
+      v0 += pair_partner(v0);
+      v1 += pair_partner(v1);
+      tile.add(row + j + member, member ? v1 : v0);
+    }
+    R v = tap(W - 1);
+    v += pair_partner(v);
+    if (member == 0) tile.add(row + W - 1, v);
+  }
+}
+
 // Spreads GC consecutive sorted points that lie in one cell (so their windows
 // start at the same offsets): per tap the GC contributions are summed in
 // registers, and the tap costs one fixed-point conversion and one LDS atomic
 // for the whole run.
-template <typename R, int D, int M, int ACC, int GC>
+// cnt (1..GC): the run's points; the others get weight zero and repeat the
+// last point, so no read leaves the run.  PAIR: see add_row (member = lane & 1).
+template <typename R, int D, int M, int ACC, int GC, bool PAIR = false>
 __device__ __forceinline__ void spread_run(Acc<R, ACC>& tile, const SpreadArgs<R>& a, const WinEval<R>& ev, int E,
-                                           int q0, double wm) {
+                                           int q0, double wm, int cnt = GC, int member = 0) {
   constexpr int W = 2 * M + 1;
   constexpr int FROM = D == 1 ? 0 : 1;
   Taps<R, D, M, FROM> tp[GC];
   R w[GC];
 #pragma unroll
   for (int p = 0; p < GC; ++p) {
-    const int q = q0 + p;
-    w[p] = R(a.w[q] * wm);
+    const int q = q0 + min(p, cnt - 1);
+    w[p] = p < cnt ? R(a.w[q] * wm) : R(0);
     R u[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) u[c] = a.coords[size_t(q) * D + c];
     tp[p].compute(u, ev);
   }
   if constexpr (D == 1) {
-#pragma unroll
-    for (int j = 0; j < W; ++j) {
+    add_row<PAIR, W, R>(tile, tp[0].off[0], member, [&](int j) {
       R v = R(0);
 #pragma unroll
       for (int p = 0; p < GC; ++p) v += w[p] * tp[p].psi[0][j];
-      tile.add(tp[0].off[0] + j, v);
-    }
+      return v;
+    });
   } else if constexpr (D == 2) {
 #pragma unroll 1
     for (int j0 = 0; j0 < W; ++j0) {
@@ -229,13 +266,12 @@ __device__ __forceinline__ void spread_run(Acc<R, ACC>& tile, const SpreadArgs<R
 #pragma unroll
       for (int p = 0; p < GC; ++p) a0[p] = w[p] * ev.tap(j0, tp[p].x[0]);
       const int row = (tp[0].off[0] + j0) * E + tp[0].off[1];
-#pragma unroll
-      for (int j1 = 0; j1 < W; ++j1) {
+      add_row<PAIR, W, R>(tile, row, member, [&](int j1) {
         R v = R(0);
 #pragma unroll
         for (int p = 0; p < GC; ++p) v += a0[p] * tp[p].psi[1][j1];
-        tile.add(row + j1, v);
-      }
+        return v;
+      });
     }
   } else {
 #pragma unroll 1
@@ -251,13 +287,12 @@ __device__ __forceinline__ void spread_run(Acc<R, ACC>& tile, const SpreadArgs<R
 #pragma unroll
           for (int p = 0; p < GC; ++p) a1[p] = b0[p] * tp[p].psi[1][j1];
           const int row = ((tp[0].off[0] + j0) * E + tp[0].off[1] + j1) * E + tp[0].off[2];
-#pragma unroll
-          for (int j2 = 0; j2 < W; ++j2) {
+          add_row<PAIR, W, R>(tile, row, member, [&](int j2) {
             R v = R(0);
 #pragma unroll
             for (int p = 0; p < GC; ++p) v += a1[p] * tp[p].psi[2][j2];
-            tile.add(row + j2, v);
-          }
+            return v;
+          });
         }
       } else {
         // FP64: the rolled j1 loop reads element 0 of the second-axis windows,
@@ -268,13 +303,12 @@ __device__ __forceinline__ void spread_run(Acc<R, ACC>& tile, const SpreadArgs<R
 #pragma unroll
           for (int p = 0; p < GC; ++p) a1[p] = b0[p] * tp[p].psi[1][0];
           const int row = ((tp[0].off[0] + j0) * E + tp[0].off[1] + j1) * E + tp[0].off[2];
-#pragma unroll
-          for (int j2 = 0; j2 < W; ++j2) {
+          add_row<PAIR, W, R>(tile, row, member, [&](int j2) {
             R v = R(0);
 #pragma unroll
             for (int p = 0; p < GC; ++p) v += a1[p] * tp[p].psi[2][j2];
-            tile.add(row + j2, v);
-          }
+            return v;
+          });
 #pragma unroll
           for (int p = 0; p < GC; ++p) rotate_left(tp[p].psi[1]);
         }
@@ -309,17 +343,43 @@ __global__ __launch_bounds__(spread_block(D)) void spread_kernel(SpreadArgs<R> a
   constexpr int G = run_length<R>(D);
   const WinEval<R> ev(a.win, a.wpoly, M);
   const double wm = a.wconst * (a.wmul ? a.wmul[ch.prob] : 1.0);
-  const int* runs = a.runs + ch.start;
-  const int nfull = a.nruns[2 * blockIdx.x], nsingle = a.nruns[2 * blockIdx.x + 1];
-  int rows = (nfull + kWave - 1) / kWave;
-  for (int slot = threadIdx.x; slot < rows * kWave; slot += BS) {
-    const int rr = run_of_slot(slot, rows);
-    if (rr < nfull) spread_run<R, D, M, ACC, G>(tile, a, ev, E, ch.start + runs[rr], wm);
-  }
-  rows = (nsingle + kWave - 1) / kWave;
-  for (int slot = threadIdx.x; slot < rows * kWave; slot += BS) {
-    const int rr = run_of_slot(slot, rows);
-    if (rr < nsingle) spread_run<R, D, M, ACC, 1>(tile, a, ev, E, ch.start + runs[nfull + rr], wm);
+  if (a.srun) {
+    // every point in a run of at most G (the last run of a cell partial);
+    // same-cell pairs of runs on adjacent lanes, 32 pairs per wave row,
+    // spread over the chunk like the runs below
+    const int* sr = a.srun + ch.start;
+    const int npe = a.nsrun[2 * blockIdx.x], nsolo = a.nsrun[2 * blockIdx.x + 1];
+    const int npairs = npe / 2;
+    int rows = (npairs + kWave / 2 - 1) / (kWave / 2);
+    for (int slot = threadIdx.x; slot < rows * kWave; slot += BS) {
+      const int lane = slot % kWave;
+      const int pair = (lane >> 1) * rows + slot / kWave;
+      if (pair < npairs) {
+        const int e = sr[2 * pair + (lane & 1)];
+        spread_run<R, D, M, ACC, G, true>(tile, a, ev, E, ch.start + (e & 0xffff), wm, (e >> 16) + 1, lane & 1);
+      }
+    }
+    rows = (nsolo + kWave - 1) / kWave;
+    for (int slot = threadIdx.x; slot < rows * kWave; slot += BS) {
+      const int rr = run_of_slot(slot, rows);
+      if (rr < nsolo) {
+        const int e = sr[npe + rr];
+        spread_run<R, D, M, ACC, G>(tile, a, ev, E, ch.start + (e & 0xffff), wm, (e >> 16) + 1);
+      }
+    }
+  } else {
+    const int* runs = a.runs + ch.start;
+    const int nfull = a.nruns[2 * blockIdx.x], nsingle = a.nruns[2 * blockIdx.x + 1];
+    int rows = (nfull + kWave - 1) / kWave;
+    for (int slot = threadIdx.x; slot < rows * kWave; slot += BS) {
+      const int rr = run_of_slot(slot, rows);
+      if (rr < nfull) spread_run<R, D, M, ACC, G>(tile, a, ev, E, ch.start + runs[rr], wm);
+    }
+    rows = (nsingle + kWave - 1) / kWave;
+    for (int slot = threadIdx.x; slot < rows * kWave; slot += BS) {
+      const int rr = run_of_slot(slot, rows);
+      if (rr < nsingle) spread_run<R, D, M, ACC, 1>(tile, a, ev, E, ch.start + runs[nfull + rr], wm);
+    }
   }
   __syncthreads();
 

@@ -387,6 +387,35 @@ __global__ __launch_bounds__(kBlock) void chunk_runs_kernel(ChunkRunArgs<R> a) {
     a.nruns[2 * blockIdx.x] = total_full;
     a.nruns[2 * blockIdx.x + 1] = total_sing;
   }
+  if (!a.srun) return;
+  // spreading's table: ceil(c / G) runs per cell (the last partial), pairs of
+  // same-cell runs first, then the odd run of each cell
+  int* srun = a.srun + ch.start;
+  int npe = 0, nsolo = 0;
+  for (int i = b0; i < b1; ++i) {
+    const int q = (start[i] + G - 1) / G;
+    npe += 2 * (q / 2);
+    nsolo += q % 2;
+  }
+  int total_pe, total_solo;
+  int ppos = block_exclusive_scan(npe, part, &total_pe);
+  int opos = total_pe + block_exclusive_scan(nsolo, part, &total_solo);
+  int p0 = pos;  // pos was advanced over this thread's cells above: rewind it
+  for (int i = b0; i < b1; ++i) p0 -= start[i];
+  for (int i = b0; i < b1; ++i) {
+    const int c = start[i];
+    const int q = (c + G - 1) / G;
+    for (int r = 0; r < q; ++r) {
+      const int e = (p0 + r * G) | ((min(G, c - r * G) - 1) << 16);
+      if (r < 2 * (q / 2)) srun[ppos++] = e;
+      else srun[opos++] = e;
+    }
+    p0 += c;
+  }
+  if (threadIdx.x == 0) {
+    a.nsrun[2 * blockIdx.x] = total_pe;
+    a.nsrun[2 * blockIdx.x + 1] = total_solo;
+  }
 }
 
 template <typename R>
