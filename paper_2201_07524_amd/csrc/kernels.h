@@ -30,9 +30,9 @@ struct SpreadArgs {
   const int* runs;       // run table of each chunk (offsets from the chunk's start)
   const int* nruns;      // per chunk: full runs, single points
   // Spreading's own run table (nullable; cell order only): every cell's points
-  // in ceil(c / G) runs, the last one partial.  Entries are offset | (count - 1) << 16;
-  // first the runs of cells with two or more, as adjacent same-cell pairs, then the
-  // rest.  nsrun: 2 per chunk (pair entries, solo runs).
+  // in ceil(c / G) runs, the last one partial.  Entries are offset | (count - 1) << 16:
+  // groups of four same-cell runs, then same-cell pairs, then the remaining runs.
+  // nsrun: 3 per chunk (quad entries, pair entries, solo runs).
   const int* srun;
   const int* nsrun;
   int cell_order;        // points sorted by cell inside each tile
@@ -264,7 +264,7 @@ struct ChunkRunArgs {
   int* runs;
   int* nruns;
   int* srun;    // nullable (cell order only): spreading's run table, see SpreadArgs::srun
-  int* nsrun;   // 2 per chunk: pair entries, solo runs
+  int* nsrun;   // 3 per chunk: quad entries, pair entries, solo runs
 };
 template <typename R>
 hipError_t launch_chunk_runs(const ChunkRunArgs<R>& a, hipStream_t st);

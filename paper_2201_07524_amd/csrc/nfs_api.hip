@@ -146,7 +146,7 @@ struct CloudBuf {
   std::vector<int> hcounts;    // host copy of counts (the chunk tables are rebuilt from it)
   int* nruns = nullptr;        // 2 x max_chunks: full runs and single points per chunk
   int* srun = nullptr;         // n: spreading's run table (cell order only)
-  int* nsrun = nullptr;        // 2 x max_chunks: its pair entries and solo runs per chunk
+  int* nsrun = nullptr;        // 3 x max_chunks: its quad entries, pair entries and solo runs per chunk
 };
 
 template <typename R>
@@ -256,7 +256,7 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
     cb.runs = cv.take<int>(n);
     cb.nruns = cv.take<int>(2 * cb.max_chunks);
     cb.srun = cv.take<int>(n);
-    cb.nsrun = cv.take<int>(2 * cb.max_chunks);
+    cb.nsrun = cv.take<int>(3 * cb.max_chunks);
     cb.w0s = nvec >= 1 ? cv.take<double>(n) : nullptr;
     cb.w1s = nvec >= 2 ? cv.take<double>(n) : nullptr;
   };

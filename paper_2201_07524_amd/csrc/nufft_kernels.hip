@@ -12,6 +12,8 @@
 //            with FP64 block reductions.
 // One lane handles one point; its 2m+1 window values per dimension stay in
 // registers.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -194,39 +196,55 @@ struct Acc<double, ACC_FIX128> {
   }
 };
 
-// The value of the partner lane (lane ^ 1) by a DPP quad permutation [1,0,3,2].
-__device__ __forceinline__ float pair_partner(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, true));
+// Lane exchanges inside a DPP quad: CTRL 0xB1 = quad permutation [1,0,3,2]
+// (the value of lane ^ 1), 0x4E = [2,3,0,1] (lane ^ 2).
+template <int CTRL>
+__device__ __forceinline__ float quad_swap(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
 }
-__device__ __forceinline__ double pair_partner(double v) {
+template <int CTRL>
+__device__ __forceinline__ double quad_swap(double v) {
   const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffLL), 0xB1, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0xB1, 0xF, 0xF, true);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xF, 0xF, true);
   return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+// Sum over the GROUP lanes (1, 2 or 4 aligned lanes) of a group, in every lane of it.
+template <int GROUP, typename R>
+__device__ __forceinline__ R group_sum(R v) {
+  if constexpr (GROUP >= 2) v += quad_swap<0xB1>(v);
+  if constexpr (GROUP >= 4) v += quad_swap<0x4E>(v);
+  return v;
 }
 
 // Adds the W taps of one tile row.  tap(j) gives this lane's value of tap j.
-// PAIR: lanes 2i and 2i+1 hold two runs of the same cell (same tap offsets);
-// each pair of taps is summed across the two lanes by DPP, and the even lane
-// adds tap j while the odd lane adds tap j + 1, so one atomic instruction
-// with every lane active does the work of two (the last, odd tap is added by
-// the even lane alone).
-template <bool PAIR, int W, typename R, typename ACCT, typename F>
+// GROUP = 2 or 4: the group's lanes hold runs of the same cell (same tap
+// offsets).  Each tap is summed across the group by DPP, and in every block
+// of GROUP taps lane `member` adds tap j + member, so one atomic instruction
+// with every lane active does the work of GROUP; the W mod GROUP last taps
+// are added by lanes 0.. of the group.
+template <int GROUP, int W, typename R, typename ACCT, typename F>
 __device__ __forceinline__ void add_row(ACCT& tile, int row, int member, F tap) {
-  if constexpr (!PAIR) {
+  if constexpr (GROUP == 1) {
 #pragma unroll
     for (int j = 0; j < W; ++j) tile.add(row + j, tap(j));
   } else {
+    constexpr int WB = W - W % GROUP;
 #pragma unroll
-    for (int j = 0; j + 1 < W; j += 2) {
-      R v0 = tap(j), v1 = tap(j + 1);
-      v0 += pair_partner(v0);
-      v1 += pair_partner(v1);
-      tile.add(row + j + member, member ? v1 : v0);
+    for (int j = 0; j < WB; j += GROUP) {
+      R mine = R(0);
+#pragma unroll
+      for (int k = 0; k < GROUP; ++k) {
+        const R v = group_sum<GROUP>(tap(j + k));
+        mine = member == k ? v : mine;
+      }
+      tile.add(row + j + member, mine);
     }
-    R v = tap(W - 1);
-    v += pair_partner(v);
-    if (member == 0) tile.add(row + W - 1, v);
+#pragma unroll
+    for (int j = WB; j < W; ++j) {
+      const R v = group_sum<GROUP>(tap(j));
+      if (member == j - WB) tile.add(row + j, v);
+    }
   }
 }
 
@@ -235,8 +253,8 @@ __device__ __forceinline__ void add_row(ACCT& tile, int row, int member, F tap) 
 // registers, and the tap costs one fixed-point conversion and one LDS atomic
 // for the whole run.
 // cnt (1..GC): the run's points; the others get weight zero and repeat the
-// last point, so no read leaves the run.  PAIR: see add_row (member = lane & 1).
-template <typename R, int D, int M, int ACC, int GC, bool PAIR = false>
+// last point, so no read leaves the run.  GROUP: see add_row (member = lane % GROUP).
+template <typename R, int D, int M, int ACC, int GC, int GROUP = 1>
 __device__ __forceinline__ void spread_run(Acc<R, ACC>& tile, const SpreadArgs<R>& a, const WinEval<R>& ev, int E,
                                            int q0, double wm, int cnt = GC, int member = 0) {
   constexpr int W = 2 * M + 1;
@@ -253,7 +271,7 @@ __device__ __forceinline__ void spread_run(Acc<R, ACC>& tile, const SpreadArgs<R
     tp[p].compute(u, ev);
   }
   if constexpr (D == 1) {
-    add_row<PAIR, W, R>(tile, tp[0].off[0], member, [&](int j) {
+    add_row<GROUP, W, R>(tile, tp[0].off[0], member, [&](int j) {
       R v = R(0);
 #pragma unroll
       for (int p = 0; p < GC; ++p) v += w[p] * tp[p].psi[0][j];
@@ -266,7 +284,7 @@ __device__ __forceinline__ void spread_run(Acc<R, ACC>& tile, const SpreadArgs<R
 #pragma unroll
       for (int p = 0; p < GC; ++p) a0[p] = w[p] * ev.tap(j0, tp[p].x[0]);
       const int row = (tp[0].off[0] + j0) * E + tp[0].off[1];
-      add_row<PAIR, W, R>(tile, row, member, [&](int j1) {
+      add_row<GROUP, W, R>(tile, row, member, [&](int j1) {
         R v = R(0);
 #pragma unroll
         for (int p = 0; p < GC; ++p) v += a0[p] * tp[p].psi[1][j1];
@@ -287,7 +305,7 @@ __device__ __forceinline__ void spread_run(Acc<R, ACC>& tile, const SpreadArgs<R
 #pragma unroll
           for (int p = 0; p < GC; ++p) a1[p] = b0[p] * tp[p].psi[1][j1];
           const int row = ((tp[0].off[0] + j0) * E + tp[0].off[1] + j1) * E + tp[0].off[2];
-          add_row<PAIR, W, R>(tile, row, member, [&](int j2) {
+          add_row<GROUP, W, R>(tile, row, member, [&](int j2) {
             R v = R(0);
 #pragma unroll
             for (int p = 0; p < GC; ++p) v += a1[p] * tp[p].psi[2][j2];
@@ -303,7 +321,7 @@ __device__ __forceinline__ void spread_run(Acc<R, ACC>& tile, const SpreadArgs<R
 #pragma unroll
           for (int p = 0; p < GC; ++p) a1[p] = b0[p] * tp[p].psi[1][0];
           const int row = ((tp[0].off[0] + j0) * E + tp[0].off[1] + j1) * E + tp[0].off[2];
-          add_row<PAIR, W, R>(tile, row, member, [&](int j2) {
+          add_row<GROUP, W, R>(tile, row, member, [&](int j2) {
             R v = R(0);
 #pragma unroll
             for (int p = 0; p < GC; ++p) v += a1[p] * tp[p].psi[2][j2];
@@ -348,22 +366,28 @@ __global__ __launch_bounds__(spread_block(D)) void spread_kernel(SpreadArgs<R> a
     // same-cell pairs of runs on adjacent lanes, 32 pairs per wave row,
     // spread over the chunk like the runs below
     const int* sr = a.srun + ch.start;
-    const int npe = a.nsrun[2 * blockIdx.x], nsolo = a.nsrun[2 * blockIdx.x + 1];
-    const int npairs = npe / 2;
-    int rows = (npairs + kWave / 2 - 1) / (kWave / 2);
-    for (int slot = threadIdx.x; slot < rows * kWave; slot += BS) {
-      const int lane = slot % kWave;
-      const int pair = (lane >> 1) * rows + slot / kWave;
-      if (pair < npairs) {
-        const int e = sr[2 * pair + (lane & 1)];
-        spread_run<R, D, M, ACC, G, true>(tile, a, ev, E, ch.start + (e & 0xffff), wm, (e >> 16) + 1, lane & 1);
+    const int nqe = a.nsrun[3 * blockIdx.x], npe = a.nsrun[3 * blockIdx.x + 1], nsolo = a.nsrun[3 * blockIdx.x + 2];
+    // groups of GROUP same-cell runs on aligned lanes, kWave / GROUP groups per wave row,
+    // spread over the chunk like single runs
+    auto grouped = [&](auto group_tag, const int* tab, int ngroups) {
+      constexpr int GR = decltype(group_tag)::value;
+      const int rows = (ngroups + kWave / GR - 1) / (kWave / GR);
+      for (int slot = threadIdx.x; slot < rows * kWave; slot += BS) {
+        const int lane = slot % kWave;
+        const int grp = (lane / GR) * rows + slot / kWave;
+        if (grp < ngroups) {
+          const int e = tab[GR * grp + lane % GR];
+          spread_run<R, D, M, ACC, G, GR>(tile, a, ev, E, ch.start + (e & 0xffff), wm, (e >> 16) + 1, lane % GR);
+        }
       }
-    }
-    rows = (nsolo + kWave - 1) / kWave;
+    };
+    grouped(std::integral_constant<int, 4>{}, sr, nqe / 4);
+    grouped(std::integral_constant<int, 2>{}, sr + nqe, npe / 2);
+    const int rows = (nsolo + kWave - 1) / kWave;
     for (int slot = threadIdx.x; slot < rows * kWave; slot += BS) {
       const int rr = run_of_slot(slot, rows);
       if (rr < nsolo) {
-        const int e = sr[npe + rr];
+        const int e = sr[nqe + npe + rr];
         spread_run<R, D, M, ACC, G>(tile, a, ev, E, ch.start + (e & 0xffff), wm, (e >> 16) + 1);
       }
     }

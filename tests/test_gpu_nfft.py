@@ -10,6 +10,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
+from oracle import direct
 from oracle import ndft
 from oracle import sinkhorn_dense as sd
 from paper_2201_07524_amd import nfs, workloads
@@ -146,6 +147,23 @@ def test_spread_paths_agree(d, N, m, tile):
         outs.append(nfs.fastsum(prm, T(src), T(w), T(tgt)).cpu().numpy())
         assert relerr(outs[-1], ref) <= 1e-10
     assert relerr(outs[0], outs[1]) <= 1e-13
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_fastsum_dense_cells_all_spreading_groups(prec, tol):
+    """Spreading groups same-cell runs on adjacent lanes: four per group in
+    cells of 64 or more runs, two per group otherwise, the last run of a cell
+    partial.  120000 of the sources lie in a square of side 0.004 (thousands of
+    points per cell), 80000 are spread out; against the oracle's direct sums
+    on 600 targets, normwise."""
+    rng = np.random.default_rng(1400)
+    src = np.concatenate([rng.uniform(0.05, 0.054, (120000, 2)), rng.uniform(-0.2, 0.2, (80000, 2))])
+    w = rng.uniform(0.0, 1.0, src.shape[0])
+    tgt = rng.uniform(-0.2, 0.2, (600, 2))
+    prm = nfs.Params(d=2, eps=0.1, N=32, m=8, precision=prec)
+    got = nfs.fastsum(prm, T(src), T(w), T(tgt)).cpu().numpy()
+    ref = direct.kv(tgt, src, w, 2, 0.1)
+    assert relerr(got, ref) <= tol
 
 
 # ------------------------------------------------------------------ r = 1 (near field)
