@@ -1,10 +1,11 @@
 // Stockham FFTs on the oversampled grid, staged in LDS (gfx950).
 //
 // The d-dimensional real FFT of fast summation is split into one pass per axis:
-//   rows_kernel  - contiguous last axis, two real rows packed into one complex
-//                  FFT; R2C keeps the half spectrum k = 0..N/2, C2R rebuilds
-//                  the rows from it.  For d = 1 the whole chain
-//                  forward -> multiplier -> inverse runs here (FUSED1D).
+//   rows_kernel  - contiguous last axis, two real rows of one problem packed
+//                  into one complex FFT; R2C keeps the half spectrum
+//                  k = 0..N/2, C2R rebuilds the rows from it.  For d = 1 the
+//                  whole chain forward -> multiplier -> inverse runs here
+//                  (FUSED1D), one problem's row per pencil.
 //   axis_kernel  - a strided axis, several adjacent pencils per workgroup so
 //                  global accesses are contiguous across pencils.  Modes: forward
 //                  with pruned centered output k = -N/2..N/2, inverse from that
@@ -24,13 +25,65 @@ __host__ __device__ inline int ilog2(int v) {
   return r;
 }
 
+// A workgroup-strided loop over i < n whose global loads are issued kBatch at
+// a time: load(i) only reads, use(i, v) consumes its result.  Every load of a
+// batch is in flight before the first use, so the loop waits on memory once
+// per batch instead of once per element (a store between two loads of the
+// plain loop keeps the second from issuing until the first has returned).
+constexpr int kBatch = 8;
+template <typename T, typename Load, typename Use>
+__device__ __forceinline__ void batched(int n, Load load, Use use) {
+  for (int base = threadIdx.x; base < n; base += kBatch * kBlock) {
+    T v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int i = base + u * kBlock;
+      if (i < n) v[u] = load(i);
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int i = base + u * kBlock;
+      if (i < n) use(i, v[u]);
+    }
+  }
+}
+
+// Staging of the twiddle table in LDS, split so that its loads travel with
+// the data loads of the pass: start() fetches the first kRegs kBlock entries
+// into registers, the data loads follow, and finish() writes them to LDS
+// (copying any rest of a longer table) before the barrier that precedes the
+// first Stockham pass.  One memory round trip instead of two.
+template <typename R>
+struct TwiddleStage {
+  static constexpr int kRegs = 4;
+  cplx<R> v[kRegs];
+  __device__ __forceinline__ void start(const cplx<R>* tw, int L) {
+#pragma unroll
+    for (int u = 0; u < kRegs; ++u) {
+      const int i = threadIdx.x + u * kBlock;
+      if (i < L) v[u] = tw[i];
+    }
+  }
+  __device__ __forceinline__ void finish(cplx<R>* t, const cplx<R>* tw, int L) {
+#pragma unroll
+    for (int u = 0; u < kRegs; ++u) {
+      const int i = threadIdx.x + u * kBlock;
+      if (i < L) t[i] = v[u];
+    }
+    constexpr int kHead = kRegs * kBlock;
+    if (L > kHead)
+      batched<cplx<R>>(
+          L - kHead, [&](int i) { return tw[kHead + i]; }, [&](int i, cplx<R> x) { t[kHead + i] = x; });
+  }
+};
+
 // One complete FFT of P pencils (each L contiguous complex values) held in
 // buffer `A`; `B` is scratch of the same size.  Returns the buffer holding the
 // result.  Forward uses exp(-2 pi i jk/L), inverse exp(+2 pi i jk/L), both
 // unnormalized.  Must be called by all threads of the block.
 template <typename R>
-__device__ cplx<R>* stockham(cplx<R>* A, cplx<R>* B, int L, int P, const cplx<R>* tw,
-                             bool inverse) {
+__device__ __forceinline__ cplx<R>* stockham(cplx<R>* A, cplx<R>* B, int L, int P, const cplx<R>* tw,
+                                             bool inverse) {
   const int log2L = ilog2(L);
   cplx<R>* src = A;
   cplx<R>* dst = B;
@@ -97,20 +150,31 @@ __device__ cplx<R>* stockham(cplx<R>* A, cplx<R>* B, int L, int P, const cplx<R>
   return src;
 }
 
+// stockham with the twiddles in LDS (tl) when staged there, else in global
+// memory (tg).  Two inlined copies, so that each reads its table through a
+// pointer of known address space: a pointer that may be either makes every
+// twiddle read a flat load, which waits on global and LDS counters alike.
 template <typename R>
-__device__ __forceinline__ R table_value(const Multiplier& mu, long prob, int d, int N, int k0, int k1, int k2) {
-  const int H = N / 2 + 1;
-  const int a0 = abs(k0), a1 = abs(k1), a2 = abs(k2);
-  long idx = a0;
-  if (d >= 2) idx = idx * H + a1;
-  if (d >= 3) idx = idx * H + a2;
-  return reinterpret_cast<const R*>(mu.tab)[prob * mu.tab_stride + idx];
+__device__ __forceinline__ cplx<R>* fft(cplx<R>* A, cplx<R>* B, int L, int P, bool tw_lds, const cplx<R>* tl,
+                                        const cplx<R>* tg, bool inverse) {
+  return tw_lds ? stockham(A, B, L, P, tl, inverse) : stockham(A, B, L, P, tg, inverse);
 }
 
+// Table entry of problem prob at |k|.  32-bit offsets: the host keeps the
+// tables of all problems below 2^32 entries.
 template <typename R>
-__device__ __forceinline__ cplx<R> apply_multiplier(cplx<R> v, const Multiplier& mu, long prob, int d, int N, int k0,
-                                                   int k1, int k2) {
-  const R m = table_value<R>(mu, prob, d, N, k0, k1, k2);
+__device__ __forceinline__ R table_value(const Multiplier& mu, long prob, int d, int N, int k0, int k1, int k2) {
+  const unsigned H = unsigned(N / 2 + 1);
+  unsigned idx = unsigned(abs(k0));
+  if (d >= 2) idx = idx * H + unsigned(abs(k1));
+  if (d >= 3) idx = idx * H + unsigned(abs(k2));
+  return reinterpret_cast<const R*>(mu.tab)[unsigned(prob) * unsigned(mu.tab_stride) + idx];
+}
+
+// v times the multiplier value m at frequency (k0, k1, k2), times i 2 pi k_c
+// for a derivative along axis c.
+template <typename R>
+__device__ __forceinline__ cplx<R> scale_multiplier(cplx<R> v, R m, const Multiplier& mu, int k0, int k1, int k2) {
   v.x *= m;
   v.y *= m;
   if (mu.deriv >= 0) {
@@ -119,6 +183,12 @@ __device__ __forceinline__ cplx<R> apply_multiplier(cplx<R> v, const Multiplier&
     v = cplx<R>{-v.y * f, v.x * f};
   }
   return v;
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R> apply_multiplier(cplx<R> v, const Multiplier& mu, long prob, int d, int N, int k0,
+                                                   int k1, int k2) {
+  return scale_multiplier(v, table_value<R>(mu, prob, d, N, k0, k1, k2), mu, k0, k1, k2);
 }
 
 template <typename R>
@@ -134,115 +204,142 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(RowArgs<R> a) {
   cplx<R>* A = reinterpret_cast<cplx<R>*>(smem_raw);
   cplx<R>* B = A + P * L;
   // twiddles staged in LDS (read by every pass) when they fit
-  const cplx<R>* tw = a.tw;
-  if (a.tw_lds) {
-    cplx<R>* t = B + P * L;
-    for (int i = threadIdx.x; i < L; i += kBlock) t[i] = a.tw[i];
-    tw = t;
-  }
+  cplx<R>* tlds = B + P * L;
+  TwiddleStage<R> tws;
+  if (a.tw_lds) tws.start(a.tw, L);
   const int K0 = a.N / 2 + 1;
-  const long row0 = long(blockIdx.x) * 2 * P;
   const int lshift = ilog2(L);
 
-  if (a.mode == ROW_R2C || a.mode == ROW_FUSED1D) {
-    const R* src = a.mode == ROW_R2C ? a.real_io : a.real_in;
-    for (int i = threadIdx.x; i < 2 * P * L; i += kBlock) {
-      const int r = i >> lshift;
-      const int c = i & (L - 1);
-      const long row = row0 + r;
-      R v = R(0);
-      if (row < a.nrows) {
-        v = src[row * L + c];
-        if (a.zero_src) const_cast<R*>(src)[row * L + c] = R(0);
-      }
-      cplx<R>* e = A + (r >> 1) * L + c;
-      if (r & 1) e->y = v;
-      else e->x = v;
-    }
+  if (a.mode == ROW_FUSED1D) {
+    // Each row is one problem, transformed alone in a pencil of its own (zero
+    // imaginary part): packed two to a complex FFT, a problem's rounding would
+    // scale with the other's grid, whatever that holds (a diverging FP32
+    // problem of a batch holds huge or negative scalings).  The multiplier
+    // is real and even, so D Z stays Hermitian and the inverse is real.
+    const long row0 = long(blockIdx.x) * P;
+    batched<R>(
+        P * L,
+        [&](int i) {
+          const long row = row0 + (i >> lshift);
+          return row < a.nrows ? a.real_in[row * L + (i & (L - 1))] : R(0);
+        },
+        [&](int i, R v) { A[i] = cplx<R>{v, R(0)}; });
+    if (a.tw_lds) tws.finish(tlds, a.tw, L);
     __syncthreads();
-    cplx<R>* res = stockham(A, B, L, P, tw, false);
-    if (a.mode == ROW_R2C) {
-      for (int i = threadIdx.x; i < P * K0; i += kBlock) {
-        const int p = i / K0;
-        const int k = i - p * K0;
-        const cplx<R> Z = res[p * L + k];
-        const cplx<R> Zm = cconj(res[p * L + ((L - k) & (L - 1))]);
-        const cplx<R> s = cadd(Z, Zm), df = csub(Z, Zm);
-        const cplx<R> Av{s.x * R(0.5), s.y * R(0.5)};
-        const cplx<R> Bv{df.y * R(0.5), -df.x * R(0.5)};
-        const long ra = row0 + 2 * p;
-        if (ra < a.nrows) a.spec[ra * K0 + k] = Av;
-        if (ra + 1 < a.nrows) a.spec[(ra + 1) * K0 + k] = Bv;
-      }
-      return;
-    }
-    // FUSED1D: each row is one problem; pencil p packs rows a = row0+2p and
-    // b = a+1 as Z = A + iB.  With real even tables Da, Db the product
-    // Da A + i Db B is ((Da+Db)/2) Z_k + ((Da-Db)/2) conj(Z_{-k}) (zero outside
-    // the symmetric set I_N, boundary weights in the tables), times i 2 pi k for
-    // a derivative.
+    cplx<R>* res = fft(A, B, L, P, a.tw_lds, tlds, a.tw, false);
     cplx<R>* other = res == A ? B : A;
-    for (int i = threadIdx.x; i < P * L; i += kBlock) {
-      const int p = i >> lshift;
-      const int j = i & (L - 1);
-      const int kk = j <= L / 2 ? j : j - L;
-      cplx<R> v{R(0), R(0)};
-      if (abs(kk) <= a.N / 2) {
-        const long ra = row0 + 2 * p;
-        const R da = ra < a.nrows ? table_value<R>(a.mul, ra, 1, a.N, kk, 0, 0) : R(0);
-        const R db = ra + 1 < a.nrows ? table_value<R>(a.mul, ra + 1, 1, a.N, kk, 0, 0) : R(0);
-        const cplx<R> z = res[i];
-        const cplx<R> zm = cconj(res[p * L + ((L - j) & (L - 1))]);
-        const R sp = R(0.5) * (da + db), sm = R(0.5) * (da - db);
-        v = cplx<R>{sp * z.x + sm * zm.x, sp * z.y + sm * zm.y};
-        if (a.mul.deriv >= 0) {
-          const R f = R(6.283185307179586476925286766559) * R(kk);
-          v = cplx<R>{-v.y * f, v.x * f};
-        }
-      }
-      other[i] = v;
-    }
+    // table value at k (zero outside the symmetric set I_N), times i 2 pi k
+    // for a derivative
+    batched<R>(
+        P * L,
+        [&](int i) {
+          const int j = i & (L - 1);
+          const int kk = j <= L / 2 ? j : j - L;
+          const long row = row0 + (i >> lshift);
+          return abs(kk) <= a.N / 2 && row < a.nrows ? table_value<R>(a.mul, row, 1, a.N, kk, 0, 0) : R(0);
+        },
+        [&](int i, R m) {
+          const int j = i & (L - 1);
+          other[i] = scale_multiplier(res[i], m, a.mul, j <= L / 2 ? j : j - L, 0, 0);
+        });
     __syncthreads();
-    cplx<R>* out = stockham(other, res, L, P, tw, true);
-    for (int i = threadIdx.x; i < 2 * P * L; i += kBlock) {
-      const int r = i >> lshift;
-      const int c = i & (L - 1);
-      const long row = row0 + r;
-      if (row < a.nrows) {
-        const cplx<R> v = out[(r >> 1) * L + c];
-        a.real_io[row * L + c] = (r & 1) ? v.y : v.x;
+    cplx<R>* out = fft(other, res, L, P, a.tw_lds, tlds, a.tw, true);
+    for (int i = threadIdx.x; i < P * L; i += kBlock) {
+      const long row = row0 + (i >> lshift);
+      if (row < a.nrows) a.real_io[row * L + (i & (L - 1))] = out[i].x;
+    }
+    // the source grid is cleared for the next spreading last, after every
+    // use of a loaded value (see zero_source below)
+    if (a.zero_src) {
+      R* z = const_cast<R*>(a.real_in);
+      for (int i = threadIdx.x; i < P * L; i += kBlock) {
+        const long row = row0 + (i >> lshift);
+        if (row < a.nrows) z[row * L + (i & (L - 1))] = R(0);
       }
     }
     return;
   }
 
-  // ROW_C2R: Z = A + i B on k = 0..N/2 and its Hermitian mirror on L - k
-  for (int i = threadIdx.x; i < P * L; i += kBlock) {
-    const int p = i >> lshift;
-    const int j = i & (L - 1);
-    const long ra = row0 + 2 * p;
-    cplx<R> Z{R(0), R(0)};
-    int k = -1;
-    bool mirror = false;
-    if (j < K0) k = j;
-    else if (L - j < K0) {
-      k = L - j;
-      mirror = true;
-    }
-    if (k >= 0) {
-      cplx<R> Av{R(0), R(0)}, Bv{R(0), R(0)};
-      if (ra < a.nrows) Av = a.spec[ra * K0 + k];
-      if (ra + 1 < a.nrows) Bv = a.spec[(ra + 1) * K0 + k];
-      if (mirror) {
-        Av.y = -Av.y;
-        Bv.y = -Bv.y;
+  // R2C and C2R: pencil p packs rows a = row0 + 2p and b = a + 1 of one
+  // problem (the rows of a 2-D or 3-D grid come in pairs) as Z = A + i B.
+  const long row0 = long(blockIdx.x) * 2 * P;
+  if (a.mode == ROW_R2C) {
+    const R* src = a.real_io;
+    // The source grid is cleared for the next spreading after the last use
+    // of anything loaded: a store issued between the loads and their use
+    // would make each use wait for it as well.
+    auto zero_source = [&]() {
+      if (!a.zero_src) return;
+      R* z = const_cast<R*>(src);
+      for (int i = threadIdx.x; i < 2 * P * L; i += kBlock) {
+        const long row = row0 + (i >> lshift);
+        if (row < a.nrows) z[row * L + (i & (L - 1))] = R(0);
       }
-      Z = cplx<R>{Av.x - Bv.y, Av.y + Bv.x};
+    };
+    batched<R>(
+        2 * P * L,
+        [&](int i) {
+          const long row = row0 + (i >> lshift);
+          return row < a.nrows ? src[row * L + (i & (L - 1))] : R(0);
+        },
+        [&](int i, R v) {
+          const int r = i >> lshift;
+          const int c = i & (L - 1);
+          cplx<R>* e = A + (r >> 1) * L + c;
+          if (r & 1) e->y = v;
+          else e->x = v;
+        });
+    if (a.tw_lds) tws.finish(tlds, a.tw, L);
+    __syncthreads();
+    cplx<R>* res = fft(A, B, L, P, a.tw_lds, tlds, a.tw, false);
+    for (int i = threadIdx.x; i < P * K0; i += kBlock) {
+      const int p = i / K0;
+      const int k = i - p * K0;
+      const cplx<R> Z = res[p * L + k];
+      const cplx<R> Zm = cconj(res[p * L + ((L - k) & (L - 1))]);
+      const cplx<R> s = cadd(Z, Zm), df = csub(Z, Zm);
+      const cplx<R> Av{s.x * R(0.5), s.y * R(0.5)};
+      const cplx<R> Bv{df.y * R(0.5), -df.x * R(0.5)};
+      const long ra = row0 + 2 * p;
+      if (ra < a.nrows) a.spec[ra * K0 + k] = Av;
+      if (ra + 1 < a.nrows) a.spec[(ra + 1) * K0 + k] = Bv;
     }
-    A[i] = Z;
+    zero_source();
+    return;
   }
+
+  // ROW_C2R: Z = A + i B on k = 0..N/2 and its Hermitian mirror on L - k
+  struct Pair {
+    cplx<R> a, b;
+  };
+  batched<Pair>(
+      P * L,
+      [&](int i) {
+        const int j = i & (L - 1);
+        const long ra = row0 + 2 * (i >> lshift);
+        const int k = j < K0 ? j : (L - j < K0 ? L - j : -1);
+        Pair s{{R(0), R(0)}, {R(0), R(0)}};
+        if (k >= 0) {
+          if (ra < a.nrows) s.a = a.spec[ra * K0 + k];
+          if (ra + 1 < a.nrows) s.b = a.spec[(ra + 1) * K0 + k];
+        }
+        return s;
+      },
+      [&](int i, Pair s) {
+        const int j = i & (L - 1);
+        cplx<R> Z{R(0), R(0)};
+        if (j < K0 || L - j < K0) {
+          if (j >= K0) {  // mirrored bin L - k
+            s.a.y = -s.a.y;
+            s.b.y = -s.b.y;
+          }
+          Z = cplx<R>{s.a.x - s.b.y, s.a.y + s.b.x};
+        }
+        A[i] = Z;
+      });
+  if (a.tw_lds) tws.finish(tlds, a.tw, L);
   __syncthreads();
-  cplx<R>* out = stockham(A, B, L, P, tw, true);
+  cplx<R>* out = fft(A, B, L, P, a.tw_lds, tlds, a.tw, true);
   for (int i = threadIdx.x; i < 2 * P * L; i += kBlock) {
     const int r = i >> lshift;
     const int c = i & (L - 1);
@@ -251,6 +348,27 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(RowArgs<R> a) {
       const cplx<R> v = out[(r >> 1) * L + c];
       a.real_io[row * L + c] = (r & 1) ? v.y : v.x;
     }
+  }
+}
+
+// Pencil q of an axis pass -> its outer group o and offset ii in the group.
+// Pencil numbers and element offsets are 32-bit: the launcher rejects passes
+// with 2^31 pencils or arrays of 2^32 elements or more.
+template <typename R>
+__device__ __forceinline__ void pencil_origin(const AxisArgs<R>& a, long q, unsigned& o, unsigned& ii) {
+  o = unsigned(q) / unsigned(a.inner);
+  ii = unsigned(q) - o * unsigned(a.inner);
+}
+
+// Frequencies (k1, k2) of the other axes for offset ii of a 2-D or 3-D pass.
+__device__ __forceinline__ void other_freqs(int d, int half, unsigned ii, int& k1, int& k2) {
+  k1 = 0;
+  k2 = 0;
+  if (d == 2) k1 = int(ii);
+  else if (d == 3) {
+    const unsigned K0 = unsigned(half + 1);
+    k1 = int(ii / K0) - half;
+    k2 = int(ii % K0);
   }
 }
 
@@ -267,91 +385,153 @@ __global__ __launch_bounds__(kBlock) void axis_kernel(AxisArgs<R> a) {
   cplx<R>* A = reinterpret_cast<cplx<R>*>(smem_raw);
   cplx<R>* B = A + P * L;
   // twiddles staged in LDS (read by every pass) when they fit
-  const cplx<R>* tw = a.tw;
-  if (a.tw_lds) {
-    cplx<R>* t = B + P * L;
-    for (int i = threadIdx.x; i < L; i += kBlock) t[i] = a.tw[i];
-    tw = t;
-  }
+  cplx<R>* tlds = B + P * L;
+  TwiddleStage<R> tws;
+  if (a.tw_lds) tws.start(a.tw, L);
   const long q0 = long(blockIdx.x) * P;
   const int half = a.N / 2;
+  const int pshift = ilog2(P);
+  const int lshift = ilog2(L);
+
+  // Fused pass: the multiplier values of the elements i = threadIdx.x +
+  // u kBlock this thread rescales after the forward FFT do not depend on the
+  // transform, so they are fetched here with the data (0 outside the
+  // symmetric set and past the last pencil).  Longer passes load them after.
+  constexpr int kMulRegs = 4;
+  R mreg[kMulRegs];
+  const bool mul_pre = a.mode == AX_FUSED && P * L <= kMulRegs * kBlock;
+  if (mul_pre) {
+#pragma unroll
+    for (int u = 0; u < kMulRegs; ++u) {
+      const int i = threadIdx.x + u * kBlock;
+      const int bin = i & (L - 1);
+      const int k0 = bin <= L / 2 ? bin : bin - L;
+      const long q = q0 + (i >> lshift);
+      mreg[u] = R(0);
+      if (i < P * L && abs(k0) <= half && q < a.npen) {
+        unsigned o, ii;
+        pencil_origin(a, q, o, ii);
+        int k1, k2;
+        other_freqs(a.d, half, ii, k1, k2);
+        mreg[u] = table_value<R>(a.mul, o, a.d, a.N, k0, k1, k2);
+      }
+    }
+  }
 
   if (a.mode == AX_INV || a.nin < L) {
     for (int i = threadIdx.x; i < P * L; i += kBlock) A[i] = cplx<R>{R(0), R(0)};
     __syncthreads();
   }
-  for (int i = threadIdx.x; i < P * a.nin; i += kBlock) {
-    const int p = i % P;
-    const int e = i / P;
-    const long q = q0 + p;
-    if (q >= a.npen) continue;
-    const long o = q / a.inner;
-    const long ii = q - o * a.inner;
-    cplx<R> v = a.in[o * a.in_ostride + ii + e * a.in_stride];
-    int bin = e;
-    if (a.in_centered) {
-      const int k = e - half;
-      bin = k < 0 ? k + L : k;
-      if (a.mode == AX_INV && a.apply_mul) {
-        int k1 = 0, k2 = 0;
-        if (a.d == 2) k1 = int(ii);
-        else if (a.d == 3) {
-          const int K0 = half + 1;
-          k1 = int(ii / K0) - half;
-          k2 = int(ii % K0);
+  // entry e of pencil p: i = e P + p, so adjacent lanes read adjacent pencils.
+  // The inverse pass from a centered spectrum may apply the multiplier on
+  // load; its table value travels with the entry and is applied on use.
+  const bool inv_mul = a.in_centered && a.mode == AX_INV && a.apply_mul;
+  struct Entry {
+    cplx<R> v;
+    R m;
+  };
+  batched<Entry>(
+      P * a.nin,
+      [&](int i) {
+        const int e = i >> pshift;
+        const long q = q0 + (i & (P - 1));
+        Entry t{{R(0), R(0)}, R(0)};
+        if (q < a.npen) {
+          unsigned o, ii;
+          pencil_origin(a, q, o, ii);
+          t.v = a.in[o * unsigned(a.in_ostride) + ii + unsigned(e) * unsigned(a.in_stride)];
+          if (inv_mul) {
+            int k1, k2;
+            other_freqs(a.d, half, ii, k1, k2);
+            t.m = table_value<R>(a.mul, o, a.d, a.N, e - half, k1, k2);
+          }
         }
-        v = apply_multiplier(v, a.mul, o, a.d, a.N, k, k1, k2);
-      }
-    }
-    A[p * L + bin] = v;
-  }
+        return t;
+      },
+      [&](int i, Entry t) {
+        const int p = i & (P - 1);
+        const int e = i >> pshift;
+        const long q = q0 + p;
+        if (q >= a.npen) return;
+        int bin = e;
+        if (a.in_centered) {
+          const int k = e - half;
+          bin = k < 0 ? k + L : k;
+          if (inv_mul) {
+            unsigned o, ii;
+            pencil_origin(a, q, o, ii);
+            int k1, k2;
+            other_freqs(a.d, half, ii, k1, k2);
+            t.v = scale_multiplier(t.v, t.m, a.mul, k, k1, k2);
+          }
+        }
+        A[p * L + bin] = t.v;
+      });
+  if (a.tw_lds) tws.finish(tlds, a.tw, L);
   __syncthreads();
 
   cplx<R>* res;
   if (a.mode == AX_INV) {
-    res = stockham(A, B, L, P, tw, true);
+    res = fft(A, B, L, P, a.tw_lds, tlds, a.tw, true);
   } else {
-    res = stockham(A, B, L, P, tw, false);
-    if (a.mode == AX_FUSED) {
-      for (int i = threadIdx.x; i < P * L; i += kBlock) {
-        const int p = i / L;
-        const int bin = i - p * L;
-        const int k0 = bin <= L / 2 ? bin : bin - L;
-        const long q = q0 + p;
-        cplx<R> v{R(0), R(0)};
-        if (abs(k0) <= half && q < a.npen) {
-          const long o = q / a.inner;
-          const long ii = q - o * a.inner;
+    res = fft(A, B, L, P, a.tw_lds, tlds, a.tw, false);
+    if (mul_pre) {
+#pragma unroll
+      for (int u = 0; u < kMulRegs; ++u) {
+        const int i = threadIdx.x + u * kBlock;
+        if (i < P * L) {
+          const int bin = i & (L - 1);
+          const int k0 = bin <= L / 2 ? bin : bin - L;
           int k1 = 0, k2 = 0;
-          if (a.d == 2) k1 = int(ii);
-          else if (a.d == 3) {
-            const int K0 = half + 1;
-            k1 = int(ii / K0) - half;
-            k2 = int(ii % K0);
+          if (a.mul.deriv > 0 && q0 + (i >> lshift) < a.npen) {
+            unsigned o, ii;
+            pencil_origin(a, q0 + (i >> lshift), o, ii);
+            other_freqs(a.d, half, ii, k1, k2);
           }
-          v = apply_multiplier(res[i], a.mul, o, a.d, a.N, k0, k1, k2);
+          res[i] = scale_multiplier(res[i], mreg[u], a.mul, k0, k1, k2);
         }
-        res[i] = v;
       }
       __syncthreads();
       cplx<R>* other = res == A ? B : A;
-      res = stockham(res, other, L, P, tw, true);
+      res = fft(res, other, L, P, a.tw_lds, tlds, a.tw, true);
+    } else if (a.mode == AX_FUSED) {
+      // in place: each element is read and rewritten by the same thread
+      batched<cplx<R>>(
+          P * L,
+          [&](int i) {
+            const int bin = i & (L - 1);
+            const int k0 = bin <= L / 2 ? bin : bin - L;
+            const long q = q0 + (i >> lshift);
+            cplx<R> v{R(0), R(0)};
+            if (abs(k0) <= half && q < a.npen) {
+              unsigned o, ii;
+              pencil_origin(a, q, o, ii);
+              int k1, k2;
+              other_freqs(a.d, half, ii, k1, k2);
+              v = apply_multiplier(res[i], a.mul, o, a.d, a.N, k0, k1, k2);
+            }
+            return v;
+          },
+          [&](int i, cplx<R> v) { res[i] = v; });
+      __syncthreads();
+      cplx<R>* other = res == A ? B : A;
+      res = fft(res, other, L, P, a.tw_lds, tlds, a.tw, true);
     }
   }
 
   for (int i = threadIdx.x; i < P * a.nout; i += kBlock) {
-    const int p = i % P;
-    const int e = i / P;
+    const int p = i & (P - 1);
+    const int e = i >> pshift;
     const long q = q0 + p;
     if (q >= a.npen) continue;
-    const long o = q / a.inner;
-    const long ii = q - o * a.inner;
+    unsigned o, ii;
+    pencil_origin(a, q, o, ii);
     int bin = e;
     if (a.out_centered) {
       const int k = e - half;
       bin = k < 0 ? k + L : k;
     }
-    a.out[o * a.out_ostride + ii + e * a.out_stride] = res[p * L + bin];
+    a.out[o * unsigned(a.out_ostride) + ii + unsigned(e) * unsigned(a.out_stride)] = res[p * L + bin];
   }
 }
 
@@ -369,7 +549,8 @@ template <typename R>
 hipError_t launch_rows(const RowArgs<R>& a_in, hipStream_t st) {
   RowArgs<R> a = a_in;
   const int P = rows_pencils<R>(a.L);
-  const long nblk = (a.nrows + 2 * P - 1) / (2 * P);
+  const int rows_per_block = a.mode == ROW_FUSED1D ? P : 2 * P;  // FUSED1D: one row per pencil
+  const long nblk = (a.nrows + rows_per_block - 1) / rows_per_block;
   const size_t shm = fft_lds<R>(P, a.L, &a.tw_lds);
   hipLaunchKernelGGL(rows_kernel<R>, dim3(nblk), dim3(kBlock), shm, st, a);
   return hipGetLastError();
@@ -378,6 +559,10 @@ hipError_t launch_rows(const RowArgs<R>& a_in, hipStream_t st) {
 template <typename R>
 hipError_t launch_axis(const AxisArgs<R>& a_in, hipStream_t st) {
   AxisArgs<R> a = a_in;
+  if (a.npen >= (long(1) << 31) || a.inner <= 0) return hipErrorInvalidValue;
+  const long groups = (a.npen + a.inner - 1) / a.inner;
+  const long ext_in = groups * a.in_ostride, ext_out = groups * a.out_ostride;
+  if (ext_in >= (long(1) << 32) || ext_out >= (long(1) << 32)) return hipErrorInvalidValue;
   const int P = axis_pencils<R>(a.L);
   const long nblk = (a.npen + P - 1) / P;
   const size_t shm = fft_lds<R>(P, a.L, &a.tw_lds);

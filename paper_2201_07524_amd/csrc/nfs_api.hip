@@ -583,6 +583,7 @@ static hipError_t fft_chain(Work<R>& w, const R* table, int deriv, hipStream_t s
   const Geom& geo = w.geo;
   const int g = geo.g, N = geo.N, d = geo.d, K0 = w.K0, B = w.B;
   Multiplier mu{table, deriv, w.H};
+  if (double(B) * double(w.H) >= 4294967296.0) return hipErrorInvalidValue;  // 32-bit table offsets
   hipError_t e;
   if (d == 1) {
     RowArgs<R> ra{};

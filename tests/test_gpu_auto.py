@@ -98,6 +98,10 @@ def test_batch_auto_promotes_only_the_failing_problems():
 
     r32 = batch("fp32")
     assert [r.n_nonpos > 0 for r in r32] == [False, True, False, True]
+    # batch members are independent: next to a diverging FP32 problem (huge or
+    # negative scalings) the others end as their solo FP32 solves
+    for b in (0, 2):
+        same(r32[b], solve("fp32", probs[b], eps[b]), 1e-6, 1e-4)
     ra = batch("auto")
     assert [r.precision_used for r in ra] == ["fp32", "fp64", "fp32", "fp64"]
     for b in (0, 2):
