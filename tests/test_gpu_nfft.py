@@ -92,6 +92,20 @@ def test_fastsum_fp32_matches_dense(d, N, eps, ns, nt):
     assert relerr(got, ref) <= 1e-5
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+@pytest.mark.parametrize("d,N", [(1, 1024), (1, 2048), (2, 1024), (2, 2048)])
+def test_fastsum_large_grids(d, N, prec, tol):
+    """Oversampled grids of 2048 and 4096 points per axis: FFT passes with
+    more twiddles than the first staging step holds, FP64 twiddles read from
+    global memory (L = 4096 leaves no LDS for them), and the axis multiplier
+    loaded after the forward FFT (pencils longer than 1024)."""
+    src, w, tgt = _clouds(d, 1500, 1200, 500 + d)
+    prm = nfs.Params(d=d, eps=0.01, N=N, m=8, precision=prec)
+    got = nfs.fastsum(prm, T(src), T(w), T(tgt)).cpu().numpy()
+    ref = sd.gibbs_kernel(tgt, src, 2, 0.01) @ w
+    assert relerr(got, ref) <= tol
+
+
 def test_fastsum_error_decays_with_m():
     """Window error of the Kaiser-Bessel NFFT decays geometrically in m
     (about e^{-2 pi m sqrt(1 - 1/sigma)} at sigma = 2) down to rounding."""
