@@ -49,11 +49,15 @@ __device__ __forceinline__ R kb_psi(R z, R m2, R b, R bm, R cnorm) {
 // Per-tap polynomial form of the FP32 window.  A point whose first tap lies at
 // distance z0 = t - M (t in [0, 1)) from it has, at tap j, the window value
 //   psi(z0 + j) = sum_k c[j][k] x^k,   x = 2 t - 1,
-// a degree-9 Chebyshev interpolant built on the host (absolute error about
-// 5e-8 for m = 2..8, the FP32 rounding level).  Tap 2M lies outside the
-// support except at t = 0 and is zero.
+// a Chebyshev interpolant built on the host with poly_coef(m) coefficients:
+// degree 7 for m >= 4 and degree 9 below (absolute error 4e-8 to 8e-8 for
+// m = 2..8, the FP32 rounding level; degree 9 gains nothing measurable for
+// m >= 4 and costs two more FMAs per window value).  Tap 2M lies outside
+// the support except at t = 0 and is zero.  Rows hold kPolyCoef entries,
+// zero past poly_coef(m).
 constexpr int kMaxM = 8;
 constexpr int kPolyCoef = 10;
+__host__ __device__ constexpr int poly_coef(int m) { return m >= 4 ? 8 : kPolyCoef; }
 struct WindowPoly {
   float c[2 * kMaxM + 1][kPolyCoef];
 };

@@ -48,11 +48,11 @@ inline double window_value(double z, const WindowConst& w) {
 
 // Per-tap polynomials of the FP32 window (see WindowPoly): for tap j the
 // function x -> psi(j - m + (x + 1)/2) on [-1, 1] is interpolated at the
-// kPolyCoef Chebyshev points, and the Chebyshev series is converted to
+// poly_coef(m) Chebyshev points, and the Chebyshev series is converted to
 // monomial coefficients (in double, then rounded to float).
 inline WindowPoly make_window_poly(int m, const WindowConst& w) {
   WindowPoly P{};
-  const int K = kPolyCoef;
+  const int K = poly_coef(m);
   for (int j = 0; j < 2 * m; ++j) {
     double f[kPolyCoef], a[kPolyCoef];
     for (int i = 0; i < K; ++i) {
@@ -78,7 +78,7 @@ inline WindowPoly make_window_poly(int m, const WindowConst& w) {
         tk[q] = tkp1[q];
       }
     }
-    for (int q = 0; q < K; ++q) P.c[j][q] = float(mono[q]);
+    for (int q = 0; q < K; ++q) P.c[j][q] = float(mono[q]);  // entries K.. stay zero
   }
   return P;
 }

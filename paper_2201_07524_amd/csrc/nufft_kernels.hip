@@ -33,11 +33,13 @@ struct WinEval<float> {
   float shift;                  // 2M - 1
   __device__ __forceinline__ WinEval(const WindowConst&, const float* p, int M) : P(p), shift(float(2 * M - 1)) {}
   __device__ __forceinline__ float arg(float z0) const { return fmaf(2.0f, z0, shift); }
+  // NC = poly_coef(m): the coefficients the host fitted for this half-width
+  template <int NC>
   __device__ __forceinline__ float tap(int j, float x) const {
     const float* c = P + j * kPolyCoef;
-    float v = c[kPolyCoef - 1];
+    float v = c[NC - 1];
 #pragma unroll
-    for (int k = kPolyCoef - 2; k >= 0; --k) v = fmaf(v, x, c[k]);
+    for (int k = NC - 2; k >= 0; --k) v = fmaf(v, x, c[k]);
     return v;
   }
 };
@@ -48,6 +50,7 @@ struct WinEval<double> {
   __device__ __forceinline__ WinEval(const WindowConst& wc, const float*, int)
       : m2(wc.m2), b(wc.b), bm(wc.bm), cn(wc.cnorm) {}
   __device__ __forceinline__ double arg(double z0) const { return z0; }
+  template <int NC>
   __device__ __forceinline__ double tap(int j, double z0) const { return kb_psi(z0 + double(j), m2, b, bm, cn); }
 };
 
@@ -70,7 +73,7 @@ struct Taps {
       x[c] = ev.arg(s - u[c]);
       if (c >= FROM) {
 #pragma unroll
-        for (int j = 0; j < W; ++j) psi[c][j] = ev.tap(j, x[c]);
+        for (int j = 0; j < W; ++j) psi[c][j] = ev.template tap<poly_coef(M)>(j, x[c]);
       }
     }
   }
@@ -282,7 +285,7 @@ __device__ __forceinline__ void spread_run(Acc<R, ACC>& tile, const SpreadArgs<R
     for (int j0 = 0; j0 < W; ++j0) {
       R a0[GC];
 #pragma unroll
-      for (int p = 0; p < GC; ++p) a0[p] = w[p] * ev.tap(j0, tp[p].x[0]);
+      for (int p = 0; p < GC; ++p) a0[p] = w[p] * ev.template tap<poly_coef(M)>(j0, tp[p].x[0]);
       const int row = (tp[0].off[0] + j0) * E + tp[0].off[1];
       add_row<GROUP, W, R>(tile, row, member, [&](int j1) {
         R v = R(0);
@@ -296,7 +299,7 @@ __device__ __forceinline__ void spread_run(Acc<R, ACC>& tile, const SpreadArgs<R
     for (int j0 = 0; j0 < W; ++j0) {
       R b0[GC];
 #pragma unroll
-      for (int p = 0; p < GC; ++p) b0[p] = w[p] * ev.tap(j0, tp[p].x[0]);
+      for (int p = 0; p < GC; ++p) b0[p] = w[p] * ev.template tap<poly_coef(M)>(j0, tp[p].x[0]);
       if constexpr (sizeof(R) == 4) {
         // FP32: j1 unrolled, every window index static
 #pragma unroll
@@ -1032,7 +1035,7 @@ __device__ __forceinline__ void interp_run(const R* tile, const InterpArgs<R>& a
         R racc = R(0);
 #pragma unroll
         for (int j1 = 0; j1 < W; ++j1) racc += gv[j1] * tp[p].psi[1][j1];
-        acc[p] += racc * ev.tap(j0, tp[p].x[0]);
+        acc[p] += racc * ev.template tap<poly_coef(M)>(j0, tp[p].x[0]);
       }
     }
   } else {
@@ -1076,7 +1079,7 @@ __device__ __forceinline__ void interp_run(const R* tile, const InterpArgs<R>& a
         }
       }
 #pragma unroll
-      for (int p = 0; p < GC; ++p) acc[p] += pacc[p] * ev.tap(j0, tp[p].x[0]);
+      for (int p = 0; p < GC; ++p) acc[p] += pacc[p] * ev.template tap<poly_coef(M)>(j0, tp[p].x[0]);
     }
   }
 }
