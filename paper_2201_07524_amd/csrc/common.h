@@ -37,15 +37,6 @@ struct WindowConst {
   double edge;   // 2 cnorm exp(-bm): psi at the support edge
 };
 
-template <typename R>
-__device__ __forceinline__ R kb_psi(R z, R m2, R b, R bm, R cnorm) {
-  const R t = m2 - z * z;
-  if (t <= R(0)) return R(0);
-  const R a = b * sqrt(t);
-  if (a < R(1e-4)) return cnorm * R(2) * exp(-bm);
-  return cnorm * (exp(a - bm) - exp(-a - bm)) / a;
-}
-
 // Per-tap polynomial form of the FP32 window.  A point whose first tap lies at
 // distance z0 = t - M (t in [0, 1)) from it has, at tap j, the window value
 //   psi(z0 + j) = sum_k c[j][k] x^k,   x = 2 t - 1,
@@ -60,6 +51,13 @@ constexpr int kPolyCoef = 10;
 __host__ __device__ constexpr int poly_coef(int m) { return m >= 4 ? 8 : kPolyCoef; }
 struct WindowPoly {
   float c[2 * kMaxM + 1][kPolyCoef];
+};
+// FP64 grids: the same per-tap interpolants with kPolyCoef64 coefficients
+// (degree 14; absolute error at most 1.6e-14 for m = 2..8 in FP64 Horner,
+// the rounding level of the closed form).
+constexpr int kPolyCoef64 = 15;
+struct WindowPoly64 {
+  double c[2 * kMaxM + 1][kPolyCoef64];
 };
 
 // Longest run of same-cell points that spreading and interpolation handle

@@ -46,15 +46,15 @@ inline double window_value(double z, const WindowConst& w) {
   return w.cnorm * (std::exp(a - w.bm) - std::exp(-a - w.bm)) / a;
 }
 
-// Per-tap polynomials of the FP32 window (see WindowPoly): for tap j the
-// function x -> psi(j - m + (x + 1)/2) on [-1, 1] is interpolated at the
-// poly_coef(m) Chebyshev points, and the Chebyshev series is converted to
-// monomial coefficients (in double, then rounded to float).
-inline WindowPoly make_window_poly(int m, const WindowConst& w) {
-  WindowPoly P{};
-  const int K = poly_coef(m);
+// Per-tap polynomials of the window (see WindowPoly, WindowPoly64): for tap
+// j the function x -> psi(j - m + (x + 1)/2) on [-1, 1] is interpolated at K
+// Chebyshev points, and the Chebyshev series is converted to monomial
+// coefficients (in double, then rounded to T).  Rows j >= 2m stay zero.
+template <typename T, int STRIDE>
+inline void fit_window_poly(int m, int K, const WindowConst& w, T (&c)[2 * kMaxM + 1][STRIDE]) {
+  constexpr int KM = 16;
   for (int j = 0; j < 2 * m; ++j) {
-    double f[kPolyCoef], a[kPolyCoef];
+    double f[KM], a[KM];
     for (int i = 0; i < K; ++i) {
       const double xi = std::cos(kPi * (i + 0.5) / K);
       f[i] = window_value(double(j - m) + 0.5 * (xi + 1.0), w);
@@ -65,7 +65,7 @@ inline WindowPoly make_window_poly(int m, const WindowConst& w) {
       a[k] = (k == 0 ? 1.0 : 2.0) * sum / K;
     }
     // monomial coefficients: accumulate a_k T_k(x) with T_{k+1} = 2x T_k - T_{k-1}
-    double mono[kPolyCoef] = {0.0}, tkm1[kPolyCoef] = {0.0}, tk[kPolyCoef] = {0.0}, tkp1[kPolyCoef];
+    double mono[KM] = {0.0}, tkm1[KM] = {0.0}, tk[KM] = {0.0}, tkp1[KM];
     tkm1[0] = 1.0;  // T_0
     tk[1] = 1.0;    // T_1
     for (int q = 0; q < K; ++q) mono[q] += a[0] * tkm1[q];
@@ -78,8 +78,19 @@ inline WindowPoly make_window_poly(int m, const WindowConst& w) {
         tk[q] = tkp1[q];
       }
     }
-    for (int q = 0; q < K; ++q) P.c[j][q] = float(mono[q]);  // entries K.. stay zero
+    for (int q = 0; q < K; ++q) c[j][q] = T(mono[q]);  // entries K.. stay zero
   }
+}
+
+inline WindowPoly make_window_poly(int m, const WindowConst& w) {
+  WindowPoly P{};
+  fit_window_poly(m, poly_coef(m), w, P.c);
+  return P;
+}
+
+inline WindowPoly64 make_window_poly64(int m, const WindowConst& w) {
+  WindowPoly64 P{};
+  fit_window_poly(m, kPolyCoef64, w, P.c);
   return P;
 }
 

@@ -40,7 +40,7 @@ struct SpreadArgs {
   long grid_stride;
   R* part;               // non-null: store each chunk's padded tile here instead of flushing
   WindowConst win;
-  const float* __restrict__ wpoly;  // FP32 window polynomials: WindowPoly::c, row-major
+  const void* __restrict__ wpoly;   // window polynomials: WindowPoly::c (FP32) or WindowPoly64::c (FP64)
 };
 
 // Sum of the padded chunk tiles into the grid: one workgroup per (tile, neighbour)
@@ -67,7 +67,7 @@ struct InterpArgs {
   const R* grid;            // problem p's grid at grid + p*grid_stride
   long grid_stride;
   WindowConst win;
-  const float* __restrict__ wpoly;  // FP32 window polynomials: WindowPoly::c, row-major
+  const void* __restrict__ wpoly;   // window polynomials: WindowPoly::c (FP32) or WindowPoly64::c (FP64)
   double norm;              // constant factor of the result
   const double* wmul_src;   // the result is divided by wmul_src[prob] (nullable); log domain:
                             // the source potentials' shift

@@ -154,7 +154,7 @@ struct Work {
   int B = 1;
   Geom geo{};
   WindowConst win{};
-  float* wpoly = nullptr;    // WindowPoly coefficients (device)
+  void* wpoly = nullptr;     // WindowPoly (FP32) or WindowPoly64 (FP64) coefficients (device)
   int K0 = 0, nbins = 0, chunk = 0;
   long ncell = 0;     // g^d
   long H = 0;         // diagonal table entries per problem, (N/2+1)^d
@@ -296,7 +296,7 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
   w.dtab = cv.take<R>(size_t(B) * H);
   w.dtab2 = cv.take<R>(size_t(B) * H);
   w.inv_phi = cv.take<double>(w.K0);
-  w.wpoly = cv.take<float>(sizeof(WindowPoly) / sizeof(float));
+  w.wpoly = cv.take<double>((sizeof(R) == 4 ? sizeof(WindowPoly) : sizeof(WindowPoly64)) / sizeof(double) + 1);
   const long maxch = std::max(w.X.max_chunks, w.Y.max_chunks);
   w.partials = cv.take<double>(size_t(std::max<long>(maxch, 1024)) * 9);
   w.ct_interp = cv.take<unsigned>(B);
@@ -530,8 +530,13 @@ static int upload_tables(Work<R>& w, const nfs_params* p, hipStream_t st) {
   std::vector<double> iphi(w.K0);
   for (int k = 0; k < w.K0; ++k) iphi[k] = 1.0 / phi[k];
   NFS_HIP(hipMemcpyAsync(w.inv_phi, iphi.data(), sizeof(double) * w.K0, hipMemcpyHostToDevice, st));
-  const WindowPoly wp = make_window_poly(p->m, w.win);
-  NFS_HIP(hipMemcpyAsync(w.wpoly, &wp, sizeof(WindowPoly), hipMemcpyHostToDevice, st));
+  if constexpr (sizeof(R) == 4) {
+    const WindowPoly wp = make_window_poly(p->m, w.win);
+    NFS_HIP(hipMemcpyAsync(w.wpoly, &wp, sizeof(WindowPoly), hipMemcpyHostToDevice, st));
+  } else {
+    const WindowPoly64 wp = make_window_poly64(p->m, w.win);
+    NFS_HIP(hipMemcpyAsync(w.wpoly, &wp, sizeof(WindowPoly64), hipMemcpyHostToDevice, st));
+  }
   std::vector<R> t1, t2;
   bool any = false;
   for (int b = 0; b < w.B; ++b) any = any || w.sc[b].eps_t > 0.0;

@@ -21,9 +21,8 @@ namespace nfs {
 
 // Window evaluation.  arg() maps the distance z0 in [-M, -M + 1) from a point
 // to its first tap to the per-point argument, and tap(j, x) is the window
-// at tap j.  FP32 evaluates the per-tap polynomials (Horner, coefficients
-// read from a small workspace table through scalar loads); FP64 evaluates the
-// closed form.
+// at tap j.  Both precisions evaluate per-tap polynomials by Horner, their
+// coefficients read from a small workspace table through scalar loads.
 template <typename R>
 struct WinEval;
 
@@ -31,7 +30,8 @@ template <>
 struct WinEval<float> {
   const float* __restrict__ P;  // (2 kMaxM + 1) x kPolyCoef, uniform across the wave
   float shift;                  // 2M - 1
-  __device__ __forceinline__ WinEval(const WindowConst&, const float* p, int M) : P(p), shift(float(2 * M - 1)) {}
+  __device__ __forceinline__ WinEval(const WindowConst&, const void* p, int M)
+      : P(static_cast<const float*>(p)), shift(float(2 * M - 1)) {}
   __device__ __forceinline__ float arg(float z0) const { return fmaf(2.0f, z0, shift); }
   // NC = poly_coef(m): the coefficients the host fitted for this half-width
   template <int NC>
@@ -44,14 +44,23 @@ struct WinEval<float> {
   }
 };
 
+// FP64: degree-14 per-tap polynomials (WindowPoly64), 14 FMAs per window
+// value instead of a square root, two exponentials and a division.
 template <>
 struct WinEval<double> {
-  double m2, b, bm, cn;
-  __device__ __forceinline__ WinEval(const WindowConst& wc, const float*, int)
-      : m2(wc.m2), b(wc.b), bm(wc.bm), cn(wc.cnorm) {}
-  __device__ __forceinline__ double arg(double z0) const { return z0; }
+  const double* __restrict__ P;  // (2 kMaxM + 1) x kPolyCoef64, uniform across the wave
+  double shift;                  // 2M - 1
+  __device__ __forceinline__ WinEval(const WindowConst&, const void* p, int M)
+      : P(static_cast<const double*>(p)), shift(double(2 * M - 1)) {}
+  __device__ __forceinline__ double arg(double z0) const { return fma(2.0, z0, shift); }
   template <int NC>
-  __device__ __forceinline__ double tap(int j, double z0) const { return kb_psi(z0 + double(j), m2, b, bm, cn); }
+  __device__ __forceinline__ double tap(int j, double x) const {
+    const double* c = P + j * kPolyCoef64;
+    double v = c[kPolyCoef64 - 1];
+#pragma unroll
+    for (int k = kPolyCoef64 - 2; k >= 0; --k) v = fma(v, x, c[k]);
+    return v;
+  }
 };
 
 // Window taps of one point: the first tap offset per axis (off), the window
