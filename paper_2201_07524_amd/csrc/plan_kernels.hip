@@ -551,20 +551,24 @@ hipError_t launch_maxsum(const double* v, long n, double* partials, unsigned* co
   return hipGetLastError();
 }
 
+// eps log alpha_i enters the weight gradient only where alpha_i > 0: a point of
+// weight zero has scaling zero and contributes 0 log 0 = 0 to the dual.
+__device__ __forceinline__ double log_or_zero(double a) { return a > 0.0 ? log(a) : 0.0; }
+
 __global__ __launch_bounds__(kBlock) void logmean_kernel(const double* alpha, long n, double* partials,
                                                          unsigned* counter, double* out) {
   constexpr int NV = 1;
   double v[NV] = {0.0};
   const bool is_min[NV] = {false}, is_max[NV] = {false};
   const long stride = long(gridDim.x) * kBlock;
-  for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) v[0] += log(alpha[i]);
+  for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) v[0] += log_or_zero(alpha[i]);
   grid_reduce_arr<NV>(v, is_min, is_max, partials, counter, out);
 }
 
 __global__ __launch_bounds__(kBlock) void gradmu_kernel(const double* alpha, long n, double eps,
                                                         const double* sumlog, double* g) {
   const long i = long(blockIdx.x) * kBlock + threadIdx.x;
-  if (i < n) g[i] = eps * (log(alpha[i]) - *sumlog / double(n));
+  if (i < n) g[i] = eps * (log_or_zero(alpha[i]) - *sumlog / double(n));
 }
 
 hipError_t launch_gradmu(const double* alpha, long n, double eps, double* partials, unsigned* counter,

@@ -81,6 +81,42 @@ def test_kernel_sum_riemann_closed_form(d, r):
         assert abs(got_dense - exact) <= tol * exact
 
 
+@pytest.mark.parametrize("eps", [0.02, 0.5])
+def test_coincident_support_upper_value_is_zero(eps):
+    """Coincident supports: c = 0, so s = -eps (H(p) + H(pt)) and the upper
+    value of Section 3.2, s + (H(P) + H(Pt))/lambda, is exactly the transport
+    cost 0 (the upper bound of Lemma 2.1 is attained).  An upper value that
+    drops the factor eps (or 1/lambda) on the entropies is nonzero here for
+    every eps != 1."""
+    n, nt = 6, 9
+    x = np.tile([[-0.2, 0.15]], (n, 1))
+    y = np.tile([[-0.2, 0.15]], (nt, 1))
+    p = workloads.dirichlet_weights(n, 21)
+    pt = workloads.dirichlet_weights(nt, 22)
+    out = sd.solve(x, p, y, pt, 2, eps, iters=2)
+    assert abs(out["cost_upper"]) <= 1e-15
+    assert abs(out["cost_primal"]) == 0.0
+
+
+def test_marginal_errors_closed_form_on_unit_kernel():
+    """eq. (Error) with the Euclidean norm, at a state where it is known by
+    hand: coincident supports make every kernel entry 1, and at alpha = 1,
+    alpha_t = 1 each row of pi sums to nt and each column to n.  With n = 3,
+    p = (1/2, 1/4, 1/4) and nt = 4, pt = 1/4 the row residual vector is
+    (3.5, 3.75, 3.75), of Euclidean norm sqrt(40.375) (its l1 norm is 11 and
+    its squared norm 40.375), and the column residual vector is 2.75 in each
+    of 4 entries, of Euclidean norm 5.5 (l1 norm 11, squared norm 30.25)."""
+    x = np.zeros((3, 2))
+    y = np.zeros((4, 2))
+    K = sd.gibbs_kernel(x, y, 2, 0.1)
+    assert np.all(K == 1.0)
+    p = np.array([0.5, 0.25, 0.25])
+    pt = np.full(4, 0.25)
+    e_row, e_col = sd.marginal_errors(K, np.ones(3), np.ones(4), p, pt)
+    assert abs(e_row - math.sqrt(40.375)) <= 1e-15
+    assert abs(e_col - 5.5) <= 1e-15
+
+
 # ---------------------------------------------------------------- the paper's lemmas
 @pytest.mark.parametrize("r", [1, 2])
 def test_dual_ascent_equals_kl(r):
@@ -365,6 +401,25 @@ def test_planted_mistakes_are_caught():
     expect = 2.0 * (p @ x - pt @ y)
     assert np.allclose(gx.sum(0), expect, atol=1e-13)
     assert not np.allclose((0.5 * gx).sum(0), expect, atol=1e-6)
+
+    # (f) upper value without the factor eps on the entropies: on coincident
+    # supports it is not the closed-form 0 of test_coincident_support_upper_value_is_zero
+    xc = np.zeros((n, 2))
+    yc = np.zeros((nt, 2))
+    sc = sd.solve(xc, p, yc, pt, 2, eps, iters=2)["cost"]
+    assert abs(sd.cost_upper_bound(sc, p, pt, eps)) <= 1e-15
+    assert abs(sc + sd.entropy(p) + sd.entropy(pt)) > 1e-2
+
+    # (g) marginal residual in the l1 or squared norm instead of the Euclidean
+    # one misses the closed form of test_marginal_errors_closed_form_on_unit_kernel
+    K1 = np.ones((3, 4))
+    p3, pt4 = np.array([0.5, 0.25, 0.25]), np.full(4, 0.25)
+    row = np.ones(3) * (K1 @ np.ones(4)) - p3
+    col = np.ones(4) * (K1.T @ np.ones(3)) - pt4
+    assert abs(float(np.sum(np.abs(row))) - math.sqrt(40.375)) > 1.0
+    assert abs(float(np.sum(row * row)) - math.sqrt(40.375)) > 1.0
+    assert abs(float(np.sum(np.abs(col))) - 5.5) > 1.0
+    assert abs(float(np.sum(col * col)) - 5.5) > 1.0
 
     # (e) Sinkhorn divergence without the factors 1/2 is not zero on identical
     # measures (the pin of property 3 rejects it)
