@@ -131,6 +131,26 @@ int nfs_fastsum_apply(const nfs_params* prm, const double* src, int64_t ns, cons
                       void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * Allocation-free variant of nfs_fastsum_apply, for callers that cannot
+ * allocate device memory or pass a workspace: code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * result, layout and errors as nfs_fastsum_apply, without the workspace: its
+ * scratch is a static device array of NFS_NOALLOC_SCRATCH_BYTES bytes that the
+ * library holds on every GPU it runs on until the process ends.  The call
+ * allocates no device memory (no hipMalloc/hipFree, no allocating library
+ * call).  A problem whose scratch need exceeds the limit (the need is at
+ * most what nfs_workspace_size() reports for the same sizes, e.g. about
+ * 24 MiB for 1e5 + 1e5 points at d = 2, N = 512, FP32) returns
+ * NFS_EWORKSPACE before any device work.  Every call on one GPU shares that
+ * GPU's array: calls that overlap in time on one GPU (from several host
+ * threads or on several streams) race and give undefined results; calls on
+ * one stream, or on different GPUs, do not.
+ */
+#define NFS_NOALLOC_SCRATCH_BYTES (64u << 20)
+int nfs_fastsum_apply_noalloc(const nfs_params* prm, const double* src, int64_t ns, const double* w,
+                              const double* tgt, int64_t nt, double* out, void* stream);
+
+/*
  * Adjoint NFFT, the inner sum of eq. (fastsum) for real weights, on the
  * period-1 torus: fhat_k = sum_j w_j exp(-2 pi i k.y_j), k in I_N.
  * pts: n x d with every coordinate in [-1/2, 1/2); fhat: N^d complex values,

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -848,6 +849,41 @@ static int do_fastsum(const nfs_params* p, const double* src, int64_t ns, const 
   return NFS_OK;
 }
 
+// Workspace bytes of do_fastsum (one weight vector per cloud).
+template <typename R>
+static size_t fastsum_bytes(const nfs_params* p, int64_t ns, int64_t nt) {
+  Work<R> w;
+  carve(w, p, 1, ns, nt, nullptr, 1);
+  return w.bytes;
+}
+
+// ----------------------------------------------------------------------------- allocation-free fast summation
+// Scratch of nfs_fastsum_apply_noalloc: a file-scope device array, one copy
+// on every GPU the library runs on, held until the process ends.  Host code
+// never passes the array's name to a kernel or a copy: that name is a host
+// stand-in, not a device address.  Each device's address is looked up once,
+// with that device current, and kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = size_t(NFS_NOALLOC_SCRATCH_BYTES);
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static int scratch_address(void** out) {
+  int dev = -1;
+  NFS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(NFS_EUNSUPPORTED, "device ordinal above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    NFS_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(NFS_EHIP, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return NFS_OK;
+}
+
 template <typename R>
 static int do_nfft(const nfs_params* p, bool adjoint, const double* pts, int64_t n, const double* wv,
                    const double* fhat_in, double* fhat_out, double* out, void* ws, size_t wsb, hipStream_t st) {
@@ -1617,6 +1653,23 @@ int nfs_fastsum_apply(const nfs_params* prm, const double* src, int64_t ns, cons
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (prm->precision == NFS_FP32) return do_fastsum<float>(prm, src, ns, w, tgt, nt, out, workspace, ws_bytes, st);
   return do_fastsum<double>(prm, src, ns, w, tgt, nt, out, workspace, ws_bytes, st);
+}
+
+int nfs_fastsum_apply_noalloc(const nfs_params* prm, const double* src, int64_t ns, const double* w,
+                              const double* tgt, int64_t nt, double* out, void* stream) {
+  g_err.clear();
+  NFS_TRY(check_params(prm, ns, nt));
+  if (!src || !w || !tgt || !out) return fail(NFS_EINVAL, "NULL pointer argument");
+  const size_t need = prm->precision == NFS_FP32 ? fastsum_bytes<float>(prm, ns, nt) : fastsum_bytes<double>(prm, ns, nt);
+  if (need > kScratchBytes)
+    return fail(NFS_EWORKSPACE, "problem needs " + std::to_string(need) + " bytes of scratch, above the " +
+                                    std::to_string(kScratchBytes) +
+                                    "-byte static scratch of nfs_fastsum_apply_noalloc; use nfs_fastsum_apply");
+  void* ws = nullptr;
+  NFS_TRY(scratch_address(&ws));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (prm->precision == NFS_FP32) return do_fastsum<float>(prm, src, ns, w, tgt, nt, out, ws, kScratchBytes, st);
+  return do_fastsum<double>(prm, src, ns, w, tgt, nt, out, ws, kScratchBytes, st);
 }
 
 int nfs_plan_apply(const nfs_params* prm, const double* x, int64_t n, const double* y, int64_t nt,

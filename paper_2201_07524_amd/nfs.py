@@ -16,9 +16,11 @@ LIB_PATH = os.path.join(HERE, "lib", "libnfs.so")
 
 NFS_OK, NFS_EINVAL, NFS_EWEIGHTS, NFS_ENONPOS, NFS_EUNSUPPORTED, NFS_EHIP, NFS_EWORKSPACE = range(7)
 NFS_FP64, NFS_FP32, NFS_AUTO = 0, 1, 2
+NOALLOC_SCRATCH_BYTES = 64 << 20   # NFS_NOALLOC_SCRATCH_BYTES of include/nfs.h
 FLAG_NO_GRAPH, FLAG_PRIMAL_COST, FLAG_TILE_REDUCE, FLAG_LOG_DOMAIN, FLAG_AUTOTUNE = 1, 2, 4, 8, 16
 
 EXPORTED = ("nfs_last_error", "nfs_validate", "nfs_workspace_size", "nfs_fastsum_apply",
+            "nfs_fastsum_apply_noalloc",
             "nfs_nfft_adjoint", "nfs_nfft_trafo", "nfs_sinkhorn_solve", "nfs_sinkhorn_solve_log",
             "nfs_sinkhorn_grad", "nfs_sinkhorn_grad_targets", "nfs_plan_apply",
             "nfs_solver_create", "nfs_solver_iterate", "nfs_solver_residual", "nfs_solver_finish",
@@ -93,6 +95,8 @@ def load_library():
     lib.nfs_workspace_size.argtypes = [PP, I64, I64, ctypes.POINTER(SZ)]
     lib.nfs_fastsum_apply.restype = ctypes.c_int
     lib.nfs_fastsum_apply.argtypes = [PP, P, I64, P, P, I64, P, P, SZ, P]
+    lib.nfs_fastsum_apply_noalloc.restype = ctypes.c_int
+    lib.nfs_fastsum_apply_noalloc.argtypes = [PP, P, I64, P, P, I64, P, P]
     lib.nfs_nfft_adjoint.restype = ctypes.c_int
     lib.nfs_nfft_adjoint.argtypes = [PP, P, I64, P, P, P, SZ, P]
     lib.nfs_nfft_trafo.restype = ctypes.c_int
@@ -195,6 +199,27 @@ def fastsum(params, src, w, tgt):
     ws, nb = _workspace(params, ns, nt, tgt.device)
     _check(lib.nfs_fastsum_apply(ctypes.byref(params.to_c()), src.data_ptr(), ns, w.data_ptr(),
                                  tgt.data_ptr(), nt, out.data_ptr(), ws.data_ptr(), nb, _stream()))
+    return out
+
+
+def fastsum_noalloc(params, src, w, tgt, out=None):
+    """fastsum() through the allocation-free entry point: no workspace, the
+    library's static device scratch (NFS_NOALLOC_SCRATCH_BYTES) instead.
+    `out` (nt float64 GPU values) may be passed in to keep the call free of
+    allocations on the Python side as well."""
+    lib = load_library()
+    src = _pts(src, params.d, "src")
+    tgt = _pts(tgt, params.d, "tgt")
+    _dev(w, "w")
+    ns, nt = src.shape[0], tgt.shape[0]
+    if out is None:
+        out = torch.empty(nt, dtype=torch.float64, device=tgt.device)
+    else:
+        _dev(out, "out")
+        if out.numel() != nt:
+            raise ValueError("out must hold one value per target")
+    _check(lib.nfs_fastsum_apply_noalloc(ctypes.byref(params.to_c()), src.data_ptr(), ns, w.data_ptr(),
+                                         tgt.data_ptr(), nt, out.data_ptr(), _stream()))
     return out
 
 
