@@ -109,6 +109,11 @@ typedef struct nfs_result {
   int32_t iters;        /* iterations done (one = alpha update then alpha_t update) */
   int32_t precision_used;
   int64_t n_nonpos;     /* number of kernel sums t <= 0 or non-finite seen */
+  double dyn_range;     /* largest ratio ||w||_1 / min_i t_i over the solve's half-steps, w the
+                           source weights of the sums t (Algorithm 3 only; NaN in the log
+                           domain, infinite once a sum t <= 0 was seen): the dynamic range
+                           the fast sums had to resolve, as their error is normwise in
+                           ||w||_1 */
 } nfs_result;
 
 /* Message for the last error on this thread ("" if none). */

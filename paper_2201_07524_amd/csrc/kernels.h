@@ -7,7 +7,8 @@ namespace nfs {
 
 enum Epilogue : int {
   EPI_OUT = 0,   // out[perm[q]*stride + comp] = t * scale_vec[q]
-  EPI_SINK = 1,  // alpha[q] = p[q]/t, residual and mass reductions (Algorithm 3 half-step)
+  EPI_SINK = 1,  // alpha[q] = p[q]/t with the residual of the old alpha[q], and the reductions
+                 // below (Algorithm 3 half-step)
   EPI_EVAL = 2,  // residual sum (alpha[q] t - p[q])^2 only, no update
   // Log domain (Algorithm 4): alpha[] holds potentials beta, the source side's
   // weights were exp((gamma - shift)/eps) with shift = wmul_src[prob], so the
@@ -18,6 +19,24 @@ enum Epilogue : int {
 
 // Per-problem constants of the log domain: leps[2 b] = 1/eps_b, leps[2 b + 1] = eps_b.
 constexpr int kLepsStride = 2;
+
+// Per-problem statistics of a half-step (doubles, stride kStat), written by
+// the last workgroup of the problem's interpolation:
+//   [0] sum (alpha_old t - p)^2: the squared residual of eq. (Error) of the
+//       state before the update (the row term at an alpha update, the column
+//       term at an alpha_t update)
+//   [1] sum alpha_new t (mass; EPI_EVAL: sum alpha_old t)
+//   [2] max alpha_new (EPI_EVAL: max alpha_old; log domain: max potential)
+//   [3] count of sums t <= 0 or non-finite in this launch, [4] running count
+//   [5] min t, [6] max t over targets of positive weight
+//   [7] sum |alpha_new| (the l1 norm of the next half-step's source weights)
+//   [8] running max of ||w||_1 / min t, w the source weights (scaling form:
+//       the dynamic range the sums had to resolve)
+constexpr int kStat = 16;
+// Per-problem state of a solve (ints, stride kPState): [0] 0 running, 1 the
+// alpha update found ||E|| <= tol for the state before it, 2 stopped (every
+// kernel of an iteration skips the problem); [1] iterations completed.
+constexpr int kPState = 2;
 
 template <typename R>
 struct SpreadArgs {
@@ -38,6 +57,7 @@ struct SpreadArgs {
   int cell_order;        // points sorted by cell inside each tile
   R* grid;               // problem p's g^d real grid at grid + p*grid_stride, zero on entry
   long grid_stride;
+  const int* pstate;     // nullable: chunks of problems in state 2 are skipped
   R* part;               // non-null: store each chunk's padded tile here instead of flushing
   WindowConst win;
   const void* __restrict__ wpoly;   // window polynomials: WindowPoly::c (FP32) or WindowPoly64::c (FP64)
@@ -52,6 +72,7 @@ struct ReduceArgs {
   const R* part;           // chunk tiles, E^d values each
   const int* tile_chunks;  // nbins + 1 offsets into the chunk list (chunks are sorted by tile)
   R* grid;
+  const int* pstate;       // nullable: nothing to do when the (single) problem is in state 2
 };
 template <typename R>
 hipError_t launch_spread_reduce(const ReduceArgs<R>& a, int nbins, hipStream_t st);
@@ -83,13 +104,15 @@ struct InterpArgs {
   // EPI_SINK / EPI_EVAL
   const double* p;
   double* alpha;
-  double* partials;         // 4 doubles per chunk
+  double* partials;         // kRedVals doubles per chunk
   unsigned* counter;        // per problem, zero on entry, left zero
   const int* prob_chunks;   // B + 1: chunks of problem p are [prob_chunks[p], prob_chunks[p+1])
-  double* stats;            // per problem (stride 8): residual^2 sum (EPI_EVAL only), mass sum, max alpha,
-                            // count(t <= 0),
-                            // running count
+  double* stats;            // per problem, stride kStat (layout above)
   double* wmul_next;        // per problem, receives 1/max alpha (log domain: max beta) (nullable)
+  const double* src_l1;     // nullable: per problem (stride kStat) the l1 norm of the source weights
+  int* pstate;              // nullable: per problem (stride kPState); stopped problems are skipped
+  const double* tol2;       // with pstate: squared tolerance on the residual (<= 0: never stop)
+  int half;                 // with pstate: 0 alpha update (residual checked), 1 alpha_t update
 };
 
 // Near-field correction for r = 1 (kernel exp(-|z|/eps) regularized inside
@@ -114,6 +137,7 @@ struct NearArgs {
   int kt;
   int ps;               // polynomial terms p
   double* out;
+  const int* pstate;    // nullable: targets of problems in state 2 are skipped
   const int* scell;     // nullable: per source tile the cell starts (TileSortArgs::cellstart);
                         // with it only the source cells within eps_I of each wave's targets are read
 };
@@ -288,8 +312,9 @@ hipError_t launch_readout(const ReadoutArgs& a, hipStream_t st);
 // Log-domain weights of a sorted cloud, one workgroup per chunk:
 //   out[q] = exp((pot[q] - shift[prob]) / eps_prob), prob = chunks[blockIdx].prob,
 // in [0, 1] when shift is the problem's largest potential (-inf gives 0).
+// Chunks of problems in state 2 of pstate (nullable) are skipped.
 hipError_t launch_logweights(const Chunk* chunks, int nchunks, const double* pot, const double* shift,
-                             const double* leps, double* out, hipStream_t st);
+                             const double* leps, double* out, const int* pstate, hipStream_t st);
 
 // out[i] = a[i] * b[i], i < n.
 hipError_t launch_mul(const double* a, const double* b, long n, double* out, hipStream_t st);

@@ -180,9 +180,11 @@ struct Work {
   double* partials = nullptr;
   unsigned* ct_interp = nullptr;  // B
   unsigned* ct_misc = nullptr;    // 8
-  double* st_row = nullptr;   // B x 8
-  double* st_col = nullptr;   // B x 8
-  double* st_eval = nullptr;  // B x 8
+  double* st_row = nullptr;   // B x kStat: statistics of the alpha updates
+  double* st_col = nullptr;   // B x kStat: statistics of the alpha_t updates
+  double* st_eval = nullptr;  // B x kStat: statistics of the evaluation half-steps
+  int* pstate = nullptr;      // B x kPState: stop state and completed iterations of each problem
+  double* tol2 = nullptr;     // squared tolerance of the stop test (0: run every iteration)
   double* st_rdx = nullptr;   // B x 4
   double* st_rdy = nullptr;   // B x 4
   double* st_cost = nullptr;  // B x 4
@@ -302,9 +304,11 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
   w.partials = cv.take<double>(size_t(std::max<long>(maxch, 1024)) * 9);
   w.ct_interp = cv.take<unsigned>(B);
   w.ct_misc = cv.take<unsigned>(8);
-  w.st_row = cv.take<double>(size_t(B) * 8);
-  w.st_col = cv.take<double>(size_t(B) * 8);
-  w.st_eval = cv.take<double>(size_t(B) * 8);
+  w.st_row = cv.take<double>(size_t(B) * kStat);
+  w.st_col = cv.take<double>(size_t(B) * kStat);
+  w.st_eval = cv.take<double>(size_t(B) * kStat);
+  w.pstate = cv.take<int>(size_t(B) * kPState);
+  w.tol2 = cv.take<double>(1);
   w.st_rdx = cv.take<double>(size_t(B) * 4);
   w.st_rdy = cv.take<double>(size_t(B) * 4);
   w.st_cost = cv.take<double>(size_t(B) * 4);
@@ -330,7 +334,9 @@ template <typename R>
 static int zero_state(Work<R>& w, hipStream_t st) {
   NFS_HIP(launch_fill(w.ct_interp, sizeof(unsigned) * w.B, st));
   NFS_HIP(launch_fill(w.ct_misc, sizeof(unsigned) * 8, st));
-  for (double* s : {w.st_row, w.st_col, w.st_eval}) NFS_HIP(launch_fill(s, sizeof(double) * 8 * w.B, st));
+  for (double* s : {w.st_row, w.st_col, w.st_eval}) NFS_HIP(launch_fill(s, sizeof(double) * kStat * w.B, st));
+  NFS_HIP(launch_fill(w.pstate, sizeof(int) * kPState * w.B, st));
+  NFS_HIP(launch_fill(w.tol2, sizeof(double), st));
   for (double* s : {w.st_rdx, w.st_rdy, w.st_cost}) NFS_HIP(launch_fill(s, sizeof(double) * 4 * w.B, st));
   return NFS_OK;
 }
@@ -712,9 +718,10 @@ static SpreadArgs<R> spread_args(Work<R>& w, const CloudBuf<R>& src, const doubl
 // chunk tiles summed per (tile, neighbour).
 template <typename R>
 static hipError_t spread(Work<R>& w, const CloudBuf<R>& src, const double* weights, const double* wmul,
-                         double wconst, hipStream_t st) {
+                         double wconst, hipStream_t st, const int* pstate = nullptr) {
   SpreadArgs<R> a = spread_args(w, src, weights, wmul);
   a.wconst = wconst;
+  a.pstate = pstate;
   if (!w.two_level) return launch_spread(a, src.nchunks, st);
   a.part = w.part;
   hipError_t e = launch_spread(a, src.nchunks, st);
@@ -724,6 +731,7 @@ static hipError_t spread(Work<R>& w, const CloudBuf<R>& src, const double* weigh
   r.part = w.part;
   r.tile_chunks = src.tile_chunks;
   r.grid = w.S;
+  r.pstate = pstate;
   return launch_spread_reduce(r, w.nbins, st);
 }
 
@@ -755,7 +763,7 @@ static InterpArgs<R> interp_args(Work<R>& w, const CloudBuf<R>& tgt, int epi, co
 // targets `tgt`, into w.nf (sorted target order, normalized like the spread).
 template <typename R>
 static hipError_t near_field(Work<R>& w, const CloudBuf<R>& src, const CloudBuf<R>& tgt, const double* weights,
-                             const double* wmul, double wconst, hipStream_t st) {
+                             const double* wmul, double wconst, hipStream_t st, const int* pstate = nullptr) {
   NearArgs<R> a{};
   a.geo = w.geo;
   a.tcoords = tgt.coords;
@@ -770,6 +778,7 @@ static hipError_t near_field(Work<R>& w, const CloudBuf<R>& src, const CloudBuf<
   a.kt = w.kt;
   a.ps = w.ps;
   a.out = w.nf;
+  a.pstate = pstate;
   a.scell = src.cellstart;
   return launch_nearfield(a, tgt.nchunks, st);
 }
@@ -779,22 +788,28 @@ static hipError_t near_field(Work<R>& w, const CloudBuf<R>& src, const CloudBuf<
 // eq. (fastsum)).  In the log domain (EPI_LOGSINK / EPI_LOGEVAL, Algorithm 4)
 // src.w1s and tgt.w1s hold potentials, wmul_* their per-problem maxima, and
 // the spread weights exp((gamma - max gamma)/eps) go through w.tmp.
+// `half` (iterations only): 0 for the alpha update, 1 for the alpha_t update;
+// it hands every kernel the problems' stop state (stopped problems are
+// skipped) and `src_l1` (the stats slot holding the l1 norm of the source
+// weights, scaling form only) to the interpolation.  Evaluation half-steps
+// pass half = -1 and run for every problem.
 template <typename R>
 static hipError_t half_step(Work<R>& w, CloudBuf<R>& src, CloudBuf<R>& tgt, double* wmul_src, double* wmul_tgt,
-                            double* stats, int epi, hipStream_t st) {
+                            double* stats, int epi, hipStream_t st, int half = -1, const double* src_l1 = nullptr) {
   const bool logd = epi == EPI_LOGSINK || epi == EPI_LOGEVAL;
+  const int* ps = half >= 0 ? w.pstate : nullptr;
   const double* wv = src.w1s;
   const double* wm = wmul_src;
   hipError_t e;
   if (logd) {
-    if ((e = launch_logweights(src.chunks, src.nchunks, src.w1s, wmul_src, w.leps, w.tmp, st)) != hipSuccess)
+    if ((e = launch_logweights(src.chunks, src.nchunks, src.w1s, wmul_src, w.leps, w.tmp, ps, st)) != hipSuccess)
       return e;
     wv = w.tmp;
     wm = nullptr;
   }
-  if ((e = spread(w, src, wv, wm, 1.0, st)) != hipSuccess) return e;
+  if ((e = spread(w, src, wv, wm, 1.0, st, ps)) != hipSuccess) return e;
   if ((e = fft_chain(w, w.dtab, -1, st)) != hipSuccess) return e;
-  if (w.r == 1 && (e = near_field(w, src, tgt, wv, wm, 1.0, st)) != hipSuccess) return e;
+  if (w.r == 1 && (e = near_field(w, src, tgt, wv, wm, 1.0, st, ps)) != hipSuccess) return e;
   InterpArgs<R> ia = interp_args(w, tgt, epi, wmul_src);
   if (w.r == 1) ia.nf = w.nf;
   ia.leps = w.leps;
@@ -802,6 +817,12 @@ static hipError_t half_step(Work<R>& w, CloudBuf<R>& src, CloudBuf<R>& tgt, doub
   ia.alpha = tgt.w1s;
   ia.stats = stats;
   ia.wmul_next = (epi == EPI_SINK || epi == EPI_LOGSINK) ? wmul_tgt : nullptr;
+  if (half >= 0) {
+    ia.pstate = w.pstate;
+    ia.tol2 = w.tol2;
+    ia.half = half;
+    ia.src_l1 = logd ? nullptr : src_l1;
+  }
   return launch_interp(ia, tgt.nchunks, st);
 }
 
@@ -1074,6 +1095,10 @@ struct SolverBase {
   virtual int finish(double* alpha, double* alpha_t, nfs_result* res, hipStream_t caller) = 0;
   virtual int profile(int k, double* stage_ms, hipStream_t caller) = 0;
   virtual int stage_info(double* info) = 0;
+  // Tolerance of the per-iteration stop test (eq. (Error)); 0 runs every iteration.
+  virtual int set_tol(double tol, hipStream_t caller) = 0;
+  // Whether every problem has stopped on the tolerance (synchronizes).
+  virtual int all_stopped(bool* all, hipStream_t caller) = 0;
 };
 
 template <typename R>
@@ -1091,10 +1116,12 @@ struct Solver : SolverBase {
   int sink() const { return logd ? EPI_LOGSINK : EPI_SINK; }
   int eval() const { return logd ? EPI_LOGEVAL : EPI_EVAL; }
 
+  // One iteration: the alpha update (sources y with alpha_t; its epilogue
+  // also gives ||E|| of the state before it) and the alpha_t update.
   hipError_t iteration(hipStream_t s) {
-    hipError_t e = half_step(w, w.Y, w.X, w.wmul_y, w.wmul_x, w.st_row, sink(), s);
+    hipError_t e = half_step(w, w.Y, w.X, w.wmul_y, w.wmul_x, w.st_row, sink(), s, 0, w.st_col + 7);
     if (e != hipSuccess) return e;
-    return half_step(w, w.X, w.Y, w.wmul_x, w.wmul_y, w.st_col, sink(), s);
+    return half_step(w, w.X, w.Y, w.wmul_x, w.wmul_y, w.st_col, sink(), s, 1, w.st_row + 7);
   }
 
   // Chunk size by measurement: rebuild the chunk and run tables for each
@@ -1107,7 +1134,8 @@ struct Solver : SolverBase {
     for (int c : {w.chunk, 2 * w.chunk, 4096, 8192})
       if (c >= w.chunk && c <= 32768 && std::find(cands.begin(), cands.end(), c) == cands.end()) cands.push_back(c);
     if (cands.size() < 2) return NFS_OK;
-    std::vector<double> hx(w.X.n), hy(w.Y.n), hwx(B), hwy(B);
+    std::vector<double> hx(w.X.n), hy(w.Y.n), hwx(B), hwy(B), hcol(size_t(B) * kStat);
+    NFS_HIP(hipMemcpyAsync(hcol.data(), w.st_col, sizeof(double) * hcol.size(), hipMemcpyDeviceToHost, st));
     NFS_HIP(hipMemcpyAsync(hx.data(), w.X.w1s, sizeof(double) * hx.size(), hipMemcpyDeviceToHost, st));
     NFS_HIP(hipMemcpyAsync(hy.data(), w.Y.w1s, sizeof(double) * hy.size(), hipMemcpyDeviceToHost, st));
     NFS_HIP(hipMemcpyAsync(hwx.data(), w.wmul_x, sizeof(double) * B, hipMemcpyDeviceToHost, st));
@@ -1148,8 +1176,9 @@ struct Solver : SolverBase {
     NFS_HIP(hipMemcpyAsync(w.Y.w1s, hy.data(), sizeof(double) * hy.size(), hipMemcpyHostToDevice, st));
     NFS_HIP(hipMemcpyAsync(w.wmul_x, hwx.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
     NFS_HIP(hipMemcpyAsync(w.wmul_y, hwy.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
-    NFS_HIP(launch_fill(w.st_row, sizeof(double) * size_t(B) * 8, st));
-    NFS_HIP(launch_fill(w.st_col, sizeof(double) * size_t(B) * 8, st));
+    NFS_HIP(launch_fill(w.st_row, sizeof(double) * size_t(B) * kStat, st));
+    NFS_HIP(hipMemcpyAsync(w.st_col, hcol.data(), sizeof(double) * hcol.size(), hipMemcpyHostToDevice, st));
+    NFS_HIP(launch_fill(w.pstate, sizeof(int) * size_t(B) * kPState, st));
     NFS_HIP(hipStreamSynchronize(st));  // the host copies above must outlive the transfers
     return NFS_OK;
   }
@@ -1157,12 +1186,18 @@ struct Solver : SolverBase {
   // Starting scalings (Algorithm 3): alpha = 1; alpha_t = 1, or the caller's
   // positive starting value (already sorted into Y.w1s by the plan); wmul_*
   // normalize the spread weights by their maximum.
+  // The l1 norm of the starting alpha_t goes to st_col[kStat b + 7], where the
+  // first alpha update reads its source norm.
   int start_scalings(int B, const std::vector<long>& oy, const double* alpha_t0, hipStream_t st) {
     NFS_HIP(launch_fill_double(w.X.w1s, w.X.n, 1.0, st));
     NFS_HIP(launch_fill_double(w.wmul_x, B, 1.0, st));
+    std::vector<double> col(size_t(B) * kStat, 0.0);
     if (!alpha_t0) {
       NFS_HIP(launch_fill_double(w.Y.w1s, w.Y.n, 1.0, st));
       NFS_HIP(launch_fill_double(w.wmul_y, B, 1.0, st));
+      for (int b = 0; b < B; ++b) col[size_t(b) * kStat + 7] = double(oy[b + 1] - oy[b]);
+      NFS_HIP(hipMemcpyAsync(w.st_col, col.data(), sizeof(double) * col.size(), hipMemcpyHostToDevice, st));
+      NFS_HIP(hipStreamSynchronize(st));  // col is read by the copy
       return NFS_OK;
     }
     for (int b = 0; b < B; ++b)
@@ -1175,9 +1210,11 @@ struct Solver : SolverBase {
       if (!(box[20 * b + 7] > 0.0) || !std::isfinite(box[20 * b + 6]))
         return fail(NFS_EINVAL, "warm-start alpha_t must be positive and finite");
       wm[b] = 1.0 / box[20 * b + 6];
+      col[size_t(b) * kStat + 7] = box[20 * b + 8];
     }
     NFS_HIP(hipMemcpyAsync(w.wmul_y, wm.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
-    NFS_HIP(hipStreamSynchronize(st));  // wm is read by the copy
+    NFS_HIP(hipMemcpyAsync(w.st_col, col.data(), sizeof(double) * col.size(), hipMemcpyHostToDevice, st));
+    NFS_HIP(hipStreamSynchronize(st));  // wm and col are read by the copies
     return NFS_OK;
   }
 
@@ -1290,11 +1327,11 @@ struct Solver : SolverBase {
   int residual(double* err_row, hipStream_t caller) override {
     NFS_TRY(enter(caller));
     NFS_HIP(half_step(w, w.Y, w.X, w.wmul_y, w.wmul_x, w.st_eval, eval(), gs));
-    std::vector<double> h(size_t(w.B) * 8);
+    std::vector<double> h(size_t(w.B) * kStat);
     NFS_HIP(hipMemcpyAsync(h.data(), w.st_eval, sizeof(double) * h.size(), hipMemcpyDeviceToHost, gs));
     NFS_HIP(hipStreamSynchronize(gs));
     double e = 0.0;
-    for (int b = 0; b < w.B; ++b) e = std::max(e, std::sqrt(h[8 * b]));
+    for (int b = 0; b < w.B; ++b) e = std::max(e, std::sqrt(h[size_t(kStat) * b]));
     *err_row = e;
     return leave(caller);
   }
@@ -1316,15 +1353,15 @@ struct Solver : SolverBase {
         const double* wv = src.w1s;
         const double* wm = ws_;
         if (logd) {
-          NFS_HIP(launch_logweights(src.chunks, src.nchunks, src.w1s, ws_, w.leps, w.tmp, gs));
+          NFS_HIP(launch_logweights(src.chunks, src.nchunks, src.w1s, ws_, w.leps, w.tmp, w.pstate, gs));
           wv = w.tmp;
           wm = nullptr;
         }
-        NFS_HIP(spread(w, src, wv, wm, 1.0, gs));
+        NFS_HIP(spread(w, src, wv, wm, 1.0, gs, w.pstate));
         NFS_HIP(hipEventRecord(evs[ie++], gs));
         NFS_HIP(fft_chain(w, w.dtab, -1, gs));
         NFS_HIP(hipEventRecord(evs[ie++], gs));
-        if (w.r == 1) NFS_HIP(near_field(w, src, tgt, wv, wm, 1.0, gs));
+        if (w.r == 1) NFS_HIP(near_field(w, src, tgt, wv, wm, 1.0, gs, w.pstate));
         NFS_HIP(hipEventRecord(evs[ie++], gs));
         InterpArgs<R> ia = interp_args(w, tgt, sink(), ws_);
         ia.leps = w.leps;
@@ -1333,6 +1370,10 @@ struct Solver : SolverBase {
         ia.alpha = tgt.w1s;
         ia.stats = h == 0 ? w.st_row : w.st_col;
         ia.wmul_next = wt_;
+        ia.pstate = w.pstate;
+        ia.tol2 = w.tol2;
+        ia.half = h;
+        ia.src_l1 = logd ? nullptr : (h == 0 ? w.st_col : w.st_row) + 7;
         NFS_HIP(launch_interp(ia, tgt.nchunks, gs));
         NFS_HIP(hipEventRecord(evs[ie++], gs));
       }
@@ -1356,6 +1397,23 @@ struct Solver : SolverBase {
     return leave(caller);
   }
 
+  int set_tol(double tol, hipStream_t caller) override {
+    NFS_TRY(enter(caller));
+    NFS_HIP(launch_fill_double(w.tol2, 1, tol > 0.0 ? tol * tol : 0.0, gs));
+    return leave(caller);
+  }
+
+  int all_stopped(bool* all, hipStream_t caller) override {
+    NFS_TRY(enter(caller));
+    std::vector<int> h(size_t(w.B) * kPState);
+    NFS_HIP(hipMemcpyAsync(h.data(), w.pstate, sizeof(int) * h.size(), hipMemcpyDeviceToHost, gs));
+    NFS_HIP(hipStreamSynchronize(gs));
+    bool a = true;
+    for (int b = 0; b < w.B; ++b) a = a && h[size_t(kPState) * b] == 2;
+    *all = a;
+    return leave(caller);
+  }
+
   int stage_info(double* info) override {
     info[0] = double(w.X.n);
     info[1] = double(w.Y.n);
@@ -1376,7 +1434,7 @@ struct Solver : SolverBase {
     const int B = w.B;
     // row residual of eq. (Error): one extra product K alpha_t
     NFS_HIP(half_step(w, w.Y, w.X, w.wmul_y, w.wmul_x, w.st_eval, eval(), st));
-    std::vector<double> ev_row(size_t(B) * 8), ev_col(size_t(B) * 8);
+    std::vector<double> ev_row(size_t(B) * kStat), ev_col(size_t(B) * kStat);
     NFS_HIP(hipMemcpyAsync(ev_row.data(), w.st_eval, sizeof(double) * ev_row.size(), hipMemcpyDeviceToHost, st));
     NFS_HIP(half_step(w, w.X, w.Y, w.wmul_x, w.wmul_y, w.st_eval, eval(), st));
     NFS_HIP(hipMemcpyAsync(ev_col.data(), w.st_eval, sizeof(double) * ev_col.size(), hipMemcpyDeviceToHost, st));
@@ -1406,8 +1464,10 @@ struct Solver : SolverBase {
     }
     if (alpha) NFS_HIP(launch_unpermute(w.X.w1s, w.X.perm, w.X.n, alpha, st));
     if (alpha_t) NFS_HIP(launch_unpermute(w.Y.w1s, w.Y.perm, w.Y.n, alpha_t, st));
-    std::vector<double> col(size_t(B) * 8), row(size_t(B) * 8), rdx(size_t(B) * 4), rdy(size_t(B) * 4),
+    std::vector<double> col(size_t(B) * kStat), row(size_t(B) * kStat), rdx(size_t(B) * 4), rdy(size_t(B) * 4),
         cost(size_t(B) * 4);
+    std::vector<int> pst(size_t(B) * kPState);
+    NFS_HIP(hipMemcpyAsync(pst.data(), w.pstate, sizeof(int) * pst.size(), hipMemcpyDeviceToHost, st));
     NFS_HIP(hipMemcpyAsync(col.data(), w.st_col, sizeof(double) * col.size(), hipMemcpyDeviceToHost, st));
     NFS_HIP(hipMemcpyAsync(row.data(), w.st_row, sizeof(double) * row.size(), hipMemcpyDeviceToHost, st));
     NFS_HIP(hipMemcpyAsync(rdx.data(), w.st_rdx, sizeof(double) * rdx.size(), hipMemcpyDeviceToHost, st));
@@ -1419,20 +1479,23 @@ struct Solver : SolverBase {
     for (int b = 0; b < B; ++b) {
       const double e = eps[b];
       nfs_result r{};
-      r.iters = done;
+      r.iters = pst[size_t(kPState) * b + 1];
       r.precision_used = p.precision;
       r.scale = w.sc[b].scale;
       r.kernel_err = w.sc[b].kernel_err;
       // s = eps (1 + sum p log a + sum pt log at - sum_j at_j tt_j), tt the last K^T alpha;
       // log domain (Algorithm 4 result): s = sum p beta + sum pt gamma - eps sum_j at_j tt_j
-      const double mass = done > 0 ? col[8 * b + 1] : ev_row[8 * b + 1];
+      const double* cb = col.data() + size_t(kStat) * b;
+      const double* rb = row.data() + size_t(kStat) * b;
+      const double mass = r.iters > 0 ? cb[1] : ev_row[size_t(kStat) * b + 1];
       r.cost = logd ? rdx[4 * b + 0] + rdy[4 * b + 0] - e * mass : e * (1.0 + rdx[4 * b + 0] + rdy[4 * b + 0] - mass);
       r.cost_upper = r.cost - e * (rdx[4 * b + 1] + rdy[4 * b + 1]);
       r.cost_primal = primal ? cost[4 * b + 2] : NAN;
-      r.marg_err_row = std::sqrt(ev_row[8 * b + 0]);
-      r.marg_err_col = std::sqrt(ev_col[8 * b + 0]);
+      r.marg_err_row = std::sqrt(ev_row[size_t(kStat) * b + 0]);
+      r.marg_err_col = std::sqrt(ev_col[size_t(kStat) * b + 0]);
       r.marg_err = r.marg_err_row + r.marg_err_col;
-      r.n_nonpos = int64_t(row[8 * b + 4] + col[8 * b + 4]);
+      r.n_nonpos = int64_t(rb[4] + cb[4]);
+      r.dyn_range = logd ? NAN : std::max(rb[8], cb[8]);
       nonpos += r.n_nonpos;
       if (res) res[b] = r;
     }
@@ -1466,19 +1529,26 @@ static int make_solver(const nfs_params* prm, int B, const int64_t* n, const int
   return NFS_OK;
 }
 
+// max_iter iterations, or, with tol > 0, until every problem has stopped:
+// each alpha update evaluates ||E|| of the state the previous iteration left
+// (eq. (Error), fused into its epilogue), and a problem whose ||E|| <= tol
+// completes that iteration and then stops (its kernels skip it).  The host
+// polls the stop state every 10 iterations; replays after the last problem
+// stopped only launch kernels that return at once.
 static int run_solver(SolverBase* s, int32_t max_iter, double tol, double* alpha, double* alpha_t, nfs_result* res,
                       hipStream_t caller) {
   int rc = NFS_OK;
   int done = 0;
   const int check_every = 10;
+  if (tol > 0.0) rc = s->set_tol(tol, caller);
   while (rc == NFS_OK && done < max_iter) {
     const int k = tol > 0.0 ? std::min(check_every, max_iter - done) : max_iter - done;
     rc = s->iterate(k, caller);
     done += k;
     if (rc == NFS_OK && tol > 0.0) {
-      double e = 0.0;
-      rc = s->residual(&e, caller);
-      if (rc == NFS_OK && e <= tol) break;
+      bool all = false;
+      rc = s->all_stopped(&all, caller);
+      if (rc == NFS_OK && all) break;
     }
   }
   if (rc == NFS_OK) rc = s->finish(alpha, alpha_t, res, caller);
@@ -1576,21 +1646,31 @@ static int auto_workspace(const nfs_params* p, int64_t n, int64_t nt, size_t* S,
   return NFS_OK;
 }
 
-// Batch: the FP32 batch, or the FP64 single-problem solve of the largest
-// problem, whichever needs more.
+// A problem is solved again with FP64 grids when its FP32 solve met a sum
+// t <= 0, or sums below 1/kAutoRange of the l1 norm of their source weights
+// (nfs_result.dyn_range): fast summation's error is normwise in that norm, so
+// at FP32 rounding such sums keep few correct digits.
+constexpr double kAutoRange = 1e5;
+
+static bool needs_fp64(const nfs_result& r) { return r.n_nonpos > 0 || !(r.dyn_range <= kAutoRange); }
+
+// Packed inputs and results of the problems re-solved in FP64: x, y, mu, nu,
+// alpha, alpha_t of every problem at most.
+static size_t auto_packed_bytes(int d, long sn, long snt) {
+  return align_up(sizeof(double) * (size_t(sn + snt) * (d + 2)));
+}
+
+// Batch: the FP32 batch, or the packed copies plus the FP64 batch of every
+// problem (the most that can be promoted), whichever needs more.
 static int auto_batch_workspace(const nfs_params* p, int32_t B, const int64_t* n, const int64_t* nt, size_t* bytes) {
   const nfs_params p32 = with_precision(p, NFS_FP32), p64 = with_precision(p, NFS_FP64);
   long sn = 0, snt = 0;
   NFS_TRY(batch_sizes(&p32, B, n, nt, &sn, &snt));
   NFS_TRY(batch_sizes(&p64, B, n, nt, &sn, &snt));
-  size_t need = 0;
-  NFS_TRY(batch_workspace(&p32, B, sn, snt, &need));
-  for (int b = 0; b < B; ++b) {
-    size_t one = 0;
-    NFS_TRY(batch_workspace(&p64, 1, n[b], nt[b], &one));
-    need = std::max(need, one);
-  }
-  *bytes = need;
+  size_t b32 = 0, b64 = 0;
+  NFS_TRY(batch_workspace(&p32, B, sn, snt, &b32));
+  NFS_TRY(batch_workspace(&p64, B, sn, snt, &b64));
+  *bytes = std::max(b32, auto_packed_bytes(p->d, sn, snt) + b64);
   return NFS_OK;
 }
 
@@ -1729,7 +1809,9 @@ int nfs_sinkhorn_solve(const nfs_params* prm, const double* x, int64_t n, const 
     nfs_result r{};
     int rc = nfs_sinkhorn_solve(&p32, x, n, mu, y, nt, nu, max_iter, tol, warm_start, alpha, alpha_t, &r, workspace,
                                 S, stream);
-    if (rc == NFS_ENONPOS) {  // again from the caller's starting value, with FP64 grids
+    const bool logd = (prm->flags & NFS_FLAG_LOG_DOMAIN) != 0;
+    if (rc == NFS_ENONPOS || (rc == NFS_OK && !logd && needs_fp64(r))) {
+      // again from the caller's starting value, with FP64 grids
       if (warm_start) NFS_HIP(hipMemcpyAsync(alpha_t, start, sizeof(double) * nt, hipMemcpyDeviceToDevice, st));
       rc = nfs_sinkhorn_solve(&p64, x, n, mu, y, nt, nu, max_iter, tol, warm_start, alpha, alpha_t, &r, workspace,
                               S, stream);
@@ -1852,25 +1934,66 @@ int nfs_batch_solve(const nfs_params* prm, int32_t nprob, const int64_t* n, cons
     const nfs_params p32 = with_precision(prm, NFS_FP32), p64 = with_precision(prm, NFS_FP64);
     int rc = nfs_batch_solve(&p32, nprob, n, nt, eps, x, mu, y, nu, max_iter, tol, alpha, alpha_t, res, workspace,
                              ws_bytes, stream);
-    if (rc != NFS_ENONPOS) return rc;
-    // each problem with kernel sums t <= 0 again, alone, with FP64 grids
+    if (rc != NFS_OK && rc != NFS_ENONPOS) return rc;
+    const bool logd = (prm->flags & NFS_FLAG_LOG_DOMAIN) != 0;
+    // the problems to solve again with FP64 grids, as one batch of their own
+    std::vector<int> sel;
+    for (int b = 0; b < nprob; ++b)
+      if (res[b].n_nonpos > 0 || (!logd && needs_fp64(res[b]))) sel.push_back(b);
+    if (sel.empty()) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
     const int d = prm->d;
-    int64_t ox = 0, oy = 0;
-    rc = NFS_OK;
+    std::vector<int64_t> ox(nprob + 1, 0), oy(nprob + 1, 0), n2, nt2;
+    std::vector<double> eps2;
     for (int b = 0; b < nprob; ++b) {
-      if (res[b].n_nonpos > 0) {
-        nfs_params pb = p64;
-        pb.eps = eps[b];
-        nfs_result r{};
-        const int rb = nfs_sinkhorn_solve(&pb, x + ox * d, n[b], mu + ox, y + oy * d, nt[b], nu + oy, max_iter, tol,
-                                          0, alpha + ox, alpha_t + oy, &r, workspace, ws_bytes, stream);
-        if (rb != NFS_OK && rb != NFS_ENONPOS) return rb;
-        res[b] = r;
-        if (rb == NFS_ENONPOS) rc = NFS_ENONPOS;
-      }
-      ox += n[b];
-      oy += nt[b];
+      ox[b + 1] = ox[b] + n[b];
+      oy[b + 1] = oy[b] + nt[b];
     }
+    long sn = 0, snt = 0;
+    for (int b : sel) {
+      n2.push_back(n[b]);
+      nt2.push_back(nt[b]);
+      eps2.push_back(eps[b]);
+      sn += n[b];
+      snt += nt[b];
+    }
+    // packed x | y | mu | nu | alpha | alpha_t of the selected problems, then their FP64 batch
+    long sn_all = 0, snt_all = 0;
+    NFS_TRY(batch_sizes(&p64, nprob, n, nt, &sn_all, &snt_all));
+    const size_t packed = auto_packed_bytes(d, sn_all, snt_all);
+    double* X2 = static_cast<double*>(workspace);
+    double* Y2 = X2 + size_t(sn) * d;
+    double* MU2 = Y2 + size_t(snt) * d;
+    double* NU2 = MU2 + sn;
+    double* A2 = NU2 + snt;
+    double* AT2 = A2 + sn;
+    long px = 0, py = 0;
+    for (int b : sel) {
+      NFS_HIP(hipMemcpyAsync(X2 + px * d, x + ox[b] * d, sizeof(double) * n[b] * d, hipMemcpyDeviceToDevice, st));
+      NFS_HIP(hipMemcpyAsync(MU2 + px, mu + ox[b], sizeof(double) * n[b], hipMemcpyDeviceToDevice, st));
+      NFS_HIP(hipMemcpyAsync(Y2 + py * d, y + oy[b] * d, sizeof(double) * nt[b] * d, hipMemcpyDeviceToDevice, st));
+      NFS_HIP(hipMemcpyAsync(NU2 + py, nu + oy[b], sizeof(double) * nt[b], hipMemcpyDeviceToDevice, st));
+      px += n[b];
+      py += nt[b];
+    }
+    std::vector<nfs_result> r2(sel.size());
+    nfs_params q = p64;
+    const int rc2 = nfs_batch_solve(&q, int32_t(sel.size()), n2.data(), nt2.data(), eps2.data(), X2, MU2, Y2, NU2,
+                                    max_iter, tol, A2, AT2, r2.data(), static_cast<char*>(workspace) + packed,
+                                    ws_bytes - packed, stream);
+    if (rc2 != NFS_OK && rc2 != NFS_ENONPOS) return rc2;
+    px = py = 0;
+    rc = NFS_OK;
+    for (size_t k = 0; k < sel.size(); ++k) {
+      const int b = sel[k];
+      NFS_HIP(hipMemcpyAsync(alpha + ox[b], A2 + px, sizeof(double) * n[b], hipMemcpyDeviceToDevice, st));
+      NFS_HIP(hipMemcpyAsync(alpha_t + oy[b], AT2 + py, sizeof(double) * nt[b], hipMemcpyDeviceToDevice, st));
+      px += n[b];
+      py += nt[b];
+      res[b] = r2[k];
+      if (r2[k].n_nonpos > 0) rc = NFS_ENONPOS;
+    }
+    NFS_HIP(hipStreamSynchronize(st));
     if (rc != NFS_OK) return fail(rc, "FP64 grids also produced kernel sums t <= 0");
     g_err.clear();
     return NFS_OK;

@@ -361,6 +361,7 @@ __global__ __launch_bounds__(spread_block(D)) void spread_kernel(SpreadArgs<R> a
   const int ncell = D == 1 ? E : (D == 2 ? E * E : E * E * E);
   Acc<R, ACC> tile(smem_raw, ncell);
   const Chunk ch = a.chunks[blockIdx.x];
+  if (a.pstate && a.pstate[kPState * ch.prob] == 2) return;  // the problem has stopped
 
   // the part store (per-tile reduction) needs the whole tile
   int lo, hi;
@@ -468,6 +469,7 @@ constexpr int kRedPerThread = 8;
 
 template <typename R, int D>
 __global__ __launch_bounds__(kBlock) void spread_reduce_kernel(ReduceArgs<R> a) {
+  if (a.pstate && a.pstate[0] == 2) return;  // the (single) problem has stopped
   const Geom geo = a.geo;
   const int T = geo.T, M = geo.M, E = geo.E, g = geo.g;
   constexpr int NNB = D == 1 ? 3 : (D == 2 ? 9 : 27);
@@ -577,6 +579,7 @@ __global__ __launch_bounds__(kBlock) void nearfield_kernel(NearArgs<R> a) {
   __shared__ R sw[kBlock];
   const Geom geo = a.geo;
   const Chunk ch = a.tchunks[blockIdx.x];
+  if (a.pstate && a.pstate[kPState * ch.prob] == 2) return;  // the problem has stopped
   const int pb = ch.prob;
   const int nbins = geo.nt[0] * geo.nt[1] * geo.nt[2];
   const double* cf = a.coef + size_t(pb) * kNearStride;
@@ -721,6 +724,7 @@ __global__ __launch_bounds__(kBlock) void nearfield_cells_kernel(NearArgs<R> a) 
   int* wp = spre + wbase;
   const Geom geo = a.geo;
   const Chunk ch = a.tchunks[blockIdx.x];
+  if (a.pstate && a.pstate[kPState * ch.prob] == 2) return;  // the problem has stopped
   const int pb = ch.prob;
   const int T = geo.T;
   const int nbins = geo.nt[0] * geo.nt[1] * geo.nt[2];
@@ -933,48 +937,68 @@ template hipError_t launch_nearfield<float>(const NearArgs<float>&, int, hipStre
 template hipError_t launch_nearfield<double>(const NearArgs<double>&, int, hipStream_t);
 
 // --------------------------------------------------------------------------- block reduction
-struct Red4 {
-  double s0, s1, mx;
-  double cnt;
+// Per-target quantities of a half-step, reduced over the problem's targets.
+struct Red {
+  double res2;  // sum of squared residuals
+  double mass;  // sum alpha t
+  double l1;    // sum |alpha_new|
+  double mx;    // max alpha (log domain: max potential)
+  double tmin;  // min t
+  double tmax;  // max t
+  double cnt;   // sums t <= 0 or non-finite
 };
+constexpr int kRedVals = 8;  // doubles per workgroup partial
 
-__device__ __forceinline__ Red4 red_combine(Red4 a, Red4 b) {
-  return {a.s0 + b.s0, a.s1 + b.s1, fmax(a.mx, b.mx), a.cnt + b.cnt};
+__device__ __forceinline__ Red red_init(bool logd) {
+  return {0.0, 0.0, 0.0, logd ? -INFINITY : 0.0, INFINITY, 0.0, 0.0};
 }
 
-__device__ Red4 block_reduce(Red4 v, Red4* sh) {
+__device__ __forceinline__ Red red_combine(Red a, Red b) {
+  return {a.res2 + b.res2, a.mass + b.mass, a.l1 + b.l1, fmax(a.mx, b.mx),
+          fmin(a.tmin, b.tmin), fmax(a.tmax, b.tmax), a.cnt + b.cnt};
+}
+
+__device__ Red block_reduce(Red v, Red* sh) {
   // wave64 butterfly, then across the 4 waves in fixed order
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
-    Red4 w;
-    w.s0 = __shfl_xor(v.s0, o, 64);
-    w.s1 = __shfl_xor(v.s1, o, 64);
+    Red w;
+    w.res2 = __shfl_xor(v.res2, o, 64);
+    w.mass = __shfl_xor(v.mass, o, 64);
+    w.l1 = __shfl_xor(v.l1, o, 64);
     w.mx = __shfl_xor(v.mx, o, 64);
+    w.tmin = __shfl_xor(v.tmin, o, 64);
+    w.tmax = __shfl_xor(v.tmax, o, 64);
     w.cnt = __shfl_xor(v.cnt, o, 64);
     v = red_combine(v, w);
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) sh[wid] = v;
   __syncthreads();
-  Red4 r = sh[0];
+  Red r = sh[0];
   for (int k = 1; k < kBlock / 64; ++k) r = red_combine(r, sh[k]);
   return r;
 }
 
-// Final reduction by the last workgroup to finish (ticket counter).  Writes
-// stats[0..3] = {sum s0, sum s1, max, count}, adds count to stats[4], and, if wmul_next is set,
-// wmul_next = 1/max (the normalization of the next spread's weights), or in the
-// log domain the max itself (the shift of the next spread's potentials).
-// The chunks of one problem are [c0, c1); the last of them to finish reduces
-// that problem's partials.
-__device__ void finish_reduce(Red4 mine, Red4* sh, double* partials, unsigned* counter, double* stats,
-                              double* wmul_next, int c0, int c1, bool logd) {
+// Final reduction by the last workgroup to finish (ticket counter).  The
+// chunks of one problem are [c0, c1); the last of them to finish reduces that
+// problem's partials into stats (layout of kStat), sets wmul_next to 1/max
+// (the normalization of the next spread's weights; log domain: the max
+// itself, the shift of the next spread's potentials) and advances the
+// problem's stop state (kPState).
+__device__ void finish_reduce(Red mine, Red* sh, double* partials, unsigned* counter, double* stats,
+                              double* wmul_next, const double* src_l1, int* pstate, const double* tol2, int half,
+                              int c0, int c1, bool logd) {
   __shared__ bool last;
   if (threadIdx.x == 0) {
-    partials[4 * blockIdx.x + 0] = mine.s0;
-    partials[4 * blockIdx.x + 1] = mine.s1;
-    partials[4 * blockIdx.x + 2] = mine.mx;
-    partials[4 * blockIdx.x + 3] = mine.cnt;
+    double* pw = partials + kRedVals * size_t(blockIdx.x);
+    pw[0] = mine.res2;
+    pw[1] = mine.mass;
+    pw[2] = mine.l1;
+    pw[3] = mine.mx;
+    pw[4] = mine.tmin;
+    pw[5] = mine.tmax;
+    pw[6] = mine.cnt;
     __threadfence();
     const unsigned ticket = atomicAdd(counter, 1u);
     last = (ticket == unsigned(c1 - c0) - 1u);
@@ -982,25 +1006,44 @@ __device__ void finish_reduce(Red4 mine, Red4* sh, double* partials, unsigned* c
   __syncthreads();
   if (!last) return;
   __threadfence();
-  Red4 v{0.0, 0.0, logd ? -INFINITY : 0.0, 0.0};
+  Red v = red_init(logd);
   const volatile double* pv = partials;
   for (int b = c0 + threadIdx.x; b < c1; b += kBlock) {
-    Red4 w{pv[4 * b + 0], pv[4 * b + 1], pv[4 * b + 2], pv[4 * b + 3]};
+    const size_t o = kRedVals * size_t(b);
+    Red w{pv[o + 0], pv[o + 1], pv[o + 2], pv[o + 3], pv[o + 4], pv[o + 5], pv[o + 6]};
     v = red_combine(v, w);
   }
   __syncthreads();
-  const Red4 r = block_reduce(v, sh);
+  const Red r = block_reduce(v, sh);
   if (threadIdx.x == 0) {
-    stats[0] = r.s0;
-    stats[1] = r.s1;
+    stats[0] = r.res2;
+    stats[1] = r.mass;
     stats[2] = r.mx;
     stats[3] = r.cnt;
     stats[4] += r.cnt;  // running count over all launches into this slot
+    stats[5] = r.tmin;
+    stats[6] = r.tmax;
+    stats[7] = r.l1;
+    if (src_l1) {
+      // ||w||_1 / min t; a sum t <= 0 (or none positive) counts as an unbounded range
+      const double range = r.tmin > 0.0 ? *src_l1 / r.tmin : INFINITY;
+      stats[8] = fmax(stats[8], range);
+    }
     if (wmul_next) {
       if (logd)
         *wmul_next = isfinite(r.mx) ? r.mx : 0.0;
       else
         *wmul_next = (r.mx > 0.0 && r.mx < 1e300) ? 1.0 / r.mx : 1.0;
+    }
+    if (pstate) {
+      if (half == 0) {
+        // ||E|| of the state the previous iteration left (its column term is
+        // zero up to rounding after an alpha_t update)
+        if (pstate[0] == 0 && *tol2 > 0.0 && r.res2 <= *tol2) pstate[0] = 1;
+      } else {
+        pstate[1] += 1;
+        if (pstate[0] == 1) pstate[0] = 2;
+      }
     }
     *counter = 0u;
   }
@@ -1100,12 +1143,13 @@ template <typename R, int D, int M, bool LOG>
 __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
-  __shared__ Red4 red_sh[kBlock / 64];
+  __shared__ Red red_sh[kBlock / 64];
   const Geom geo = a.geo;
   const int E = geo.E;
   const int g = geo.g;
   const int ncell = D == 1 ? E : (D == 2 ? E * E : E * E * E);
   const Chunk ch = a.chunks[blockIdx.x];
+  if (a.pstate && a.pstate[kPState * ch.prob] == 2) return;  // the problem has stopped
 
   int org[3] = {0, 0, 0};
   {
@@ -1138,64 +1182,69 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
   const double shift = logd ? a.wmul_src[ch.prob] : 0.0;
   const double linv = logd ? a.leps[kLepsStride * ch.prob] : 0.0;
   const double leps = logd ? a.leps[kLepsStride * ch.prob + 1] : 0.0;
-  Red4 acc_red{0.0, 0.0, logd ? -INFINITY : 0.0, 0.0};
+  Red acc_red = red_init(logd);
   // nfq: the point's near-field sum, loaded by the caller before the
   // interpolation (a load inside here lets the compiler hoist it above the
   // tap loop together with the LDS reads, at a large cost in registers)
   auto epilogue = [&](int q, R acc, double nfq) {
     const double t = (double(acc) + nfq) * outmul;
     if constexpr (LOG) {
+      // alpha_old t = exp((beta_old + shift)/eps - 1) S: the marginal entry of
+      // the state before the update
+      const double p = a.p[q];
+      const double bold = a.alpha[q];
+      const double m = p > 0.0 ? exp((bold + shift) * linv - 1.0) * t : 0.0;
+      const double res = m - p;
+      acc_red.res2 += res * res;
       if (a.epi == EPI_LOGSINK) {
         // beta = eps (log p - log t) + eps/2 with log t = shift/eps - 1/2 + log S;
         // a zero weight, or a sum t <= 0 (counted), gives the potential -inf
-        const double p = a.p[q];
         double b = -INFINITY;
         if (p > 0.0) {
           if (t > 0.0 && isfinite(t)) {
             b = leps * (log(p) - log(t) + 1.0) - shift;
             acc_red.mx = fmax(acc_red.mx, b);
+            acc_red.tmin = fmin(acc_red.tmin, t);
+            acc_red.tmax = fmax(acc_red.tmax, t);
           } else {
             acc_red.cnt += 1.0;
           }
-          acc_red.s1 += p;
+          acc_red.mass += p;
         }
         a.alpha[q] = b;
       } else {
-        const double p = a.p[q];
-        const double bold = a.alpha[q];
-        const double m = p > 0.0 ? exp((bold + shift) * linv - 1.0) * t : 0.0;
-        const double res = m - p;
-        acc_red.s0 += res * res;
         if (p > 0.0) {
           if (!(t > 0.0) || !isfinite(t)) acc_red.cnt += 1.0;
-          acc_red.s1 += m;
+          acc_red.mass += m;
           acc_red.mx = fmax(acc_red.mx, bold);
         }
       }
     } else if (a.epi == EPI_OUT) {
       const double sc = a.scale_vec ? a.scale_vec[q] : 1.0;
       a.out[size_t(a.perm[q]) * a.out_stride + a.out_comp] = t * sc;
-    } else if (a.epi == EPI_SINK) {
-      // the update reads no old scaling: the row residual of eq. (Error) is
-      // evaluated by EPI_EVAL when it is wanted
-      const double p = a.p[q];
-      if (p > 0.0) {
-        if (!(t > 0.0) || !isfinite(t)) acc_red.cnt += 1.0;
-        const double anew = p / t;
-        a.alpha[q] = anew;
-        acc_red.s1 += anew * t;
-        acc_red.mx = fmax(acc_red.mx, anew);
-      } else {
-        a.alpha[q] = 0.0;
-      }
-    } else if (a.epi == EPI_EVAL) {
+    } else {
+      // EPI_SINK and EPI_EVAL: the residual of eq. (Error) of the state before
+      // the update, alpha_old t - p (fused: no extra kernel product)
       const double p = a.p[q];
       const double aold = a.alpha[q];
       const double res = aold * t - p;
-      acc_red.s0 += res * res;
+      acc_red.res2 += res * res;
       if (p > 0.0) {
         if (!(t > 0.0) || !isfinite(t)) acc_red.cnt += 1.0;
-        acc_red.s1 += aold * t;
+        acc_red.tmin = fmin(acc_red.tmin, t);
+        acc_red.tmax = fmax(acc_red.tmax, t);
+      }
+      if (a.epi == EPI_SINK) {
+        // a point of weight zero gets scaling zero
+        const double anew = p > 0.0 ? p / t : 0.0;
+        a.alpha[q] = anew;
+        if (p > 0.0) {
+          acc_red.mass += anew * t;
+          acc_red.l1 += fabs(anew);
+          acc_red.mx = fmax(acc_red.mx, anew);
+        }
+      } else if (p > 0.0) {
+        acc_red.mass += aold * t;
         acc_red.mx = fmax(acc_red.mx, aold);
       }
     }
@@ -1228,10 +1277,12 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
     epilogue(q0, acc[0], nfq);
   }
   if (a.epi != EPI_OUT) {
-    const Red4 r = block_reduce(acc_red, red_sh);
+    const Red r = block_reduce(acc_red, red_sh);
     const int pb = ch.prob;
-    finish_reduce(r, red_sh, a.partials, a.counter + pb, a.stats + 8 * pb, a.wmul_next ? a.wmul_next + pb : nullptr,
-                  a.prob_chunks[pb], a.prob_chunks[pb + 1], logd);
+    finish_reduce(r, red_sh, a.partials, a.counter + pb, a.stats + kStat * pb,
+                  a.wmul_next ? a.wmul_next + pb : nullptr, a.src_l1 ? a.src_l1 + kStat * pb : nullptr,
+                  a.pstate ? a.pstate + kPState * pb : nullptr, a.tol2, a.half, a.prob_chunks[pb],
+                  a.prob_chunks[pb + 1], logd);
   }
 }
 

@@ -506,8 +506,10 @@ hipError_t launch_readout(const ReadoutArgs& a, hipStream_t st) {
 
 // Log domain: the spread weights exp((pot - shift)/eps) of one chunk per workgroup.
 __global__ __launch_bounds__(kBlock) void logweights_kernel(const Chunk* chunks, const double* pot,
-                                                            const double* shift, const double* leps, double* out) {
+                                                            const double* shift, const double* leps, double* out,
+                                                            const int* pstate) {
   const Chunk ch = chunks[blockIdx.x];
+  if (pstate && pstate[kPState * ch.prob] == 2) return;  // the problem has stopped
   const double sh = shift[ch.prob], inv = leps[kLepsStride * ch.prob];
   for (int i = threadIdx.x; i < ch.count; i += kBlock) {
     const int q = ch.start + i;
@@ -516,9 +518,9 @@ __global__ __launch_bounds__(kBlock) void logweights_kernel(const Chunk* chunks,
 }
 
 hipError_t launch_logweights(const Chunk* chunks, int nchunks, const double* pot, const double* shift,
-                             const double* leps, double* out, hipStream_t st) {
+                             const double* leps, double* out, const int* pstate, hipStream_t st) {
   if (nchunks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(logweights_kernel, dim3(nchunks), dim3(kBlock), 0, st, chunks, pot, shift, leps, out);
+  hipLaunchKernelGGL(logweights_kernel, dim3(nchunks), dim3(kBlock), 0, st, chunks, pot, shift, leps, out, pstate);
   return hipGetLastError();
 }
 

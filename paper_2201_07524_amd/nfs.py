@@ -49,7 +49,7 @@ class _Result(ctypes.Structure):
                 ("marg_err_row", ctypes.c_double), ("marg_err_col", ctypes.c_double),
                 ("scale", ctypes.c_double), ("kernel_err", ctypes.c_double),
                 ("iters", ctypes.c_int32), ("precision_used", ctypes.c_int32),
-                ("n_nonpos", ctypes.c_int64)]
+                ("n_nonpos", ctypes.c_int64), ("dyn_range", ctypes.c_double)]
 
 
 @dataclass
@@ -270,6 +270,7 @@ class SinkhornResult:
     kernel_err: float
     precision_used: str = ""
     extra: dict = field(default_factory=dict)
+    dyn_range: float = float("nan")   # max over half-steps of ||w||_1 / min t (see include/nfs.h)
 
 
 def sinkhorn(params, x, mu, y, nu, iters, tol=0.0, alpha_t0=None, workspace=None, check=True):
@@ -298,7 +299,7 @@ def sinkhorn(params, x, mu, y, nu, iters, tol=0.0, alpha_t0=None, workspace=None
         _check(rc)
     return SinkhornResult(alpha, alpha_t, res.cost, res.cost_upper, res.cost_primal, res.marg_err,
                           res.marg_err_row, res.marg_err_col, res.iters, res.n_nonpos, res.scale,
-                          res.kernel_err, _PREC_NAME.get(res.precision_used, ""))
+                          res.kernel_err, _PREC_NAME.get(res.precision_used, ""), dyn_range=res.dyn_range)
 
 
 @dataclass
@@ -449,7 +450,7 @@ class Solver:
             _check(rc)
         return SinkhornResult(alpha, alpha_t, res.cost, res.cost_upper, res.cost_primal, res.marg_err,
                               res.marg_err_row, res.marg_err_col, res.iters, res.n_nonpos, res.scale,
-                              res.kernel_err)
+                              res.kernel_err, dyn_range=res.dyn_range)
 
     def profile(self, k):
         """Average device ms per launch of (spread, fft chain, interp+update, iteration, near field)
@@ -477,7 +478,8 @@ def _results(arr, alpha, alpha_t, offs_x, offs_y):
     for b, r in enumerate(arr):
         out.append(SinkhornResult(alpha[offs_x[b]:offs_x[b + 1]], alpha_t[offs_y[b]:offs_y[b + 1]], r.cost,
                                   r.cost_upper, r.cost_primal, r.marg_err, r.marg_err_row, r.marg_err_col,
-                                  r.iters, r.n_nonpos, r.scale, r.kernel_err, _PREC_NAME.get(r.precision_used, "")))
+                                  r.iters, r.n_nonpos, r.scale, r.kernel_err, _PREC_NAME.get(r.precision_used, ""),
+                                  dyn_range=r.dyn_range))
     return out
 
 

@@ -75,3 +75,32 @@ def test_batched_warm_and_residual_api():
     assert e50 < e5
     assert max(r.marg_err_row for r in res) == pytest.approx(e50, rel=1e-6)
     assert all(r.iters == 50 for r in res)
+
+
+def test_batched_problems_stop_on_their_own_tolerance():
+    """With a tolerance, each problem of a batch stops on its own: the
+    iteration after its first state with ||E|| <= tol (eq. (Error)); the
+    others keep iterating.  Every problem matches the oracle after its own
+    iteration count."""
+    sizes = [400, 900, 250, 600]
+    eps_list = [0.08, 0.03, 0.05, 0.02]
+    probs = make_batch(2, sizes, eps_list, seed=990)
+    prm = nfs.Params(d=2, eps=1.0, N=64, m=8, precision="fp64")
+    tol = 1e-7
+    res = nfs.batch_sinkhorn(prm, [T(p["x"]) for p in probs], [T(p["p"]) for p in probs],
+                             [T(p["y"]) for p in probs], [T(p["pt"]) for p in probs], eps_list, 3000, tol=tol)
+    iters = [r.iters for r in res]
+    assert len(set(iters)) > 1 and max(iters) < 3000
+    for p, r in zip(probs, res):
+        K = sd.gibbs_kernel(p["x"], p["y"], 2, p["eps"])
+        a_t = np.ones(len(p["pt"]))
+        errs = []
+        for _ in range(r.iters):
+            a = p["p"] / (K @ a_t)
+            a_t = p["pt"] / (K.T @ a)
+            errs.append(float(np.linalg.norm(a * (K @ a_t) - p["p"])))
+        assert errs[-2] <= tol * (1 + 1e-4) and (r.iters < 3 or errs[-3] > tol * (1 - 1e-4))
+        assert r.marg_err <= tol
+        ref = sd.solve(p["x"], p["p"], p["y"], p["pt"], 2, p["eps"], r.iters)
+        assert abs(r.cost - ref["cost"]) <= 1e-10 * abs(ref["cost"])
+        assert np.max(np.abs(r.alpha.cpu().numpy() / ref["alpha"] - 1)) <= 1e-9

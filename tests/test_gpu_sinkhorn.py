@@ -109,11 +109,58 @@ def test_warm_start_resume_equals_continuous_run():
     assert rel(second.cost, full.cost) <= 1e-12
 
 
+def oracle_errors(K, p, pt, iters):
+    """||E|| of eq. (Error) after each of `iters` oracle iterations (the
+    column term is zero after an alpha_t update)."""
+    out = []
+    a_t = np.ones(K.shape[1])
+    for _ in range(iters):
+        a = p / (K @ a_t)
+        a_t = pt / (K.T @ a)
+        out.append(float(np.linalg.norm(a * (K @ a_t) - p)))
+    return np.array(out)
+
+
 def test_tolerance_stops_early():
+    """Each alpha update evaluates ||E|| of the state the previous iteration
+    left; the solve finishes that iteration and stops.  So the state after
+    iters - 1 iterations is the first one within the tolerance, and the
+    result is the oracle's after `iters` iterations."""
     cfg = workloads.plain_1d(512)
-    res = run_gpu(cfg, 5000, "fp64", 256, 8, 0.05, tol=1e-9)
-    assert res.iters < 5000 and res.iters % 10 == 0
-    assert res.marg_err <= 1e-9 * 1.0001
+    tol, eps = 1e-9, 0.05
+    res = run_gpu(cfg, 5000, "fp64", 256, 8, eps, tol=tol)
+    K = sd.gibbs_kernel(cfg["x"], cfg["y"], 2, eps)
+    errs = oracle_errors(K, cfg["p"], cfg["pt"], res.iters)
+    k = res.iters
+    assert k < 5000
+    assert errs[k - 2] <= tol * (1 + 1e-4) and errs[k - 3] > tol * (1 - 1e-4)
+    assert res.marg_err <= tol
+    ref = sd.solve(cfg["x"], cfg["p"], cfg["y"], cfg["pt"], 2, eps, k)
+    assert abs(res.cost - ref["cost"]) <= 1e-10 * abs(ref["cost"])
+    assert np.max(np.abs(res.alpha.cpu().numpy() / ref["alpha"] - 1)) <= 1e-9
+
+
+def test_dynamic_range_statistic_matches_oracle_iterates():
+    """nfs_result.dyn_range is the largest ||w||_1 / min_i t_i over the
+    solve's half-steps, w the source weights of the sums t (the quantity the
+    fast sums' normwise error is measured against); the same on the oracle's
+    dense iterates."""
+    cfg = workloads.subsample(workloads.gmm_2d(10000), 800, seed=6)
+    eps, iters = 0.02, 12
+    res = run_gpu(cfg, iters, "fp64", 128, 8, eps)
+    K = sd.gibbs_kernel(cfg["x"], cfg["y"], 2, eps)
+    p, pt = cfg["p"], cfg["pt"]
+    a_t = np.ones(len(pt))
+    worst = 0.0
+    for _ in range(iters):
+        t = K @ a_t
+        worst = max(worst, a_t.sum() / t[p > 0].min())
+        a = p / t
+        tt = K.T @ a
+        worst = max(worst, a.sum() / tt[pt > 0].min())
+        a_t = pt / tt
+    assert worst > 10.0
+    assert res.dyn_range == pytest.approx(worst, rel=1e-6)
 
 
 def test_kl_identity_on_device_iterates():
