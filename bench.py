@@ -142,8 +142,9 @@ def batched_leg(nfs, workloads, torch, T, iters=10, sample_every=16):
         one.close()
     t_plain *= len(probs) / len(sample)
     npts = sum(p["x"].shape[0] + p["y"].shape[0] for p in probs)
-    # one-shot solve with automatic promotion of the problems whose FP32 sums
-    # hit t <= 0 (each re-solved alone with FP64 grids)
+    # one-shot solve with automatic promotion: problems whose FP32 sums hit
+    # t <= 0 or a dynamic range above 1e5 again as one FP64 batch, and those
+    # beyond FP64's range in the centred form
     aprm = nfs.Params(d=2, eps=1.0, N=cfg["N"], m=cfg["m"], precision="auto")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -157,13 +158,15 @@ def batched_leg(nfs, workloads, torch, T, iters=10, sample_every=16):
             "problems_with_nonpositive_sums_fp32": nonpos,
             "auto_solve_ms": t_auto * 1e3, "auto_iterations": iters,
             "auto_promoted_to_fp64": sum(1 for r in ares if r.precision_used == "fp64"),
+            "auto_centred": sum(1 for r in ares if r.centred),
             "auto_nonpositive_after_promotion": sum(1 for r in ares if r.n_nonpos > 0)}
 
 
 def grad_leg(nfs, workloads, torch, T, iters=5):
     """The differentiated form: 3-D mixtures, n = nt = 1e6, eps = 0.01, N = 128,
-    m = 8, FP32; time of one forward iteration vs one envelope gradient
-    (positions and weights) at the resulting scalings."""
+    m = 8, FP32; time of one forward iteration vs one envelope gradient in
+    positions and weights of both clouds, on the solver's own plan
+    (nfs_solver_grad), and vs the one-shot entry point that plans again."""
     cfg = workloads.gmm_3d()
     prm = nfs.Params(d=3, eps=cfg["eps"], N=cfg["N"], m=cfg["m"], precision="fp32")
     x, p, y, pt = T(cfg["x"]), T(cfg["p"]), T(cfg["y"]), T(cfg["pt"])
@@ -175,15 +178,26 @@ def grad_leg(nfs, workloads, torch, T, iters=5):
     torch.cuda.synchronize()
     t_fwd = (time.perf_counter() - t0) / iters
     res = s.finish(check=False)
+    s.grad(True, True, False, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.grad(True, True, False, False)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    s.grad(True, True, True, True)
+    torch.cuda.synchronize()
+    t_grad4 = time.perf_counter() - t0
     s.close()
     nfs.sinkhorn_grad(prm, x, p, y, pt, res.alpha, res.alpha_t)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nfs.sinkhorn_grad(prm, x, p, y, pt, res.alpha, res.alpha_t)
     torch.cuda.synchronize()
-    t_grad = time.perf_counter() - t0
-    return {"forward_ms_per_iteration": t_fwd * 1e3, "gradient_ms_incl_plan": t_grad * 1e3,
-            "gradient_over_forward_iteration": t_grad / t_fwd}
+    t_once = time.perf_counter() - t0
+    return {"forward_ms_per_iteration": t_fwd * 1e3, "gradient_x_mu_ms": t_grad * 1e3,
+            "gradient_over_forward_iteration": t_grad / t_fwd, "gradient_x_mu_y_nu_ms": t_grad4 * 1e3,
+            "one_shot_gradient_ms_incl_plan": t_once * 1e3}
 
 
 def log_leg(nfs, prm, x, p, y, pt, torch, iters=20):

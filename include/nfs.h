@@ -72,6 +72,19 @@ extern "C" {
                                     time a few iterations at each candidate chunk size (the default,
                                     twice it, 4096, 8192 points; r = 2 only) and keep the fastest;
                                     the starting values are restored before the first iteration */
+#define NFS_FLAG_CENTER 32       /* solve calls, r = 2: the centred form.  For the squared cost,
+                                    |x - y|^2 = |x' - y'|^2 - 2 delta.(x' - y') + |delta|^2 with
+                                    x' = x + delta/2, y' = y - delta/2 and delta = mean_nu y -
+                                    mean_mu x; the middle term is separable, so the coupling of the
+                                    shifted clouds (equal weighted means) is the same and the
+                                    scalings differ by factors exp(-/+2 delta.x'/eps).  The
+                                    iteration runs on the shifted clouds from alpha_t' = 1, where
+                                    the scalings (hence the sums the fast summation must resolve)
+                                    have far less dynamic range when the clouds are apart; the
+                                    result is mapped back: cost + |delta|^2, scalings times those
+                                    factors (potentials plus eps times their logs).  Starting from
+                                    alpha_t' = 1 is Algorithm 3 from alpha_t = exp((2 delta.y' +
+                                    |delta|^2/2)/eps).  No warm start, no primal cost (NaN) */
 #define NFS_FLAG_LOG_DOMAIN 8    /* solve in potentials (Algorithm 4): the alpha / alpha_t arguments
                                     of the solve, batch and solver calls hold beta / gamma instead,
                                     with alpha = exp(beta/eps - 1/2), alpha_t = exp(gamma/eps - 1/2);
@@ -114,6 +127,8 @@ typedef struct nfs_result {
                            domain, infinite once a sum t <= 0 was seen): the dynamic range
                            the fast sums had to resolve, as their error is normwise in
                            ||w||_1 */
+  int32_t centred;      /* 1 if the result comes from the centred form (NFS_FLAG_CENTER) */
+  int32_t reserved;
 } nfs_result;
 
 /* Message for the last error on this thread ("" if none). */
@@ -237,6 +252,15 @@ int nfs_solver_finish(nfs_solver* s, double* alpha, double* alpha_t, nfs_result*
  * iteration, and of the near-field sum (r = 1; about 0 for r = 2).  info (nullable, 8 doubles): n, nt, d, grid cells, bytes per grid
  * value, chunks of x, chunks of y, taps per point. */
 int nfs_solver_profile(nfs_solver* s, int32_t iters, double* stage_ms, double* info, void* stream);
+/* Envelope gradient of the cost at the solver's current scalings (as
+ * nfs_sinkhorn_grad and nfs_sinkhorn_grad_targets; Proposition 2.3, eq. (14)),
+ * on the solver's own plan: no re-sort, no new tables.  grad_x (n x d),
+ * grad_mu (n), grad_y (nt x d), grad_nu (nt), in the caller's point order
+ * (for a batch solver, packed by problem, each problem's weight gradient
+ * centred over that problem); any may be NULL.  r = 2 only; the log domain
+ * and the centred form return NFS_EUNSUPPORTED.  The scalings are not
+ * changed, so iterate may continue afterwards. */
+int nfs_solver_grad(nfs_solver* s, double* grad_x, double* grad_mu, double* grad_y, double* grad_nu, void* stream);
 int nfs_solver_destroy(nfs_solver* s);
 
 /*

@@ -191,6 +191,26 @@ __device__ __forceinline__ cplx<R> apply_multiplier(cplx<R> v, const Multiplier&
   return scale_multiplier(v, table_value<R>(mu, prob, d, N, k0, k1, k2), mu, k0, k1, k2);
 }
 
+// Cell idx of the spread grid as an R value, in the grid's format (GridMode),
+// and its clearing for the next spreading.
+template <typename R>
+__device__ __forceinline__ R grid_value(const R* g, int mode, long plane, long idx) {
+  if (mode == GRID_REAL) return g[idx];
+  const long long* w = reinterpret_cast<const long long*>(g);
+  if (mode == GRID_FIX64) return R(double(w[idx]) * 2.3283064365386963e-10);
+  return R(double(w[idx]) * 9.313225746154785e-10 + double(w[plane + idx]) * 8.673617379884035e-19);
+}
+template <typename R>
+__device__ __forceinline__ void grid_clear(R* g, int mode, long plane, long idx) {
+  if (mode == GRID_REAL) {
+    g[idx] = R(0);
+    return;
+  }
+  long long* w = reinterpret_cast<long long*>(g);
+  w[idx] = 0;
+  if (mode == GRID_FIX128) w[plane + idx] = 0;
+}
+
 template <typename R>
 __host__ __device__ inline int rows_pencils(int L) {
   return L >= 1024 ? 1 : 1024 / L;
@@ -221,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(RowArgs<R> a) {
         P * L,
         [&](int i) {
           const long row = row0 + (i >> lshift);
-          return row < a.nrows ? a.real_in[row * L + (i & (L - 1))] : R(0);
+          return row < a.nrows ? grid_value(a.real_in, a.gmode, a.grid_plane, row * L + (i & (L - 1))) : R(0);
         },
         [&](int i, R v) { A[i] = cplx<R>{v, R(0)}; });
     if (a.tw_lds) tws.finish(tlds, a.tw, L);
@@ -254,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(RowArgs<R> a) {
       R* z = const_cast<R*>(a.real_in);
       for (int i = threadIdx.x; i < P * L; i += kBlock) {
         const long row = row0 + (i >> lshift);
-        if (row < a.nrows) z[row * L + (i & (L - 1))] = R(0);
+        if (row < a.nrows) grid_clear(z, a.gmode, a.grid_plane, row * L + (i & (L - 1)));
       }
     }
     return;
@@ -273,14 +293,14 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(RowArgs<R> a) {
       R* z = const_cast<R*>(src);
       for (int i = threadIdx.x; i < 2 * P * L; i += kBlock) {
         const long row = row0 + (i >> lshift);
-        if (row < a.nrows) z[row * L + (i & (L - 1))] = R(0);
+        if (row < a.nrows) grid_clear(z, a.gmode, a.grid_plane, row * L + (i & (L - 1)));
       }
     };
     batched<R>(
         2 * P * L,
         [&](int i) {
           const long row = row0 + (i >> lshift);
-          return row < a.nrows ? src[row * L + (i & (L - 1))] : R(0);
+          return row < a.nrows ? grid_value(src, a.gmode, a.grid_plane, row * L + (i & (L - 1))) : R(0);
         },
         [&](int i, R v) {
           const int r = i >> lshift;

@@ -115,6 +115,10 @@ struct Scaling {
   double scale;
   double eps_t;       // temperature in torus units (eps * scale^r)
   double kernel_err;  // a-priori kernel approximation error estimate
+  // Centred form (r = 2): the x cloud is mapped as x + shift, the y cloud as
+  // y - shift, with shift = (mean_nu y - mean_mu x)/2, so both clouds have the
+  // same weighted mean; zero otherwise.
+  double shift[3];
 };
 
 inline Scaling choose_scaling(int d, int r, double eps, int N, const double* lo, const double* hi) {

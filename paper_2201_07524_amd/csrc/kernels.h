@@ -38,6 +38,21 @@ constexpr int kStat = 16;
 // kernel of an iteration skips the problem); [1] iterations completed.
 constexpr int kPState = 2;
 
+// Format of the spread grid S, written by the spreading flush and read by
+// the forward row pass: R values summed with float atomics (GRID_REAL), or
+// the exact integer sums of the LDS tiles' fixed-point words (int64 atomics,
+// so S does not depend on the order of the flushes): GRID_FIX64 one word per
+// cell in units of 2^-32, GRID_FIX128 two planes (2^-30, then 2^-60 units,
+// the second `grid_plane` words after the first).
+enum GridMode : int { GRID_REAL = 0, GRID_FIX64 = 1, GRID_FIX128 = 2 };
+// Mode of the spreading kernel for this geometry and value type (two_level:
+// the per-tile reduction, which sums R values).
+int spread_grid_mode(const Geom& geo, int rbytes, bool two_level);
+// Bytes per grid cell of S in that mode.
+inline size_t grid_cell_bytes(int mode, size_t rbytes) {
+  return mode == GRID_FIX128 ? 16 : (mode == GRID_FIX64 ? 8 : rbytes);
+}
+
 template <typename R>
 struct SpreadArgs {
   Geom geo;
@@ -55,8 +70,10 @@ struct SpreadArgs {
   const int* srun;
   const int* nsrun;
   int cell_order;        // points sorted by cell inside each tile
-  R* grid;               // problem p's g^d real grid at grid + p*grid_stride, zero on entry
+  R* grid;               // problem p's g^d grid at cell p*grid_stride, zero on entry, in the format gmode
   long grid_stride;
+  int gmode;             // GridMode of grid (GRID_REAL when part is set)
+  long grid_plane;       // GRID_FIX128: words between the two planes
   const int* pstate;     // nullable: chunks of problems in state 2 are skipped
   R* part;               // non-null: store each chunk's padded tile here instead of flushing
   WindowConst win;
@@ -170,6 +187,8 @@ struct RowArgs {
   int nrows;        // number of real rows
   R* real_io;       // R2C: input rows (zeroed after reading if zero_src); C2R/FUSED1D: output rows
   const R* real_in; // FUSED1D input row
+  int gmode;        // R2C / FUSED1D input: GridMode of the spread grid
+  long grid_plane;  // GRID_FIX128: words between its two planes
   cplx<R>* spec;    // R2C: output [nrows][K0]; C2R: input [nrows][K0]
   int zero_src;
   const cplx<R>* tw;
@@ -201,17 +220,44 @@ template <typename R>
 hipError_t launch_axis(const AxisArgs<R>& a, hipStream_t st);
 
 // ----------------------------------------------------------------------------- plan / misc
+// out[kBoxVals]: min_c (c < 3), max_c, max |w|, min w, sum w, then, with
+// wsum set (w the weights of pts[0], nw = n[0]), sum_i w_i pts[0][i][c].
+constexpr int kBoxVals = 12;
 struct BoxArgs {
   const double* pts[2];
   long n[2];
   const double* w;    // optional weights (for max |w|, min w, sum w)
   long nw;
   int d;
-  double* partials;   // per block: 2*d (min,max) + 3
+  int wsum;
+  double* partials;   // kBoxVals per block, 1024 blocks
   unsigned* counter;
-  double* out;        // 2*d + 3 : min_c, max_c, max|w|, min w, sum w
+  double* out;
 };
 hipError_t launch_bbox(const BoxArgs& a, hipStream_t st);
+
+// Scalings between the centred form and the caller's variables: with x'
+// the mapped point (torus coordinate tau, x' = center + tau/scale) and
+// lf = (sign 2 delta . x' + |delta|^2/2)/eps (delta = 2 shift), the caller's
+// scaling is the centred one times exp(lf) (potentials: plus eps lf).
+// perm set: out[perm[q]] = src[q] exp(lf), the read-out in the caller's
+// order; perm NULL: out[q] = src[q] exp(-lf) in sorted order (the start of
+// the centred iteration from the caller's start; out may be src).  One
+// workgroup per chunk.
+template <typename R>
+struct UncenterArgs {
+  Geom geo;
+  const Chunk* chunks;
+  const R* coords;       // sorted tile-local coordinates
+  const int* perm;
+  const double* src;     // sorted scalings (potentials when logd)
+  double* out;
+  const double* pb;      // per problem (stride kUncStride): scale, center[3], coef[3] = sign 2 delta/eps, cst, eps
+  int logd;
+};
+constexpr int kUncStride = 10;
+template <typename R>
+hipError_t launch_uncenter(const UncenterArgs<R>& a, int nchunks, hipStream_t st);
 
 struct KeyArgs {
   const double* pts;
@@ -322,9 +368,10 @@ hipError_t launch_mul(const double* a, const double* b, long n, double* out, hip
 // out[0] = max v, out[1] = sum v (non-finite if any entry is), over n values.
 hipError_t launch_maxsum(const double* v, long n, double* partials, unsigned* counter, double* out, hipStream_t st);
 
-// grad_mu: out[perm[q]] = eps*log(alpha_s[q]) - shift, with shift = eps*mean(log alpha) read from device
+// grad_mu: out[i] = eps*log(alpha[i]) - shift (out[perm[i]] with perm), with shift = eps*mean(log alpha)
+// over the n entries (zero scalings count as log 0 = 0: weight zero, see Proposition 2.3)
 hipError_t launch_gradmu(const double* alpha, long n, double eps, double* partials, unsigned* counter,
-                         double* mean_out, double* grad_mu, hipStream_t st);
+                         double* mean_out, double* grad_mu, hipStream_t st, const int* perm = nullptr);
 
 // NFFT spectrum conversion between user layout (full I_N, complex FP64) and
 // the internal half spectrum (R), with deconvolution by 1/Phi.

@@ -107,6 +107,9 @@ static int check_params(const nfs_params* p, int64_t n, int64_t nt) {
   return NFS_OK;
 }
 
+// Per-problem slot of the bounding-box buffer: the x box, then the y box.
+constexpr int kBoxSlot = 2 * kBoxVals;
+
 // Near-field radius on the torus and smoothness for r = 1.
 static double near_radius(const nfs_params* p) { return (p->eps_I > 0.0 ? p->eps_I : 4.0) / p->N; }
 static int near_smooth(const nfs_params* p) { return p->p_smooth ? p->p_smooth : 8; }
@@ -168,7 +171,9 @@ struct Work {
   bool two_level = false;
   R* part = nullptr;
   long ecell = 0;
-  R* S = nullptr;     // B spread grids
+  R* S = nullptr;     // B spread grids, in the format gmode (exact int64 sums unless GRID_REAL)
+  int gmode = GRID_REAL;
+  long gplane = 0;    // cells of all B grids: the offset of the second plane of GRID_FIX128
   R* U = nullptr;     // B interpolation grids
   cplx<R>* W = nullptr;
   cplx<R>* V = nullptr;
@@ -191,7 +196,9 @@ struct Work {
   double* wmul_x = nullptr;   // B
   double* wmul_y = nullptr;   // B
   double* leps = nullptr;     // B x kLepsStride: log-domain constants {1/eps, eps}
-  double* st_box = nullptr;   // B x 20 + 20: per problem, x box at 0, y weight box at 10
+  double* st_box = nullptr;   // B x kBoxSlot + kBoxSlot: per problem, x box at 0, y box at kBoxVals
+  double* unc = nullptr;      // 2 x B x kUncStride: centred form read-out constants (x side, then y)
+  double* gfac = nullptr;     // 2 x B: per-problem factors of the gradient on a solver
   double* tmp = nullptr;
   int r = 2;
   double* nf = nullptr;       // near-field sums (r = 1), per sorted target
@@ -287,7 +294,9 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
   for (int c = 0; c < d; ++c) two = two && w.geo.nt[c] >= 3;
   w.two_level = two;
   w.part = two ? cv.take<R>(size_t(std::max(w.X.max_chunks, w.Y.max_chunks)) * ecell) : nullptr;
-  w.S = cv.take<R>(size_t(B) * ncell);
+  w.gmode = spread_grid_mode(w.geo, int(sizeof(R)), two);
+  w.gplane = long(B) * ncell;
+  w.S = reinterpret_cast<R*>(cv.take<unsigned char>(size_t(B) * ncell * grid_cell_bytes(w.gmode, sizeof(R))));
   w.U = cv.take<R>(size_t(B) * ncell);
   const long rows = ncell / g;
   w.W = cv.take<cplx<R>>(size_t(B) * rows * w.K0);
@@ -301,7 +310,7 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
   w.inv_phi = cv.take<double>(w.K0);
   w.wpoly = cv.take<double>((sizeof(R) == 4 ? sizeof(WindowPoly) : sizeof(WindowPoly64)) / sizeof(double) + 1);
   const long maxch = std::max(w.X.max_chunks, w.Y.max_chunks);
-  w.partials = cv.take<double>(size_t(std::max<long>(maxch, 1024)) * 9);
+  w.partials = cv.take<double>(size_t(std::max<long>(maxch, 1024)) * kBoxVals);
   w.ct_interp = cv.take<unsigned>(B);
   w.ct_misc = cv.take<unsigned>(8);
   w.st_row = cv.take<double>(size_t(B) * kStat);
@@ -315,7 +324,9 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
   w.wmul_x = cv.take<double>(B);
   w.wmul_y = cv.take<double>(B);
   w.leps = cv.take<double>(size_t(B) * kLepsStride);
-  w.st_box = cv.take<double>(size_t(B) * 20 + 20);
+  w.st_box = cv.take<double>(size_t(B) * kBoxSlot + kBoxSlot);
+  w.unc = cv.take<double>(size_t(2) * B * kUncStride);
+  w.gfac = cv.take<double>(size_t(2) * B);
   w.tmp = cv.take<double>(size_t(std::max(nA, nB)) * std::max(d, 1));
   w.r = p->r;
   if (p->r == 1) {
@@ -345,8 +356,9 @@ static int zero_state(Work<R>& w, hipStream_t st) {
 // Bounding box of up to two clouds plus the statistics of one weight vector,
 // written to out[0..8] on the device (no synchronization).
 static int box_launch(double* out, double* partials, unsigned* counter, int d, const double* p0, long n0,
-                      const double* p1, long n1, const double* w, long nw, hipStream_t st) {
+                      const double* p1, long n1, const double* w, long nw, hipStream_t st, int wsum = 0) {
   BoxArgs b{};
+  b.wsum = wsum;
   b.pts[0] = p0;
   b.n[0] = n0;
   b.pts[1] = p1;
@@ -421,9 +433,11 @@ static int build_chunks(Work<R>& w, CloudBuf<R>& cb, int chunk, bool runs, hipSt
   return NFS_OK;
 }
 
+// side: the cloud is mapped with the centre center + side * shift (x: -1, y: +1;
+// the shift is zero outside the centred form).
 template <typename R>
 static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const std::vector<Scaling>& sc,
-                      const double* v0, const double* v1, hipStream_t st) {
+                      const double* v0, const double* v1, hipStream_t st, double side = 0.0) {
   const Geom& geo = w.geo;
   const int B = w.B, nb = w.nbins, d = geo.d;
   NFS_HIP(launch_fill(cb.counts, sizeof(int) * size_t(B) * nb, st));
@@ -439,7 +453,7 @@ static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const std:
     ka.T = geo.T;
     for (int c = 0; c < 3; ++c) {
       ka.nt[c] = geo.nt[c];
-      ka.center[c] = sc[b].center[c];
+      ka.center[c] = sc[b].center[c] + side * sc[b].shift[c];
     }
     ka.scale = sc[b].scale;
     ka.keys = cb.keys + o;
@@ -472,7 +486,7 @@ static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const std:
     sa.T = geo.T;
     for (int c = 0; c < 3; ++c) {
       sa.nt[c] = geo.nt[c];
-      sa.center[c] = sc[b].center[c];
+      sa.center[c] = sc[b].center[c] + side * sc[b].shift[c];
     }
     sa.scale = sc[b].scale;
     sa.keys = cb.keys + o;
@@ -604,6 +618,8 @@ static hipError_t fft_chain(Work<R>& w, const R* table, int deriv, hipStream_t s
     ra.N = N;
     ra.nrows = B;
     ra.real_in = w.S;
+    ra.gmode = w.gmode;
+    ra.grid_plane = w.gplane;
     ra.real_io = w.U;
     ra.zero_src = keep_src ? 0 : 1;
     ra.tw = w.tw;
@@ -617,6 +633,8 @@ static hipError_t fft_chain(Work<R>& w, const R* table, int deriv, hipStream_t s
   ra.N = N;
   ra.nrows = int(rows * B);
   ra.real_io = w.S;
+  ra.gmode = w.gmode;
+  ra.grid_plane = w.gplane;
   ra.spec = w.W;
   ra.zero_src = keep_src ? 0 : 1;
   ra.tw = w.tw;
@@ -708,6 +726,8 @@ static SpreadArgs<R> spread_args(Work<R>& w, const CloudBuf<R>& src, const doubl
   a.cell_order = w.cell_order;
   a.grid = w.S;
   a.grid_stride = w.ncell;
+  a.gmode = w.gmode;
+  a.grid_plane = w.gplane;
   a.win = w.win;
   a.wpoly = w.wpoly;
   return a;
@@ -844,7 +864,7 @@ static int do_fastsum(const nfs_params* p, const double* src, int64_t ns, const 
     NFS_HIP(launch_mul(wv, wv2, ns, w.tmp, st));
     wv = w.tmp;
   }
-  double box[9];
+  double box[kBoxVals];
   NFS_TRY(box_launch(w.st_box, w.partials, w.ct_misc, p->d, src, ns, tgt, nt, wv, ns, st));
   NFS_HIP(hipMemcpyAsync(box, w.st_box, sizeof(box), hipMemcpyDeviceToHost, st));
   NFS_HIP(hipStreamSynchronize(st));
@@ -855,7 +875,7 @@ static int do_fastsum(const nfs_params* p, const double* src, int64_t ns, const 
   NFS_TRY(sort_cloud(w, w.X, src, w.sc, wv, nullptr, st));
   NFS_TRY(sort_cloud(w, w.Y, tgt, w.sc, tscale, nullptr, st));
   NFS_TRY(upload_tables(w, p, st));
-  NFS_HIP(launch_fill(w.S, sizeof(R) * w.ncell, st));
+  NFS_HIP(launch_fill(w.S, grid_cell_bytes(w.gmode, sizeof(R)) * w.ncell, st));
   const double wmax = box[6] > 0.0 ? box[6] : 1.0;
   NFS_HIP(spread(w, w.X, w.X.w0s, nullptr, 1.0 / wmax, st));
   NFS_HIP(fft_chain(w, w.dtab, -1, st));
@@ -915,7 +935,7 @@ static int do_nfft(const nfs_params* p, bool adjoint, const double* pts, int64_t
   w.X.off = {0, n};
   w.Y.off = {0, 0};
   NFS_TRY(zero_state(w, st));
-  double box[9];
+  double box[kBoxVals];
   NFS_TRY(box_launch(w.st_box, w.partials, w.ct_misc, p->d, pts, n, nullptr, 0, wv, wv ? n : 0, st));
   NFS_HIP(hipMemcpyAsync(box, w.st_box, sizeof(box), hipMemcpyDeviceToHost, st));
   NFS_HIP(hipStreamSynchronize(st));
@@ -941,7 +961,7 @@ static int do_nfft(const nfs_params* p, bool adjoint, const double* pts, int64_t
   ax.tw = w.tw;
   ax.mul = Multiplier{nullptr, -1, 0};
   if (adjoint) {
-    NFS_HIP(launch_fill(w.S, sizeof(R) * w.ncell, st));
+    NFS_HIP(launch_fill(w.S, grid_cell_bytes(w.gmode, sizeof(R)) * w.ncell, st));
     // weights normalized by max |w| so every spread contribution is at most one in size
     const double wmax = box[6] > 0.0 ? box[6] : 1.0;
     NFS_HIP(spread(w, w.X, w.X.w0s, nullptr, 1.0 / wmax, st));
@@ -952,6 +972,8 @@ static int do_nfft(const nfs_params* p, bool adjoint, const double* pts, int64_t
     ra.N = N;
     ra.nrows = int(rows);
     ra.real_io = w.S;
+    ra.gmode = w.gmode;
+    ra.grid_plane = w.gplane;
     ra.spec = d == 1 ? w.spec : w.W;
     ra.tw = w.tw;
     NFS_HIP(launch_rows(ra, st));
@@ -1042,7 +1064,7 @@ static int do_nfft(const nfs_params* p, bool adjoint, const double* pts, int64_t
 }
 
 // ----------------------------------------------------------------------------- Sinkhorn
-static int check_weights(const double box[9], long n, long nt_other, const char* name, int b) {
+static int check_weights(const double* box, long n, long nt_other, const char* name, int b) {
   const double tol = 1e-12 * double(std::max(n, nt_other));
   const std::string who = std::string(name) + (b >= 0 ? " of problem " + std::to_string(b) : "");
   if (box[7] < 0.0) return fail(NFS_EWEIGHTS, who + " has a negative weight");
@@ -1056,33 +1078,56 @@ template <typename R>
 static int plan_sinkhorn(Work<R>& w, const nfs_params* p, const double* eps, const double* x, const double* mu,
                          const double* y, const double* nu, const double* ax, const double* ay, hipStream_t st) {
   const int B = w.B, d = p->d;
+  const bool centred = (p->flags & NFS_FLAG_CENTER) != 0;
   NFS_TRY(zero_state(w, st));
   for (int b = 0; b < B; ++b) {
     const long ox = w.X.off[b], nx = w.X.off[b + 1] - ox, oy = w.Y.off[b], ny = w.Y.off[b + 1] - oy;
     if (nx < 1 || ny < 1) return fail(NFS_EINVAL, "every problem needs at least one point per cloud");
-    NFS_TRY(box_launch(w.st_box + 20 * b, w.partials, w.ct_misc, d, x + ox * d, nx, y + oy * d, ny, mu + ox, nx, st));
-    NFS_TRY(box_launch(w.st_box + 20 * b + 10, w.partials, w.ct_misc, d, nullptr, 0, nullptr, 0, nu + oy, ny, st));
+    double* slot = w.st_box + kBoxSlot * b;
+    if (centred) {
+      // separate boxes and weighted means of the two clouds
+      NFS_TRY(box_launch(slot, w.partials, w.ct_misc, d, x + ox * d, nx, nullptr, 0, mu + ox, nx, st, 1));
+      NFS_TRY(box_launch(slot + kBoxVals, w.partials, w.ct_misc, d, y + oy * d, ny, nullptr, 0, nu + oy, ny, st, 1));
+    } else {
+      NFS_TRY(box_launch(slot, w.partials, w.ct_misc, d, x + ox * d, nx, y + oy * d, ny, mu + ox, nx, st));
+      NFS_TRY(box_launch(slot + kBoxVals, w.partials, w.ct_misc, d, nullptr, 0, nullptr, 0, nu + oy, ny, st));
+    }
   }
-  std::vector<double> box(size_t(B) * 20);
+  std::vector<double> box(size_t(B) * kBoxSlot);
   NFS_HIP(hipMemcpyAsync(box.data(), w.st_box, sizeof(double) * box.size(), hipMemcpyDeviceToHost, st));
   NFS_HIP(hipStreamSynchronize(st));
   w.sc.resize(B);
   for (int b = 0; b < B; ++b) {
-    const double* bx = box.data() + 20 * b;
-    const double* by = bx + 10;
-    for (int i = 0; i < 9; ++i)
-      if (!std::isfinite(bx[i]) || (i >= 6 && !std::isfinite(by[i])))
+    const double* bx = box.data() + size_t(kBoxSlot) * b;
+    const double* by = bx + kBoxVals;
+    for (int i = 0; i < kBoxVals; ++i) {
+      const bool used = centred ? (i < 9 || i < 9 + d) : (i < 9);
+      if (used && (!std::isfinite(bx[i]) || (centred || i >= 6) && !std::isfinite(by[i])))
         return fail(NFS_EINVAL, "non-finite point coordinates or weights");
+    }
     const long nx = w.X.off[b + 1] - w.X.off[b], ny = w.Y.off[b + 1] - w.Y.off[b];
     NFS_TRY(check_weights(bx, nx, ny, "mu", B > 1 ? b : -1));
     NFS_TRY(check_weights(by, ny, nx, "nu", B > 1 ? b : -1));
-    w.sc[b] = p->r == 1 ? choose_scaling_r1(d, eps[b], p->precision == NFS_FP32 ? 20.0 : 36.0, bx, bx + 3)
-                        : choose_scaling(d, p->r, eps[b], p->N, bx, bx + 3);
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, shift[3] = {0, 0, 0};
+    for (int c = 0; c < d; ++c) {
+      if (centred) {
+        // shift = (mean y - mean x)/2: x + shift and y - shift have the same weighted mean
+        shift[c] = 0.5 * (by[9 + c] / by[8] - bx[9 + c] / bx[8]);
+        lo[c] = std::min(bx[c] + shift[c], by[c] - shift[c]);
+        hi[c] = std::max(bx[3 + c] + shift[c], by[3 + c] - shift[c]);
+      } else {
+        lo[c] = bx[c];
+        hi[c] = bx[3 + c];
+      }
+    }
+    w.sc[b] = p->r == 1 ? choose_scaling_r1(d, eps[b], p->precision == NFS_FP32 ? 20.0 : 36.0, lo, hi)
+                        : choose_scaling(d, p->r, eps[b], p->N, lo, hi);
+    for (int c = 0; c < d; ++c) w.sc[b].shift[c] = shift[c];
   }
-  NFS_TRY(sort_cloud(w, w.X, x, w.sc, mu, ax, st));
-  NFS_TRY(sort_cloud(w, w.Y, y, w.sc, nu, ay, st));
+  NFS_TRY(sort_cloud(w, w.X, x, w.sc, mu, ax, st, -1.0));
+  NFS_TRY(sort_cloud(w, w.Y, y, w.sc, nu, ay, st, 1.0));
   NFS_TRY(upload_tables(w, p, st));
-  NFS_HIP(launch_fill(w.S, sizeof(R) * size_t(w.B) * w.ncell, st));
+  NFS_HIP(launch_fill(w.S, grid_cell_bytes(w.gmode, sizeof(R)) * size_t(w.B) * w.ncell, st));
   return NFS_OK;
 }
 
@@ -1097,6 +1142,8 @@ struct SolverBase {
   virtual int stage_info(double* info) = 0;
   // Tolerance of the per-iteration stop test (eq. (Error)); 0 runs every iteration.
   virtual int set_tol(double tol, hipStream_t caller) = 0;
+  // Envelope gradient at the current scalings, on the solver's plan.
+  virtual int grad(double* gx, double* gmu, double* gy, double* gnu, hipStream_t caller) = 0;
   // Whether every problem has stopped on the tolerance (synchronizes).
   virtual int all_stopped(bool* all, hipStream_t caller) = 0;
 };
@@ -1112,8 +1159,81 @@ struct Solver : SolverBase {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   bool logd = false;  // log domain (Algorithm 4): w1s holds potentials, wmul_* their maxima
+  bool centred = false;  // NFS_FLAG_CENTER: the iteration runs on the shifted clouds (Scaling::shift)
 
   int sink() const { return logd ? EPI_LOGSINK : EPI_SINK; }
+
+  // Constants of the centred form's change of variables (UncenterArgs::pb),
+  // x side then y side, uploaded once after the plan.
+  int upload_centring(hipStream_t st) {
+    const int B = w.B;
+    std::vector<double> unc(size_t(2) * B * kUncStride, 0.0);
+    for (int side = 0; side < 2; ++side)
+      for (int b = 0; b < B; ++b) {
+        double* u = unc.data() + (size_t(side) * B + b) * kUncStride;
+        const Scaling& sc = w.sc[b];
+        double d2 = 0.0;
+        u[0] = sc.scale;
+        for (int c = 0; c < p.d; ++c) {
+          const double delta = 2.0 * sc.shift[c];
+          u[1 + c] = sc.center[c];
+          u[4 + c] = (side == 0 ? -2.0 : 2.0) * delta / eps[b];
+          d2 += delta * delta;
+        }
+        u[7] = 0.5 * d2 / eps[b];
+        u[8] = eps[b];
+      }
+    NFS_HIP(hipMemcpyAsync(w.unc, unc.data(), sizeof(double) * unc.size(), hipMemcpyHostToDevice, st));
+    NFS_HIP(hipStreamSynchronize(st));  // unc is read by the copy
+    return NFS_OK;
+  }
+
+  // Centred scalings of one cloud (side 0: x, 1: y) to the caller's variables
+  // in the caller's order (out), or, with out NULL, the cloud's sorted
+  // starting values from the caller's variables to the centred ones in place.
+  hipError_t map_centred(CloudBuf<R>& cb, int side, double* out, hipStream_t st) {
+    UncenterArgs<R> ua{};
+    ua.geo = w.geo;
+    ua.chunks = cb.chunks;
+    ua.coords = cb.coords;
+    ua.perm = out ? cb.perm : nullptr;
+    ua.src = cb.w1s;
+    ua.out = out ? out : cb.w1s;
+    ua.pb = w.unc + size_t(side) * w.B * kUncStride;
+    ua.logd = logd;
+    return launch_uncenter(ua, cb.nchunks, st);
+  }
+
+  // The centred iteration starts from the image of the caller's start (ones,
+  // zeros, or the warm start), so its iterates are exactly Algorithm 3's
+  // (Algorithm 4's) under the change of variables.  The spread normalization
+  // of the y side (scaling form: 1 / max; log domain: the max potential) and
+  // the l1 norm the first alpha update reads are taken again from the mapped
+  // values.
+  int centre_start(hipStream_t st) {
+    const int B = w.B;
+    NFS_TRY(upload_centring(st));
+    NFS_HIP(map_centred(w.X, 0, nullptr, st));
+    NFS_HIP(map_centred(w.Y, 1, nullptr, st));
+    for (int b = 0; b < B; ++b)
+      NFS_HIP(launch_maxsum(w.Y.w1s + w.Y.off[b], w.Y.off[b + 1] - w.Y.off[b], w.partials, w.ct_misc,
+                            w.st_box + 2 * b, st));
+    std::vector<double> ms(size_t(B) * 2), wm(B), col(size_t(B) * kStat);
+    NFS_HIP(hipMemcpyAsync(ms.data(), w.st_box, sizeof(double) * ms.size(), hipMemcpyDeviceToHost, st));
+    NFS_HIP(hipMemcpyAsync(col.data(), w.st_col, sizeof(double) * col.size(), hipMemcpyDeviceToHost, st));
+    NFS_HIP(hipStreamSynchronize(st));
+    for (int b = 0; b < B; ++b) {
+      const double mx = ms[2 * b], sum = ms[2 * b + 1];
+      if (!std::isfinite(mx) || !std::isfinite(sum) || (!logd && !(mx > 0.0)))
+        return fail(NFS_EINVAL, "the centred starting values over- or underflow (use the log domain)");
+      wm[b] = logd ? mx : 1.0 / mx;
+      col[size_t(b) * kStat + 7] = sum;
+    }
+    NFS_HIP(hipMemcpyAsync(w.wmul_y, wm.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
+    NFS_HIP(hipMemcpyAsync(w.st_col, col.data(), sizeof(double) * col.size(), hipMemcpyHostToDevice, st));
+    NFS_HIP(hipStreamSynchronize(st));  // wm and col are read by the copies
+    return NFS_OK;
+  }
   int eval() const { return logd ? EPI_LOGEVAL : EPI_EVAL; }
 
   // One iteration: the alpha update (sources y with alpha_t; its epilogue
@@ -1201,16 +1321,16 @@ struct Solver : SolverBase {
       return NFS_OK;
     }
     for (int b = 0; b < B; ++b)
-      NFS_TRY(box_launch(w.st_box + 20 * b, w.partials, w.ct_misc, p.d, nullptr, 0, nullptr, 0, alpha_t0 + oy[b],
-                         oy[b + 1] - oy[b], st));
-    std::vector<double> box(size_t(B) * 20), wm(B);
+      NFS_TRY(box_launch(w.st_box + kBoxSlot * b, w.partials, w.ct_misc, p.d, nullptr, 0, nullptr, 0,
+                         alpha_t0 + oy[b], oy[b + 1] - oy[b], st));
+    std::vector<double> box(size_t(B) * kBoxSlot), wm(B);
     NFS_HIP(hipMemcpyAsync(box.data(), w.st_box, sizeof(double) * box.size(), hipMemcpyDeviceToHost, st));
     NFS_HIP(hipStreamSynchronize(st));
     for (int b = 0; b < B; ++b) {
-      if (!(box[20 * b + 7] > 0.0) || !std::isfinite(box[20 * b + 6]))
-        return fail(NFS_EINVAL, "warm-start alpha_t must be positive and finite");
-      wm[b] = 1.0 / box[20 * b + 6];
-      col[size_t(b) * kStat + 7] = box[20 * b + 8];
+      const double* bb = box.data() + size_t(kBoxSlot) * b;
+      if (!(bb[7] > 0.0) || !std::isfinite(bb[6])) return fail(NFS_EINVAL, "warm-start alpha_t must be positive and finite");
+      wm[b] = 1.0 / bb[6];
+      col[size_t(b) * kStat + 7] = bb[8];
     }
     NFS_HIP(hipMemcpyAsync(w.wmul_y, wm.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
     NFS_HIP(hipMemcpyAsync(w.st_col, col.data(), sizeof(double) * col.size(), hipMemcpyHostToDevice, st));
@@ -1255,6 +1375,9 @@ struct Solver : SolverBase {
              size_t wsb, hipStream_t caller) {
     p = *prm;
     logd = (p.flags & NFS_FLAG_LOG_DOMAIN) != 0;
+    centred = (p.flags & NFS_FLAG_CENTER) != 0;
+    if (centred && p.r != 2) return fail(NFS_EUNSUPPORTED, "NFS_FLAG_CENTER needs the squared Euclidean cost (r = 2)");
+
     eps.assign(eps_in, eps_in + B);
     std::vector<long> ox(B + 1, 0), oy(B + 1, 0);
     for (int b = 0; b < B; ++b) {
@@ -1273,6 +1396,7 @@ struct Solver : SolverBase {
     } else {
       NFS_TRY(start_scalings(B, oy, alpha_t0, st));
     }
+    if (centred) NFS_TRY(centre_start(st));
     if ((p.flags & NFS_FLAG_AUTOTUNE) && p.r == 2 && !w.two_level) NFS_TRY(autotune(st));
     NFS_HIP(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
     NFS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -1397,6 +1521,53 @@ struct Solver : SolverBase {
     return leave(caller);
   }
 
+  // Envelope gradient (Proposition 2.3, eq. (14)) at the current scalings,
+  // on the plan the iteration uses: the sorted clouds, tables and scalings
+  // stay where they are.  x side: alpha_t is spread once, and each axis c
+  // applies (2 pi i k_c) D_k to its transform and interpolates at x, times
+  // -eps s alpha_i (s the torus scaling); the y side is the same with the
+  // clouds exchanged (the kernel is even).  grad_mu = eps log alpha minus its
+  // mean over the problem.  Outputs in the caller's (packed) point order.
+  int grad(double* gx, double* gmu, double* gy, double* gnu, hipStream_t caller) override {
+    if (p.r != 2) return fail(NFS_EUNSUPPORTED, "the gradient is implemented for r = 2");
+    if (logd || centred) return fail(NFS_EUNSUPPORTED, "the solver gradient needs the scaling form, uncentred");
+    NFS_TRY(enter(caller));
+    hipStream_t st = gs;
+    const int B = w.B, d = p.d;
+    // per problem: -eps_b s_b, whose reciprocal times the spread normalization divides the sums
+    std::vector<double> rec(B);
+    for (int b = 0; b < B; ++b) rec[b] = 1.0 / (-eps[b] * w.sc[b].scale);
+    NFS_HIP(hipMemcpyAsync(w.gfac + B, rec.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
+    for (int side = 0; side < 2; ++side) {
+      CloudBuf<R>& src = side == 0 ? w.Y : w.X;
+      CloudBuf<R>& tgt = side == 0 ? w.X : w.Y;
+      double* wm = side == 0 ? w.wmul_y : w.wmul_x;
+      double* out = side == 0 ? gx : gy;
+      double* outm = side == 0 ? gmu : gnu;
+      if (out) {
+        NFS_HIP(launch_mul(wm, w.gfac + B, B, w.gfac, st));
+        NFS_HIP(spread(w, src, src.w1s, wm, 1.0, st));
+        for (int c = 0; c < d; ++c) {
+          NFS_HIP(fft_chain(w, w.dtab, c, st, c + 1 < d));
+          InterpArgs<R> ia = interp_args(w, tgt, EPI_OUT, w.gfac);
+          ia.scale_vec = tgt.w1s;
+          ia.out = out;
+          ia.out_stride = d;
+          ia.out_comp = c;
+          NFS_HIP(launch_interp(ia, tgt.nchunks, st));
+        }
+      }
+      if (outm)
+        for (int b = 0; b < B; ++b) {
+          const long o = tgt.off[b];
+          NFS_HIP(launch_gradmu(tgt.w1s + o, tgt.off[b + 1] - o, eps[b], w.partials, w.ct_misc + 2, w.st_cost, outm, st,
+                                tgt.perm + o));
+        }
+    }
+    NFS_HIP(hipStreamSynchronize(st));  // rec is read by the copy
+    return leave(caller);
+  }
+
   int set_tol(double tol, hipStream_t caller) override {
     NFS_TRY(enter(caller));
     NFS_HIP(launch_fill_double(w.tol2, 1, tol > 0.0 ? tol * tol : 0.0, gs));
@@ -1447,7 +1618,7 @@ struct Solver : SolverBase {
                      w.st_rdy + 4 * b};
       NFS_HIP(launch_readout(rb, st));
     }
-    const bool primal = (p.flags & NFS_FLAG_PRIMAL_COST) && p.r == 2 && !logd;
+    const bool primal = (p.flags & NFS_FLAG_PRIMAL_COST) && p.r == 2 && !logd && !centred;
     if (primal) {
       NFS_HIP(spread(w, w.Y, w.Y.w1s, w.wmul_y, 1.0, st));
       NFS_HIP(fft_chain(w, w.dtab2, -1, st));
@@ -1462,8 +1633,15 @@ struct Solver : SolverBase {
         NFS_HIP(launch_readout(rc, st));
       }
     }
-    if (alpha) NFS_HIP(launch_unpermute(w.X.w1s, w.X.perm, w.X.n, alpha, st));
-    if (alpha_t) NFS_HIP(launch_unpermute(w.Y.w1s, w.Y.perm, w.Y.n, alpha_t, st));
+    if (centred) {
+      // back to the caller's variables: alpha = alpha' exp((-2 delta.x' + |delta|^2/2)/eps),
+      // alpha_t = alpha_t' exp((2 delta.y' + |delta|^2/2)/eps), delta = 2 shift
+      if (alpha) NFS_HIP(map_centred(w.X, 0, alpha, st));
+      if (alpha_t) NFS_HIP(map_centred(w.Y, 1, alpha_t, st));
+    } else {
+      if (alpha) NFS_HIP(launch_unpermute(w.X.w1s, w.X.perm, w.X.n, alpha, st));
+      if (alpha_t) NFS_HIP(launch_unpermute(w.Y.w1s, w.Y.perm, w.Y.n, alpha_t, st));
+    }
     std::vector<double> col(size_t(B) * kStat), row(size_t(B) * kStat), rdx(size_t(B) * 4), rdy(size_t(B) * 4),
         cost(size_t(B) * 4);
     std::vector<int> pst(size_t(B) * kPState);
@@ -1489,6 +1667,13 @@ struct Solver : SolverBase {
       const double* rb = row.data() + size_t(kStat) * b;
       const double mass = r.iters > 0 ? cb[1] : ev_row[size_t(kStat) * b + 1];
       r.cost = logd ? rdx[4 * b + 0] + rdy[4 * b + 0] - e * mass : e * (1.0 + rdx[4 * b + 0] + rdy[4 * b + 0] - mass);
+      if (centred) {
+        // the shifted problem's cost plus |mean y - mean x|^2 (the separable part of the
+        // squared cost the shift removed; the coupling is the same)
+        double d2 = 0.0;
+        for (int c = 0; c < p.d; ++c) d2 += 4.0 * w.sc[b].shift[c] * w.sc[b].shift[c];
+        r.cost += d2;
+      }
       r.cost_upper = r.cost - e * (rdx[4 * b + 1] + rdy[4 * b + 1]);
       r.cost_primal = primal ? cost[4 * b + 2] : NAN;
       r.marg_err_row = std::sqrt(ev_row[size_t(kStat) * b + 0]);
@@ -1496,6 +1681,7 @@ struct Solver : SolverBase {
       r.marg_err = r.marg_err_row + r.marg_err_col;
       r.n_nonpos = int64_t(rb[4] + cb[4]);
       r.dyn_range = logd ? NAN : std::max(rb[8], cb[8]);
+      r.centred = centred ? 1 : 0;
       nonpos += r.n_nonpos;
       if (res) res[b] = r;
     }
@@ -1566,10 +1752,13 @@ static int do_grad(const nfs_params* p, const double* x, int64_t n, const double
   w.X.off = {0, n};
   w.Y.off = {0, nt};
   const double eps = p->eps;
-  NFS_TRY(plan_sinkhorn(w, p, &eps, x, mu, y, nu, alpha, alpha_t, st));
+  // the gradient takes the scalings in the caller's variables: no centred mapping
+  nfs_params q = *p;
+  q.flags &= ~NFS_FLAG_CENTER;
+  NFS_TRY(plan_sinkhorn(w, &q, &eps, x, mu, y, nu, alpha, alpha_t, st));
   if (grad_mu) NFS_HIP(launch_gradmu(alpha, n, p->eps, w.partials, w.ct_misc + 2, w.st_cost, grad_mu, st));
   if (grad_x) {
-    double box[9];
+    double box[kBoxVals];
     NFS_TRY(box_launch(w.st_box, w.partials, w.ct_misc, p->d, nullptr, 0, nullptr, 0, alpha_t, nt, st));
     NFS_HIP(hipMemcpyAsync(box, w.st_box, sizeof(box), hipMemcpyDeviceToHost, st));
     NFS_HIP(hipStreamSynchronize(st));
@@ -1653,6 +1842,17 @@ static int auto_workspace(const nfs_params* p, int64_t n, int64_t nt, size_t* S,
 constexpr double kAutoRange = 1e5;
 
 static bool needs_fp64(const nfs_result& r) { return r.n_nonpos > 0 || !(r.dyn_range <= kAutoRange); }
+
+// With FP64 grids the sums' error is about 1e-16 of the l1 norm of their
+// weights, so the FP64 tolerance 1e-10 holds for sums down to 1e-6 of it;
+// beyond that (or at t <= 0) the problem is solved once more in the centred
+// form (NFS_FLAG_CENTER), whose iterates are the same but whose sums span far
+// less range when the clouds are apart.
+constexpr double kAutoRange64 = 1e6;
+
+static bool needs_centring(const nfs_result& r, bool logd) {
+  return r.n_nonpos > 0 || (!logd && !(r.dyn_range <= kAutoRange64));
+}
 
 // Packed inputs and results of the problems re-solved in FP64: x, y, mu, nu,
 // alpha, alpha_t of every problem at most.
@@ -1816,6 +2016,15 @@ int nfs_sinkhorn_solve(const nfs_params* prm, const double* x, int64_t n, const 
       rc = nfs_sinkhorn_solve(&p64, x, n, mu, y, nt, nu, max_iter, tol, warm_start, alpha, alpha_t, &r, workspace,
                               S, stream);
     }
+    if ((rc == NFS_ENONPOS || (rc == NFS_OK && r.precision_used == NFS_FP64 && needs_centring(r, logd))) &&
+        prm->r == 2 && !(prm->flags & NFS_FLAG_CENTER)) {
+      // beyond FP64's range too: the centred form (NFS_FLAG_CENTER) with FP64 grids, same start
+      nfs_params pc = p64;
+      pc.flags |= NFS_FLAG_CENTER;
+      if (warm_start) NFS_HIP(hipMemcpyAsync(alpha_t, start, sizeof(double) * nt, hipMemcpyDeviceToDevice, st));
+      rc = nfs_sinkhorn_solve(&pc, x, n, mu, y, nt, nu, max_iter, tol, warm_start, alpha, alpha_t, &r, workspace, S,
+                              stream);
+    }
     if (res) *res = r;
     return rc;
   }
@@ -1885,6 +2094,12 @@ int nfs_solver_profile(nfs_solver* s, int32_t iters, double* stage_ms, double* i
   return b->profile(iters, stage_ms, static_cast<hipStream_t>(stream));
 }
 
+int nfs_solver_grad(nfs_solver* s, double* grad_x, double* grad_mu, double* grad_y, double* grad_nu, void* stream) {
+  g_err.clear();
+  if (!s) return fail(NFS_EINVAL, "solver is NULL");
+  return reinterpret_cast<SolverBase*>(s)->grad(grad_x, grad_mu, grad_y, grad_nu, static_cast<hipStream_t>(stream));
+}
+
 int nfs_solver_destroy(nfs_solver* s) {
   delete reinterpret_cast<SolverBase*>(s);
   return NFS_OK;
@@ -1936,65 +2151,82 @@ int nfs_batch_solve(const nfs_params* prm, int32_t nprob, const int64_t* n, cons
                              ws_bytes, stream);
     if (rc != NFS_OK && rc != NFS_ENONPOS) return rc;
     const bool logd = (prm->flags & NFS_FLAG_LOG_DOMAIN) != 0;
-    // the problems to solve again with FP64 grids, as one batch of their own
-    std::vector<int> sel;
-    for (int b = 0; b < nprob; ++b)
-      if (res[b].n_nonpos > 0 || (!logd && needs_fp64(res[b]))) sel.push_back(b);
-    if (sel.empty()) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int d = prm->d;
-    std::vector<int64_t> ox(nprob + 1, 0), oy(nprob + 1, 0), n2, nt2;
-    std::vector<double> eps2;
+    std::vector<int64_t> ox(nprob + 1, 0), oy(nprob + 1, 0);
     for (int b = 0; b < nprob; ++b) {
       ox[b + 1] = ox[b] + n[b];
       oy[b + 1] = oy[b] + nt[b];
     }
-    long sn = 0, snt = 0;
-    for (int b : sel) {
-      n2.push_back(n[b]);
-      nt2.push_back(nt[b]);
-      eps2.push_back(eps[b]);
-      sn += n[b];
-      snt += nt[b];
-    }
-    // packed x | y | mu | nu | alpha | alpha_t of the selected problems, then their FP64 batch
     long sn_all = 0, snt_all = 0;
     NFS_TRY(batch_sizes(&p64, nprob, n, nt, &sn_all, &snt_all));
     const size_t packed = auto_packed_bytes(d, sn_all, snt_all);
-    double* X2 = static_cast<double*>(workspace);
-    double* Y2 = X2 + size_t(sn) * d;
-    double* MU2 = Y2 + size_t(snt) * d;
-    double* NU2 = MU2 + sn;
-    double* A2 = NU2 + snt;
-    double* AT2 = A2 + sn;
-    long px = 0, py = 0;
-    for (int b : sel) {
-      NFS_HIP(hipMemcpyAsync(X2 + px * d, x + ox[b] * d, sizeof(double) * n[b] * d, hipMemcpyDeviceToDevice, st));
-      NFS_HIP(hipMemcpyAsync(MU2 + px, mu + ox[b], sizeof(double) * n[b], hipMemcpyDeviceToDevice, st));
-      NFS_HIP(hipMemcpyAsync(Y2 + py * d, y + oy[b] * d, sizeof(double) * nt[b] * d, hipMemcpyDeviceToDevice, st));
-      NFS_HIP(hipMemcpyAsync(NU2 + py, nu + oy[b], sizeof(double) * nt[b], hipMemcpyDeviceToDevice, st));
-      px += n[b];
-      py += nt[b];
+    // Solve the problems `sel` again with parameters q, as one batch of their
+    // own: inputs packed at the start of the workspace (x | y | mu | nu |
+    // alpha | alpha_t), the batch workspace after them; results copied back.
+    auto resolve = [&](const std::vector<int>& sel, const nfs_params& q) -> int {
+      std::vector<int64_t> n2, nt2;
+      std::vector<double> eps2;
+      long sn = 0, snt = 0;
+      for (int b : sel) {
+        n2.push_back(n[b]);
+        nt2.push_back(nt[b]);
+        eps2.push_back(eps[b]);
+        sn += n[b];
+        snt += nt[b];
+      }
+      double* X2 = static_cast<double*>(workspace);
+      double* Y2 = X2 + size_t(sn) * d;
+      double* MU2 = Y2 + size_t(snt) * d;
+      double* NU2 = MU2 + sn;
+      double* A2 = NU2 + snt;
+      double* AT2 = A2 + sn;
+      long px = 0, py = 0;
+      for (int b : sel) {
+        NFS_HIP(hipMemcpyAsync(X2 + px * d, x + ox[b] * d, sizeof(double) * n[b] * d, hipMemcpyDeviceToDevice, st));
+        NFS_HIP(hipMemcpyAsync(MU2 + px, mu + ox[b], sizeof(double) * n[b], hipMemcpyDeviceToDevice, st));
+        NFS_HIP(hipMemcpyAsync(Y2 + py * d, y + oy[b] * d, sizeof(double) * nt[b] * d, hipMemcpyDeviceToDevice, st));
+        NFS_HIP(hipMemcpyAsync(NU2 + py, nu + oy[b], sizeof(double) * nt[b], hipMemcpyDeviceToDevice, st));
+        px += n[b];
+        py += nt[b];
+      }
+      std::vector<nfs_result> r2(sel.size());
+      nfs_params qq = q;
+      const int rc2 = nfs_batch_solve(&qq, int32_t(sel.size()), n2.data(), nt2.data(), eps2.data(), X2, MU2, Y2, NU2,
+                                      max_iter, tol, A2, AT2, r2.data(), static_cast<char*>(workspace) + packed,
+                                      ws_bytes - packed, stream);
+      if (rc2 != NFS_OK && rc2 != NFS_ENONPOS) return rc2;
+      px = py = 0;
+      for (size_t k = 0; k < sel.size(); ++k) {
+        const int b = sel[k];
+        NFS_HIP(hipMemcpyAsync(alpha + ox[b], A2 + px, sizeof(double) * n[b], hipMemcpyDeviceToDevice, st));
+        NFS_HIP(hipMemcpyAsync(alpha_t + oy[b], AT2 + py, sizeof(double) * nt[b], hipMemcpyDeviceToDevice, st));
+        px += n[b];
+        py += nt[b];
+        res[b] = r2[k];
+      }
+      NFS_HIP(hipStreamSynchronize(st));
+      return NFS_OK;
+    };
+    // FP64 grids for the problems FP32 cannot resolve, from the same start
+    std::vector<int> sel;
+    for (int b = 0; b < nprob; ++b)
+      if (res[b].n_nonpos > 0 || (!logd && needs_fp64(res[b]))) sel.push_back(b);
+    if (sel.empty()) return rc;
+    NFS_TRY(resolve(sel, p64));
+    // beyond FP64's range too: the centred form (NFS_FLAG_CENTER) with FP64 grids
+    std::vector<int> sel3;
+    for (int b : sel)
+      if (needs_centring(res[b], logd)) sel3.push_back(b);
+    if (!sel3.empty() && prm->r == 2 && !(prm->flags & NFS_FLAG_CENTER)) {
+      nfs_params pc = p64;
+      pc.flags |= NFS_FLAG_CENTER;
+      NFS_TRY(resolve(sel3, pc));
     }
-    std::vector<nfs_result> r2(sel.size());
-    nfs_params q = p64;
-    const int rc2 = nfs_batch_solve(&q, int32_t(sel.size()), n2.data(), nt2.data(), eps2.data(), X2, MU2, Y2, NU2,
-                                    max_iter, tol, A2, AT2, r2.data(), static_cast<char*>(workspace) + packed,
-                                    ws_bytes - packed, stream);
-    if (rc2 != NFS_OK && rc2 != NFS_ENONPOS) return rc2;
-    px = py = 0;
     rc = NFS_OK;
-    for (size_t k = 0; k < sel.size(); ++k) {
-      const int b = sel[k];
-      NFS_HIP(hipMemcpyAsync(alpha + ox[b], A2 + px, sizeof(double) * n[b], hipMemcpyDeviceToDevice, st));
-      NFS_HIP(hipMemcpyAsync(alpha_t + oy[b], AT2 + py, sizeof(double) * nt[b], hipMemcpyDeviceToDevice, st));
-      px += n[b];
-      py += nt[b];
-      res[b] = r2[k];
-      if (r2[k].n_nonpos > 0) rc = NFS_ENONPOS;
-    }
-    NFS_HIP(hipStreamSynchronize(st));
-    if (rc != NFS_OK) return fail(rc, "FP64 grids also produced kernel sums t <= 0");
+    for (int b = 0; b < nprob; ++b)
+      if (res[b].n_nonpos > 0) rc = NFS_ENONPOS;
+    if (rc != NFS_OK) return fail(rc, "FP64 grids (and the centred form) also produced kernel sums t <= 0");
     g_err.clear();
     return NFS_OK;
   }

@@ -146,8 +146,10 @@ __device__ __forceinline__ int wrap(int v, int g) {
 // whatever the number of adds, as long as |sum q| < 2^47; that bounds the sum
 // of |v| landing on one cell of one chunk by 2^15 (FIX64) and 2^17 (FIX128),
 // which chunks of at most 32768 points respect.  Integer sums are exact and
-// order independent, so the spread grid is deterministic.  ACC_FLOAT keeps
-// native float atomics for tiles too large for the fixed-point LDS footprint.
+// order independent, so the LDS tile is deterministic; its words are flushed
+// as exact integers into an int64 grid (GRID_FIX64 / GRID_FIX128), so the
+// spread grid is too.  ACC_FLOAT keeps native float atomics (LDS and grid)
+// for tiles too large for the fixed-point LDS footprint.
 enum AccMode : int { ACC_FLOAT = 0, ACC_FIX64 = 1, ACC_FIX128 = 2 };
 
 constexpr double kFixMagic = 6755399441055744.0;  // 1.5 * 2^52
@@ -183,6 +185,7 @@ struct Acc<float, ACC_FIX64> {
     atomicAdd(reinterpret_cast<unsigned long long*>(&t[i]), fix_bits(y));
   }
   __device__ __forceinline__ float get(int i) const { return float(double(fix_sum(t[i])) * 2.3283064365386963e-10); }
+  __device__ __forceinline__ long long word(int i) const { return fix_sum(t[i]); }  // units of 2^-32
 };
 
 template <>
@@ -206,6 +209,8 @@ struct Acc<double, ACC_FIX128> {
   __device__ __forceinline__ double get(int i) const {
     return double(fix_sum(hi_[i])) * 9.313225746154785e-10 + double(fix_sum(lo_[i])) * 8.673617379884035e-19;
   }
+  __device__ __forceinline__ long long word_hi(int i) const { return fix_sum(hi_[i]); }  // units of 2^-30
+  __device__ __forceinline__ long long word_lo(int i) const { return fix_sum(lo_[i]); }  // units of 2^-60
 };
 
 // Lane exchanges inside a DPP quad: CTRL 0xB1 = quad permutation [1,0,3,2]
@@ -436,9 +441,7 @@ __global__ __launch_bounds__(spread_block(D)) void spread_kernel(SpreadArgs<R> a
     }
   }
   const int g = geo.g;
-  for (int i = lo + threadIdx.x; i < hi; i += BS) {
-    const R v = tile.get(i);
-    if (v == R(0)) continue;
+  auto cell_of = [&](int i) {
     size_t lin;
     if constexpr (D == 1) {
       lin = wrap(org[0] + i, g);
@@ -449,7 +452,25 @@ __global__ __launch_bounds__(spread_block(D)) void spread_kernel(SpreadArgs<R> a
       const int e0 = i / (E * E), rem = i - e0 * E * E, e1 = rem / E, e2 = rem - e1 * E;
       lin = (size_t(wrap(org[0] + e0, g)) * g + wrap(org[1] + e1, g)) * g + wrap(org[2] + e2, g);
     }
-    atomicAdd(&a.grid[size_t(ch.prob) * a.grid_stride + lin], v);
+    return size_t(ch.prob) * a.grid_stride + lin;
+  };
+  for (int i = lo + threadIdx.x; i < hi; i += BS) {
+    if constexpr (ACC == ACC_FLOAT) {
+      const R v = tile.get(i);
+      if (v != R(0)) atomicAdd(&a.grid[cell_of(i)], v);
+    } else if constexpr (ACC == ACC_FIX64) {
+      // exact integer sums: the grid does not depend on the order of the flushes
+      const long long q = tile.word(i);
+      if (q != 0)
+        atomicAdd(reinterpret_cast<unsigned long long*>(a.grid) + cell_of(i), static_cast<unsigned long long>(q));
+    } else {
+      const long long qh = tile.word_hi(i), ql = tile.word_lo(i);
+      if (qh != 0 || ql != 0) {
+        unsigned long long* gw = reinterpret_cast<unsigned long long*>(a.grid) + cell_of(i);
+        if (qh != 0) atomicAdd(gw, static_cast<unsigned long long>(qh));
+        if (ql != 0) atomicAdd(gw + a.grid_plane, static_cast<unsigned long long>(ql));
+      }
+    }
   }
 }
 
@@ -1361,11 +1382,23 @@ hipError_t launch_spread_acc(const SpreadArgs<R>& a, int nchunks, size_t shm, hi
   return hipGetLastError();
 }
 
+int spread_grid_mode(const Geom& geo, int rbytes, bool two_level) {
+  if (two_level) return GRID_REAL;
+  size_t shm = 0;
+  const int mode = rbytes == 4 ? acc_mode_for<float>(geo, &shm) : acc_mode_for<double>(geo, &shm);
+  return mode == ACC_FIX64 ? GRID_FIX64 : (mode == ACC_FIX128 ? GRID_FIX128 : GRID_REAL);
+}
+
 template <typename R>
 hipError_t launch_spread(const SpreadArgs<R>& a, int nchunks, hipStream_t st) {
   if (nchunks <= 0) return hipSuccess;
   size_t shm = 0;
   const int mode = acc_mode_for<R>(a.geo, &shm);
+  // the flush writes the grid format of the accumulation mode (the chunk-tile
+  // store of the per-tile reduction writes R values)
+  const int want = a.part ? GRID_REAL
+                          : (mode == ACC_FIX64 ? GRID_FIX64 : (mode == ACC_FIX128 ? GRID_FIX128 : GRID_REAL));
+  if (!a.part && a.gmode != want) return hipErrorInvalidValue;
   if constexpr (sizeof(R) == 4) {
     if (mode == ACC_FIX64) return launch_spread_acc<R, ACC_FIX64>(a, nchunks, shm, st);
   } else {

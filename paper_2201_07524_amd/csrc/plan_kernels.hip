@@ -58,9 +58,10 @@ __device__ void grid_reduce_arr(double (&v)[NV], const bool (&is_min)[NV], const
 constexpr int kGridBlocks = 1024;
 
 // ------------------------------------------------------------------ bounding box
-// out = {min_0..min_{d-1}, max_0..max_{d-1}} padded to 3 dims, then max|w|, min w, sum w.
+// out = {min_0..min_{d-1}, max_0..max_{d-1}} padded to 3 dims, then max|w|, min w, sum w,
+// and with a.wsum the weighted coordinate sums of pts[0].
 __global__ __launch_bounds__(kBlock) void bbox_kernel(BoxArgs a) {
-  constexpr int NV = 9;
+  constexpr int NV = kBoxVals;
   double v[NV];
   bool is_min[NV], is_max[NV];
   for (int k = 0; k < NV; ++k) {
@@ -85,9 +86,52 @@ __global__ __launch_bounds__(kBlock) void bbox_kernel(BoxArgs a) {
       v[6] = fmax(v[6], fabs(w));
       v[7] = fmin(v[7], w);
       v[8] += w;
+      if (a.wsum)
+        for (int c = 0; c < a.d; ++c) v[9 + c] += w * a.pts[0][i * a.d + c];
     }
   grid_reduce_arr<NV>(v, is_min, is_max, a.partials, a.counter, a.out);
 }
+
+// ------------------------------------------------------------------ centred form read-out
+template <typename R>
+__global__ __launch_bounds__(kBlock) void uncenter_kernel(UncenterArgs<R> a) {
+  const Chunk ch = a.chunks[blockIdx.x];
+  const Geom geo = a.geo;
+  const double* pb = a.pb + size_t(kUncStride) * ch.prob;
+  const double scale = pb[0], cst = pb[7], eps = pb[8];
+  int org[3] = {0, 0, 0};
+  {
+    int t = ch.tile;
+    for (int c = geo.d - 1; c >= 0; --c) {
+      org[c] = (t % geo.nt[c]) * geo.T;
+      t /= geo.nt[c];
+    }
+  }
+  for (int i = threadIdx.x; i < ch.count; i += kBlock) {
+    const int q = ch.start + i;
+    double lf = cst;
+    for (int c = 0; c < geo.d; ++c) {
+      // torus coordinate in [-1/2, 1/2): the grid coordinate is tau g wrapped into [0, g)
+      double tau = (double(org[c]) + double(a.coords[size_t(q) * geo.d + c])) / double(geo.g);
+      if (tau >= 0.5) tau -= 1.0;
+      lf += pb[4 + c] * (pb[1 + c] + tau / scale);
+    }
+    const double v = a.src[q];
+    if (a.perm)
+      a.out[a.perm[q]] = a.logd ? v + eps * lf : v * exp(lf);
+    else
+      a.out[q] = a.logd ? v - eps * lf : v * exp(-lf);
+  }
+}
+
+template <typename R>
+hipError_t launch_uncenter(const UncenterArgs<R>& a, int nchunks, hipStream_t st) {
+  if (nchunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(uncenter_kernel<R>, dim3(nchunks), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+template hipError_t launch_uncenter<float>(const UncenterArgs<float>&, int, hipStream_t);
+template hipError_t launch_uncenter<double>(const UncenterArgs<double>&, int, hipStream_t);
 
 hipError_t launch_bbox(const BoxArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(bbox_kernel, dim3(kGridBlocks), dim3(kBlock), 0, st, a);
@@ -568,16 +612,16 @@ __global__ __launch_bounds__(kBlock) void logmean_kernel(const double* alpha, lo
 }
 
 __global__ __launch_bounds__(kBlock) void gradmu_kernel(const double* alpha, long n, double eps,
-                                                        const double* sumlog, double* g) {
+                                                        const double* sumlog, const int* perm, double* g) {
   const long i = long(blockIdx.x) * kBlock + threadIdx.x;
-  if (i < n) g[i] = eps * (log_or_zero(alpha[i]) - *sumlog / double(n));
+  if (i < n) g[perm ? long(perm[i]) : i] = eps * (log_or_zero(alpha[i]) - *sumlog / double(n));
 }
 
 hipError_t launch_gradmu(const double* alpha, long n, double eps, double* partials, unsigned* counter,
-                         double* mean_out, double* grad_mu, hipStream_t st) {
+                         double* mean_out, double* grad_mu, hipStream_t st, const int* perm) {
   hipLaunchKernelGGL(logmean_kernel, dim3(256), dim3(kBlock), 0, st, alpha, n, partials, counter, mean_out);
   hipLaunchKernelGGL(gradmu_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, alpha, n, eps,
-                     (const double*)mean_out, grad_mu);
+                     (const double*)mean_out, perm, grad_mu);
   return hipGetLastError();
 }
 

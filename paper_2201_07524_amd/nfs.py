@@ -17,14 +17,14 @@ LIB_PATH = os.path.join(HERE, "lib", "libnfs.so")
 NFS_OK, NFS_EINVAL, NFS_EWEIGHTS, NFS_ENONPOS, NFS_EUNSUPPORTED, NFS_EHIP, NFS_EWORKSPACE = range(7)
 NFS_FP64, NFS_FP32, NFS_AUTO = 0, 1, 2
 NOALLOC_SCRATCH_BYTES = 64 << 20   # NFS_NOALLOC_SCRATCH_BYTES of include/nfs.h
-FLAG_NO_GRAPH, FLAG_PRIMAL_COST, FLAG_TILE_REDUCE, FLAG_LOG_DOMAIN, FLAG_AUTOTUNE = 1, 2, 4, 8, 16
+FLAG_NO_GRAPH, FLAG_PRIMAL_COST, FLAG_TILE_REDUCE, FLAG_LOG_DOMAIN, FLAG_AUTOTUNE, FLAG_CENTER = 1, 2, 4, 8, 16, 32
 
 EXPORTED = ("nfs_last_error", "nfs_validate", "nfs_workspace_size", "nfs_fastsum_apply",
             "nfs_fastsum_apply_noalloc",
             "nfs_nfft_adjoint", "nfs_nfft_trafo", "nfs_sinkhorn_solve", "nfs_sinkhorn_solve_log",
             "nfs_sinkhorn_grad", "nfs_sinkhorn_grad_targets", "nfs_plan_apply",
             "nfs_solver_create", "nfs_solver_iterate", "nfs_solver_residual", "nfs_solver_finish",
-            "nfs_solver_profile", "nfs_solver_destroy", "nfs_batch_workspace_size",
+            "nfs_solver_profile", "nfs_solver_grad", "nfs_solver_destroy", "nfs_batch_workspace_size",
             "nfs_batch_solver_create", "nfs_batch_solve", "nfs_divergence_workspace_size",
             "nfs_sinkhorn_divergence")
 
@@ -49,7 +49,8 @@ class _Result(ctypes.Structure):
                 ("marg_err_row", ctypes.c_double), ("marg_err_col", ctypes.c_double),
                 ("scale", ctypes.c_double), ("kernel_err", ctypes.c_double),
                 ("iters", ctypes.c_int32), ("precision_used", ctypes.c_int32),
-                ("n_nonpos", ctypes.c_int64), ("dyn_range", ctypes.c_double)]
+                ("n_nonpos", ctypes.c_int64), ("dyn_range", ctypes.c_double), ("centred", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 @dataclass
@@ -122,6 +123,8 @@ def load_library():
     lib.nfs_solver_finish.argtypes = [P, P, P, ctypes.POINTER(_Result), P]
     lib.nfs_solver_profile.restype = ctypes.c_int
     lib.nfs_solver_profile.argtypes = [P, ctypes.c_int32, P, P, P]
+    lib.nfs_solver_grad.restype = ctypes.c_int
+    lib.nfs_solver_grad.argtypes = [P, P, P, P, P, P]
     lib.nfs_solver_destroy.restype = ctypes.c_int
     lib.nfs_solver_destroy.argtypes = [P]
     PI64, PD = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
@@ -271,6 +274,7 @@ class SinkhornResult:
     precision_used: str = ""
     extra: dict = field(default_factory=dict)
     dyn_range: float = float("nan")   # max over half-steps of ||w||_1 / min t (see include/nfs.h)
+    centred: bool = False             # solved in the centred form (FLAG_CENTER)
 
 
 def sinkhorn(params, x, mu, y, nu, iters, tol=0.0, alpha_t0=None, workspace=None, check=True):
@@ -299,7 +303,8 @@ def sinkhorn(params, x, mu, y, nu, iters, tol=0.0, alpha_t0=None, workspace=None
         _check(rc)
     return SinkhornResult(alpha, alpha_t, res.cost, res.cost_upper, res.cost_primal, res.marg_err,
                           res.marg_err_row, res.marg_err_col, res.iters, res.n_nonpos, res.scale,
-                          res.kernel_err, _PREC_NAME.get(res.precision_used, ""), dyn_range=res.dyn_range)
+                          res.kernel_err, _PREC_NAME.get(res.precision_used, ""), dyn_range=res.dyn_range,
+                          centred=bool(res.centred))
 
 
 @dataclass
@@ -450,7 +455,21 @@ class Solver:
             _check(rc)
         return SinkhornResult(alpha, alpha_t, res.cost, res.cost_upper, res.cost_primal, res.marg_err,
                               res.marg_err_row, res.marg_err_col, res.iters, res.n_nonpos, res.scale,
-                              res.kernel_err, dyn_range=res.dyn_range)
+                              res.kernel_err, dyn_range=res.dyn_range, centred=bool(res.centred))
+
+    def grad(self, want_x=True, want_mu=True, want_y=False, want_nu=False):
+        """Envelope gradient at the current scalings on the solver's own plan
+        (nfs_solver_grad): (grad_x (n, d), grad_mu (n,), grad_y (nt, d),
+        grad_nu (nt,)), None where not wanted; batch solvers return the packed
+        arrays."""
+        dev, d = self.x.device, self.params.d
+        gx = torch.empty((self.n, d), dtype=torch.float64, device=dev) if want_x else None
+        gm = torch.empty(self.n, dtype=torch.float64, device=dev) if want_mu else None
+        gy = torch.empty((self.nt, d), dtype=torch.float64, device=dev) if want_y else None
+        gn = torch.empty(self.nt, dtype=torch.float64, device=dev) if want_nu else None
+        ptr = lambda t: t.data_ptr() if t is not None else None
+        _check(load_library().nfs_solver_grad(self.h, ptr(gx), ptr(gm), ptr(gy), ptr(gn), _stream()))
+        return gx, gm, gy, gn
 
     def profile(self, k):
         """Average device ms per launch of (spread, fft chain, interp+update, iteration, near field)
@@ -479,7 +498,7 @@ def _results(arr, alpha, alpha_t, offs_x, offs_y):
         out.append(SinkhornResult(alpha[offs_x[b]:offs_x[b + 1]], alpha_t[offs_y[b]:offs_y[b + 1]], r.cost,
                                   r.cost_upper, r.cost_primal, r.marg_err, r.marg_err_row, r.marg_err_col,
                                   r.iters, r.n_nonpos, r.scale, r.kernel_err, _PREC_NAME.get(r.precision_used, ""),
-                                  dyn_range=r.dyn_range))
+                                  dyn_range=r.dyn_range, centred=bool(r.centred)))
     return out
 
 
@@ -592,26 +611,46 @@ def sinkhorn_divergence(params, x, mu, y, nu, iters, tol=0.0, check=True):
 class SinkhornCost(torch.autograd.Function):
     """Sinkhorn cost s(x, mu; y, nu) with gradients w.r.t. x, mu, y and nu.
 
-    Forward runs the NFFT-accelerated Sinkhorn solve and saves the scalings;
-    backward evaluates the envelope gradient with the adjoint fast summation.
+    Forward runs the NFFT-accelerated Sinkhorn solve; backward evaluates the
+    envelope gradient with the adjoint fast summation.  With a fixed
+    iteration count and FP32 or FP64 grids the solve runs on a solver handle
+    that backward reuses (its plan, tables and scalings: no re-sort); with a
+    tolerance or NFS_AUTO the one-shot solve runs and backward plans again,
+    at the grid precision the solve ended with.
     """
 
     @staticmethod
     def forward(ctx, x, mu, y, nu, params, iters, tol=0.0):
-        res = sinkhorn(params, x.detach(), mu.detach(), y.detach(), nu.detach(), iters, tol)
-        ctx.save_for_backward(x.detach(), mu.detach(), y.detach(), nu.detach(), res.alpha, res.alpha_t)
         ctx.params = params
+        ctx.solver = None
+        if tol <= 0.0 and params.precision != "auto":
+            s = Solver(params, x.detach(), mu.detach(), y.detach(), nu.detach())
+            s.iterate(iters)
+            res = s.finish()
+            ctx.solver = s
+            ctx.save_for_backward(x.detach(), mu.detach(), y.detach(), nu.detach())
+        else:
+            res = sinkhorn(params, x.detach(), mu.detach(), y.detach(), nu.detach(), iters, tol)
+            ctx.save_for_backward(x.detach(), mu.detach(), y.detach(), nu.detach(), res.alpha, res.alpha_t)
+            if params.precision == "auto":
+                from dataclasses import replace
+                ctx.params = replace(params, precision=res.precision_used or "fp64")
         return torch.tensor(res.cost, dtype=torch.float64, device=x.device)
 
     @staticmethod
     def backward(ctx, grad_out):
-        x, mu, y, nu, a, at = ctx.saved_tensors
         need = ctx.needs_input_grad
         gx = gm = gy = gn = None
-        if need[0] or need[1]:
-            gx, gm = sinkhorn_grad(ctx.params, x, mu, y, nu, a, at, want_x=need[0], want_mu=need[1])
-        if need[2] or need[3]:
-            gy, gn = sinkhorn_grad_targets(ctx.params, x, mu, y, nu, a, at, want_y=need[2], want_nu=need[3])
+        if ctx.solver is not None:
+            gx, gm, gy, gn = ctx.solver.grad(need[0], need[1], need[2], need[3])
+            ctx.solver.close()
+            ctx.solver = None
+        else:
+            x, mu, y, nu, a, at = ctx.saved_tensors
+            if need[0] or need[1]:
+                gx, gm = sinkhorn_grad(ctx.params, x, mu, y, nu, a, at, want_x=need[0], want_mu=need[1])
+            if need[2] or need[3]:
+                gy, gn = sinkhorn_grad_targets(ctx.params, x, mu, y, nu, a, at, want_y=need[2], want_nu=need[3])
         g = grad_out.to(torch.float64)
         scale = lambda t: t * g if t is not None else None
         return scale(gx), scale(gm), scale(gy), scale(gn), None, None, None

@@ -1,5 +1,7 @@
-"""NFS_AUTO: FP32 grids, with every problem whose FP32 sums hit t <= 0 (the
-FP32 dynamic-range floor of fast summation) solved again with FP64 grids.
+"""NFS_AUTO: FP32 grids, with every problem whose FP32 sums hit t <= 0 or
+fell below 1e-5 of the l1 norm of their source weights (the FP32
+dynamic-range floor of fast summation, nfs_result.dyn_range > 1e5) solved
+again with FP64 grids.
 
 The failing shape is two well separated clusters (0.4 apart, eps 0.008 to
 0.0085): targets far from every source have kernel sums of 2e-9 to 7e-9 of
@@ -18,6 +20,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
+from oracle import sinkhorn_dense as sd
 from paper_2201_07524_amd import nfs
 
 pytestmark = pytest.mark.gpu
@@ -98,6 +101,7 @@ def test_batch_auto_promotes_only_the_failing_problems():
 
     r32 = batch("fp32")
     assert [r.n_nonpos > 0 for r in r32] == [False, True, False, True]
+    assert r32[0].dyn_range <= 1e5 and r32[2].dyn_range <= 1e5
     # batch members are independent: next to a diverging FP32 problem (huge or
     # negative scalings) the others end as their solo FP32 solves
     for b in (0, 2):
@@ -106,6 +110,12 @@ def test_batch_auto_promotes_only_the_failing_problems():
     assert [r.precision_used for r in ra] == ["fp32", "fp64", "fp32", "fp64"]
     for b in (0, 2):
         same(ra[b], r32[b], 1e-6, 1e-4)
+    # the promoted problems end on FP64 grids, in the centred form when their
+    # plain FP64 sums span more than 1e10 of their weights' l1 norm; either
+    # way the result is Algorithm 1's
     for b in (1, 3):
+        x, p, y, pt = probs[b]
+        ref = sd.solve(x, p, y, pt, 2, eps[b], 20)
         assert ra[b].n_nonpos == 0
-        same(ra[b], solve("fp64", probs[b], eps[b]), 1e-6, 1e-5)
+        assert abs(ra[b].cost - ref["cost"]) <= 1e-10 * abs(ref["cost"])
+        assert np.max(np.abs(ra[b].alpha.cpu().numpy() / ref["alpha"] - 1)) <= 1e-8

@@ -240,3 +240,4 @@ def test_sinkhorn_r1_3d_vs_oracle():
     K = sd.gibbs_kernel(x, y, 1, eps)
     e_row, e_col = sd.marginal_errors(K, a, res.alpha_t.cpu().numpy(), p, pt)
     assert e_row + e_col <= 10 * ref["marg_err"] + 1e-5 * np.linalg.norm(p)
+
