@@ -78,6 +78,28 @@ def measured_traffic(kernel):
         return None
 
 
+def measured_util(kernel):
+    """VALU and LDS busy fractions of `kernel` from the committed counter
+    summary (profiles/util_<kernel>_gmm2d_1e6_fp32.md: rocprofv3's VALUBusy
+    and LdsUtil derived metrics), or (None, None) when it is missing or the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"util_{kernel}_gmm2d_1e6_fp32.md")
+    if not os.path.exists(path):
+        return None, None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].strip().split(": ", 1)
+                vals[k.strip("`")] = v.strip().strip("`")
+    if vals.get("source_sha256") != source_digest():
+        return None, None
+    try:
+        return float(vals["valu_frac"]), float(vals["lds_frac"])
+    except (KeyError, ValueError):
+        return None, None
+
+
 def cpu_baseline(cfg, budget_rows=8192):
     """Oracle (FP64 matrix-free direct sums in C/OpenMP) timed on a bounded
     sample: one kernel product K v over all sources for `budget_rows` sampled
@@ -98,6 +120,42 @@ def cpu_baseline(cfg, budget_rows=8192):
     return dict(value=1.0 / sec_per_iter, unit="iter/s", cores=direct.num_threads(), kind="oracle",
                 sample=f"one FP64 kernel product on {len(rows)} sampled targets x {n} sources "
                        f"({dt:.1f} s), scaled to 2 full products per iteration")
+
+
+def plain_1d_leg(nfs, workloads, torch, T):
+    """The latency-bound workload: d = 1, n = nt = 2048 points uniform on
+    [-1/4, 1/4], eps = 0.05, N = 256, m = 8, FP64, its 200 iterations.  GPU:
+    plan and ms per iteration (graph replay).  CPU: the oracle's dense FP64
+    Algorithm 1 for the same 200 iterations, on all host cores and on one."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import sinkhorn_dense as sd
+    cfg = workloads.plain_1d()
+    prm = nfs.Params(d=1, eps=cfg["eps"], N=cfg["N"], m=cfg["m"], precision="fp64")
+    x, p, y, pt = T(cfg["x"]), T(cfg["p"]), T(cfg["y"]), T(cfg["pt"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = nfs.Solver(prm, x, p, y, pt)
+    torch.cuda.synchronize()
+    plan = time.perf_counter() - t0
+    s.iterate(5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.iterate(cfg["iters"])
+    torch.cuda.synchronize()
+    t_it = (time.perf_counter() - t0) / cfg["iters"]
+    s.close()
+    out = {"n": 2048, "iters": cfg["iters"], "plan_ms": plan * 1e3, "ms_per_iteration": t_it * 1e3,
+           "solve_ms": (plan + cfg["iters"] * t_it) * 1e3}
+    # all cores: the threads this process may use (the box's CPU share; OMP_NUM_THREADS when set)
+    all_threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    for name, threads in (("oracle_all_cores", all_threads), ("oracle_one_core", 1)):
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            sd.solve(cfg["x"], cfg["p"], cfg["y"], cfg["pt"], 2, cfg["eps"], cfg["iters"])
+            out[name + "_s"] = time.perf_counter() - t0
+    out["oracle_threads_all"] = all_threads
+    return out
 
 
 def batched_leg(nfs, workloads, torch, T, iters=10, sample_every=16):
@@ -288,7 +346,7 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-legs", action="store_true", help="skip the log-domain, batched, gradient, ball/shell and paper-shape legs")
-    ap.add_argument("--only-leg", choices=("batched", "gradient", "ball_shell", "paper_shapes"),
+    ap.add_argument("--only-leg", choices=("batched", "gradient", "ball_shell", "paper_shapes", "plain_1d"),
                     help="run one secondary leg alone and print its JSON (for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with one device copy of 256 MiB (calibrates HBM byte counters)")
@@ -306,7 +364,7 @@ def main():
         dev = torch.device("cuda:0")
         T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
         leg = {"batched": batched_leg, "gradient": grad_leg, "ball_shell": ball_shell_leg,
-               "paper_shapes": paper_shapes_leg}[args.only_leg]
+               "paper_shapes": paper_shapes_leg, "plain_1d": plain_1d_leg}[args.only_leg]
         print(json.dumps({args.only_leg: leg(nfs, workloads, torch, T)}), flush=True)
         return
 
@@ -378,11 +436,26 @@ def main():
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved[names[dom]],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved[names[dom]] / HBM_PEAK_GBS, "traffic": measured_traffic(names[dom]),
-                     "algorithmic_bytes": kernel_bytes(info, d, names[dom])},
+                     "algorithmic_bytes": kernel_bytes(info, d, names[dom]),
+                     "valu_frac": measured_util(names[dom])[0], "lds_frac": measured_util(names[dom])[1]},
     }
     solver.close()
     del solver
     if not args.no_legs:
+        log("bench: FP64-grid figure for the same workload")
+        from dataclasses import replace
+        s64 = nfs.Solver(replace(prm, precision="fp64"), x, p, y, pt)
+        s64.iterate(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s64.iterate(20)
+        torch.cuda.synchronize()
+        out["fp64_grids_ms_per_iteration"] = (time.perf_counter() - t0) / 20 * 1e3
+        s64.close()
+        del s64
+        log("bench: 1-D latency-bound leg")
+        out["plain_1d"] = plain_1d_leg(nfs, workloads, torch, T)
+        log("bench: plain 1-D " + json.dumps(out["plain_1d"]))
         log("bench: log-domain leg")
         out["log_domain"] = log_leg(nfs, prm, x, p, y, pt, torch)
         out["log_domain"]["over_scaling_iteration"] = out["log_domain"]["ms_per_iteration"] / ms_per_step

@@ -93,7 +93,7 @@ extern "C" {
 typedef struct nfs_params {
   int32_t d;          /* dimension, 1..3 */
   int32_t r;          /* cost exponent: 2 -> c = |x-y|^2; 1 -> c = |x-y| (near-field corrected,
-                         Remark 3.2; not for nfs_sinkhorn_grad, no primal cost) */
+                         Remark 3.2; no primal cost) */
   double eps;         /* temperature > 0; K = exp(-c/eps) (the paper's 1/lambda) */
   int32_t N;          /* bandwidth per dimension: I_N = {-N/2..N/2-1}^d, even, >= 4 */
   int32_t m;          /* window cutoff: 2m+1 grid taps per dimension, 2 <= m <= 8 */
@@ -257,8 +257,8 @@ int nfs_solver_profile(nfs_solver* s, int32_t iters, double* stage_ms, double* i
  * on the solver's own plan: no re-sort, no new tables.  grad_x (n x d),
  * grad_mu (n), grad_y (nt x d), grad_nu (nt), in the caller's point order
  * (for a batch solver, packed by problem, each problem's weight gradient
- * centred over that problem); any may be NULL.  r = 2 only; the log domain
- * and the centred form return NFS_EUNSUPPORTED.  The scalings are not
+ * centred over that problem); any may be NULL.  The log domain and the
+ * centred form return NFS_EUNSUPPORTED.  The scalings are not
  * changed, so iterate may continue afterwards. */
 int nfs_solver_grad(nfs_solver* s, double* grad_x, double* grad_mu, double* grad_y, double* grad_nu, void* stream);
 int nfs_solver_destroy(nfs_solver* s);
@@ -307,8 +307,11 @@ int nfs_sinkhorn_divergence(const nfs_params* prm, const double* x, int64_t n, c
  * envelope theorem applied to the dual (Proposition 2.3, eq. (14)):
  *   grad_x[i]  = sum_j pi_ij grad_x c(x_i, y_j) = -eps alpha_i (grad K * alpha_t)(x_i)   (n x d)
  *   grad_mu[i] = eps log alpha_i - mean_k(eps log alpha_k)                               (n)
- * with the kernel gradient summed by fast summation (coefficients 2 pi i k b_k).
- * Either output may be NULL.
+ * with the kernel gradient summed by fast summation (coefficients 2 pi i k b_k
+ * of the regularized kernel); for r = 1 (grad_x c = (x - y)/|x - y|, zero
+ * where points coincide) the gradient of the near-field correction K - K_R is
+ * added by direct sums over the pairs closer than eps_I.  Either output may
+ * be NULL.
  */
 int nfs_sinkhorn_grad(const nfs_params* prm, const double* x, int64_t n, const double* mu,
                       const double* y, int64_t nt, const double* nu,
@@ -321,8 +324,8 @@ int nfs_sinkhorn_grad(const nfs_params* prm, const double* x, int64_t n, const d
  * computation above with the roles of the two clouds exchanged):
  *   grad_y[j]  = sum_i pi_ij grad_y c(x_i, y_j) = -eps alpha_t_j (grad K * alpha)(y_j)   (nt x d)
  *   grad_nu[j] = eps log alpha_t_j - mean_k(eps log alpha_t_k)                            (nt)
- * Same arguments, workspace size and errors as nfs_sinkhorn_grad (r = 2
- * only).  Either output may be NULL.
+ * Same arguments, workspace size and errors as nfs_sinkhorn_grad.  Either
+ * output may be NULL.
  */
 int nfs_sinkhorn_grad_targets(const nfs_params* prm, const double* x, int64_t n, const double* mu,
                               const double* y, int64_t nt, const double* nu,

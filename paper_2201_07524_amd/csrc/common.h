@@ -78,6 +78,19 @@ struct Geom {
   int nt[3];    // tiles per dimension (nt[c] = ceil(g / T)), unused dims = 1
 };
 
+// Workgroups are dealt to the 8 XCDs round robin (workgroup b runs on XCD
+// b mod 8), each XCD with its own L2.  xcd_block numbers the work items of a
+// launch of G workgroups so that each XCD takes one contiguous block of them
+// (the first G mod 8 blocks one longer): workgroup b gets item
+// block(b mod 8) + b / 8.  Neighbouring items (adjacent pencils of a strided
+// FFT pass, chunks of adjacent tiles) then share lines in one L2 instead of
+// each XCD fetching every line.
+constexpr int kXcds = 8;
+__device__ __forceinline__ long xcd_block(long b, long G) {
+  const long x = b % kXcds, k = b / kXcds, q = G / kXcds, r = G % kXcds;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 // A chunk is a run of at most `chunk` sorted points of one problem that share
 // one tile of that problem's grid.
 struct Chunk {

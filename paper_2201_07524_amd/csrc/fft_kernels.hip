@@ -408,7 +408,9 @@ __global__ __launch_bounds__(kBlock) void axis_kernel(AxisArgs<R> a) {
   cplx<R>* tlds = B + P * L;
   TwiddleStage<R> tws;
   if (a.tw_lds) tws.start(a.tw, L);
-  const long q0 = long(blockIdx.x) * P;
+  // pencils numbered per XCD: a strided line holds 16 adjacent pencils' values,
+  // which then come from one XCD's L2
+  const long q0 = xcd_block(blockIdx.x, gridDim.x) * P;
   const int half = a.N / 2;
   const int pshift = ilog2(P);
   const int lshift = ilog2(L);

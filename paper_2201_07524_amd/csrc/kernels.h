@@ -154,12 +154,17 @@ struct NearArgs {
   int kt;
   int ps;               // polynomial terms p
   double* out;
+  long out_plane;       // gradient: entries between the components of out
   const int* pstate;    // nullable: targets of problems in state 2 are skipped
   const int* scell;     // nullable: per source tile the cell starts (TileSortArgs::cellstart);
                         // with it only the source cells within eps_I of each wave's targets are read
 };
 template <typename R>
 hipError_t launch_nearfield(const NearArgs<R>& a, int nchunks, hipStream_t st);
+// Gradient of the same near-field sum at the targets, d components in torus
+// units: out[c * out_plane + q] (q in sorted target order).
+template <typename R>
+hipError_t launch_nearfield_grad(const NearArgs<R>& a, int nchunks, hipStream_t st);
 
 template <typename R>
 hipError_t launch_spread(const SpreadArgs<R>& a, int nchunks, hipStream_t st);
@@ -303,10 +308,10 @@ struct TileSortArgs {
   const int* offsets;   // B x nbins first position of each tile
   int ntiles;           // B x nbins
   int d, T;
-  const R* in_coords;   // staging, n x d
-  const int* in_perm;
-  const double* in_w0;  // nullable
-  const double* in_w1;  // nullable
+  R* in_coords;         // staging, n x d (also the scratch of the in-cell ordering)
+  int* in_perm;
+  double* in_w0;        // nullable
+  double* in_w1;        // nullable
   R* coords;
   int* perm;
   double* w0s;          // nullable

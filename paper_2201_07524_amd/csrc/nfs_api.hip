@@ -72,6 +72,15 @@ static int default_chunk(const nfs_params* p) {
   return 1024;
 }
 
+// Near-field radius (times N) and smoothness of the r = 1 regularization by
+// default: eps_I N = 4, p = 8.  A sweep of eps_I N in {2, ..., 4} x p in
+// {4, ..., 12} (ball/shell, eps = 0.02, N = 128) shows the near field's cost
+// falling as eps_I^3 (47 ms per half-step at 4e6 points down to 11 ms at
+// eps_I N = 2), but the fast sums' error over all targets rising from 5e-6
+// at (4, 8) to 1.5e-4 at (2, 4): smaller radii miss the FP32 bar.
+static double default_eps_I(const nfs_params*) { return 4.0; }
+static int default_p_smooth(const nfs_params*) { return 8; }
+
 static int check_params(const nfs_params* p, int64_t n, int64_t nt) {
   if (!p) return fail(NFS_EINVAL, "params is NULL");
   if (p->d < 1 || p->d > 3) return fail(NFS_EINVAL, "d must be 1, 2 or 3");
@@ -95,8 +104,8 @@ static int check_params(const nfs_params* p, int64_t n, int64_t nt) {
   const double tb = std::pow(double(E), p->d) * (p->precision == NFS_FP32 ? 4.0 : 8.0);
   if (tb > 160.0 * 1024.0) return fail(NFS_EINVAL, "LDS tile (tile + 2m + 1)^d exceeds 160 KiB; use a smaller tile");
   if (p->r == 1) {
-    const double eIN = p->eps_I > 0.0 ? p->eps_I : 4.0;
-    const int ps = p->p_smooth ? p->p_smooth : 8;
+    const double eIN = p->eps_I > 0.0 ? p->eps_I : default_eps_I(p);
+    const int ps = p->p_smooth ? p->p_smooth : default_p_smooth(p);
     if (!(eIN > 0.0) || eIN > 0.25 * p->N) return fail(NFS_EINVAL, "eps_I (near-field radius times N) must be in (0, N/4]");
     if (ps < 2 || ps > 16) return fail(NFS_EINVAL, "p_smooth must be in [2, 16]");
     if (p->chunk > 1024) return fail(NFS_EINVAL, "r = 1 needs chunk <= 1024");
@@ -111,8 +120,8 @@ static int check_params(const nfs_params* p, int64_t n, int64_t nt) {
 constexpr int kBoxSlot = 2 * kBoxVals;
 
 // Near-field radius on the torus and smoothness for r = 1.
-static double near_radius(const nfs_params* p) { return (p->eps_I > 0.0 ? p->eps_I : 4.0) / p->N; }
-static int near_smooth(const nfs_params* p) { return p->p_smooth ? p->p_smooth : 8; }
+static double near_radius(const nfs_params* p) { return (p->eps_I > 0.0 ? p->eps_I : default_eps_I(p)) / p->N; }
+static int near_smooth(const nfs_params* p) { return p->p_smooth ? p->p_smooth : default_p_smooth(p); }
 
 // ----------------------------------------------------------------------------- workspace layout
 struct Carver {
@@ -801,6 +810,30 @@ static hipError_t near_field(Work<R>& w, const CloudBuf<R>& src, const CloudBuf<
   a.pstate = pstate;
   a.scell = src.cellstart;
   return launch_nearfield(a, tgt.nchunks, st);
+}
+
+// Gradient of the near-field correction (r = 1) of the product with sources
+// `src` at the targets `tgt`: d components in torus units, component c at
+// out + c * tgt.n (sorted target order, normalized like the spread).
+template <typename R>
+static hipError_t near_field_grad(Work<R>& w, const CloudBuf<R>& src, const CloudBuf<R>& tgt, const double* weights,
+                                  const double* wmul, double wconst, double* out, hipStream_t st) {
+  NearArgs<R> a{};
+  a.geo = w.geo;
+  a.tcoords = tgt.coords;
+  a.tchunks = tgt.chunks;
+  a.scoords = src.coords;
+  a.sw = weights;
+  a.soffsets = src.offsets;
+  a.scounts = src.counts;
+  a.wmul = wmul;
+  a.wconst = wconst;
+  a.coef = w.nfcoef;
+  a.kt = w.kt;
+  a.ps = w.ps;
+  a.out = out;
+  a.out_plane = tgt.n;
+  return launch_nearfield_grad(a, tgt.nchunks, st);
 }
 
 // One Sinkhorn half-step for every problem: spread the scalings of `src`,
@@ -1529,7 +1562,6 @@ struct Solver : SolverBase {
   // clouds exchanged (the kernel is even).  grad_mu = eps log alpha minus its
   // mean over the problem.  Outputs in the caller's (packed) point order.
   int grad(double* gx, double* gmu, double* gy, double* gnu, hipStream_t caller) override {
-    if (p.r != 2) return fail(NFS_EUNSUPPORTED, "the gradient is implemented for r = 2");
     if (logd || centred) return fail(NFS_EUNSUPPORTED, "the solver gradient needs the scaling form, uncentred");
     NFS_TRY(enter(caller));
     hipStream_t st = gs;
@@ -1547,9 +1579,11 @@ struct Solver : SolverBase {
       if (out) {
         NFS_HIP(launch_mul(wm, w.gfac + B, B, w.gfac, st));
         NFS_HIP(spread(w, src, src.w1s, wm, 1.0, st));
+        if (w.r == 1) NFS_HIP(near_field_grad(w, src, tgt, src.w1s, wm, 1.0, w.tmp, st));
         for (int c = 0; c < d; ++c) {
           NFS_HIP(fft_chain(w, w.dtab, c, st, c + 1 < d));
           InterpArgs<R> ia = interp_args(w, tgt, EPI_OUT, w.gfac);
+          if (w.r == 1) ia.nf = w.tmp + size_t(c) * tgt.n;
           ia.scale_vec = tgt.w1s;
           ia.out = out;
           ia.out_stride = d;
@@ -1767,9 +1801,12 @@ static int do_grad(const nfs_params* p, const double* x, int64_t n, const double
     // alpha_t is spread once; each derivative axis applies (2 pi i k_c) b_k / Phi^2
     // to its transform and interpolates at x (the last pass clears the grid).
     NFS_HIP(spread(w, w.Y, w.Y.w1s, nullptr, 1.0 / wmax, st));
+    // r = 1: the gradient of the near-field correction K - K_R, added to each axis
+    if (w.r == 1) NFS_HIP(near_field_grad(w, w.Y, w.X, w.Y.w1s, nullptr, 1.0 / wmax, w.tmp, st));
     for (int c = 0; c < p->d; ++c) {
       NFS_HIP(fft_chain(w, w.dtab, c, st, c + 1 < p->d));
       InterpArgs<R> ia = interp_args(w, w.X, EPI_OUT, nullptr);
+      if (w.r == 1) ia.nf = w.tmp + size_t(c) * w.X.n;
       // grad_x_i = -eps alpha_i s (dK'/dx'_c * alpha_t)(x'_i), x' = s (x - center)
       ia.norm = -p->eps * w.sc[0].scale * wmax;
       ia.scale_vec = w.X.w1s;
@@ -2296,7 +2333,6 @@ int nfs_sinkhorn_grad(const nfs_params* prm, const double* x, int64_t n, const d
                       double* grad_mu, void* workspace, size_t ws_bytes, void* stream) {
   g_err.clear();
   NFS_TRY(check_params(prm, n, nt));
-  if (prm->r != 2) return fail(NFS_EUNSUPPORTED, "the gradient is implemented for r = 2");
   if (!x || !mu || !y || !nu || !alpha || !alpha_t || !workspace) return fail(NFS_EINVAL, "NULL pointer argument");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (prm->precision == NFS_FP32)
@@ -2309,7 +2345,6 @@ int nfs_sinkhorn_grad_targets(const nfs_params* prm, const double* x, int64_t n,
                               double* grad_y, double* grad_nu, void* workspace, size_t ws_bytes, void* stream) {
   g_err.clear();
   NFS_TRY(check_params(prm, n, nt));
-  if (prm->r != 2) return fail(NFS_EUNSUPPORTED, "the gradient is implemented for r = 2");
   if (!x || !mu || !y || !nu || !alpha || !alpha_t || !workspace) return fail(NFS_EINVAL, "NULL pointer argument");
   hipStream_t st = static_cast<hipStream_t>(stream);
   // the kernel is even: the target-side gradient is the source-side one with the roles swapped

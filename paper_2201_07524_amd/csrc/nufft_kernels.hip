@@ -365,7 +365,8 @@ __global__ __launch_bounds__(spread_block(D)) void spread_kernel(SpreadArgs<R> a
   const int E = geo.E;
   const int ncell = D == 1 ? E : (D == 2 ? E * E : E * E * E);
   Acc<R, ACC> tile(smem_raw, ncell);
-  const Chunk ch = a.chunks[blockIdx.x];
+  const int cb = blockIdx.x;
+  const Chunk ch = a.chunks[cb];
   if (a.pstate && a.pstate[kPState * ch.prob] == 2) return;  // the problem has stopped
 
   // the part store (per-tile reduction) needs the whole tile
@@ -384,7 +385,7 @@ __global__ __launch_bounds__(spread_block(D)) void spread_kernel(SpreadArgs<R> a
     // same-cell pairs of runs on adjacent lanes, 32 pairs per wave row,
     // spread over the chunk like the runs below
     const int* sr = a.srun + ch.start;
-    const int nqe = a.nsrun[3 * blockIdx.x], npe = a.nsrun[3 * blockIdx.x + 1], nsolo = a.nsrun[3 * blockIdx.x + 2];
+    const int nqe = a.nsrun[3 * cb], npe = a.nsrun[3 * cb + 1], nsolo = a.nsrun[3 * cb + 2];
     // groups of GROUP same-cell runs on aligned lanes, kWave / GROUP groups per wave row,
     // spread over the chunk like single runs
     auto grouped = [&](auto group_tag, const int* tab, int ngroups) {
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(spread_block(D)) void spread_kernel(SpreadArgs<R> a
     }
   } else {
     const int* runs = a.runs + ch.start;
-    const int nfull = a.nruns[2 * blockIdx.x], nsingle = a.nruns[2 * blockIdx.x + 1];
+    const int nfull = a.nruns[2 * cb], nsingle = a.nruns[2 * cb + 1];
     int rows = (nfull + kWave - 1) / kWave;
     for (int slot = threadIdx.x; slot < rows * kWave; slot += BS) {
       const int rr = run_of_slot(slot, rows);
@@ -426,7 +427,7 @@ __global__ __launch_bounds__(spread_block(D)) void spread_kernel(SpreadArgs<R> a
   __syncthreads();
 
   if (a.part) {
-    R* dst = a.part + size_t(blockIdx.x) * ncell;
+    R* dst = a.part + size_t(cb) * ncell;
     for (int i = threadIdx.x; i < ncell; i += BS) dst[i] = tile.get(i);
     return;
   }
@@ -689,6 +690,110 @@ __global__ __launch_bounds__(kBlock) void nearfield_kernel(NearArgs<R> a) {
   for (int k = 0; k < kNearTPT; ++k) {
     const int q = ch.start + threadIdx.x + k * kBlock;
     if (q < ch.start + ch.count) a.out[q] = double(acc[k]);
+  }
+}
+
+// Gradient of the near-field sum at the targets (r = 1): for every target,
+//   out[c * plane + q] = sum_{sources j within eps_I} w_j wm d/dx'_c (K - K_R)(x'_q - y'_j),
+// the derivative in torus units (x' = g x_cells).  With z the target-source
+// offset in cells, r = |z| and rho = r^2 / eps_I^2 (cells),
+//   grad (K - K_R) = -g [inv_e e^{-r inv_e} / r + 2 inv_ei2 sum_{j>=1} j c_j rho^{j-1}] z,
+// the first term taken as 0 at r = 0 (the cost's gradient is zero where the
+// points coincide).  Same tiling as nearfield_kernel.
+template <typename R, int D, int PS>
+__global__ __launch_bounds__(kBlock) void nearfield_grad_kernel(NearArgs<R> a) {
+  __shared__ R su[D][kBlock];
+  __shared__ R sw[kBlock];
+  const Geom geo = a.geo;
+  const Chunk ch = a.tchunks[blockIdx.x];
+  const int pb = ch.prob;
+  const int nbins = geo.nt[0] * geo.nt[1] * geo.nt[2];
+  const double* cf = a.coef + size_t(pb) * kNearStride;
+  const R inv_e = R(cf[0]), ei2 = R(cf[1]), inv_ei2 = R(cf[2]);
+  // derivative coefficients j c_j of the inner polynomial, in rho
+  R dc[PS > 1 ? PS - 1 : 1];
+#pragma unroll
+  for (int j = 1; j < PS; ++j) dc[j - 1] = R(double(j) * cf[4 + j]);
+  const double wm = a.wconst * (a.wmul ? a.wmul[pb] : 1.0);
+
+  int tc[3] = {0, 0, 0};
+  {
+    int t = ch.tile;
+    for (int k = D - 1; k >= 0; --k) {
+      tc[k] = t % geo.nt[k];
+      t /= geo.nt[k];
+    }
+  }
+  R ut[kNearTPT][D];
+  R acc[kNearTPT][D];
+#pragma unroll
+  for (int k = 0; k < kNearTPT; ++k) {
+    const int q = ch.start + threadIdx.x + k * kBlock;
+#pragma unroll
+    for (int cc = 0; cc < D; ++cc) {
+      acc[k][cc] = R(0);
+      ut[k][cc] = (q < ch.start + ch.count) ? a.tcoords[size_t(q) * D + cc] : R(1e30);
+    }
+  }
+  const int span = 2 * a.kt + 1;
+  int nnb = 1;
+  for (int k = 0; k < D; ++k) nnb *= span;
+  for (int nbi = 0; nbi < nnb; ++nbi) {
+    int rem = nbi, tile = 0;
+    R shift[3] = {R(0), R(0), R(0)};
+    for (int k = 0; k < D; ++k) {
+      const int dl = rem % span - a.kt;
+      rem /= span;
+      int t = tc[k] + dl;
+      t = ((t % geo.nt[k]) + geo.nt[k]) % geo.nt[k];
+      tile = tile * geo.nt[k] + t;
+      shift[k] = R(dl * geo.T);
+    }
+    const int so = a.soffsets[size_t(pb) * nbins + tile];
+    const int sc = a.scounts[size_t(pb) * nbins + tile];
+    for (int s0 = 0; s0 < sc; s0 += kBlock) {
+      const int nb = min(kBlock, sc - s0);
+      __syncthreads();
+      if (threadIdx.x < nb) {
+        const int j = so + s0 + threadIdx.x;
+#pragma unroll
+        for (int cc = 0; cc < D; ++cc) su[cc][threadIdx.x] = a.scoords[size_t(j) * D + cc] + shift[cc];
+        sw[threadIdx.x] = R(a.sw[j] * wm);
+      }
+      __syncthreads();
+      for (int j = 0; j < nb; ++j) {
+        const R wj = sw[j];
+#pragma unroll
+        for (int k = 0; k < kNearTPT; ++k) {
+          R z[D];
+          R r2 = R(0);
+#pragma unroll
+          for (int cc = 0; cc < D; ++cc) {
+            z[cc] = ut[k][cc] - su[cc][j];
+            r2 += z[cc] * z[cc];
+          }
+          if (r2 < ei2) {
+            const R rho = r2 * inv_ei2;
+            R dP = PS > 1 ? dc[PS - 2] : R(0);
+#pragma unroll
+            for (int jj = PS - 3; jj >= 0; --jj) dP = dP * rho + dc[jj];
+            const R r = sqrt(r2);
+            const R ek = r > R(0) ? inv_e * exp(-r * inv_e) / r : R(0);
+            const R h = wj * (ek + R(2) * inv_ei2 * dP);
+#pragma unroll
+            for (int cc = 0; cc < D; ++cc) acc[k][cc] += h * z[cc];
+          }
+        }
+      }
+    }
+  }
+  const R ng = -R(geo.g);
+#pragma unroll
+  for (int k = 0; k < kNearTPT; ++k) {
+    const int q = ch.start + threadIdx.x + k * kBlock;
+    if (q < ch.start + ch.count)
+#pragma unroll
+      for (int cc = 0; cc < D; ++cc) a.out[size_t(cc) * a.out_plane + q] = double(ng * acc[k][cc]);
   }
 }
 
@@ -957,6 +1062,21 @@ hipError_t launch_nearfield(const NearArgs<R>& a, int nchunks, hipStream_t st) {
 template hipError_t launch_nearfield<float>(const NearArgs<float>&, int, hipStream_t);
 template hipError_t launch_nearfield<double>(const NearArgs<double>&, int, hipStream_t);
 
+template <typename R>
+hipError_t launch_nearfield_grad(const NearArgs<R>& a, int nchunks, hipStream_t st) {
+  if (nchunks <= 0) return hipSuccess;
+  if (a.geo.d == 1) {
+    NFS_NEAR_P(nearfield_grad_kernel, 1)
+  } else if (a.geo.d == 2) {
+    NFS_NEAR_P(nearfield_grad_kernel, 2)
+  } else {
+    NFS_NEAR_P(nearfield_grad_kernel, 3)
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_nearfield_grad<float>(const NearArgs<float>&, int, hipStream_t);
+template hipError_t launch_nearfield_grad<double>(const NearArgs<double>&, int, hipStream_t);
+
 // --------------------------------------------------------------------------- block reduction
 // Per-target quantities of a half-step, reduced over the problem's targets.
 struct Red {
@@ -1009,10 +1129,10 @@ __device__ Red block_reduce(Red v, Red* sh) {
 // problem's stop state (kPState).
 __device__ void finish_reduce(Red mine, Red* sh, double* partials, unsigned* counter, double* stats,
                               double* wmul_next, const double* src_l1, int* pstate, const double* tol2, int half,
-                              int c0, int c1, bool logd) {
+                              int c0, int c1, bool logd, int chunk) {
   __shared__ bool last;
   if (threadIdx.x == 0) {
-    double* pw = partials + kRedVals * size_t(blockIdx.x);
+    double* pw = partials + kRedVals * size_t(chunk);
     pw[0] = mine.res2;
     pw[1] = mine.mass;
     pw[2] = mine.l1;
@@ -1169,7 +1289,8 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
   const int E = geo.E;
   const int g = geo.g;
   const int ncell = D == 1 ? E : (D == 2 ? E * E : E * E * E);
-  const Chunk ch = a.chunks[blockIdx.x];
+  const int cb = blockIdx.x;
+  const Chunk ch = a.chunks[cb];
   if (a.pstate && a.pstate[kPState * ch.prob] == 2) return;  // the problem has stopped
 
   int org[3] = {0, 0, 0};
@@ -1279,7 +1400,7 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
   constexpr int GI = kInterpRun < G ? kInterpRun : G;  // points per interpolation run, divides G
   constexpr int SUB = G / GI;
   const int* runs = a.runs + ch.start;
-  const int nfull = a.nruns[2 * blockIdx.x], nsingle = a.nruns[2 * blockIdx.x + 1];
+  const int nfull = a.nruns[2 * cb], nsingle = a.nruns[2 * cb + 1];
   for (int rr = threadIdx.x; rr < nfull * SUB; rr += kBlock) {
     const int q0 = ch.start + runs[rr / SUB] + (rr % SUB) * GI;
     double nfq[GI];
@@ -1303,7 +1424,7 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
     finish_reduce(r, red_sh, a.partials, a.counter + pb, a.stats + kStat * pb,
                   a.wmul_next ? a.wmul_next + pb : nullptr, a.src_l1 ? a.src_l1 + kStat * pb : nullptr,
                   a.pstate ? a.pstate + kPState * pb : nullptr, a.tol2, a.half, a.prob_chunks[pb],
-                  a.prob_chunks[pb + 1], logd);
+                  a.prob_chunks[pb + 1], logd, cb);
   }
 }
 

@@ -334,11 +334,14 @@ __device__ int scan_bins(int* hist, int nc, int* part) {
 }
 
 // One workgroup per (problem, tile): LDS histogram of the tile's points over
-// its T^d cells, exclusive scan, then each point goes to its cell's next slot.
-// The order inside a cell is arbitrary.
+// its T^d cells, exclusive scan, then each point goes to its cell's next slot,
+// and the points of each cell are put in the order of their input index.
+constexpr int kCanonCell = 1024;
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void tile_sort_kernel(TileSortArgs<R> a) {
   __shared__ int slot[kSortBins];
+  __shared__ int first[kSortBins];
   __shared__ int part[kBlock];
   const int cnt = a.counts[blockIdx.x];
   const int d = a.d, T = a.T;
@@ -360,6 +363,7 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(TileSortArgs<R> a) {
     for (int i = threadIdx.x; i < nc; i += kBlock) cs[i] = slot[i];
     if (threadIdx.x == 0) cs[nc] = cnt;
   }
+  for (int i = threadIdx.x; i < nc; i += kBlock) first[i] = slot[i];
   __syncthreads();
   for (int i = threadIdx.x; i < cnt; i += kBlock) {
     const size_t q = off + i;
@@ -368,6 +372,39 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(TileSortArgs<R> a) {
     a.perm[pos] = a.in_perm[q];
     if (a.w0s) a.w0s[pos] = a.in_w0[q];
     if (a.w1s) a.w1s[pos] = a.in_w1[q];
+  }
+  // Canonical order inside each cell: by the points' input index.  The
+  // scatter and the placement above leave a cell's points in the order their
+  // atomics happened to run; ranking them by input index makes the sorted
+  // clouds, hence every sum over them, the same from run to run.  The ranks
+  // go through the staging arrays (free now), then back.  Cells of more than
+  // kCanonCell points keep their placement order.
+  __threadfence_block();
+  __syncthreads();
+  for (int i = threadIdx.x; i < cnt; i += kBlock) {
+    const size_t q = off + i;
+    const int cell = cell_key_at(a.coords, q, d, T);
+    const int c0 = first[cell], c1 = slot[cell];
+    const int pq = a.perm[q];
+    int rank = i - c0;
+    if (c1 - c0 <= kCanonCell) {
+      rank = 0;
+      for (int e = c0; e < c1; ++e) rank += a.perm[off + e] < pq ? 1 : 0;
+    }
+    const size_t dst = off + c0 + rank;
+    for (int c = 0; c < d; ++c) a.in_coords[dst * d + c] = a.coords[q * d + c];
+    a.in_perm[dst] = pq;
+    if (a.w0s) a.in_w0[dst] = a.w0s[q];
+    if (a.w1s) a.in_w1[dst] = a.w1s[q];
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (int i = threadIdx.x; i < cnt; i += kBlock) {
+    const size_t q = off + i;
+    for (int c = 0; c < d; ++c) a.coords[q * d + c] = a.in_coords[q * d + c];
+    a.perm[q] = a.in_perm[q];
+    if (a.w0s) a.w0s[q] = a.in_w0[q];
+    if (a.w1s) a.w1s[q] = a.in_w1[q];
   }
 }
 

@@ -241,3 +241,24 @@ def test_sinkhorn_r1_3d_vs_oracle():
     e_row, e_col = sd.marginal_errors(K, a, res.alpha_t.cpu().numpy(), p, pt)
     assert e_row + e_col <= 10 * ref["marg_err"] + 1e-5 * np.linalg.norm(p)
 
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_repeated_solves_are_bit_identical(prec):
+    """The plan puts the points of each cell in the order of their input
+    index, the spread grid holds exact integer sums of the LDS tiles'
+    fixed-point words, and every reduction runs in a fixed order, so a solve
+    does not depend on the order in which workgroups or atomics run: two runs
+    agree bit for bit (single problem and batch)."""
+    cfg = workloads.subsample(workloads.gmm_2d(20000), 5000, seed=21)
+    prm = nfs.Params(d=2, eps=0.01, N=256, m=8, precision=prec)
+    runs = [nfs.sinkhorn(prm, T(cfg["x"]), T(cfg["p"]), T(cfg["y"]), T(cfg["pt"]), 30) for _ in range(2)]
+    assert runs[0].cost == runs[1].cost and runs[0].marg_err == runs[1].marg_err
+    assert torch.equal(runs[0].alpha, runs[1].alpha) and torch.equal(runs[0].alpha_t, runs[1].alpha_t)
+    probs = [workloads.subsample(workloads.gmm_2d(8000), n, seed=30 + n) for n in (900, 2500, 400)]
+    bprm = nfs.Params(d=2, eps=1.0, N=128, m=8, precision=prec)
+    b = [nfs.batch_sinkhorn(bprm, [T(q["x"]) for q in probs], [T(q["p"]) for q in probs],
+                            [T(q["y"]) for q in probs], [T(q["pt"]) for q in probs], [0.02, 0.03, 0.05], 25)
+         for _ in range(2)]
+    for r0, r1 in zip(*b):
+        assert r0.cost == r1.cost and torch.equal(r0.alpha, r1.alpha) and torch.equal(r0.alpha_t, r1.alpha_t)
