@@ -97,7 +97,7 @@ typedef struct nfs_params {
   double eps;         /* temperature > 0; K = exp(-c/eps) (the paper's 1/lambda) */
   int32_t N;          /* bandwidth per dimension: I_N = {-N/2..N/2-1}^d, even, >= 4 */
   int32_t m;          /* window cutoff: 2m+1 grid taps per dimension, 2 <= m <= 8 */
-  double sigma;       /* oversampling: grid g = sigma*N rounded up to even, g >= N + 2 */
+  double sigma;       /* oversampling: grid g = sigma*N rounded up to a power of two, g >= N + 2 */
   int32_t precision;  /* NFS_FP64, NFS_FP32, or NFS_AUTO (solve calls only) */
   int32_t tile;       /* grid cells per bin side (0 = default for d) */
   int32_t chunk;      /* max points per workgroup chunk, 0..32768 (0 = default: for r = 2, 1536
