@@ -13,7 +13,15 @@
 //                  (the diagonal of eq. (fastsum) applied in LDS, so the
 //                  spectrum never goes back to HBM).
 // Each pencil of length L = 2^p is transformed by radix-4 Stockham passes plus
-// one radix-2 pass when p is odd, ping-ponging between two LDS buffers.
+// one radix-2 pass when p is odd, ping-ponging between two LDS buffers.  Both
+// kernels are compiled once per p (2..12): with L, the pencils per workgroup
+// and every pass's stride and twiddle offset known at compile time, a pass is
+// a few dozen instructions with no integer multiply or divide, which is what
+// bounds these latency-bound passes (one wave per SIMD, one pass after the
+// other).  Twiddles come from per-pass tables (fft_pass_bits) whose entries
+// the lanes of a wave read contiguously.
+#pragma once
+
 #include "common.h"
 #include "kernels.h"
 
@@ -77,72 +85,78 @@ struct TwiddleStage {
   }
 };
 
-// One complete FFT of P pencils (each L contiguous complex values) held in
-// buffer `A`; `B` is scratch of the same size.  Returns the buffer holding the
-// result.  Forward uses exp(-2 pi i jk/L), inverse exp(+2 pi i jk/L), both
-// unnormalized.  Must be called by all threads of the block.
-template <typename R>
-__device__ __forceinline__ cplx<R>* stockham(cplx<R>* A, cplx<R>* B, int L, int P, const cplx<R>* tw,
-                                             bool inverse) {
-  const int log2L = ilog2(L);
+// One complete FFT of P pencils (each L = 2^LG contiguous complex values) held
+// in buffer `A`; `B` is scratch of the same size.  Returns the buffer holding
+// the result.  Forward uses exp(-2 pi i jk/L), inverse exp(+2 pi i jk/L), both
+// unnormalized.  Pass s (Ns = 4^s) takes butterfly j (k = j mod Ns) from
+// entries j + m L/4, multiplies entry m by e^(-+2 pi i m k/(4 Ns)) (the pass
+// table's entry (m - 1) Ns + k), and writes output m to (j - k) 4 + k + m Ns;
+// an odd LG ends with the radix-2 pass at Ns = L/2.  Must be called by all
+// threads of the block.
+template <typename R, int LG, int P>
+__device__ __forceinline__ cplx<R>* stockham(cplx<R>* A, cplx<R>* B, const cplx<R>* tw, bool inverse) {
+  constexpr int L = 1 << LG;
+  constexpr int Q = L >> 2;
   cplx<R>* src = A;
   cplx<R>* dst = B;
-  int Ns = 1;
-  int rem = log2L;
-  const int Q = L >> 2;
-  const int qshift = log2L - 2;
-  while (rem >= 2) {
-    const int step = L / (4 * Ns);
-    for (int b = threadIdx.x; b < P * Q; b += kBlock) {
-      const int p = b >> qshift;
-      const int j = b & (Q - 1);
-      const int k = j & (Ns - 1);
-      const cplx<R>* s = src + p * L;
-      cplx<R> a0 = s[j], a1 = s[j + Q], a2 = s[j + 2 * Q], a3 = s[j + 3 * Q];
-      if (Ns > 1) {
-        const int i1 = k * step;
-        cplx<R> w1 = tw[i1], w2 = tw[2 * i1], w3 = tw[3 * i1];
-        if (inverse) {
-          w1.y = -w1.y;
-          w2.y = -w2.y;
-          w3.y = -w3.y;
+  int off = 0;
+#pragma unroll
+  for (int s = 0; s < LG / 2; ++s) {
+    const int Ns = 1 << (2 * s);
+#pragma unroll
+    for (int b0 = 0; b0 < P * Q; b0 += kBlock) {
+      const int b = b0 + int(threadIdx.x);
+      if ((P * Q) % kBlock == 0 || b < P * Q) {
+        const int p = b >> (LG - 2);
+        const int j = b & (Q - 1);
+        const int k = j & (Ns - 1);
+        const cplx<R>* sp = src + p * L + j;
+        cplx<R> a0 = sp[0], a1 = sp[Q], a2 = sp[2 * Q], a3 = sp[3 * Q];
+        if (Ns > 1) {
+          const cplx<R>* t = tw + off + k;
+          cplx<R> w1 = t[0], w2 = t[Ns], w3 = t[2 * Ns];
+          if (inverse) {
+            w1.y = -w1.y;
+            w2.y = -w2.y;
+            w3.y = -w3.y;
+          }
+          a1 = cmul(a1, w1);
+          a2 = cmul(a2, w2);
+          a3 = cmul(a3, w3);
         }
-        a1 = cmul(a1, w1);
-        a2 = cmul(a2, w2);
-        a3 = cmul(a3, w3);
+        const cplx<R> t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = csub(a1, a3);
+        // forward: b1 = t1 - i t3, b3 = t1 + i t3; inverse swaps the signs
+        const cplx<R> it3 = inverse ? cplx<R>{-t3.y, t3.x} : cplx<R>{t3.y, -t3.x};
+        cplx<R>* d = dst + p * L + (j - k) * 4 + k;
+        d[0] = cadd(t0, t2);
+        d[Ns] = cadd(t1, it3);
+        d[2 * Ns] = csub(t0, t2);
+        d[3 * Ns] = csub(t1, it3);
       }
-      const cplx<R> t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = csub(a1, a3);
-      // forward: b1 = t1 - i t3, b3 = t1 + i t3; inverse swaps the signs
-      const cplx<R> it3 = inverse ? cplx<R>{-t3.y, t3.x} : cplx<R>{t3.y, -t3.x};
-      cplx<R>* d = dst + p * L + (j - k) * 4 + k;
-      d[0] = cadd(t0, t2);
-      d[Ns] = cadd(t1, it3);
-      d[2 * Ns] = csub(t0, t2);
-      d[3 * Ns] = csub(t1, it3);
     }
+    if (Ns > 1) off += 3 * Ns;
     __syncthreads();
     cplx<R>* t = src;
     src = dst;
     dst = t;
-    Ns *= 4;
-    rem -= 2;
   }
-  if (rem == 1) {
-    const int H = L >> 1;
-    const int hshift = log2L - 1;
-    const int step = L / (2 * Ns);
-    for (int b = threadIdx.x; b < P * H; b += kBlock) {
-      const int p = b >> hshift;
-      const int j = b & (H - 1);
-      const int k = j & (Ns - 1);
-      const cplx<R>* s = src + p * L;
-      cplx<R> w = tw[k * step];
-      if (inverse) w.y = -w.y;
-      const cplx<R> a0 = s[j];
-      const cplx<R> a1 = cmul(s[j + H], w);
-      cplx<R>* d = dst + p * L + (j - k) * 2 + k;
-      d[0] = cadd(a0, a1);
-      d[Ns] = csub(a0, a1);
+  if (LG & 1) {
+    constexpr int H = L >> 1;  // = Ns of this pass, so k = j
+#pragma unroll
+    for (int b0 = 0; b0 < P * H; b0 += kBlock) {
+      const int b = b0 + int(threadIdx.x);
+      if ((P * H) % kBlock == 0 || b < P * H) {
+        const int p = b >> (LG - 1);
+        const int j = b & (H - 1);
+        const cplx<R>* sp = src + p * L + j;
+        cplx<R> w = H > 1 ? tw[off + j] : cplx<R>{R(1), R(0)};
+        if (inverse) w.y = -w.y;
+        const cplx<R> a0 = sp[0];
+        const cplx<R> a1 = cmul(sp[H], w);
+        cplx<R>* d = dst + p * L + j;
+        d[0] = cadd(a0, a1);
+        d[H] = csub(a0, a1);
+      }
     }
     __syncthreads();
     src = dst;
@@ -154,10 +168,10 @@ __device__ __forceinline__ cplx<R>* stockham(cplx<R>* A, cplx<R>* B, int L, int 
 // memory (tg).  Two inlined copies, so that each reads its table through a
 // pointer of known address space: a pointer that may be either makes every
 // twiddle read a flat load, which waits on global and LDS counters alike.
-template <typename R>
-__device__ __forceinline__ cplx<R>* fft(cplx<R>* A, cplx<R>* B, int L, int P, bool tw_lds, const cplx<R>* tl,
-                                        const cplx<R>* tg, bool inverse) {
-  return tw_lds ? stockham(A, B, L, P, tl, inverse) : stockham(A, B, L, P, tg, inverse);
+template <typename R, int LG, int P>
+__device__ __forceinline__ cplx<R>* fft(cplx<R>* A, cplx<R>* B, bool tw_lds, const cplx<R>* tl, const cplx<R>* tg,
+                                        bool inverse) {
+  return tw_lds ? stockham<R, LG, P>(A, B, tl, inverse) : stockham<R, LG, P>(A, B, tg, inverse);
 }
 
 // Table entry of problem prob at |k|.  32-bit offsets: the host keeps the
@@ -211,16 +225,13 @@ __device__ __forceinline__ void grid_clear(R* g, int mode, long plane, long idx)
   if (mode == GRID_FIX128) w[plane + idx] = 0;
 }
 
-template <typename R>
-__host__ __device__ inline int rows_pencils(int L) {
-  return L >= 1024 ? 1 : 1024 / L;
-}
+__host__ __device__ constexpr int rows_pencils(int L) { return L >= 1024 ? 1 : 1024 / L; }
 
-template <typename R>
+template <typename R, int LG>
 __global__ __launch_bounds__(kBlock) void rows_kernel(RowArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int L = a.L;
-  const int P = rows_pencils<R>(L);
+  constexpr int L = 1 << LG;
+  constexpr int P = rows_pencils(L);
   cplx<R>* A = reinterpret_cast<cplx<R>*>(smem_raw);
   cplx<R>* B = A + P * L;
   // twiddles staged in LDS (read by every pass) when they fit
@@ -228,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(RowArgs<R> a) {
   TwiddleStage<R> tws;
   if (a.tw_lds) tws.start(a.tw, L);
   const int K0 = a.N / 2 + 1;
-  const int lshift = ilog2(L);
+  constexpr int lshift = LG;
 
   if (a.mode == ROW_FUSED1D) {
     // Each row is one problem, transformed alone in a pencil of its own (zero
@@ -246,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(RowArgs<R> a) {
         [&](int i, R v) { A[i] = cplx<R>{v, R(0)}; });
     if (a.tw_lds) tws.finish(tlds, a.tw, L);
     __syncthreads();
-    cplx<R>* res = fft(A, B, L, P, a.tw_lds, tlds, a.tw, false);
+    cplx<R>* res = fft<R, LG, P>(A, B, a.tw_lds, tlds, a.tw, false);
     cplx<R>* other = res == A ? B : A;
     // table value at k (zero outside the symmetric set I_N), times i 2 pi k
     // for a derivative
@@ -263,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(RowArgs<R> a) {
           other[i] = scale_multiplier(res[i], m, a.mul, j <= L / 2 ? j : j - L, 0, 0);
         });
     __syncthreads();
-    cplx<R>* out = fft(other, res, L, P, a.tw_lds, tlds, a.tw, true);
+    cplx<R>* out = fft<R, LG, P>(other, res, a.tw_lds, tlds, a.tw, true);
     for (int i = threadIdx.x; i < P * L; i += kBlock) {
       const long row = row0 + (i >> lshift);
       if (row < a.nrows) a.real_io[row * L + (i & (L - 1))] = out[i].x;
@@ -311,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(RowArgs<R> a) {
         });
     if (a.tw_lds) tws.finish(tlds, a.tw, L);
     __syncthreads();
-    cplx<R>* res = fft(A, B, L, P, a.tw_lds, tlds, a.tw, false);
+    cplx<R>* res = fft<R, LG, P>(A, B, a.tw_lds, tlds, a.tw, false);
     for (int i = threadIdx.x; i < P * K0; i += kBlock) {
       const int p = i / K0;
       const int k = i - p * K0;
@@ -359,7 +370,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(RowArgs<R> a) {
       });
   if (a.tw_lds) tws.finish(tlds, a.tw, L);
   __syncthreads();
-  cplx<R>* out = fft(A, B, L, P, a.tw_lds, tlds, a.tw, true);
+  cplx<R>* out = fft<R, LG, P>(A, B, a.tw_lds, tlds, a.tw, true);
   for (int i = threadIdx.x; i < 2 * P * L; i += kBlock) {
     const int r = i >> lshift;
     const int c = i & (L - 1);
@@ -392,16 +403,13 @@ __device__ __forceinline__ void other_freqs(int d, int half, unsigned ii, int& k
   }
 }
 
-template <typename R>
-__host__ __device__ inline int axis_pencils(int L) {
-  return L >= 1024 ? 1 : 1024 / L;
-}
+__host__ __device__ constexpr int axis_pencils(int L) { return L >= 1024 ? 1 : 1024 / L; }
 
-template <typename R>
+template <typename R, int LG>
 __global__ __launch_bounds__(kBlock) void axis_kernel(AxisArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int L = a.L;
-  const int P = axis_pencils<R>(L);
+  constexpr int L = 1 << LG;
+  constexpr int P = axis_pencils(L);
   cplx<R>* A = reinterpret_cast<cplx<R>*>(smem_raw);
   cplx<R>* B = A + P * L;
   // twiddles staged in LDS (read by every pass) when they fit
@@ -412,8 +420,8 @@ __global__ __launch_bounds__(kBlock) void axis_kernel(AxisArgs<R> a) {
   // which then come from one XCD's L2
   const long q0 = xcd_block(blockIdx.x, gridDim.x) * P;
   const int half = a.N / 2;
-  const int pshift = ilog2(P);
-  const int lshift = ilog2(L);
+  constexpr int pshift = LG >= 10 ? 0 : 10 - LG;
+  constexpr int lshift = LG;
 
   // Fused pass: the multiplier values of the elements i = threadIdx.x +
   // u kBlock this thread rescales after the forward FFT do not depend on the
@@ -494,9 +502,9 @@ __global__ __launch_bounds__(kBlock) void axis_kernel(AxisArgs<R> a) {
 
   cplx<R>* res;
   if (a.mode == AX_INV) {
-    res = fft(A, B, L, P, a.tw_lds, tlds, a.tw, true);
+    res = fft<R, LG, P>(A, B, a.tw_lds, tlds, a.tw, true);
   } else {
-    res = fft(A, B, L, P, a.tw_lds, tlds, a.tw, false);
+    res = fft<R, LG, P>(A, B, a.tw_lds, tlds, a.tw, false);
     if (mul_pre) {
 #pragma unroll
       for (int u = 0; u < kMulRegs; ++u) {
@@ -515,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void axis_kernel(AxisArgs<R> a) {
       }
       __syncthreads();
       cplx<R>* other = res == A ? B : A;
-      res = fft(res, other, L, P, a.tw_lds, tlds, a.tw, true);
+      res = fft<R, LG, P>(res, other, a.tw_lds, tlds, a.tw, true);
     } else if (a.mode == AX_FUSED) {
       // in place: each element is read and rewritten by the same thread
       batched<cplx<R>>(
@@ -537,7 +545,7 @@ __global__ __launch_bounds__(kBlock) void axis_kernel(AxisArgs<R> a) {
           [&](int i, cplx<R> v) { res[i] = v; });
       __syncthreads();
       cplx<R>* other = res == A ? B : A;
-      res = fft(res, other, L, P, a.tw_lds, tlds, a.tw, true);
+      res = fft<R, LG, P>(res, other, a.tw_lds, tlds, a.tw, true);
     }
   }
 
@@ -567,34 +575,52 @@ static size_t fft_lds(int P, int L, int* tw_lds) {
   return buf + (*tw_lds ? twb : 0);
 }
 
+// Kernel instance for L = 2^lg, lg in [kMinLg, kMaxLg] (grids of 4 to 4096).
+constexpr int kMinLg = 2, kMaxLg = 12;
+template <typename R, int LG>
+static void* rows_instance(int lg) {
+  if constexpr (LG > kMaxLg) {
+    return nullptr;
+  } else {
+    return lg == LG ? reinterpret_cast<void*>(&rows_kernel<R, LG>) : rows_instance<R, LG + 1>(lg);
+  }
+}
+template <typename R, int LG>
+static void* axis_instance(int lg) {
+  if constexpr (LG > kMaxLg) {
+    return nullptr;
+  } else {
+    return lg == LG ? reinterpret_cast<void*>(&axis_kernel<R, LG>) : axis_instance<R, LG + 1>(lg);
+  }
+}
+
 template <typename R>
 hipError_t launch_rows(const RowArgs<R>& a_in, hipStream_t st) {
   RowArgs<R> a = a_in;
-  const int P = rows_pencils<R>(a.L);
+  const int lg = ilog2(a.L);
+  if ((1 << lg) != a.L || lg < kMinLg || lg > kMaxLg) return hipErrorInvalidValue;
+  const int P = rows_pencils(a.L);
   const int rows_per_block = a.mode == ROW_FUSED1D ? P : 2 * P;  // FUSED1D: one row per pencil
   const long nblk = (a.nrows + rows_per_block - 1) / rows_per_block;
   const size_t shm = fft_lds<R>(P, a.L, &a.tw_lds);
-  hipLaunchKernelGGL(rows_kernel<R>, dim3(nblk), dim3(kBlock), shm, st, a);
-  return hipGetLastError();
+  void* args[] = {&a};
+  return hipLaunchKernel(rows_instance<R, kMinLg>(lg), dim3(nblk), dim3(kBlock), args, shm, st);
 }
 
 template <typename R>
 hipError_t launch_axis(const AxisArgs<R>& a_in, hipStream_t st) {
   AxisArgs<R> a = a_in;
+  const int lg = ilog2(a.L);
+  if ((1 << lg) != a.L || lg < kMinLg || lg > kMaxLg) return hipErrorInvalidValue;
   if (a.npen >= (long(1) << 31) || a.inner <= 0) return hipErrorInvalidValue;
   const long groups = (a.npen + a.inner - 1) / a.inner;
   const long ext_in = groups * a.in_ostride, ext_out = groups * a.out_ostride;
   if (ext_in >= (long(1) << 32) || ext_out >= (long(1) << 32)) return hipErrorInvalidValue;
-  const int P = axis_pencils<R>(a.L);
+  const int P = axis_pencils(a.L);
   const long nblk = (a.npen + P - 1) / P;
   const size_t shm = fft_lds<R>(P, a.L, &a.tw_lds);
-  hipLaunchKernelGGL(axis_kernel<R>, dim3(nblk), dim3(kBlock), shm, st, a);
-  return hipGetLastError();
+  void* args[] = {&a};
+  return hipLaunchKernel(axis_instance<R, kMinLg>(lg), dim3(nblk), dim3(kBlock), args, shm, st);
 }
-
-template hipError_t launch_rows<float>(const RowArgs<float>&, hipStream_t);
-template hipError_t launch_rows<double>(const RowArgs<double>&, hipStream_t);
-template hipError_t launch_axis<float>(const AxisArgs<float>&, hipStream_t);
-template hipError_t launch_axis<double>(const AxisArgs<double>&, hipStream_t);
 
 }  // namespace nfs

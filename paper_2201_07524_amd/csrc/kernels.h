@@ -181,6 +181,11 @@ struct Multiplier {
   long tab_stride;   // entries between the tables of consecutive problems
 };
 
+// FFT pass plan for a length 2^rem: radix-4 passes while two or more bits
+// remain, then one radix-2 pass.  The device passes and the host twiddle
+// table (pass tables of (radix - 1) Ns entries, end to end) both follow it.
+__host__ __device__ inline int fft_pass_bits(int rem) { return rem >= 2 ? 2 : rem; }
+
 enum RowMode : int { ROW_R2C = 0, ROW_C2R = 1, ROW_FUSED1D = 2 };
 enum AxisMode : int { AX_FWD = 0, AX_INV = 1, AX_FUSED = 2 };
 
@@ -196,7 +201,7 @@ struct RowArgs {
   long grid_plane;  // GRID_FIX128: words between its two planes
   cplx<R>* spec;    // R2C: output [nrows][K0]; C2R: input [nrows][K0]
   int zero_src;
-  const cplx<R>* tw;
+  const cplx<R>* tw;  // pass twiddle tables (fft_pass_bits), L entries
   int tw_lds;       // set by the launcher: twiddles staged in LDS
   Multiplier mul;   // FUSED1D only
 };

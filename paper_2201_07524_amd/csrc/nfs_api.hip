@@ -550,10 +550,27 @@ static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const std:
 template <typename R>
 static int upload_tables(Work<R>& w, const nfs_params* p, hipStream_t st) {
   const int g = w.geo.g;
-  std::vector<cplx<R>> tw(g);
-  for (int j = 0; j < g; ++j) {
-    const double a = -2.0 * kPi * double(j) / double(g);
-    tw[j] = cplx<R>{R(std::cos(a)), R(std::sin(a))};
+  // FFT twiddles, pass by pass in the device's pass order: a pass of radix Rd
+  // after Ns = (product of the earlier radices) > 1 holds e^(-2 pi i m k /
+  // (Rd Ns)) at (m - 1) Ns + k, m = 1..Rd-1, k < Ns.  The tables telescope to
+  // g - (first radix) < g entries.
+  std::vector<cplx<R>> tw(g, cplx<R>{R(0), R(0)});
+  int bits_g = 0;
+  while ((1 << bits_g) < g) ++bits_g;
+  long off = 0, Ns = 1;
+  for (int rem = bits_g; rem > 0;) {
+    const int bits = fft_pass_bits(rem);
+    const long Rd = 1L << bits;
+    if (Ns > 1) {
+      for (long m = 1; m < Rd; ++m)
+        for (long k = 0; k < Ns; ++k) {
+          const double a = -2.0 * kPi * double(m * k) / double(Rd * Ns);
+          tw[off + (m - 1) * Ns + k] = cplx<R>{R(std::cos(a)), R(std::sin(a))};
+        }
+      off += (Rd - 1) * Ns;
+    }
+    Ns <<= bits;
+    rem -= bits;
   }
   NFS_HIP(hipMemcpyAsync(w.tw, tw.data(), sizeof(cplx<R>) * g, hipMemcpyHostToDevice, st));
   const std::vector<double> phi = window_hat_table(p->N, p->m, g, w.win);
