@@ -337,12 +337,19 @@ __device__ int scan_bins(int* hist, int nc, int* part) {
 // its T^d cells, exclusive scan, then each point goes to its cell's next slot,
 // and the points of each cell are put in the order of their input index.
 constexpr int kCanonCell = 1024;
+// Tiles of up to kCanonStage points rank from a copy of their input indices
+// in LDS (dynamic, 112 KiB next to the 33 KiB of bins); a rank costs one LDS
+// read per point of the cell instead of one global load.  Larger tiles read
+// global memory, kCanonBatch loads in flight at a time.
+constexpr int kCanonStage = 28 * 1024;
+constexpr int kCanonBatch = 8;
 
 template <typename R>
 __global__ __launch_bounds__(kBlock) void tile_sort_kernel(TileSortArgs<R> a) {
   __shared__ int slot[kSortBins];
   __shared__ int first[kSortBins];
   __shared__ int part[kBlock];
+  extern __shared__ int stage[];  // kCanonStage entries
   const int cnt = a.counts[blockIdx.x];
   const int d = a.d, T = a.T;
   int nc = 1;
@@ -381,6 +388,11 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(TileSortArgs<R> a) {
   // kCanonCell points keep their placement order.
   __threadfence_block();
   __syncthreads();
+  const bool staged = cnt <= kCanonStage;
+  if (staged) {
+    for (int i = threadIdx.x; i < cnt; i += kBlock) stage[i] = a.perm[off + i];
+    __syncthreads();
+  }
   for (int i = threadIdx.x; i < cnt; i += kBlock) {
     const size_t q = off + i;
     const int cell = cell_key_at(a.coords, q, d, T);
@@ -389,7 +401,20 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(TileSortArgs<R> a) {
     int rank = i - c0;
     if (c1 - c0 <= kCanonCell) {
       rank = 0;
-      for (int e = c0; e < c1; ++e) rank += a.perm[off + e] < pq ? 1 : 0;
+      if (staged) {
+        for (int e = c0; e < c1; ++e) rank += stage[e] < pq ? 1 : 0;
+      } else {
+        const int* pc = a.perm + off;
+        int e = c0;
+        for (; e + kCanonBatch <= c1; e += kCanonBatch) {
+          int v[kCanonBatch];
+#pragma unroll
+          for (int u = 0; u < kCanonBatch; ++u) v[u] = pc[e + u];
+#pragma unroll
+          for (int u = 0; u < kCanonBatch; ++u) rank += v[u] < pq ? 1 : 0;
+        }
+        for (; e < c1; ++e) rank += pc[e] < pq ? 1 : 0;
+      }
     }
     const size_t dst = off + c0 + rank;
     for (int c = 0; c < d; ++c) a.in_coords[dst * d + c] = a.coords[q * d + c];
@@ -411,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(TileSortArgs<R> a) {
 template <typename R>
 hipError_t launch_tile_sort(const TileSortArgs<R>& a, hipStream_t st) {
   if (a.ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(tile_sort_kernel<R>, dim3(a.ntiles), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL(tile_sort_kernel<R>, dim3(a.ntiles), dim3(kBlock), kCanonStage * sizeof(int), st, a);
   return hipGetLastError();
 }
 template hipError_t launch_tile_sort<float>(const TileSortArgs<float>&, hipStream_t);
