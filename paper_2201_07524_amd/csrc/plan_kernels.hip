@@ -291,19 +291,20 @@ template hipError_t launch_scatter<float>(const ScatterArgs<float>&, hipStream_t
 template hipError_t launch_scatter<double>(const ScatterArgs<double>&, hipStream_t);
 
 // ------------------------------------------------------------------ cell order and run tables
-// Exclusive prefix sum over the workgroup; returns this thread's prefix and
-// the total in *total.  `part` holds kBlock ints of LDS.
+// Exclusive prefix sum over the workgroup of NT threads; returns this
+// thread's prefix and the total in *total.  `part` holds NT ints of LDS.
+template <int NT = kBlock>
 __device__ int block_exclusive_scan(int v, int* part, int* total) {
   part[threadIdx.x] = v;
   __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
+  for (int off = 1; off < NT; off <<= 1) {
     const int u = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
     __syncthreads();
     part[threadIdx.x] += u;
     __syncthreads();
   }
   const int incl = part[threadIdx.x];
-  *total = part[kBlock - 1];
+  *total = part[NT - 1];
   __syncthreads();
   return incl - v;
 }
@@ -315,15 +316,16 @@ __device__ __forceinline__ int cell_key_at(const R* coords, size_t q, int d, int
   return k;
 }
 
-// Exclusive scan of hist[0..nc) in place (nc <= kSortBins); each thread owns
-// a contiguous run of bins.  Returns the total.
+// Exclusive scan of hist[0..nc) in place (nc <= kSortBins) by a workgroup of
+// NT threads; each thread owns a contiguous run of bins.  Returns the total.
+template <int NT>
 __device__ int scan_bins(int* hist, int nc, int* part) {
-  const int per = (nc + kBlock - 1) / kBlock;
+  const int per = (nc + NT - 1) / NT;
   const int b0 = min(int(threadIdx.x) * per, nc), b1 = min(b0 + per, nc);
   int s = 0;
   for (int i = b0; i < b1; ++i) s += hist[i];
   int total;
-  int run = block_exclusive_scan(s, part, &total);
+  int run = block_exclusive_scan<NT>(s, part, &total);
   for (int i = b0; i < b1; ++i) {
     const int c = hist[i];
     hist[i] = run;
@@ -336,19 +338,32 @@ __device__ int scan_bins(int* hist, int nc, int* part) {
 // One workgroup per (problem, tile): LDS histogram of the tile's points over
 // its T^d cells, exclusive scan, then each point goes to its cell's next slot,
 // and the points of each cell are put in the order of their input index.
+// Each pass over the tile's points is a chain of dependent global accesses
+// per thread, and the densest tile (85K points on the 2-D mixture) sets the
+// plan time: 1024 threads per workgroup cut that chain by four.
+constexpr int kSortThreads = 1024;
 constexpr int kCanonCell = 1024;
-// Tiles of up to kCanonStage points rank from a copy of their input indices
-// in LDS (dynamic, 112 KiB next to the 33 KiB of bins); a rank costs one LDS
-// read per point of the cell instead of one global load.  Larger tiles read
-// global memory, kCanonBatch loads in flight at a time.
+// Ranks are counted from a copy of the input indices in LDS (dynamic, 112 KiB
+// next to the 33 KiB of bins), one window of whole cells of at most
+// kCanonStage points at a time: one LDS read per point of the cell instead of
+// one global load.
 constexpr int kCanonStage = 28 * 1024;
-constexpr int kCanonBatch = 8;
 
 template <typename R>
-__global__ __launch_bounds__(kBlock) void tile_sort_kernel(TileSortArgs<R> a) {
+__global__ __launch_bounds__(kSortThreads) void tile_sort_kernel(TileSortArgs<R> a) {
+  // distinct buffers: unrolled iterations may issue their loads before the
+  // stores of the ones before
+  R* __restrict__ in_coords = a.in_coords;
+  int* __restrict__ in_perm = a.in_perm;
+  double* __restrict__ in_w0 = a.in_w0;
+  double* __restrict__ in_w1 = a.in_w1;
+  R* __restrict__ coords = a.coords;
+  int* __restrict__ perm = a.perm;
+  double* __restrict__ w0s = a.w0s;
+  double* __restrict__ w1s = a.w1s;
   __shared__ int slot[kSortBins];
   __shared__ int first[kSortBins];
-  __shared__ int part[kBlock];
+  __shared__ int part[kSortThreads];
   extern __shared__ int stage[];  // kCanonStage entries
   const int cnt = a.counts[blockIdx.x];
   const int d = a.d, T = a.T;
@@ -357,28 +372,30 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(TileSortArgs<R> a) {
   int* cs = a.cellstart ? a.cellstart + size_t(blockIdx.x) * (nc + 1) : nullptr;
   if (cnt == 0) {
     if (cs)
-      for (int i = threadIdx.x; i <= nc; i += kBlock) cs[i] = 0;
+      for (int i = threadIdx.x; i <= nc; i += kSortThreads) cs[i] = 0;
     return;
   }
   const size_t off = size_t(a.offsets[blockIdx.x]);
-  for (int i = threadIdx.x; i < nc; i += kBlock) slot[i] = 0;
+  for (int i = threadIdx.x; i < nc; i += kSortThreads) slot[i] = 0;
   __syncthreads();
-  for (int i = threadIdx.x; i < cnt; i += kBlock) atomicAdd(&slot[cell_key_at(a.in_coords, off + i, d, T)], 1);
+#pragma unroll 4
+  for (int i = threadIdx.x; i < cnt; i += kSortThreads) atomicAdd(&slot[cell_key_at(in_coords, off + i, d, T)], 1);
   __syncthreads();
-  scan_bins(slot, nc, part);
+  scan_bins<kSortThreads>(slot, nc, part);
   if (cs) {
-    for (int i = threadIdx.x; i < nc; i += kBlock) cs[i] = slot[i];
+    for (int i = threadIdx.x; i < nc; i += kSortThreads) cs[i] = slot[i];
     if (threadIdx.x == 0) cs[nc] = cnt;
   }
-  for (int i = threadIdx.x; i < nc; i += kBlock) first[i] = slot[i];
+  for (int i = threadIdx.x; i < nc; i += kSortThreads) first[i] = slot[i];
   __syncthreads();
-  for (int i = threadIdx.x; i < cnt; i += kBlock) {
+#pragma unroll 4
+  for (int i = threadIdx.x; i < cnt; i += kSortThreads) {
     const size_t q = off + i;
-    const size_t pos = off + atomicAdd(&slot[cell_key_at(a.in_coords, q, d, T)], 1);
-    for (int c = 0; c < d; ++c) a.coords[pos * d + c] = a.in_coords[q * d + c];
-    a.perm[pos] = a.in_perm[q];
-    if (a.w0s) a.w0s[pos] = a.in_w0[q];
-    if (a.w1s) a.w1s[pos] = a.in_w1[q];
+    const size_t pos = off + atomicAdd(&slot[cell_key_at(in_coords, q, d, T)], 1);
+    for (int c = 0; c < d; ++c) coords[pos * d + c] = in_coords[q * d + c];
+    perm[pos] = in_perm[q];
+    if (w0s) w0s[pos] = in_w0[q];
+    if (w1s) w1s[pos] = in_w1[q];
   }
   // Canonical order inside each cell: by the points' input index.  The
   // scatter and the placement above leave a cell's points in the order their
@@ -388,55 +405,62 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(TileSortArgs<R> a) {
   // kCanonCell points keep their placement order.
   __threadfence_block();
   __syncthreads();
-  const bool staged = cnt <= kCanonStage;
-  if (staged) {
-    for (int i = threadIdx.x; i < cnt; i += kBlock) stage[i] = a.perm[off + i];
-    __syncthreads();
-  }
-  for (int i = threadIdx.x; i < cnt; i += kBlock) {
-    const size_t q = off + i;
-    const int cell = cell_key_at(a.coords, q, d, T);
-    const int c0 = first[cell], c1 = slot[cell];
-    const int pq = a.perm[q];
-    int rank = i - c0;
-    if (c1 - c0 <= kCanonCell) {
-      rank = 0;
-      if (staged) {
-        for (int e = c0; e < c1; ++e) rank += stage[e] < pq ? 1 : 0;
-      } else {
-        const int* pc = a.perm + off;
-        int e = c0;
-        for (; e + kCanonBatch <= c1; e += kCanonBatch) {
-          int v[kCanonBatch];
-#pragma unroll
-          for (int u = 0; u < kCanonBatch; ++u) v[u] = pc[e + u];
-#pragma unroll
-          for (int u = 0; u < kCanonBatch; ++u) rank += v[u] < pq ? 1 : 0;
-        }
-        for (; e < c1; ++e) rank += pc[e] < pq ? 1 : 0;
-      }
+  // The cells occupy consecutive positions now, so a window of whole cells
+  // is a contiguous range [s, e); it takes the most cells whose points fit
+  // the stage.  A cell larger than the stage (beyond kCanonCell, so it keeps
+  // its placement order) is a window of its own, not staged.
+  auto pos = [&](int c) { return c < nc ? first[c] : cnt; };
+  for (int c_lo = 0; c_lo < nc;) {
+    const int s = first[c_lo];
+    int lo = c_lo, hi = nc;  // largest c_hi in [c_lo, nc] with pos(c_hi) - s <= kCanonStage
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pos(mid) - s <= kCanonStage) lo = mid;
+      else hi = mid - 1;
     }
-    const size_t dst = off + c0 + rank;
-    for (int c = 0; c < d; ++c) a.in_coords[dst * d + c] = a.coords[q * d + c];
-    a.in_perm[dst] = pq;
-    if (a.w0s) a.in_w0[dst] = a.w0s[q];
-    if (a.w1s) a.in_w1[dst] = a.w1s[q];
+    const bool staged = lo > c_lo;
+    const int c_hi = staged ? lo : c_lo + 1;
+    const int e = pos(c_hi);
+    if (staged) {
+      for (int i = s + int(threadIdx.x); i < e; i += kSortThreads) stage[i - s] = perm[off + i];
+      __syncthreads();
+    }
+#pragma unroll 4
+    for (int i = s + int(threadIdx.x); i < e; i += kSortThreads) {
+      const size_t q = off + i;
+      const int cell = cell_key_at(coords, q, d, T);
+      const int c0 = first[cell], c1 = slot[cell];
+      const int pq = perm[q];
+      int rank = i - c0;
+      if (staged && c1 - c0 <= kCanonCell) {
+        rank = 0;
+        for (int j = c0; j < c1; ++j) rank += stage[j - s] < pq ? 1 : 0;
+      }
+      const size_t dst = off + c0 + rank;
+      for (int c = 0; c < d; ++c) in_coords[dst * d + c] = coords[q * d + c];
+      in_perm[dst] = pq;
+      if (w0s) in_w0[dst] = w0s[q];
+      if (w1s) in_w1[dst] = w1s[q];
+    }
+    __syncthreads();  // the next window overwrites the stage
+    c_lo = c_hi;
   }
   __threadfence_block();
   __syncthreads();
-  for (int i = threadIdx.x; i < cnt; i += kBlock) {
+#pragma unroll 4
+  for (int i = threadIdx.x; i < cnt; i += kSortThreads) {
     const size_t q = off + i;
-    for (int c = 0; c < d; ++c) a.coords[q * d + c] = a.in_coords[q * d + c];
-    a.perm[q] = a.in_perm[q];
-    if (a.w0s) a.w0s[q] = a.in_w0[q];
-    if (a.w1s) a.w1s[q] = a.in_w1[q];
+    for (int c = 0; c < d; ++c) coords[q * d + c] = in_coords[q * d + c];
+    perm[q] = in_perm[q];
+    if (w0s) w0s[q] = in_w0[q];
+    if (w1s) w1s[q] = in_w1[q];
   }
 }
 
 template <typename R>
 hipError_t launch_tile_sort(const TileSortArgs<R>& a, hipStream_t st) {
   if (a.ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(tile_sort_kernel<R>, dim3(a.ntiles), dim3(kBlock), kCanonStage * sizeof(int), st, a);
+  hipLaunchKernelGGL(tile_sort_kernel<R>, dim3(a.ntiles), dim3(kSortThreads), kCanonStage * sizeof(int), st, a);
   return hipGetLastError();
 }
 template hipError_t launch_tile_sort<float>(const TileSortArgs<float>&, hipStream_t);
