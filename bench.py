@@ -103,7 +103,7 @@ def measured_util(kernel):
 def cpu_baseline(cfg, budget_rows=8192):
     """Oracle (FP64 matrix-free direct sums in C/OpenMP) timed on a bounded
     sample: one kernel product K v over all sources for `budget_rows` sampled
-    targets, scaled to the two full products of one iteration."""
+    targets, scaled to the two full products of one iteration (extrapolated)."""
     import numpy as np
     from oracle import direct
 
@@ -255,7 +255,7 @@ def grad_leg(nfs, workloads, torch, T, iters=5):
     t_once = time.perf_counter() - t0
     return {"forward_ms_per_iteration": t_fwd * 1e3, "gradient_x_mu_ms": t_grad * 1e3,
             "gradient_over_forward_iteration": t_grad / t_fwd, "gradient_x_mu_y_nu_ms": t_grad4 * 1e3,
-            "one_shot_gradient_ms_incl_plan": t_once * 1e3}
+            "one_shot_gradient_ms_incl_plan": t_once * 1e3, "cpu_oracle": cpu_baseline(cfg, budget_rows=2048)}
 
 
 def log_leg(nfs, prm, x, p, y, pt, torch, iters=20):
@@ -299,7 +299,8 @@ def ball_shell_leg(nfs, workloads, torch, T, iters=3):
     s.close()
     return {"points": int(cfg["x"].shape[0]), "ms_per_iteration": t_it * 1e3, "plan_ms": plan * 1e3,
             "stage_ms": dict(zip(("spread", "fft", "interp", "iteration", "near_field"), stage_ms)),
-            "near_field_share": 2.0 * stage_ms[4] / stage_ms[3], "cost": res.cost, "n_nonpos": res.n_nonpos}
+            "near_field_share": 2.0 * stage_ms[4] / stage_ms[3], "cost": res.cost, "n_nonpos": res.n_nonpos,
+            "cpu_oracle": cpu_baseline(cfg, budget_rows=512)}
 
 
 def paper_shapes_leg(nfs, workloads, torch, T, iters=10):
