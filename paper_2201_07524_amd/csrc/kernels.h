@@ -122,7 +122,7 @@ struct InterpArgs {
   const double* p;
   double* alpha;
   double* partials;         // kRedVals doubles per chunk
-  unsigned* counter;        // per problem, zero on entry, left zero
+  int nprob;                // problems B
   const int* prob_chunks;   // B + 1: chunks of problem p are [prob_chunks[p], prob_chunks[p+1])
   double* stats;            // per problem, stride kStat (layout above)
   double* wmul_next;        // per problem, receives 1/max alpha (log domain: max beta) (nullable)

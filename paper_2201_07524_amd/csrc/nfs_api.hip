@@ -192,7 +192,6 @@ struct Work {
   R* dtab2 = nullptr;  // B cost tables
   double* inv_phi = nullptr;
   double* partials = nullptr;
-  unsigned* ct_interp = nullptr;  // B
   unsigned* ct_misc = nullptr;    // 8
   double* st_row = nullptr;   // B x kStat: statistics of the alpha updates
   double* st_col = nullptr;   // B x kStat: statistics of the alpha_t updates
@@ -320,7 +319,6 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
   w.wpoly = cv.take<double>((sizeof(R) == 4 ? sizeof(WindowPoly) : sizeof(WindowPoly64)) / sizeof(double) + 1);
   const long maxch = std::max(w.X.max_chunks, w.Y.max_chunks);
   w.partials = cv.take<double>(size_t(std::max<long>(maxch, 1024)) * kBoxVals);
-  w.ct_interp = cv.take<unsigned>(B);
   w.ct_misc = cv.take<unsigned>(8);
   w.st_row = cv.take<double>(size_t(B) * kStat);
   w.st_col = cv.take<double>(size_t(B) * kStat);
@@ -352,7 +350,6 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
 // never records a memset).
 template <typename R>
 static int zero_state(Work<R>& w, hipStream_t st) {
-  NFS_HIP(launch_fill(w.ct_interp, sizeof(unsigned) * w.B, st));
   NFS_HIP(launch_fill(w.ct_misc, sizeof(unsigned) * 8, st));
   for (double* s : {w.st_row, w.st_col, w.st_eval}) NFS_HIP(launch_fill(s, sizeof(double) * kStat * w.B, st));
   NFS_HIP(launch_fill(w.pstate, sizeof(int) * kPState * w.B, st));
@@ -800,7 +797,7 @@ static InterpArgs<R> interp_args(Work<R>& w, const CloudBuf<R>& tgt, int epi, co
   a.perm = tgt.perm;
   a.out_stride = 1;
   a.partials = w.partials;
-  a.counter = w.ct_interp;
+  a.nprob = w.B;
   a.prob_chunks = tgt.prob_chunks;
   return a;
 }

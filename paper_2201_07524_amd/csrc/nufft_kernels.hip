@@ -1121,72 +1121,64 @@ __device__ Red block_reduce(Red v, Red* sh) {
   return r;
 }
 
-// Final reduction by the last workgroup to finish (ticket counter).  The
-// chunks of one problem are [c0, c1); the last of them to finish reduces that
-// problem's partials into stats (layout of kStat), sets wmul_next to 1/max
-// (the normalization of the next spread's weights; log domain: the max
-// itself, the shift of the next spread's potentials) and advances the
-// problem's stop state (kPState).
-__device__ void finish_reduce(Red mine, Red* sh, double* partials, unsigned* counter, double* stats,
-                              double* wmul_next, const double* src_l1, int* pstate, const double* tol2, int half,
-                              int c0, int c1, bool logd, int chunk) {
-  __shared__ bool last;
-  if (threadIdx.x == 0) {
-    double* pw = partials + kRedVals * size_t(chunk);
-    pw[0] = mine.res2;
-    pw[1] = mine.mass;
-    pw[2] = mine.l1;
-    pw[3] = mine.mx;
-    pw[4] = mine.tmin;
-    pw[5] = mine.tmax;
-    pw[6] = mine.cnt;
-    __threadfence();
-    const unsigned ticket = atomicAdd(counter, 1u);
-    last = (ticket == unsigned(c1 - c0) - 1u);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
+// Per-problem reduction of the interpolation's per-chunk partials, in chunk
+// order, by a kernel launched right after the interpolation (the kernel
+// boundary makes the partials visible).  The chunks of problem pb are
+// [prob_chunks[pb], prob_chunks[pb + 1]).  Writes the problem's statistics
+// (layout kStat), sets wmul_next to 1/max (the normalization of the next
+// spread's weights; log domain: the max itself, the shift of the next
+// spread's potentials) and advances its stop state (kPState).  A problem that
+// had stopped was skipped by the interpolation and is skipped here.
+//
+// A fence and a ticket per workgroup, the last one reducing, would save the
+// launch but not time: on a part with one L2 per XCD the device-scope fence
+// writes the L2 back, once per workgroup (22K per interpolation of the
+// 512-problem batch, 2.9 ms per iteration).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void reduce_stats_kernel(InterpArgs<R> a) {
+  __shared__ Red red_sh[kBlock / 64];
+  const int pb = blockIdx.x;
+  int* pstate = a.pstate ? a.pstate + kPState * pb : nullptr;
+  if (pstate && pstate[0] == 2) return;
+  const bool logd = a.epi == EPI_LOGSINK || a.epi == EPI_LOGEVAL;
+  const int c0 = a.prob_chunks[pb], c1 = a.prob_chunks[pb + 1];
   Red v = red_init(logd);
-  const volatile double* pv = partials;
   for (int b = c0 + threadIdx.x; b < c1; b += kBlock) {
-    const size_t o = kRedVals * size_t(b);
-    Red w{pv[o + 0], pv[o + 1], pv[o + 2], pv[o + 3], pv[o + 4], pv[o + 5], pv[o + 6]};
+    const double* pw = a.partials + kRedVals * size_t(b);
+    const Red w{pw[0], pw[1], pw[2], pw[3], pw[4], pw[5], pw[6]};
     v = red_combine(v, w);
   }
-  __syncthreads();
-  const Red r = block_reduce(v, sh);
-  if (threadIdx.x == 0) {
-    stats[0] = r.res2;
-    stats[1] = r.mass;
-    stats[2] = r.mx;
-    stats[3] = r.cnt;
-    stats[4] += r.cnt;  // running count over all launches into this slot
-    stats[5] = r.tmin;
-    stats[6] = r.tmax;
-    stats[7] = r.l1;
-    if (src_l1) {
-      // ||w||_1 / min t; a sum t <= 0 (or none positive) counts as an unbounded range
-      const double range = r.tmin > 0.0 ? *src_l1 / r.tmin : INFINITY;
-      stats[8] = fmax(stats[8], range);
+  const Red r = block_reduce(v, red_sh);
+  if (threadIdx.x != 0) return;
+  double* stats = a.stats + kStat * pb;
+  stats[0] = r.res2;
+  stats[1] = r.mass;
+  stats[2] = r.mx;
+  stats[3] = r.cnt;
+  stats[4] += r.cnt;  // running count over all launches into this slot
+  stats[5] = r.tmin;
+  stats[6] = r.tmax;
+  stats[7] = r.l1;
+  if (a.src_l1) {
+    // ||w||_1 / min t; a sum t <= 0 (or none positive) counts as an unbounded range
+    const double range = r.tmin > 0.0 ? a.src_l1[kStat * pb] / r.tmin : INFINITY;
+    stats[8] = fmax(stats[8], range);
+  }
+  if (a.wmul_next) {
+    if (logd)
+      a.wmul_next[pb] = isfinite(r.mx) ? r.mx : 0.0;
+    else
+      a.wmul_next[pb] = (r.mx > 0.0 && r.mx < 1e300) ? 1.0 / r.mx : 1.0;
+  }
+  if (pstate) {
+    if (a.half == 0) {
+      // ||E|| of the state the previous iteration left (its column term is
+      // zero up to rounding after an alpha_t update)
+      if (pstate[0] == 0 && *a.tol2 > 0.0 && r.res2 <= *a.tol2) pstate[0] = 1;
+    } else {
+      pstate[1] += 1;
+      if (pstate[0] == 1) pstate[0] = 2;
     }
-    if (wmul_next) {
-      if (logd)
-        *wmul_next = isfinite(r.mx) ? r.mx : 0.0;
-      else
-        *wmul_next = (r.mx > 0.0 && r.mx < 1e300) ? 1.0 / r.mx : 1.0;
-    }
-    if (pstate) {
-      if (half == 0) {
-        // ||E|| of the state the previous iteration left (its column term is
-        // zero up to rounding after an alpha_t update)
-        if (pstate[0] == 0 && *tol2 > 0.0 && r.res2 <= *tol2) pstate[0] = 1;
-      } else {
-        pstate[1] += 1;
-        if (pstate[0] == 1) pstate[0] = 2;
-      }
-    }
-    *counter = 0u;
   }
 }
 
@@ -1196,17 +1188,14 @@ constexpr int kInterpRun = 2;
 // Interpolates GC consecutive sorted points that lie in one cell: each row of
 // taps is read from the LDS tile once and dotted with the GC windows.
 template <typename R, int D, int M, int GC>
-__device__ __forceinline__ void interp_run(const R* tile, const InterpArgs<R>& a, const WinEval<R>& ev, int E, int q0,
+__device__ __forceinline__ void interp_run(const R* tile, const WinEval<R>& ev, int E, const R (&u)[GC][D],
                                            R (&acc)[GC]) {
   constexpr int W = 2 * M + 1;
   constexpr int FROM = D == 1 ? 0 : 1;
   Taps<R, D, M, FROM> tp[GC];
 #pragma unroll
   for (int p = 0; p < GC; ++p) {
-    R u[D];
-#pragma unroll
-    for (int c = 0; c < D; ++c) u[c] = a.coords[size_t(q0 + p) * D + c];
-    tp[p].compute(u, ev);
+    tp[p].compute(u[p], ev);
     acc[p] = R(0);
   }
   if constexpr (D == 1) {
@@ -1277,11 +1266,34 @@ __device__ __forceinline__ void interp_run(const R* tile, const InterpArgs<R>& a
   }
 }
 
+// Inputs of one interpolation step (GC consecutive sorted points from q0):
+// their coordinates and, for the scaling epilogues, p and the old scaling
+// (or potential).
+template <typename R, int D, int GC>
+struct PointIn {
+  R u[GC][D];
+  double p[GC], al[GC];
+  __device__ __forceinline__ void load(const InterpArgs<R>& a, int q0, bool pa) {
+#pragma unroll
+    for (int k = 0; k < GC; ++k) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) u[k][c] = a.coords[size_t(q0 + k) * D + c];
+      p[k] = pa ? a.p[q0 + k] : 0.0;
+      al[k] = pa ? a.alpha[q0 + k] : 0.0;
+    }
+  }
+};
+
 // LOG: the log-domain epilogues (EPI_LOGSINK / EPI_LOGEVAL), instantiated
 // apart so that their log and exp do not raise the register count of the
 // others.
+// Minimum waves per SIMD the interpolation keeps: the FP32 3-D scaling
+// instances sit at the 128-register edge of 4 waves and are held there.
+template <typename R, int D, bool LOG>
+constexpr int interp_min_waves() { return sizeof(R) == 4 && D == 3 && !LOG ? 4 : 1; }
+
 template <typename R, int D, int M, bool LOG>
-__global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
+__global__ __launch_bounds__(kBlock, (interp_min_waves<R, D, LOG>())) void interp_kernel(InterpArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
   __shared__ Red red_sh[kBlock / 64];
@@ -1301,9 +1313,37 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
       t /= geo.nt[c];
     }
   }
+  // FP32 in 1-D and 2-D: each step's inputs are loaded one step ahead (the
+  // first ones before the tile), so a thread waits on the run table and the
+  // point data while it computes the step before, not after it.  FP64 and
+  // 3-D load the coordinates at the step and p and the old scaling in the
+  // epilogue: a second set of live registers would cost them occupancy.
+  constexpr bool ahead = sizeof(R) == 4 && D <= 2;
+  constexpr int G = run_length<R>(D);
+  constexpr int GI = kInterpRun < G ? kInterpRun : G;  // points per interpolation run, divides G
+  constexpr int SUB = G / GI;
+  const bool pa = ahead && a.epi != EPI_OUT;
+  const int* runs = a.runs + ch.start;
+  const int nfull = a.nruns[2 * cb], nsingle = a.nruns[2 * cb + 1];
+  const int nit = nfull * SUB;
+  auto step_q0 = [&](int rr) { return ch.start + runs[rr / SUB] + (rr % SUB) * GI; };
+  PointIn<R, D, GI> cur;
+  int qc = 0;
+  if constexpr (ahead) {
+    if (int(threadIdx.x) < nit) {
+      qc = step_q0(threadIdx.x);
+      cur.load(a, qc, pa);
+    }
+  }
+
   int lo, hi;
   chunk_rows<R, D, M>(a.coords, ch, geo, a.cell_order, lo, hi);
-  for (int i = lo + threadIdx.x; i < hi; i += kBlock) {
+  // The tile's grid values, kTileBatch loads per thread in flight before the
+  // first LDS store: a store waits for its load, so the plain loop paid one
+  // memory round trip per element, which sets the time of a chunk of few
+  // points (small or sparse problems of a batch).
+  const R* gp = a.grid + size_t(ch.prob) * a.grid_stride;
+  auto grid_at = [&](int i) {
     size_t lin;
     if constexpr (D == 1) {
       lin = wrap(org[0] + i, g);
@@ -1314,7 +1354,21 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
       const int e0 = i / (E * E), rem = i - e0 * E * E, e1 = rem / E, e2 = rem - e1 * E;
       lin = (size_t(wrap(org[0] + e0, g)) * g + wrap(org[1] + e1, g)) * g + wrap(org[2] + e2, g);
     }
-    tile[i] = a.grid[size_t(ch.prob) * a.grid_stride + lin];
+    return gp[lin];
+  };
+  constexpr int kTileBatch = 8;
+  for (int base = lo + int(threadIdx.x); base < hi; base += kTileBatch * kBlock) {
+    R v[kTileBatch];
+#pragma unroll
+    for (int u = 0; u < kTileBatch; ++u) {
+      const int i = base + u * kBlock;
+      if (i < hi) v[u] = grid_at(i);
+    }
+#pragma unroll
+    for (int u = 0; u < kTileBatch; ++u) {
+      const int i = base + u * kBlock;
+      if (i < hi) tile[i] = v[u];
+    }
   }
   __syncthreads();
 
@@ -1328,13 +1382,16 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
   // nfq: the point's near-field sum, loaded by the caller before the
   // interpolation (a load inside here lets the compiler hoist it above the
   // tap loop together with the LDS reads, at a large cost in registers)
-  auto epilogue = [&](int q, R acc, double nfq) {
+  auto epilogue = [&](int q, R acc, double nfq, double p, double aold) {
     const double t = (double(acc) + nfq) * outmul;
+    if (!pa && a.epi != EPI_OUT) {
+      p = a.p[q];
+      aold = a.alpha[q];
+    }
     if constexpr (LOG) {
       // alpha_old t = exp((beta_old + shift)/eps - 1) S: the marginal entry of
       // the state before the update
-      const double p = a.p[q];
-      const double bold = a.alpha[q];
+      const double bold = aold;
       const double m = p > 0.0 ? exp((bold + shift) * linv - 1.0) * t : 0.0;
       const double res = m - p;
       acc_red.res2 += res * res;
@@ -1367,8 +1424,6 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
     } else {
       // EPI_SINK and EPI_EVAL: the residual of eq. (Error) of the state before
       // the update, alpha_old t - p (fused: no extra kernel product)
-      const double p = a.p[q];
-      const double aold = a.alpha[q];
       const double res = aold * t - p;
       acc_red.res2 += res * res;
       if (p > 0.0) {
@@ -1396,35 +1451,74 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(InterpArgs<R> a) {
   // consecutive runs: global accesses stay coalesced, and lanes in the same
   // cell read the same LDS words (a broadcast).
   const WinEval<R> ev(a.win, a.wpoly, M);
-  constexpr int G = run_length<R>(D);
-  constexpr int GI = kInterpRun < G ? kInterpRun : G;  // points per interpolation run, divides G
-  constexpr int SUB = G / GI;
-  const int* runs = a.runs + ch.start;
-  const int nfull = a.nruns[2 * cb], nsingle = a.nruns[2 * cb + 1];
-  for (int rr = threadIdx.x; rr < nfull * SUB; rr += kBlock) {
-    const int q0 = ch.start + runs[rr / SUB] + (rr % SUB) * GI;
-    double nfq[GI];
+  auto step = [&](int q0, const auto& in) {
+    constexpr int GC = sizeof(in.u) / sizeof(in.u[0]);
+    double nfq[GC];
 #pragma unroll
-    for (int p = 0; p < GI; ++p) nfq[p] = a.nf ? a.nf[q0 + p] : 0.0;
-    R acc[GI];
-    interp_run<R, D, M, GI>(tile, a, ev, E, q0, acc);
+    for (int p = 0; p < GC; ++p) nfq[p] = a.nf ? a.nf[q0 + p] : 0.0;
+    R acc[GC];
+    interp_run<R, D, M, GC>(tile, ev, E, in.u, acc);
 #pragma unroll
-    for (int p = 0; p < GI; ++p) epilogue(q0 + p, acc[p], nfq[p]);
-  }
-  for (int rr = threadIdx.x; rr < nsingle; rr += kBlock) {
-    const int q0 = ch.start + runs[nfull + rr];
-    const double nfq = a.nf ? a.nf[q0] : 0.0;
-    R acc[1];
-    interp_run<R, D, M, 1>(tile, a, ev, E, q0, acc);
-    epilogue(q0, acc[0], nfq);
+    for (int p = 0; p < GC; ++p) epilogue(q0 + p, acc[p], nfq[p], in.p[p], in.al[p]);
+  };
+  if constexpr (ahead) {
+    for (int rr = threadIdx.x; rr < nit; rr += kBlock) {
+      const int rn = rr + kBlock;
+      PointIn<R, D, GI> nxt;
+      int qn = 0;
+      if (rn < nit) {
+        qn = step_q0(rn);
+        nxt.load(a, qn, pa);
+      }
+      step(qc, cur);
+      cur = nxt;
+      qc = qn;
+    }
+    PointIn<R, D, 1> one;
+    int q1 = 0;
+    if (int(threadIdx.x) < nsingle) {
+      q1 = ch.start + runs[nfull + threadIdx.x];
+      one.load(a, q1, pa);
+    }
+    for (int rr = threadIdx.x; rr < nsingle; rr += kBlock) {
+      const int rn = rr + kBlock;
+      PointIn<R, D, 1> nxt;
+      int qn = 0;
+      if (rn < nsingle) {
+        qn = ch.start + runs[nfull + rn];
+        nxt.load(a, qn, pa);
+      }
+      step(q1, one);
+      one = nxt;
+      q1 = qn;
+    }
+  } else {
+    for (int rr = threadIdx.x; rr < nit; rr += kBlock) {
+      const int q0 = step_q0(rr);
+      PointIn<R, D, GI> in;
+      in.load(a, q0, false);
+      step(q0, in);
+    }
+    for (int rr = threadIdx.x; rr < nsingle; rr += kBlock) {
+      const int q0 = ch.start + runs[nfull + rr];
+      PointIn<R, D, 1> in;
+      in.load(a, q0, false);
+      step(q0, in);
+    }
   }
   if (a.epi != EPI_OUT) {
+    // this chunk's partial; reduce_stats_kernel combines them per problem
     const Red r = block_reduce(acc_red, red_sh);
-    const int pb = ch.prob;
-    finish_reduce(r, red_sh, a.partials, a.counter + pb, a.stats + kStat * pb,
-                  a.wmul_next ? a.wmul_next + pb : nullptr, a.src_l1 ? a.src_l1 + kStat * pb : nullptr,
-                  a.pstate ? a.pstate + kPState * pb : nullptr, a.tol2, a.half, a.prob_chunks[pb],
-                  a.prob_chunks[pb + 1], logd, cb);
+    if (threadIdx.x == 0) {
+      double* pw = a.partials + kRedVals * size_t(cb);
+      pw[0] = r.res2;
+      pw[1] = r.mass;
+      pw[2] = r.l1;
+      pw[3] = r.mx;
+      pw[4] = r.tmin;
+      pw[5] = r.tmax;
+      pw[6] = r.cnt;
+    }
   }
 }
 
@@ -1554,6 +1648,10 @@ hipError_t launch_interp(const InterpArgs<R>& a, int nchunks, hipStream_t st) {
       NFS_DISPATCH_M_X(3, R, interp_kernel, false, a, nchunks, shm, st)
     }
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.epi == EPI_OUT) return e;
+  if (a.nprob <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(reduce_stats_kernel<R>, dim3(a.nprob), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
 
