@@ -175,7 +175,13 @@ def batched_leg(nfs, workloads, torch, T, iters=10, sample_every=16):
     ys = [T(p["y"]) for p in probs]
     pts = [T(p["pt"]) for p in probs]
     eps = [p["eps"] for p in probs]
+    s = nfs.BatchSolver(prm, xs, ps, ys, pts, eps)  # loads the code objects
+    s.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     s = nfs.BatchSolver(prm, xs, ps, ys, pts, eps)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
     s.iterate(2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -209,7 +215,7 @@ def batched_leg(nfs, workloads, torch, T, iters=10, sample_every=16):
     ares = nfs.batch_sinkhorn(aprm, xs, ps, ys, pts, eps, iters, check=False)
     torch.cuda.synchronize()
     t_auto = time.perf_counter() - t0
-    return {"problems": len(probs), "points": npts, "ms_per_iteration": t_batch * 1e3,
+    return {"problems": len(probs), "points": npts, "plan_ms": t_plan * 1e3, "ms_per_iteration": t_batch * 1e3,
             "problem_iterations_per_s": len(probs) / t_batch,
             "plain_sequential_ms_per_iteration_est": t_plain * 1e3,
             "speedup_vs_plain": t_plain / t_batch,

@@ -240,8 +240,7 @@ struct BoxArgs {
   long nw;
   int d;
   int wsum;
-  double* partials;   // kBoxVals per block, 1024 blocks
-  unsigned* counter;
+  double* partials;   // kBoxVals per block, up to 1024 blocks
   double* out;
 };
 hipError_t launch_bbox(const BoxArgs& a, hipStream_t st);
@@ -359,8 +358,7 @@ struct ReadoutArgs {
   const double* b;
   long n;
   int logv;  // b holds potentials: sum a b instead of sum a log b
-  double* partials;
-  unsigned* counter;
+  double* partials;   // 3 per block, 256 blocks
   double* out;
 };
 hipError_t launch_readout(const ReadoutArgs& a, hipStream_t st);
@@ -376,11 +374,11 @@ hipError_t launch_logweights(const Chunk* chunks, int nchunks, const double* pot
 hipError_t launch_mul(const double* a, const double* b, long n, double* out, hipStream_t st);
 
 // out[0] = max v, out[1] = sum v (non-finite if any entry is), over n values.
-hipError_t launch_maxsum(const double* v, long n, double* partials, unsigned* counter, double* out, hipStream_t st);
+hipError_t launch_maxsum(const double* v, long n, double* partials, double* out, hipStream_t st);
 
 // grad_mu: out[i] = eps*log(alpha[i]) - shift (out[perm[i]] with perm), with shift = eps*mean(log alpha)
 // over the n entries (zero scalings count as log 0 = 0: weight zero, see Proposition 2.3)
-hipError_t launch_gradmu(const double* alpha, long n, double eps, double* partials, unsigned* counter,
+hipError_t launch_gradmu(const double* alpha, long n, double eps, double* partials,
                          double* mean_out, double* grad_mu, hipStream_t st, const int* perm = nullptr);
 
 // NFFT spectrum conversion between user layout (full I_N, complex FP64) and

@@ -192,7 +192,6 @@ struct Work {
   R* dtab2 = nullptr;  // B cost tables
   double* inv_phi = nullptr;
   double* partials = nullptr;
-  unsigned* ct_misc = nullptr;    // 8
   double* st_row = nullptr;   // B x kStat: statistics of the alpha updates
   double* st_col = nullptr;   // B x kStat: statistics of the alpha_t updates
   double* st_eval = nullptr;  // B x kStat: statistics of the evaluation half-steps
@@ -319,7 +318,6 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
   w.wpoly = cv.take<double>((sizeof(R) == 4 ? sizeof(WindowPoly) : sizeof(WindowPoly64)) / sizeof(double) + 1);
   const long maxch = std::max(w.X.max_chunks, w.Y.max_chunks);
   w.partials = cv.take<double>(size_t(std::max<long>(maxch, 1024)) * kBoxVals);
-  w.ct_misc = cv.take<unsigned>(8);
   w.st_row = cv.take<double>(size_t(B) * kStat);
   w.st_col = cv.take<double>(size_t(B) * kStat);
   w.st_eval = cv.take<double>(size_t(B) * kStat);
@@ -350,7 +348,6 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
 // never records a memset).
 template <typename R>
 static int zero_state(Work<R>& w, hipStream_t st) {
-  NFS_HIP(launch_fill(w.ct_misc, sizeof(unsigned) * 8, st));
   for (double* s : {w.st_row, w.st_col, w.st_eval}) NFS_HIP(launch_fill(s, sizeof(double) * kStat * w.B, st));
   NFS_HIP(launch_fill(w.pstate, sizeof(int) * kPState * w.B, st));
   NFS_HIP(launch_fill(w.tol2, sizeof(double), st));
@@ -361,7 +358,7 @@ static int zero_state(Work<R>& w, hipStream_t st) {
 // ----------------------------------------------------------------------------- plan stage
 // Bounding box of up to two clouds plus the statistics of one weight vector,
 // written to out[0..8] on the device (no synchronization).
-static int box_launch(double* out, double* partials, unsigned* counter, int d, const double* p0, long n0,
+static int box_launch(double* out, double* partials, int d, const double* p0, long n0,
                       const double* p1, long n1, const double* w, long nw, hipStream_t st, int wsum = 0) {
   BoxArgs b{};
   b.wsum = wsum;
@@ -373,7 +370,6 @@ static int box_launch(double* out, double* partials, unsigned* counter, int d, c
   b.nw = nw;
   b.d = d;
   b.partials = partials;
-  b.counter = counter;
   b.out = out;
   NFS_HIP(launch_bbox(b, st));
   return NFS_OK;
@@ -912,7 +908,7 @@ static int do_fastsum(const nfs_params* p, const double* src, int64_t ns, const 
     wv = w.tmp;
   }
   double box[kBoxVals];
-  NFS_TRY(box_launch(w.st_box, w.partials, w.ct_misc, p->d, src, ns, tgt, nt, wv, ns, st));
+  NFS_TRY(box_launch(w.st_box, w.partials, p->d, src, ns, tgt, nt, wv, ns, st));
   NFS_HIP(hipMemcpyAsync(box, w.st_box, sizeof(box), hipMemcpyDeviceToHost, st));
   NFS_HIP(hipStreamSynchronize(st));
   for (int i = 0; i < 9; ++i)
@@ -983,7 +979,7 @@ static int do_nfft(const nfs_params* p, bool adjoint, const double* pts, int64_t
   w.Y.off = {0, 0};
   NFS_TRY(zero_state(w, st));
   double box[kBoxVals];
-  NFS_TRY(box_launch(w.st_box, w.partials, w.ct_misc, p->d, pts, n, nullptr, 0, wv, wv ? n : 0, st));
+  NFS_TRY(box_launch(w.st_box, w.partials, p->d, pts, n, nullptr, 0, wv, wv ? n : 0, st));
   NFS_HIP(hipMemcpyAsync(box, w.st_box, sizeof(box), hipMemcpyDeviceToHost, st));
   NFS_HIP(hipStreamSynchronize(st));
   for (int c = 0; c < p->d; ++c)
@@ -1133,11 +1129,11 @@ static int plan_sinkhorn(Work<R>& w, const nfs_params* p, const double* eps, con
     double* slot = w.st_box + kBoxSlot * b;
     if (centred) {
       // separate boxes and weighted means of the two clouds
-      NFS_TRY(box_launch(slot, w.partials, w.ct_misc, d, x + ox * d, nx, nullptr, 0, mu + ox, nx, st, 1));
-      NFS_TRY(box_launch(slot + kBoxVals, w.partials, w.ct_misc, d, y + oy * d, ny, nullptr, 0, nu + oy, ny, st, 1));
+      NFS_TRY(box_launch(slot, w.partials, d, x + ox * d, nx, nullptr, 0, mu + ox, nx, st, 1));
+      NFS_TRY(box_launch(slot + kBoxVals, w.partials, d, y + oy * d, ny, nullptr, 0, nu + oy, ny, st, 1));
     } else {
-      NFS_TRY(box_launch(slot, w.partials, w.ct_misc, d, x + ox * d, nx, y + oy * d, ny, mu + ox, nx, st));
-      NFS_TRY(box_launch(slot + kBoxVals, w.partials, w.ct_misc, d, nullptr, 0, nullptr, 0, nu + oy, ny, st));
+      NFS_TRY(box_launch(slot, w.partials, d, x + ox * d, nx, y + oy * d, ny, mu + ox, nx, st));
+      NFS_TRY(box_launch(slot + kBoxVals, w.partials, d, nullptr, 0, nullptr, 0, nu + oy, ny, st));
     }
   }
   std::vector<double> box(size_t(B) * kBoxSlot);
@@ -1269,7 +1265,7 @@ struct Solver : SolverBase {
     NFS_HIP(map_centred(w.X, 0, nullptr, st));
     NFS_HIP(map_centred(w.Y, 1, nullptr, st));
     for (int b = 0; b < B; ++b)
-      NFS_HIP(launch_maxsum(w.Y.w1s + w.Y.off[b], w.Y.off[b + 1] - w.Y.off[b], w.partials, w.ct_misc,
+      NFS_HIP(launch_maxsum(w.Y.w1s + w.Y.off[b], w.Y.off[b + 1] - w.Y.off[b], w.partials,
                             w.st_box + 2 * b, st));
     std::vector<double> ms(size_t(B) * 2), wm(B), col(size_t(B) * kStat);
     NFS_HIP(hipMemcpyAsync(ms.data(), w.st_box, sizeof(double) * ms.size(), hipMemcpyDeviceToHost, st));
@@ -1374,7 +1370,7 @@ struct Solver : SolverBase {
       return NFS_OK;
     }
     for (int b = 0; b < B; ++b)
-      NFS_TRY(box_launch(w.st_box + kBoxSlot * b, w.partials, w.ct_misc, p.d, nullptr, 0, nullptr, 0,
+      NFS_TRY(box_launch(w.st_box + kBoxSlot * b, w.partials, p.d, nullptr, 0, nullptr, 0,
                          alpha_t0 + oy[b], oy[b + 1] - oy[b], st));
     std::vector<double> box(size_t(B) * kBoxSlot), wm(B);
     NFS_HIP(hipMemcpyAsync(box.data(), w.st_box, sizeof(double) * box.size(), hipMemcpyDeviceToHost, st));
@@ -1407,7 +1403,7 @@ struct Solver : SolverBase {
     } else {
       std::vector<double> ms(size_t(B) * 2);
       for (int b = 0; b < B; ++b)
-        NFS_HIP(launch_maxsum(gamma0 + oy[b], oy[b + 1] - oy[b], w.partials, w.ct_misc, w.st_box + 2 * b, st));
+        NFS_HIP(launch_maxsum(gamma0 + oy[b], oy[b + 1] - oy[b], w.partials, w.st_box + 2 * b, st));
       NFS_HIP(hipMemcpyAsync(ms.data(), w.st_box, sizeof(double) * ms.size(), hipMemcpyDeviceToHost, st));
       NFS_HIP(hipStreamSynchronize(st));
       for (int b = 0; b < B; ++b) {
@@ -1626,7 +1622,7 @@ struct Solver : SolverBase {
       if (outm)
         for (int b = 0; b < B; ++b) {
           const long o = tgt.off[b];
-          NFS_HIP(launch_gradmu(tgt.w1s + o, tgt.off[b + 1] - o, eps[b], w.partials, w.ct_misc + 2, w.st_cost, outm, st,
+          NFS_HIP(launch_gradmu(tgt.w1s + o, tgt.off[b + 1] - o, eps[b], w.partials, w.st_cost, outm, st,
                                 tgt.perm + o));
         }
     }
@@ -1677,10 +1673,10 @@ struct Solver : SolverBase {
     NFS_HIP(hipMemcpyAsync(ev_col.data(), w.st_eval, sizeof(double) * ev_col.size(), hipMemcpyDeviceToHost, st));
     for (int b = 0; b < B; ++b) {
       const long ox = w.X.off[b], oy = w.Y.off[b];
-      ReadoutArgs ra{w.X.w0s + ox, w.X.w1s + ox, w.X.off[b + 1] - ox, int(logd), w.partials, w.ct_misc + 1,
+      ReadoutArgs ra{w.X.w0s + ox, w.X.w1s + ox, w.X.off[b + 1] - ox, int(logd), w.partials,
                      w.st_rdx + 4 * b};
       NFS_HIP(launch_readout(ra, st));
-      ReadoutArgs rb{w.Y.w0s + oy, w.Y.w1s + oy, w.Y.off[b + 1] - oy, int(logd), w.partials, w.ct_misc + 1,
+      ReadoutArgs rb{w.Y.w0s + oy, w.Y.w1s + oy, w.Y.off[b + 1] - oy, int(logd), w.partials,
                      w.st_rdy + 4 * b};
       NFS_HIP(launch_readout(rb, st));
     }
@@ -1694,7 +1690,7 @@ struct Solver : SolverBase {
       NFS_HIP(launch_interp(ia, w.X.nchunks, st));
       for (int b = 0; b < B; ++b) {
         const long ox = w.X.off[b];
-        ReadoutArgs rc{w.tmp + ox, w.tmp + ox, w.X.off[b + 1] - ox, 0, w.partials, w.ct_misc + 1,
+        ReadoutArgs rc{w.tmp + ox, w.tmp + ox, w.X.off[b + 1] - ox, 0, w.partials,
                        w.st_cost + 4 * b};
         NFS_HIP(launch_readout(rc, st));
       }
@@ -1822,10 +1818,10 @@ static int do_grad(const nfs_params* p, const double* x, int64_t n, const double
   nfs_params q = *p;
   q.flags &= ~NFS_FLAG_CENTER;
   NFS_TRY(plan_sinkhorn(w, &q, &eps, x, mu, y, nu, alpha, alpha_t, st));
-  if (grad_mu) NFS_HIP(launch_gradmu(alpha, n, p->eps, w.partials, w.ct_misc + 2, w.st_cost, grad_mu, st));
+  if (grad_mu) NFS_HIP(launch_gradmu(alpha, n, p->eps, w.partials, w.st_cost, grad_mu, st));
   if (grad_x) {
     double box[kBoxVals];
-    NFS_TRY(box_launch(w.st_box, w.partials, w.ct_misc, p->d, nullptr, 0, nullptr, 0, alpha_t, nt, st));
+    NFS_TRY(box_launch(w.st_box, w.partials, p->d, nullptr, 0, nullptr, 0, alpha_t, nt, st));
     NFS_HIP(hipMemcpyAsync(box, w.st_box, sizeof(box), hipMemcpyDeviceToHost, st));
     NFS_HIP(hipStreamSynchronize(st));
     if (!(box[6] > 0.0) || !std::isfinite(box[6])) return fail(NFS_EINVAL, "alpha_t must be positive and finite");

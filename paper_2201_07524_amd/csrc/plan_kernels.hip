@@ -1,5 +1,7 @@
 // Plan-stage kernels (bounding box, tile keys, counting-sort scatter) and the
 // small elementwise / reduction kernels around the fast summation.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -24,36 +26,54 @@ __device__ void block_reduce_arr(double (&v)[NV], const bool (&is_min)[NV], cons
   __syncthreads();
 }
 
-// Writes this block's values to partials, and lets the last block reduce all
-// partials into out.  Returns nothing; uses a ticket counter left at zero.
+// Writes this block's values to partials[blockIdx.x NV + k]; the
+// finish_partials kernel launched after the kernel combines them.
 template <int NV>
 __device__ void grid_reduce_arr(double (&v)[NV], const bool (&is_min)[NV], const bool (&is_max)[NV],
-                                double* partials, unsigned* counter, double* out) {
+                                double* partials) {
   __shared__ double sh[NV][kBlock];
-  __shared__ bool last;
   block_reduce_arr<NV>(v, is_min, is_max, sh);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0)
     for (int k = 0; k < NV; ++k) partials[size_t(blockIdx.x) * NV + k] = v[k];
-    __threadfence();
-    last = atomicAdd(counter, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
+}
+
+// Combines the nb partials of a grid reduction, in block order, into out[NV]:
+// entry k is a min where bit k of min_mask is set, a max where it is set in
+// max_mask, else a sum.  Launched right after the kernel that wrote them, so
+// that the kernel boundary makes them visible.  (A fence and a ticket per
+// workgroup, the last one combining, write the L2 back once per workgroup on
+// a part with one L2 per XCD.)
+template <int NV>
+__global__ __launch_bounds__(kBlock) void finish_partials_kernel(const double* partials, int nb, unsigned min_mask,
+                                                                 unsigned max_mask, double* out) {
+  __shared__ double sh[NV][kBlock];
+  bool is_min[NV], is_max[NV];
   double acc[NV];
-  for (int k = 0; k < NV; ++k) acc[k] = is_min[k] ? 1e308 : (is_max[k] ? -1e308 : 0.0);
-  const volatile double* pv = partials;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
+  for (int k = 0; k < NV; ++k) {
+    is_min[k] = (min_mask >> k) & 1u;
+    is_max[k] = (max_mask >> k) & 1u;
+    acc[k] = is_min[k] ? 1e308 : (is_max[k] ? -1e308 : 0.0);
+  }
+  for (int b = threadIdx.x; b < nb; b += kBlock)
     for (int k = 0; k < NV; ++k) {
-      const double x = pv[size_t(b) * NV + k];
+      const double x = partials[size_t(b) * NV + k];
       acc[k] = is_min[k] ? fmin(acc[k], x) : (is_max[k] ? fmax(acc[k], x) : acc[k] + x);
     }
   block_reduce_arr<NV>(acc, is_min, is_max, sh);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0)
     for (int k = 0; k < NV; ++k) out[k] = acc[k];
-    *counter = 0u;
-  }
 }
+
+template <int NV>
+static hipError_t finish_partials(const double* partials, int nb, unsigned min_mask, unsigned max_mask, double* out,
+                                  hipStream_t st) {
+  hipLaunchKernelGGL(finish_partials_kernel<NV>, dim3(1), dim3(kBlock), 0, st, partials, nb, min_mask, max_mask, out);
+  return hipGetLastError();
+}
+
+// Per-entry kinds of the grid reductions below (bit k: entry k is a min / a max).
+constexpr unsigned kBoxMin = 0x87u, kBoxMax = 0x78u;  // box: min_c (0-2), max_c (3-5), max|w|, min w (7)
+constexpr unsigned kMaxSumMax = 0x1u;                 // maxsum: max, sum
 
 constexpr int kGridBlocks = 1024;
 
@@ -65,8 +85,8 @@ __global__ __launch_bounds__(kBlock) void bbox_kernel(BoxArgs a) {
   double v[NV];
   bool is_min[NV], is_max[NV];
   for (int k = 0; k < NV; ++k) {
-    is_min[k] = (k < 3) || k == 7;
-    is_max[k] = (k >= 3 && k < 7);
+    is_min[k] = (kBoxMin >> k) & 1u;
+    is_max[k] = (kBoxMax >> k) & 1u;
     v[k] = is_min[k] ? 1e308 : (is_max[k] ? -1e308 : 0.0);
   }
   const long stride = long(gridDim.x) * kBlock;
@@ -89,7 +109,7 @@ __global__ __launch_bounds__(kBlock) void bbox_kernel(BoxArgs a) {
       if (a.wsum)
         for (int c = 0; c < a.d; ++c) v[9 + c] += w * a.pts[0][i * a.d + c];
     }
-  grid_reduce_arr<NV>(v, is_min, is_max, a.partials, a.counter, a.out);
+  grid_reduce_arr<NV>(v, is_min, is_max, a.partials);
 }
 
 // ------------------------------------------------------------------ centred form read-out
@@ -134,8 +154,13 @@ template hipError_t launch_uncenter<float>(const UncenterArgs<float>&, int, hipS
 template hipError_t launch_uncenter<double>(const UncenterArgs<double>&, int, hipStream_t);
 
 hipError_t launch_bbox(const BoxArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(bbox_kernel, dim3(kGridBlocks), dim3(kBlock), 0, st, a);
-  return hipGetLastError();
+  // about eight values per thread, so the boxes of small problems are a few workgroups
+  const long n = std::max(std::max(a.n[0], a.n[1]), a.nw);
+  const int nb = int(std::min<long>(kGridBlocks, std::max<long>(1, (n + 8 * kBlock - 1) / (8 * kBlock))));
+  hipLaunchKernelGGL(bbox_kernel, dim3(nb), dim3(kBlock), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return finish_partials<kBoxVals>(a.partials, nb, kBoxMin, kBoxMax, a.out, st);
 }
 
 // ------------------------------------------------------------------ keys + histogram
@@ -626,12 +651,14 @@ __global__ __launch_bounds__(kBlock) void readout_kernel(ReadoutArgs a) {
     }
     v[2] += x;
   }
-  grid_reduce_arr<NV>(v, is_min, is_max, a.partials, a.counter, a.out);
+  grid_reduce_arr<NV>(v, is_min, is_max, a.partials);
 }
 
 hipError_t launch_readout(const ReadoutArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(readout_kernel, dim3(256), dim3(kBlock), 0, st, a);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return finish_partials<3>(a.partials, 256, 0u, 0u, a.out, st);
 }
 
 // Log domain: the spread weights exp((pot - shift)/eps) of one chunk per workgroup.
@@ -665,36 +692,36 @@ hipError_t launch_mul(const double* a, const double* b, long n, double* out, hip
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kBlock) void maxsum_kernel(const double* vals, long n, double* partials,
-                                                        unsigned* counter, double* out) {
+__global__ __launch_bounds__(kBlock) void maxsum_kernel(const double* vals, long n, double* partials) {
   constexpr int NV = 2;
   double v[NV] = {-INFINITY, 0.0};
-  const bool is_min[NV] = {false, false}, is_max[NV] = {true, false};
+  const bool is_min[NV] = {false, false}, is_max[NV] = {(kMaxSumMax & 1u) != 0, false};
   const long stride = long(gridDim.x) * kBlock;
   for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
     v[0] = fmax(v[0], vals[i]);
     v[1] += vals[i];
   }
-  grid_reduce_arr<NV>(v, is_min, is_max, partials, counter, out);
+  grid_reduce_arr<NV>(v, is_min, is_max, partials);
 }
 
-hipError_t launch_maxsum(const double* v, long n, double* partials, unsigned* counter, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(maxsum_kernel, dim3(256), dim3(kBlock), 0, st, v, n, partials, counter, out);
-  return hipGetLastError();
+hipError_t launch_maxsum(const double* v, long n, double* partials, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(maxsum_kernel, dim3(256), dim3(kBlock), 0, st, v, n, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return finish_partials<2>(partials, 256, 0u, kMaxSumMax, out, st);
 }
 
 // eps log alpha_i enters the weight gradient only where alpha_i > 0: a point of
 // weight zero has scaling zero and contributes 0 log 0 = 0 to the dual.
 __device__ __forceinline__ double log_or_zero(double a) { return a > 0.0 ? log(a) : 0.0; }
 
-__global__ __launch_bounds__(kBlock) void logmean_kernel(const double* alpha, long n, double* partials,
-                                                         unsigned* counter, double* out) {
+__global__ __launch_bounds__(kBlock) void logmean_kernel(const double* alpha, long n, double* partials) {
   constexpr int NV = 1;
   double v[NV] = {0.0};
   const bool is_min[NV] = {false}, is_max[NV] = {false};
   const long stride = long(gridDim.x) * kBlock;
   for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) v[0] += log_or_zero(alpha[i]);
-  grid_reduce_arr<NV>(v, is_min, is_max, partials, counter, out);
+  grid_reduce_arr<NV>(v, is_min, is_max, partials);
 }
 
 __global__ __launch_bounds__(kBlock) void gradmu_kernel(const double* alpha, long n, double eps,
@@ -703,9 +730,12 @@ __global__ __launch_bounds__(kBlock) void gradmu_kernel(const double* alpha, lon
   if (i < n) g[perm ? long(perm[i]) : i] = eps * (log_or_zero(alpha[i]) - *sumlog / double(n));
 }
 
-hipError_t launch_gradmu(const double* alpha, long n, double eps, double* partials, unsigned* counter,
-                         double* mean_out, double* grad_mu, hipStream_t st, const int* perm) {
-  hipLaunchKernelGGL(logmean_kernel, dim3(256), dim3(kBlock), 0, st, alpha, n, partials, counter, mean_out);
+hipError_t launch_gradmu(const double* alpha, long n, double eps, double* partials, double* mean_out,
+                         double* grad_mu, hipStream_t st, const int* perm) {
+  hipLaunchKernelGGL(logmean_kernel, dim3(256), dim3(kBlock), 0, st, alpha, n, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = finish_partials<1>(partials, 256, 0u, 0u, mean_out, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(gradmu_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, alpha, n, eps,
                      (const double*)mean_out, perm, grad_mu);
   return hipGetLastError();
