@@ -68,10 +68,15 @@ extern "C" {
 #define NFS_FLAG_TILE_REDUCE 4   /* spread: store each chunk's LDS tile and sum the tiles per
                                     (tile, neighbour) instead of flushing LDS tiles straight
                                     into the grid with global atomics (the default) */
-#define NFS_FLAG_AUTOTUNE 16     /* solver handles (and the solves built on them): after the plan,
-                                    time a few iterations at each candidate chunk size (the default,
-                                    twice it, 4096, 8192 points; r = 2 only) and keep the fastest;
-                                    the starting values are restored before the first iteration */
+#define NFS_FLAG_AUTOTUNE 16     /* solver handles (and the solves built on them), r = 2 only: the
+                                    spreading tile and bin sizes by measurement.  With tile = 0,
+                                    plan and time a warm-up and three iterations at half, one and
+                                    two times the default tile (those whose LDS tile fits) and keep
+                                    the fastest; then time a few iterations at each candidate chunk
+                                    size (the points a workgroup takes: the default, twice it, 4096,
+                                    8192) and keep the fastest.  The starting values are restored
+                                    before the first iteration; nfs_workspace_size() covers every
+                                    candidate tile */
 #define NFS_FLAG_CENTER 32       /* solve calls, r = 2: the centred form.  For the squared cost,
                                     |x - y|^2 = |x' - y'|^2 - 2 delta.(x' - y') + |delta|^2 with
                                     x' = x + delta/2, y' = y - delta/2 and delta = mean_nu y -
@@ -249,8 +254,8 @@ int nfs_solver_finish(nfs_solver* s, double* alpha, double* alpha_t, nfs_result*
 /* Runs `iters` iterations with direct launches and events between kernels;
  * stage_ms[5] receives the average device time per launch of spreading, of
  * the FFT chain, of interpolation with the scaling update, of one whole
- * iteration, and of the near-field sum (r = 1; about 0 for r = 2).  info (nullable, 8 doubles): n, nt, d, grid cells, bytes per grid
- * value, chunks of x, chunks of y, taps per point. */
+ * iteration, and of the near-field sum (r = 1; about 0 for r = 2).  info (nullable, 9 doubles): n, nt, d, grid cells, bytes per grid
+ * value, chunks of x, chunks of y, taps per point, tile size T. */
 int nfs_solver_profile(nfs_solver* s, int32_t iters, double* stage_ms, double* info, void* stream);
 /* Envelope gradient of the cost at the solver's current scalings (as
  * nfs_sinkhorn_grad and nfs_sinkhorn_grad_targets; Proposition 2.3, eq. (14)),

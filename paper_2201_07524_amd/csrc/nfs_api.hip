@@ -58,6 +58,22 @@ static int default_tile(int d, int precision) {
   return d == 1 ? 64 : (d == 2 ? 32 : 8);
 }
 
+// Tile sizes that NFS_FLAG_AUTOTUNE times on a solver (r = 2, tile left at
+// 0): half, one and two times the default, those whose (T + 2m + 1)^d LDS
+// tile fits and whose T^d cells the per-tile cell sort can order.  Empty
+// when the tile is not tuned.
+static std::vector<int> tile_candidates(const nfs_params* p) {
+  std::vector<int> c;
+  if (!(p->flags & NFS_FLAG_AUTOTUNE) || p->tile != 0 || p->r != 2) return c;
+  const int T0 = default_tile(p->d, p->precision);
+  for (int T : {T0 / 2, T0, 2 * T0}) {
+    if (T < 4) continue;
+    const double tb = std::pow(double(T + 2 * p->m + 1), p->d) * (p->precision == NFS_FP32 ? 4.0 : 8.0);
+    if (tb <= 160.0 * 1024.0 && std::pow(double(T), p->d) <= double(kSortBins)) c.push_back(T);
+  }
+  return c;
+}
+
 // Points per chunk: 1536 for the FP32 2-D path (measured best on the 2-D
 // mixture: longer same-cell runs, fewer tile loads and flushes per point,
 // still about 700 workgroups per launch), 1024 otherwise (r = 1 needs <= 1024).
@@ -1433,19 +1449,58 @@ struct Solver : SolverBase {
       ox[b + 1] = ox[b] + n[b];
       oy[b + 1] = oy[b] + nt[b];
     }
-    carve(w, &p, B, ox[B], oy[B], nullptr, 2);
-    if (wsb < w.bytes) return fail(NFS_EWORKSPACE, "workspace too small");
-    carve(w, &p, B, ox[B], oy[B], static_cast<char*>(ws), 2);
-    w.X.off = ox;
-    w.Y.off = oy;
     hipStream_t st = caller;
-    NFS_TRY(plan_sinkhorn(w, &p, eps.data(), x, mu, y, nu, nullptr, alpha_t0, st));
-    if (logd) {
-      NFS_TRY(start_log(B, oy, alpha_t0, st));
-    } else {
-      NFS_TRY(start_scalings(B, oy, alpha_t0, st));
+    // carve the workspace for the parameters q, plan, and set the starting values
+    auto prepare = [&](const nfs_params& q) -> int {
+      w = Work<R>{};
+      carve(w, &q, B, ox[B], oy[B], nullptr, 2);
+      if (wsb < w.bytes) return fail(NFS_EWORKSPACE, "workspace too small");
+      carve(w, &q, B, ox[B], oy[B], static_cast<char*>(ws), 2);
+      w.X.off = ox;
+      w.Y.off = oy;
+      NFS_TRY(plan_sinkhorn(w, &q, eps.data(), x, mu, y, nu, nullptr, alpha_t0, st));
+      if (logd) {
+        NFS_TRY(start_log(B, oy, alpha_t0, st));
+      } else {
+        NFS_TRY(start_scalings(B, oy, alpha_t0, st));
+      }
+      if (centred) NFS_TRY(centre_start(st));
+      return NFS_OK;
+    };
+    const std::vector<int> tiles = tile_candidates(&p);
+    if (tiles.size() > 1) {
+      // the tile: plan and time one warm-up and three iterations per candidate
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      NFS_HIP(hipEventCreate(&e0));
+      NFS_HIP(hipEventCreate(&e1));
+      float best = 0.0f;
+      int best_tile = tiles.front(), rc = NFS_OK;
+      for (int T : tiles) {
+        nfs_params q = p;
+        q.tile = T;
+        if ((rc = prepare(q)) != NFS_OK) break;
+        hipError_t e = iteration(st);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int i = 0; i < 3 && e == hipSuccess; ++i) e = iteration(st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          rc = fail(NFS_EHIP, std::string("tile autotune: ") + hipGetErrorString(e));
+          break;
+        }
+        if (T == tiles.front() || ms < best) {
+          best = ms;
+          best_tile = T;
+        }
+      }
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      NFS_TRY(rc);
+      p.tile = best_tile;
     }
-    if (centred) NFS_TRY(centre_start(st));
+    NFS_TRY(prepare(p));
     if ((p.flags & NFS_FLAG_AUTOTUNE) && p.r == 2 && !w.two_level) NFS_TRY(autotune(st));
     NFS_HIP(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
     NFS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -1656,6 +1711,7 @@ struct Solver : SolverBase {
     info[5] = w.X.nchunks;
     info[6] = w.Y.nchunks;
     info[7] = std::pow(2.0 * p.m + 1.0, p.d);
+    info[8] = w.geo.T;
     return NFS_OK;
   }
 
@@ -1865,14 +1921,22 @@ static int batch_sizes(const nfs_params* prm, int32_t B, const int64_t* n, const
 }
 
 static int batch_workspace(const nfs_params* prm, int32_t B, long sn, long snt, size_t* bytes) {
-  if (prm->precision == NFS_FP32) {
-    Work<float> w;
-    carve(w, prm, B, sn, snt, nullptr, 2);
-    *bytes = w.bytes;
-  } else {
-    Work<double> w;
-    carve(w, prm, B, sn, snt, nullptr, 2);
-    *bytes = w.bytes;
+  // a solver that tunes its tile plans once per candidate in the same workspace
+  std::vector<int> tiles = tile_candidates(prm);
+  if (tiles.empty()) tiles.push_back(prm->tile);
+  nfs_params q = *prm;
+  *bytes = 0;
+  for (int T : tiles) {
+    q.tile = T;
+    if (prm->precision == NFS_FP32) {
+      Work<float> w;
+      carve(w, &q, B, sn, snt, nullptr, 2);
+      *bytes = std::max(*bytes, w.bytes);
+    } else {
+      Work<double> w;
+      carve(w, &q, B, sn, snt, nullptr, 2);
+      *bytes = std::max(*bytes, w.bytes);
+    }
   }
   return NFS_OK;
 }

@@ -475,9 +475,9 @@ class Solver:
         """Average device ms per launch of (spread, fft chain, interp+update, iteration, near field)
         and sizes."""
         st = (ctypes.c_double * 5)()
-        info = (ctypes.c_double * 8)()
+        info = (ctypes.c_double * 9)()
         _check(load_library().nfs_solver_profile(self.h, int(k), st, info, _stream()))
-        keys = ("n", "nt", "d", "grid_cells", "grid_value_bytes", "chunks_x", "chunks_y", "taps_per_point")
+        keys = ("n", "nt", "d", "grid_cells", "grid_value_bytes", "chunks_x", "chunks_y", "taps_per_point", "tile")
         return list(st), dict(zip(keys, list(info)))
 
     def close(self):

@@ -1,9 +1,11 @@
-"""NFS_FLAG_AUTOTUNE: the solver times a few iterations at each candidate
-chunk size after the plan and keeps the fastest, then restores the starting
-values.  The chunking only changes the order of the sums, so the tuned and the
-plain solves agree to rounding (FP64), the iteration count and the t <= 0
-counters are unaffected, and the tuned chunk is never smaller than the
-default (fewer or as many chunks)."""
+"""NFS_FLAG_AUTOTUNE: the solver plans and times a few iterations at each
+candidate tile size (half, one and two times the default) and then at each
+candidate chunk size, keeps the fastest, and restores the starting values.
+The fixed-point grids make the spread sums exact, so tiles and chunks only
+change the order of the FP64 reductions: the tuned and the plain solves agree
+to rounding, the iteration count and the t <= 0 counters are unaffected, and
+at the default tile the tuned chunk is never smaller than the default (fewer
+or as many chunks)."""
 import numpy as np
 import pytest
 
@@ -37,7 +39,9 @@ def test_autotuned_solve_matches_plain(warm):
     plain, ip = solve(cfg, 0, 15, alpha_t0=start)
     tuned, it = solve(cfg, nfs.FLAG_AUTOTUNE, 15, alpha_t0=start)
     assert tuned.iters == plain.iters == 16 and tuned.n_nonpos == 0
-    assert it["chunks_x"] <= ip["chunks_x"]
+    assert ip["tile"] == 32 and it["tile"] in (16, 32, 64)
+    if it["tile"] == ip["tile"]:
+        assert it["chunks_x"] <= ip["chunks_x"]
     a, b = tuned.alpha.cpu().numpy(), plain.alpha.cpu().numpy()
     assert np.max(np.abs(a / b - 1)) <= 1e-12
     assert abs(tuned.cost - plain.cost) <= 1e-13 * abs(plain.cost)
@@ -48,7 +52,9 @@ def test_autotune_dense_cloud_and_batch():
     cfg = workloads.uniform_square(10**6)
     plain, ip = solve(cfg, 0, 4, prec="fp32", N=64, eps=0.05)
     tuned, it = solve(cfg, nfs.FLAG_AUTOTUNE, 4, prec="fp32", N=64, eps=0.05)
-    assert it["chunks_x"] <= ip["chunks_x"]
+    assert ip["tile"] == 32 and it["tile"] in (16, 32, 64)
+    if it["tile"] == ip["tile"]:
+        assert it["chunks_x"] <= ip["chunks_x"]
     assert abs(tuned.cost - plain.cost) <= 1e-6 * abs(plain.cost)
     probs = [workloads.subsample(workloads.gmm_2d(20000), n, seed=10 + n) for n in (3000, 800, 5000)]
     eps = [0.03, 0.05, 0.02]
