@@ -303,51 +303,11 @@ inline std::vector<double> r1_table(int d, int N, double e, double eI, const std
   return tab;
 }
 
-// Tables of the fused diagonal over |k_c| = 0..N/2 per axis (extent H = N/2+1,
-// row-major).  With the periodized Gaussian of temperature eps_t (period 1),
-// whose Fourier coefficient is prod_c sqrt(pi eps_t) exp(-pi^2 eps_t k_c^2)
-// (Poisson summation), and the window transform Phi:
-//   kernel: D(k) = prod_c f(k_c),  f(k) = sqrt(pi eps_t) exp(-pi^2 eps_t k^2) hw(k) / Phi(k)^2
-//   cost:   C(k) = D(k) (d eps_t / 2 - pi^2 eps_t^2 |k|^2) / scale^2
-//           (the coefficients of |z|^2 exp(-|z|^2/eps_t), back in the caller's units)
-// hw = 1/2 on |k_c| = N/2: the symmetric form of the real part of the sum over I_N.
-struct DiagTables {
-  std::vector<double> kernel, cost;
-};
-
 inline std::vector<double> window_hat_table(int N, int m, int g, const WindowConst& w) {
   const int H = N / 2 + 1;
   std::vector<double> phi(H);
   for (int k = 0; k < H; ++k) phi[k] = window_hat(k, m, g, w);
   return phi;
-}
-
-inline DiagTables gauss_tables(int d, int N, double eps_t, double scale, const std::vector<double>& phi) {
-  const int H = N / 2 + 1;
-  std::vector<double> f(H);
-  for (int k = 0; k < H; ++k) {
-    f[k] = std::sqrt(kPi * eps_t) * std::exp(-kPi * kPi * eps_t * double(k) * k) / (phi[k] * phi[k]);
-    if (k == N / 2) f[k] *= 0.5;
-  }
-  long total = 1;
-  for (int c = 0; c < d; ++c) total *= H;
-  DiagTables t;
-  t.kernel.resize(total);
-  t.cost.resize(total);
-  const double inv_s2 = 1.0 / (scale * scale);
-  for (long i = 0; i < total; ++i) {
-    long rem = i;
-    double prod = 1.0, k2 = 0.0;
-    for (int c = d - 1; c >= 0; --c) {
-      const int kc = int(rem % H);
-      rem /= H;
-      prod *= f[kc];
-      k2 += double(kc) * kc;
-    }
-    t.kernel[i] = prod;
-    t.cost[i] = prod * (0.5 * d * eps_t - kPi * kPi * eps_t * eps_t * k2) * inv_s2;
-  }
-  return t;
 }
 
 }  // namespace nfs

@@ -352,6 +352,21 @@ hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_fill_double(double* p, long n, double v, hipStream_t st);
 hipError_t launch_unpermute(const double* src_sorted, const int* perm, long n, double* dst, hipStream_t st);
 
+// Tables of the fused diagonal of the Gaussian kernel (r = 2) over |k_c| =
+// 0..N/2 per axis (extent H = (N/2+1)^d, row-major) for every problem.  The
+// periodized Gaussian of torus temperature e (period 1) has the Fourier
+// coefficient prod_c sqrt(pi e) exp(-pi^2 e k_c^2) (Poisson summation); with
+// the window transform Phi (inv_phi = 1/Phi):
+//   kernel: D(k) = prod_c f(k_c),  f(k) = sqrt(pi e) exp(-pi^2 e k^2) hw(k) / Phi(k)^2
+//   cost:   C(k) = D(k) (d e / 2 - pi^2 e^2 |k|^2) / s^2
+//           (the coefficients of |z|^2 exp(-|z|^2/e), back in the caller's units)
+// hw = 1/2 on |k_c| = N/2: the symmetric form of the real part of the sum over
+// I_N.  Problem b: pb[2b] = e, pb[2b + 1] = scale s (e <= 0 leaves zeros); its
+// tables start at b H.  Evaluated in FP64, stored as R.
+template <typename R>
+hipError_t launch_gauss_tables(int d, int N, int B, const double* pb, const double* inv_phi, R* kernel, R* cost,
+                               hipStream_t st);
+
 // readout: over sorted arrays, out[0] += sum a*log(b) (a>0), out[1] += sum a*log(a), out[2] += sum a
 struct ReadoutArgs {
   const double* a;

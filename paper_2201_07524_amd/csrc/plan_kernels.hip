@@ -637,6 +637,51 @@ hipError_t launch_unpermute(const double* src, const int* perm, long n, double* 
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ diagonal tables (r = 2)
+template <typename R>
+__global__ __launch_bounds__(kBlock) void gauss_tables_kernel(int d, int N, long H, const double* pb,
+                                                              const double* inv_phi, R* kernel, R* cost) {
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  const int b = blockIdx.y;
+  if (i >= H) return;
+  const double e = pb[2 * b], s = pb[2 * b + 1];
+  const size_t o = size_t(b) * H + i;
+  if (!(e > 0.0)) {
+    kernel[o] = R(0);
+    cost[o] = R(0);
+    return;
+  }
+  const int h = N / 2 + 1;
+  const double pi = 3.14159265358979323846;
+  long rem = i;
+  double prod = 1.0, k2 = 0.0;
+  for (int c = d - 1; c >= 0; --c) {
+    const int kc = int(rem % h);
+    rem /= h;
+    double f = sqrt(pi * e) * exp(-pi * pi * e * double(kc) * kc) * inv_phi[kc] * inv_phi[kc];
+    if (kc == N / 2) f *= 0.5;
+    prod *= f;
+    k2 += double(kc) * kc;
+  }
+  kernel[o] = R(prod);
+  cost[o] = R(prod * (0.5 * d * e - pi * pi * e * e * k2) / (s * s));
+}
+
+template <typename R>
+hipError_t launch_gauss_tables(int d, int N, int B, const double* pb, const double* inv_phi, R* kernel, R* cost,
+                               hipStream_t st) {
+  long H = 1;
+  for (int c = 0; c < d; ++c) H *= N / 2 + 1;
+  if (B <= 0 || B > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gauss_tables_kernel<R>, dim3(unsigned((H + kBlock - 1) / kBlock), unsigned(B)), dim3(kBlock), 0,
+                     st, d, N, H, pb, inv_phi, kernel, cost);
+  return hipGetLastError();
+}
+template hipError_t launch_gauss_tables<float>(int, int, int, const double*, const double*, float*, float*,
+                                               hipStream_t);
+template hipError_t launch_gauss_tables<double>(int, int, int, const double*, const double*, double*, double*,
+                                                hipStream_t);
+
 // ------------------------------------------------------------------ read-out sums
 __global__ __launch_bounds__(kBlock) void readout_kernel(ReadoutArgs a) {
   constexpr int NV = 3;
