@@ -244,6 +244,18 @@ struct BoxArgs {
   double* out;
 };
 hipError_t launch_bbox(const BoxArgs& a, hipStream_t st);
+// Many boxes in one launch (the per-problem boxes of a batched plan): box j
+// is jobs[j] (its partials and d ignored) over workgroups [blk0[j], blk0[j] +
+// nblk[j]) of the launch, nblocks in all; partials holds kBoxVals per
+// workgroup of the launch.
+struct BoxJob {
+  BoxArgs box;
+  long blk0;
+  int nblk;
+};
+// Workgroups per box: about eight values per thread, at most 1024.
+int bbox_blocks(long n);
+hipError_t launch_bbox_jobs(const BoxJob* jobs, int njobs, long nblocks, int d, double* partials, hipStream_t st);
 
 // Scalings between the centred form and the caller's variables: with x'
 // the mapped point (torus coordinate tau, x' = center + tau/scale) and
@@ -277,7 +289,26 @@ struct KeyArgs {
   double scale;       // torus coordinate = scale*(x - center); scale = 0: points already on the torus
   int* keys;
   int* counts;        // histogram per tile
+  // Batched form (probs non-null, one launch for all problems of a plan):
+  // pts, keys are the cloud's arrays, counts (and the scatter's offsets and
+  // cursor) hold nbins entries per problem, and problem b's points, mapping
+  // and first workgroup come from probs[b] (n, center, scale unused).
+  const struct PlanProb* probs;
+  int nprob;
 };
+// One problem of a batched plan launch: its points [o, o + n) of the cloud,
+// its torus mapping, and the first of the ceil(n / plan_block_points())
+// workgroups that take its points.
+struct PlanProb {
+  long o, n;
+  double center[3];
+  double scale;
+  long blk0;
+};
+// Points per workgroup of the key and scatter kernels; whether a grid of
+// nbins tiles takes their batched form.
+long plan_block_points();
+bool plan_batchable(int nbins);
 hipError_t launch_keys(const KeyArgs& a, hipStream_t st);
 
 template <typename R>
@@ -298,6 +329,8 @@ struct ScatterArgs {
   double* w0s;
   const double* w1;
   double* w1s;
+  const PlanProb* probs;  // batched form, as in KeyArgs (idx_base then unused)
+  int nprob;
 };
 template <typename R>
 hipError_t launch_scatter(const ScatterArgs<R>& a, hipStream_t st);

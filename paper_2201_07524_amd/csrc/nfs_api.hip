@@ -223,6 +223,9 @@ struct Work {
   double* unc = nullptr;      // 2 x B x kUncStride: centred form read-out constants (x side, then y)
   double* gfac = nullptr;     // 2 x B: per-problem factors of the gradient on a solver
   double* tabpar = nullptr;   // 2 x B: torus temperature and scale per problem (diagonal tables)
+  PlanProb* planprobs = nullptr;  // B: batched key / scatter launches of the plan
+  BoxJob* boxjobs = nullptr;      // 2 x B: batched boxes of the plan
+  long npartials = 0;             // workgroup partials (kBoxVals doubles each) the partials buffer holds
   double* tmp = nullptr;
   int r = 2;
   double* nf = nullptr;       // near-field sums (r = 1), per sorted target
@@ -334,7 +337,8 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
   w.inv_phi = cv.take<double>(w.K0);
   w.wpoly = cv.take<double>((sizeof(R) == 4 ? sizeof(WindowPoly) : sizeof(WindowPoly64)) / sizeof(double) + 1);
   const long maxch = std::max(w.X.max_chunks, w.Y.max_chunks);
-  w.partials = cv.take<double>(size_t(std::max<long>(maxch, 1024)) * kBoxVals);
+  w.npartials = std::max<long>(maxch, 1024);
+  w.partials = cv.take<double>(size_t(w.npartials) * kBoxVals);
   w.st_row = cv.take<double>(size_t(B) * kStat);
   w.st_col = cv.take<double>(size_t(B) * kStat);
   w.st_eval = cv.take<double>(size_t(B) * kStat);
@@ -350,6 +354,8 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
   w.unc = cv.take<double>(size_t(2) * B * kUncStride);
   w.gfac = cv.take<double>(size_t(2) * B);
   w.tabpar = cv.take<double>(size_t(2) * B);
+  w.planprobs = cv.take<PlanProb>(B);
+  w.boxjobs = cv.take<BoxJob>(size_t(2) * B);
   w.tmp = cv.take<double>(size_t(std::max(nA, nB)) * std::max(d, 1));
   w.r = p->r;
   if (p->r == 1) {
@@ -462,7 +468,36 @@ static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const std:
   const int B = w.B, nb = w.nbins, d = geo.d;
   NFS_HIP(launch_fill(cb.counts, sizeof(int) * size_t(B) * nb, st));
   NFS_HIP(launch_fill(cb.cursor, sizeof(int) * size_t(B) * nb, st));
-  for (int b = 0; b < B; ++b) {
+  // a batch keys and scatters all its problems in one launch each
+  const bool batched = B > 1 && plan_batchable(nb);
+  std::vector<PlanProb> probs;
+  long pblocks = 0;
+  if (batched) {
+    probs.resize(B);
+    for (int b = 0; b < B; ++b) {
+      PlanProb& pp = probs[b];
+      pp.o = cb.off[b];
+      pp.n = cb.off[b + 1] - cb.off[b];
+      for (int c = 0; c < 3; ++c) pp.center[c] = sc[b].center[c] + side * sc[b].shift[c];
+      pp.scale = sc[b].scale;
+      pp.blk0 = pblocks;
+      pblocks += (pp.n + plan_block_points() - 1) / plan_block_points();
+    }
+    NFS_HIP(hipMemcpyAsync(w.planprobs, probs.data(), sizeof(PlanProb) * B, hipMemcpyHostToDevice, st));
+    KeyArgs ka{};
+    ka.pts = pts;
+    ka.n = pblocks;
+    ka.d = d;
+    ka.g = geo.g;
+    ka.T = geo.T;
+    for (int c = 0; c < 3; ++c) ka.nt[c] = geo.nt[c];
+    ka.keys = cb.keys;
+    ka.counts = cb.counts;
+    ka.probs = w.planprobs;
+    ka.nprob = B;
+    if (pblocks > 0) NFS_HIP(launch_keys(ka, st));
+  }
+  for (int b = 0; b < B && !batched; ++b) {
     const long o = cb.off[b], n = cb.off[b + 1] - o;
     if (n == 0) continue;
     KeyArgs ka{};
@@ -495,7 +530,28 @@ static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const std:
   }
   NFS_HIP(hipMemcpyAsync(cb.offsets, offsets.data(), sizeof(int) * offsets.size(), hipMemcpyHostToDevice, st));
   NFS_TRY(build_chunks(w, cb, w.chunk, false, st));
-  for (int b = 0; b < B; ++b) {
+  if (batched) {
+    ScatterArgs<R> sa{};
+    sa.pts = pts;
+    sa.n = pblocks;
+    sa.d = d;
+    sa.g = geo.g;
+    sa.T = geo.T;
+    for (int c = 0; c < 3; ++c) sa.nt[c] = geo.nt[c];
+    sa.keys = cb.keys;
+    sa.offsets = cb.offsets;
+    sa.cursor = cb.cursor;
+    sa.coords = w.cell_order ? w.stage_coords : cb.coords;
+    sa.perm = w.cell_order ? w.stage_perm : cb.perm;
+    sa.w0 = v0;
+    sa.w0s = w.cell_order ? w.stage_w0 : cb.w0s;
+    sa.w1 = v1;
+    sa.w1s = w.cell_order ? w.stage_w1 : cb.w1s;
+    sa.probs = w.planprobs;
+    sa.nprob = B;
+    if (pblocks > 0) NFS_HIP(launch_scatter(sa, st));
+  }
+  for (int b = 0; b < B && !batched; ++b) {
     const long o = cb.off[b], n = cb.off[b + 1] - o;
     if (n == 0) continue;
     ScatterArgs<R> sa{};
@@ -1138,18 +1194,64 @@ static int plan_sinkhorn(Work<R>& w, const nfs_params* p, const double* eps, con
   const int B = w.B, d = p->d;
   const bool centred = (p->flags & NFS_FLAG_CENTER) != 0;
   NFS_TRY(zero_state(w, st));
+  // per problem, the box of x (with y unless centred) and the weight
+  // statistics of mu, then those of nu (with y's box when centred); a batch
+  // takes all of them in one launch
+  std::vector<BoxJob> jobs;
   for (int b = 0; b < B; ++b) {
     const long ox = w.X.off[b], nx = w.X.off[b + 1] - ox, oy = w.Y.off[b], ny = w.Y.off[b + 1] - oy;
     if (nx < 1 || ny < 1) return fail(NFS_EINVAL, "every problem needs at least one point per cloud");
     double* slot = w.st_box + kBoxSlot * b;
+    BoxJob jx{}, jy{};
+    jx.box.pts[0] = x + ox * d;
+    jx.box.n[0] = nx;
+    jx.box.w = mu + ox;
+    jx.box.nw = nx;
+    jx.box.out = slot;
+    jy.box.w = nu + oy;
+    jy.box.nw = ny;
+    jy.box.out = slot + kBoxVals;
     if (centred) {
       // separate boxes and weighted means of the two clouds
-      NFS_TRY(box_launch(slot, w.partials, d, x + ox * d, nx, nullptr, 0, mu + ox, nx, st, 1));
-      NFS_TRY(box_launch(slot + kBoxVals, w.partials, d, y + oy * d, ny, nullptr, 0, nu + oy, ny, st, 1));
+      jx.box.wsum = 1;
+      jy.box.pts[0] = y + oy * d;
+      jy.box.n[0] = ny;
+      jy.box.wsum = 1;
     } else {
-      NFS_TRY(box_launch(slot, w.partials, d, x + ox * d, nx, y + oy * d, ny, mu + ox, nx, st));
-      NFS_TRY(box_launch(slot + kBoxVals, w.partials, d, nullptr, 0, nullptr, 0, nu + oy, ny, st));
+      jx.box.pts[1] = y + oy * d;
+      jx.box.n[1] = ny;
     }
+    jobs.push_back(jx);
+    jobs.push_back(jy);
+  }
+  if (B == 1) {
+    for (BoxJob& j : jobs) {
+      const BoxArgs& a = j.box;
+      NFS_TRY(box_launch(a.out, w.partials, d, a.pts[0], a.n[0], a.pts[1], a.n[1], a.w, a.nw, st, a.wsum));
+    }
+  } else {
+    long total = 0;
+    for (BoxJob& j : jobs) {
+      j.nblk = bbox_blocks(std::max(std::max(j.box.n[0], j.box.n[1]), j.box.nw));
+      total += j.nblk;
+    }
+    const long njobs = long(jobs.size());
+    if (total > w.npartials) {  // fewer workgroups per box, within the partials buffer (>= 2B + 1 slots)
+      const long spare = w.npartials - njobs;
+      long t2 = 0;
+      for (BoxJob& j : jobs) {
+        j.nblk = int(std::max<long>(1, long(j.nblk) * spare / total));
+        t2 += j.nblk;
+      }
+      total = t2;
+    }
+    long blk0 = 0;
+    for (BoxJob& j : jobs) {
+      j.blk0 = blk0;
+      blk0 += j.nblk;
+    }
+    NFS_HIP(hipMemcpyAsync(w.boxjobs, jobs.data(), sizeof(BoxJob) * jobs.size(), hipMemcpyHostToDevice, st));
+    NFS_HIP(launch_bbox_jobs(w.boxjobs, int(njobs), total, d, w.partials, st));
   }
   std::vector<double> box(size_t(B) * kBoxSlot);
   NFS_HIP(hipMemcpyAsync(box.data(), w.st_box, sizeof(double) * box.size(), hipMemcpyDeviceToHost, st));

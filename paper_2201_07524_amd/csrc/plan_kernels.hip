@@ -80,8 +80,25 @@ constexpr int kGridBlocks = 1024;
 // ------------------------------------------------------------------ bounding box
 // out = {min_0..min_{d-1}, max_0..max_{d-1}} padded to 3 dims, then max|w|, min w, sum w,
 // and with a.wsum the weighted coordinate sums of pts[0].
-__global__ __launch_bounds__(kBlock) void bbox_kernel(BoxArgs a) {
+__global__ __launch_bounds__(kBlock) void bbox_kernel(BoxArgs a, const BoxJob* jobs, int njobs) {
   constexpr int NV = kBoxVals;
+  long blk = blockIdx.x, nblk = gridDim.x;
+  if (jobs) {
+    // this workgroup's box: the last job whose first workgroup is at or before it
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].blk0 <= blk) lo = mid;
+      else hi = mid - 1;
+    }
+    const int d = a.d;
+    double* partials = a.partials;
+    a = jobs[lo].box;
+    a.d = d;
+    a.partials = partials;
+    blk -= jobs[lo].blk0;
+    nblk = jobs[lo].nblk;
+  }
   double v[NV];
   bool is_min[NV], is_max[NV];
   for (int k = 0; k < NV; ++k) {
@@ -89,11 +106,11 @@ __global__ __launch_bounds__(kBlock) void bbox_kernel(BoxArgs a) {
     is_max[k] = (kBoxMax >> k) & 1u;
     v[k] = is_min[k] ? 1e308 : (is_max[k] ? -1e308 : 0.0);
   }
-  const long stride = long(gridDim.x) * kBlock;
+  const long stride = nblk * kBlock;
   for (int s = 0; s < 2; ++s) {
     const double* p = a.pts[s];
     if (!p) continue;
-    for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < a.n[s]; i += stride)
+    for (long i = blk * kBlock + threadIdx.x; i < a.n[s]; i += stride)
       for (int c = 0; c < a.d; ++c) {
         const double x = p[i * a.d + c];
         v[c] = fmin(v[c], x);
@@ -101,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void bbox_kernel(BoxArgs a) {
       }
   }
   if (a.w)
-    for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < a.nw; i += stride) {
+    for (long i = blk * kBlock + threadIdx.x; i < a.nw; i += stride) {
       const double w = a.w[i];
       v[6] = fmax(v[6], fabs(w));
       v[7] = fmin(v[7], w);
@@ -153,14 +170,49 @@ hipError_t launch_uncenter(const UncenterArgs<R>& a, int nchunks, hipStream_t st
 template hipError_t launch_uncenter<float>(const UncenterArgs<float>&, int, hipStream_t);
 template hipError_t launch_uncenter<double>(const UncenterArgs<double>&, int, hipStream_t);
 
+int bbox_blocks(long n) { return int(std::min<long>(kGridBlocks, std::max<long>(1, (n + 8 * kBlock - 1) / (8 * kBlock)))); }
+
 hipError_t launch_bbox(const BoxArgs& a, hipStream_t st) {
-  // about eight values per thread, so the boxes of small problems are a few workgroups
-  const long n = std::max(std::max(a.n[0], a.n[1]), a.nw);
-  const int nb = int(std::min<long>(kGridBlocks, std::max<long>(1, (n + 8 * kBlock - 1) / (8 * kBlock))));
-  hipLaunchKernelGGL(bbox_kernel, dim3(nb), dim3(kBlock), 0, st, a);
+  const int nb = bbox_blocks(std::max(std::max(a.n[0], a.n[1]), a.nw));
+  hipLaunchKernelGGL(bbox_kernel, dim3(nb), dim3(kBlock), 0, st, a, (const BoxJob*)nullptr, 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return finish_partials<kBoxVals>(a.partials, nb, kBoxMin, kBoxMax, a.out, st);
+}
+
+// One workgroup per box: its workgroups' partials, in order, into its out.
+__global__ __launch_bounds__(kBlock) void bbox_finish_kernel(const double* partials, const BoxJob* jobs) {
+  constexpr int NV = kBoxVals;
+  __shared__ double sh[NV][kBlock];
+  const BoxJob& jb = jobs[blockIdx.x];
+  bool is_min[NV], is_max[NV];
+  double acc[NV];
+  for (int k = 0; k < NV; ++k) {
+    is_min[k] = (kBoxMin >> k) & 1u;
+    is_max[k] = (kBoxMax >> k) & 1u;
+    acc[k] = is_min[k] ? 1e308 : (is_max[k] ? -1e308 : 0.0);
+  }
+  for (int b = threadIdx.x; b < jb.nblk; b += kBlock)
+    for (int k = 0; k < NV; ++k) {
+      const double x = partials[size_t(jb.blk0 + b) * NV + k];
+      acc[k] = is_min[k] ? fmin(acc[k], x) : (is_max[k] ? fmax(acc[k], x) : acc[k] + x);
+    }
+  block_reduce_arr<NV>(acc, is_min, is_max, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NV; ++k) jb.box.out[k] = acc[k];
+}
+
+hipError_t launch_bbox_jobs(const BoxJob* jobs, int njobs, long nblocks, int d, double* partials, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  if (nblocks >= (long(1) << 31)) return hipErrorInvalidValue;
+  BoxArgs a{};
+  a.d = d;
+  a.partials = partials;
+  hipLaunchKernelGGL(bbox_kernel, dim3(unsigned(nblocks)), dim3(kBlock), 0, st, a, jobs, njobs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(bbox_finish_kernel, dim3(njobs), dim3(kBlock), 0, st, (const double*)partials, jobs);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ keys + histogram
@@ -194,6 +246,22 @@ constexpr int kPlanBins = 8192;
 constexpr int kPlanPerThread = 16;
 constexpr int kPlanPerBlock = kPlanPerThread * kBlock;
 
+long plan_block_points() { return kPlanPerBlock; }
+bool plan_batchable(int nbins) { return nbins <= kPlanBins; }
+
+// Batched form: the problem whose workgroups include blk (the last with blk0
+// <= blk), and blk made relative to its first workgroup.
+__device__ __forceinline__ int plan_problem(const PlanProb* probs, int nprob, long& blk) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (probs[mid].blk0 <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  blk -= probs[lo].blk0;
+  return lo;
+}
+
 __device__ __forceinline__ int tile_key(const double* pts, long i, int d, const double* center, double scale, int g,
                                         int T, const int* nt) {
   int key = 0;
@@ -208,9 +276,20 @@ __device__ __forceinline__ int tile_key(const double* pts, long i, int d, const 
 __global__ __launch_bounds__(kBlock) void keys_lds_kernel(KeyArgs a) {
   extern __shared__ int hist[];
   const int nbins = a.nt[0] * a.nt[1] * a.nt[2];
+  long blk = blockIdx.x;
+  if (a.probs) {
+    const int pb = plan_problem(a.probs, a.nprob, blk);
+    const PlanProb& pp = a.probs[pb];
+    a.pts += pp.o * a.d;
+    a.n = pp.n;
+    for (int c = 0; c < 3; ++c) a.center[c] = pp.center[c];
+    a.scale = pp.scale;
+    a.keys += pp.o;
+    a.counts += size_t(pb) * nbins;
+  }
   for (int b = threadIdx.x; b < nbins; b += kBlock) hist[b] = 0;
   __syncthreads();
-  const long base = long(blockIdx.x) * kPlanPerBlock;
+  const long base = blk * kPlanPerBlock;
   const long end = min(base + kPlanPerBlock, a.n);
   for (long i = base + threadIdx.x; i < end; i += kBlock) {
     const int key = tile_key(a.pts, i, a.d, a.center, a.scale, a.g, a.T, a.nt);
@@ -223,8 +302,14 @@ __global__ __launch_bounds__(kBlock) void keys_lds_kernel(KeyArgs a) {
 }
 
 hipError_t launch_keys(const KeyArgs& a, hipStream_t st) {
-  if (a.n <= 0) return hipSuccess;
   const int nbins = a.nt[0] * a.nt[1] * a.nt[2];
+  if (a.probs) {
+    // a.n: the launch's workgroups (the last problem's blk0 + its workgroups)
+    if (!plan_batchable(nbins) || a.n <= 0 || a.n >= (long(1) << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(keys_lds_kernel, dim3(unsigned(a.n)), dim3(kBlock), sizeof(int) * nbins, st, a);
+    return hipGetLastError();
+  }
+  if (a.n <= 0) return hipSuccess;
   if (nbins <= kPlanBins) {
     const long nblk = (a.n + kPlanPerBlock - 1) / kPlanPerBlock;
     hipLaunchKernelGGL(keys_lds_kernel, dim3(nblk), dim3(kBlock), sizeof(int) * nbins, st, a);
@@ -278,9 +363,24 @@ __global__ __launch_bounds__(kBlock) void scatter_lds_kernel(ScatterArgs<R> a, i
   extern __shared__ int sh[];
   int* hist = sh;
   int* slot = sh + nbins;
+  long blk = blockIdx.x;
+  if (a.probs) {
+    const int pb = plan_problem(a.probs, a.nprob, blk);
+    const PlanProb& pp = a.probs[pb];
+    a.pts += pp.o * a.d;
+    a.n = pp.n;
+    for (int c = 0; c < 3; ++c) a.center[c] = pp.center[c];
+    a.scale = pp.scale;
+    a.keys += pp.o;
+    a.offsets += size_t(pb) * nbins;
+    a.cursor += size_t(pb) * nbins;
+    a.idx_base = int(pp.o);
+    if (a.w0) a.w0 += pp.o;
+    if (a.w1) a.w1 += pp.o;
+  }
   for (int b = threadIdx.x; b < nbins; b += kBlock) hist[b] = 0;
   __syncthreads();
-  const long base = long(blockIdx.x) * kPlanPerBlock;
+  const long base = blk * kPlanPerBlock;
   int key[kPlanPerThread], rank[kPlanPerThread];
 #pragma unroll
   for (int k = 0; k < kPlanPerThread; ++k) {
@@ -302,8 +402,15 @@ __global__ __launch_bounds__(kBlock) void scatter_lds_kernel(ScatterArgs<R> a, i
 
 template <typename R>
 hipError_t launch_scatter(const ScatterArgs<R>& a, hipStream_t st) {
-  if (a.n <= 0) return hipSuccess;
   const int nbins = a.nt[0] * a.nt[1] * a.nt[2];
+  if (a.probs) {
+    // a.n: the launch's workgroups, as for launch_keys
+    if (!plan_batchable(nbins) || a.n <= 0 || a.n >= (long(1) << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(scatter_lds_kernel<R>, dim3(unsigned(a.n)), dim3(kBlock), sizeof(int) * 2 * nbins, st, a,
+                       nbins);
+    return hipGetLastError();
+  }
+  if (a.n <= 0) return hipSuccess;
   if (nbins <= kPlanBins) {
     const long nblk = (a.n + kPlanPerBlock - 1) / kPlanPerBlock;
     hipLaunchKernelGGL(scatter_lds_kernel<R>, dim3(nblk), dim3(kBlock), sizeof(int) * 2 * nbins, st, a, nbins);
