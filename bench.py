@@ -284,12 +284,13 @@ def log_leg(nfs, prm, x, p, y, pt, torch, iters=20):
             "stage_ms": dict(zip(("spread_incl_weights", "fft", "interp", "iteration"), stage_ms))}
 
 
-def ball_shell_leg(nfs, workloads, torch, T, iters=3):
+def ball_shell_leg(nfs, workloads, torch, T, iters=3, rho=1):
     """The Euclidean-cost form (r = 1, with the near field): ball against
     shell, 4e6 points per cloud, eps = 0.02, N = 128, m = 6, FP32; ms per
-    iteration and per-stage device times."""
-    cfg = workloads.ball_shell_3d()
-    prm = nfs.Params(d=3, r=1, eps=cfg["eps"], N=cfg["N"], m=cfg["m"], precision="fp32")
+    iteration and per-stage device times.  rho: the exponent of the distance
+    (a real rho goes through the sampled-kernel tables)."""
+    cfg = dict(workloads.ball_shell_3d(), r=rho)
+    prm = nfs.Params(d=3, r=rho, eps=cfg["eps"], N=cfg["N"], m=cfg["m"], precision="fp32")
     t0 = time.perf_counter()
     s = nfs.Solver(prm, T(cfg["x"]), T(cfg["p"]), T(cfg["y"]), T(cfg["pt"]))
     torch.cuda.synchronize()
@@ -353,7 +354,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-legs", action="store_true", help="skip the log-domain, batched, gradient, ball/shell and paper-shape legs")
-    ap.add_argument("--only-leg", choices=("batched", "gradient", "ball_shell", "paper_shapes", "plain_1d"),
+    ap.add_argument("--only-leg", choices=("batched", "gradient", "ball_shell", "ball_shell_rho", "paper_shapes",
+                                           "plain_1d"),
                     help="run one secondary leg alone and print its JSON (for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with one device copy of 256 MiB (calibrates HBM byte counters)")
@@ -371,6 +373,7 @@ def main():
         dev = torch.device("cuda:0")
         T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
         leg = {"batched": batched_leg, "gradient": grad_leg, "ball_shell": ball_shell_leg,
+               "ball_shell_rho": lambda *a: ball_shell_leg(*a, rho=1.5),
                "paper_shapes": paper_shapes_leg, "plain_1d": plain_1d_leg}[args.only_leg]
         print(json.dumps({args.only_leg: leg(nfs, workloads, torch, T)}), flush=True)
         return
@@ -486,6 +489,10 @@ def main():
         log("bench: ball/shell (r = 1) leg")
         out["ball_shell_r1"] = ball_shell_leg(nfs, workloads, torch, T)
         log("bench: ball/shell " + json.dumps(out["ball_shell_r1"]))
+        torch.cuda.empty_cache()
+        log("bench: ball/shell (real rho = 1.5) leg")
+        out["ball_shell_rho1.5"] = ball_shell_leg(nfs, workloads, torch, T, rho=1.5)
+        log("bench: ball/shell rho " + json.dumps(out["ball_shell_rho1.5"]))
         torch.cuda.empty_cache()
         log("bench: paper-shaped workloads leg")
         out["paper_shapes"] = paper_shapes_leg(nfs, workloads, torch, T)

@@ -98,7 +98,7 @@ extern "C" {
 typedef struct nfs_params {
   int32_t d;          /* dimension, 1..3 */
   int32_t r;          /* cost exponent: 2 -> c = |x-y|^2; 1 -> c = |x-y| (near-field corrected,
-                         Remark 3.2; no primal cost) */
+                         Remark 3.2; no primal cost); 0 -> the real exponent rexp */
   double eps;         /* temperature > 0; K = exp(-c/eps) (the paper's 1/lambda) */
   int32_t N;          /* bandwidth per dimension: I_N = {-N/2..N/2-1}^d, even, >= 4 */
   int32_t m;          /* window cutoff: 2m+1 grid taps per dimension, 2 <= m <= 8 */
@@ -109,10 +109,17 @@ typedef struct nfs_params {
                          (FP32, d = 2) or 4096 (FP32, d = 3), 4096 for clouds with more than 8
                          points per grid cell and n >= 200 * 4096; else 1024) */
   int32_t flags;      /* NFS_FLAG_* */
-  double eps_I;       /* r = 1: near-field radius times N on the period-1 torus (0 = default 4);
+  double eps_I;       /* r = 0, 1: near-field radius times N on the period-1 torus (0 = default 4);
                          the radius must fit in 2 kt + 1 tiles, kt = ceil(eps_I sigma / tile) */
-  int32_t p_smooth;   /* r = 1: derivatives matched by the inner polynomial (0 = default 8, max 16) */
+  int32_t p_smooth;   /* r = 0, 1: derivatives matched by the inner polynomial (0 = default 8, max 16) */
   int32_t reserved;
+  double rexp;        /* r = 0: real cost exponent in (1, 4], not 2: c = |x-y|^rexp (Definition 2.1
+                         with real r).  Treated as r = 1 is: the kernel exp(-|z|^rexp/eps) is
+                         replaced inside |z| < eps_I by the even polynomial matching its first
+                         p_smooth - 1 derivatives at eps_I (Section 3.1), the Fourier
+                         coefficients of the regularized kernel come from its samples on the
+                         oversampled grid, and the near field adds K - K_R.  No gradient
+                         (NFS_EUNSUPPORTED) and no primal cost.  Ignored unless r = 0 */
 } nfs_params;
 
 typedef struct nfs_result {

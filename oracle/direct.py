@@ -36,6 +36,9 @@ def load():
             fn.restype = None
             fn.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, P, P, ctypes.c_int64,
                            P, ctypes.c_int64, P, P]
+        lib.oracle_kv_rows_real.restype = None
+        lib.oracle_kv_rows_real.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, P, P, ctypes.c_int64,
+                                            P, ctypes.c_int64, P, P]
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -63,8 +66,12 @@ def kv(tgt, src, w, r, eps, rows=None):
         rows = np.ascontiguousarray(rows, dtype=np.int64)
         nrows, rp = rows.shape[0], rows.ctypes.data
     out = np.empty(nrows)
-    lib.oracle_kv_rows(d, int(r), float(eps), tgt.ctypes.data, rp, nrows,
-                       src.ctypes.data, src.shape[0], w.ctypes.data, out.ctypes.data)
+    if float(r) in (1.0, 2.0):
+        lib.oracle_kv_rows(d, int(r), float(eps), tgt.ctypes.data, rp, nrows,
+                           src.ctypes.data, src.shape[0], w.ctypes.data, out.ctypes.data)
+    else:
+        lib.oracle_kv_rows_real(d, float(r), float(eps), tgt.ctypes.data, rp, nrows,
+                                src.ctypes.data, src.shape[0], w.ctypes.data, out.ctypes.data)
     return out
 
 

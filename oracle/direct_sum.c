@@ -41,6 +41,22 @@ void oracle_kv_rows(int d, int r, double eps,
   }
 }
 
+/* The same sums for a real exponent rho of the distance (Definition 2.1 with
+ * the cost |x - y|^rho): out[q] = sum_j w[j] exp(-|x_i - y_j|^rho / eps). */
+void oracle_kv_rows_real(int d, double rho, double eps,
+                         const double* tgt, const int64_t* rows, int64_t nrows,
+                         const double* src, int64_t ns, const double* w,
+                         double* out) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < nrows; ++q) {
+    const int64_t i = rows ? rows[q] : q;
+    const double* xi = tgt + i * d;
+    double acc = 0.0;
+    for (int64_t j = 0; j < ns; ++j) acc += w[j] * exp(-pow(pair_cost(xi, src + j * d, d, 1), rho) / eps);
+    out[q] = acc;
+  }
+}
+
 /* g[q*d + c] = sum_j w[j] k(x_i, y_j) d c(x_i, y_j)/d x_i[c] for i = rows[q]:
  * r = 2: 2 (x_i - y_j); r = 1: (x_i - y_j)/|x_i - y_j| (zero when equal). */
 void oracle_grad_rows(int d, int r, double eps,

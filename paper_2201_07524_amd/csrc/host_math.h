@@ -163,14 +163,62 @@ inline Scaling choose_scaling_r1(int d, double eps, double L, const double* lo, 
   return s;
 }
 
+// Real exponent rho in (1, 4] (kernel exp(-|z|^rho/eps)): the torus mapping as
+// for r = 1 with the periodization error exp(-((1 - 2 R s)/s)^rho / eps) below
+// exp(-L), so s = 1 / (2R + (L eps)^(1/rho)); eps_t = eps s^rho.
+inline Scaling choose_scaling_rho(int d, double eps, double rho, double L, const double* lo, const double* hi) {
+  Scaling s{};
+  double R = 0.0;
+  for (int c = 0; c < d; ++c) {
+    s.center[c] = 0.5 * (lo[c] + hi[c]);
+    R = std::max(R, 0.5 * (hi[c] - lo[c]));
+  }
+  s.scale = 1.0 / (2.0 * R + std::pow(L * eps, 1.0 / rho));
+  s.eps_t = eps * std::pow(s.scale, rho);
+  s.kernel_err = std::exp(-std::pow(1.0 - 2.0 * R * s.scale, rho) / s.eps_t);
+  return s;
+}
+
 // Near-field regularization of K(r) = exp(-r/e) (r = |z| on the torus): inside
 // r < eI the kernel is replaced by the even polynomial
 //   K_R(r) = sum_{j<p} c_j (r/eI)^{2j},
 // whose first p-1 derivatives match K at r = eI, so K_R is smooth at the origin
 // and p-1 times differentiable at eI.  The difference K - K_R on r < eI is the
 // near-field correction.  The p x p system is solved in long double.
-inline std::vector<double> nearfield_poly(double e, double eI, int p) {
+// With a real exponent rho, K(r) = exp(-r^rho/e): its derivatives in u = r/eI at
+// u = 1 come from the Taylor series of exp(h(t)), h(t) = -(eI^rho/e) (1 + t)^rho
+// = -(eI^rho/e) sum_j binom(rho, j) t^j, truncated at degree p - 1.
+inline std::vector<double> nearfield_poly(double e, double eI, int p, double rho = 1.0) {
   std::vector<long double> A(size_t(p) * p, 0.0L), b(p);
+  std::vector<long double> dk(p);  // d^q/du^q K at u = 1
+  if (rho == 1.0) {
+    for (int q = 0; q < p; ++q) dk[q] = std::pow(-(long double)(eI / e), (long double)q) * std::exp(-(long double)(eI / e));
+  } else {
+    const long double a = std::pow((long double)eI, (long double)rho) / (long double)e;
+    std::vector<long double> h(p, 0.0L), ex(p, 0.0L), term(p, 0.0L);
+    long double bin = 1.0L;  // binom(rho, j)
+    for (int j = 0; j < p; ++j) {
+      h[j] = -a * bin;
+      bin *= ((long double)rho - j) / (long double)(j + 1);
+    }
+    // exp(h0 + H(t)), H = h without its constant: exp(h0) sum_k H^k / k!
+    term[0] = 1.0L;
+    ex[0] = 1.0L;
+    for (int k = 1; k < p; ++k) {
+      std::vector<long double> nt(p, 0.0L);
+      for (int i = 0; i < p; ++i)
+        for (int j = 1; i + j < p; ++j) nt[i + j] += term[i] * h[j];
+      for (int i = 0; i < p; ++i) {
+        term[i] = nt[i] / (long double)k;
+        ex[i] += term[i];
+      }
+    }
+    long double fact = 1.0L;
+    for (int q = 0; q < p; ++q) {
+      if (q > 0) fact *= q;
+      dk[q] = std::exp(h[0]) * ex[q] * fact;
+    }
+  }
   for (int q = 0; q < p; ++q) {
     for (int j = 0; j < p; ++j) {
       if (2 * j >= q) {
@@ -179,7 +227,7 @@ inline std::vector<double> nearfield_poly(double e, double eI, int p) {
         A[size_t(q) * p + j] = f;
       }
     }
-    b[q] = std::pow(-(long double)(eI / e), (long double)q) * std::exp(-(long double)(eI / e));
+    b[q] = dk[q];
   }
   for (int c = 0; c < p; ++c) {  // Gaussian elimination with partial pivoting
     int piv = c;

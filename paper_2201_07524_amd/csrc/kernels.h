@@ -132,13 +132,18 @@ struct InterpArgs {
   int half;                 // with pstate: 0 alpha update (residual checked), 1 alpha_t update
 };
 
-// Near-field correction for r = 1 (kernel exp(-|z|/eps) regularized inside
-// |z| < eps_I by an even polynomial): for every target,
+// Near-field correction for r = 1 and real exponents rho (kernel
+// exp(-|z|^rho/eps) regularized inside |z| < eps_I by an even polynomial): for
+// every target,
 //   out[q] = sum_{sources j within eps_I} w_j wm (K - K_R)(x_q - y_j),
 // over the sources of the (2 kt + 1)^d neighbour tiles.  Per-problem constants
 // (stride kNearStride doubles): [0] 1/(eps_t g) (cell distance -> r/eps),
-// [1] eps_I^2 in cells^2, [2] 1/eps_I^2 in cells^-2, [3] p, [4 + j] c_j (j < p <= 16).
+// [1] eps_I^2 in cells^2, [2] 1/eps_I^2 in cells^-2, [3] p, [4 + j] c_j (j < p <= 16),
+// [kNearRhoHalf] rho/2, [kNearRhoInv] 1/(eps_t g^rho) ((cell distance)^rho -> r^rho/eps).
+// NearArgs::real_exp selects K = exp(-(r2 cells)^(rho/2) [kNearRhoInv]); else rho = 1.
 constexpr int kNearStride = 24;
+constexpr int kNearRhoHalf = 20;
+constexpr int kNearRhoInv = 21;
 template <typename R>
 struct NearArgs {
   Geom geo;
@@ -158,6 +163,7 @@ struct NearArgs {
   const int* pstate;    // nullable: targets of problems in state 2 are skipped
   const int* scell;     // nullable: per source tile the cell starts (TileSortArgs::cellstart);
                         // with it only the source cells within eps_I of each wave's targets are read
+  int real_exp;         // kernel exp(-|z|^rho/eps) with the real rho of coef (else rho = 1)
 };
 template <typename R>
 hipError_t launch_nearfield(const NearArgs<R>& a, int nchunks, hipStream_t st);
@@ -399,6 +405,22 @@ hipError_t launch_unpermute(const double* src_sorted, const int* perm, long n, d
 template <typename R>
 hipError_t launch_gauss_tables(int d, int N, int B, const double* pb, const double* inv_phi, R* kernel, R* cost,
                                hipStream_t st);
+
+// Diagonal table of a real cost exponent rho (r = 0), in two steps around a
+// forward FFT of the grid.  kernel_samples: out[l] = K_R at the grid node l
+// (row-major, g per axis, last axis fastest) on the torus, taken at the
+// nearest image of the origin, from a near-field coefficient block cf
+// (NearArgs::coef layout): the even polynomial inside (cf[1] = (eps_I g)^2
+// squared cells) and exp(-r2^(rho/2) cf[kNearRhoInv]) outside; r2 in squared
+// cells.  spec_table: from the forward spectrum of those samples (the row
+// transform's k = 0..N/2 on the last axis, centered k = -N/2..N/2 on the
+// others, as the adjoint NFFT leaves it), tab[i] = Re(spec) hw / (g^d prod_c
+// Phi(k_c)^2) over |k_c| = 0..N/2 (extent (N/2+1)^d, row-major), the same
+// table as the Gaussian's.  Evaluated in FP64, stored as R.
+template <typename R>
+hipError_t launch_kernel_samples(int d, int g, const double* cf, R* out, hipStream_t st);
+template <typename R>
+hipError_t launch_spec_table(int d, int N, int g, const cplx<R>* spec, const double* inv_phi, R* tab, hipStream_t st);
 
 // readout: over sorted arrays, out[0] += sum a*log(b) (a>0), out[1] += sum a*log(a), out[2] += sum a
 struct ReadoutArgs {

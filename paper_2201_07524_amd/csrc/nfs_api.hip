@@ -100,7 +100,9 @@ static int default_p_smooth(const nfs_params*) { return 8; }
 static int check_params(const nfs_params* p, int64_t n, int64_t nt) {
   if (!p) return fail(NFS_EINVAL, "params is NULL");
   if (p->d < 1 || p->d > 3) return fail(NFS_EINVAL, "d must be 1, 2 or 3");
-  if (p->r != 1 && p->r != 2) return fail(NFS_EUNSUPPORTED, "cost exponent r must be 1 or 2");
+  if (p->r != 0 && p->r != 1 && p->r != 2) return fail(NFS_EUNSUPPORTED, "cost exponent r must be 0, 1 or 2");
+  if (p->r == 0 && (!(p->rexp > 1.0 && p->rexp <= 4.0) || p->rexp == 2.0))
+    return fail(NFS_EINVAL, "r = 0 needs a real exponent rexp in (1, 4] other than 2 (use r = 1 or r = 2)");
   if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(NFS_EINVAL, "eps must be positive and finite");
   if (p->N < 4 || (p->N & 1)) return fail(NFS_EINVAL, "N must be even and >= 4");
   if (p->m < 2 || p->m > 8) return fail(NFS_EINVAL, "m must be in [2, 8]");
@@ -119,7 +121,7 @@ static int check_params(const nfs_params* p, int64_t n, int64_t nt) {
   const int E = T + 2 * p->m + 1;
   const double tb = std::pow(double(E), p->d) * (p->precision == NFS_FP32 ? 4.0 : 8.0);
   if (tb > 160.0 * 1024.0) return fail(NFS_EINVAL, "LDS tile (tile + 2m + 1)^d exceeds 160 KiB; use a smaller tile");
-  if (p->r == 1) {
+  if (p->r != 2) {
     const double eIN = p->eps_I > 0.0 ? p->eps_I : default_eps_I(p);
     const int ps = p->p_smooth ? p->p_smooth : default_p_smooth(p);
     if (!(eIN > 0.0) || eIN > 0.25 * p->N) return fail(NFS_EINVAL, "eps_I (near-field radius times N) must be in (0, N/4]");
@@ -138,6 +140,19 @@ constexpr int kBoxSlot = 2 * kBoxVals;
 // Near-field radius on the torus and smoothness for r = 1.
 static double near_radius(const nfs_params* p) { return (p->eps_I > 0.0 ? p->eps_I : default_eps_I(p)) / p->N; }
 static int near_smooth(const nfs_params* p) { return p->p_smooth ? p->p_smooth : default_p_smooth(p); }
+
+// The cost exponent: r, or the real rexp when r = 0.
+static double cost_exponent(const nfs_params* p) { return p->r ? double(p->r) : p->rexp; }
+
+// Torus mapping of one problem with temperature eps and bounding box [lo, hi]:
+// closed-form Gaussian (r = 2), else a periodization error below exp(-L)
+// (L = 20 for FP32 grids, 36 for FP64).
+static Scaling near_scaling(const nfs_params* p, double eps, const double* lo, const double* hi) {
+  const double L = p->precision == NFS_FP32 ? 20.0 : 36.0;
+  if (p->r == 2) return choose_scaling(p->d, 2, eps, p->N, lo, hi);
+  if (p->r == 1) return choose_scaling_r1(p->d, eps, L, lo, hi);
+  return choose_scaling_rho(p->d, eps, p->rexp, L, lo, hi);
+}
 
 // ----------------------------------------------------------------------------- workspace layout
 struct Carver {
@@ -227,7 +242,8 @@ struct Work {
   BoxJob* boxjobs = nullptr;      // 2 x B: batched boxes of the plan
   long npartials = 0;             // workgroup partials (kBoxVals doubles each) the partials buffer holds
   double* tmp = nullptr;
-  int r = 2;
+  int r = 2;                  // 2: Gaussian; 1: a kernel with a near field (r = 1 or a real exponent)
+  double rho = 2.0;           // the cost exponent
   double* nf = nullptr;       // near-field sums (r = 1), per sorted target
   double* nfcoef = nullptr;   // B x kNearStride (r = 1)
   int kt = 0;
@@ -306,7 +322,7 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
   }
   w.ecell = ecell;
   w.cell_order = tcells <= kSortBins;
-  if (w.cell_order && p->r == 1) {
+  if (w.cell_order && p->r != 2) {
     w.X.cellstart = cv.take<int>(size_t(B) * nbins * (tcells + 1));
     w.Y.cellstart = cv.take<int>(size_t(B) * nbins * (tcells + 1));
   }
@@ -357,8 +373,10 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
   w.planprobs = cv.take<PlanProb>(B);
   w.boxjobs = cv.take<BoxJob>(size_t(2) * B);
   w.tmp = cv.take<double>(size_t(std::max(nA, nB)) * std::max(d, 1));
-  w.r = p->r;
-  if (p->r == 1) {
+  // w.r: 2 for the Gaussian, 1 for every kernel with a near field (r = 1 and real exponents)
+  w.r = p->r == 2 ? 2 : 1;
+  w.rho = cost_exponent(p);
+  if (p->r != 2) {
     w.nf = cv.take<double>(size_t(std::max(nA, nB)));
     w.nfcoef = cv.take<double>(size_t(B) * kNearStride);
     w.kt = int(std::ceil(near_radius(p) * g / T - 1e-12));
@@ -614,6 +632,78 @@ static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const std:
   return NFS_OK;
 }
 
+// Diagonal tables of a real cost exponent: the Fourier coefficients of the
+// regularized kernel K_R on the torus (Section 3.1: the polynomial inside the
+// near-field radius, the kernel outside) as the DFT of its samples on the
+// oversampled grid, truncated to |k_c| <= N/2.  One problem at a time through
+// the adjoint NFFT's forward passes (w.U -> w.W [-> w.V] -> w.spec); the
+// coefficient blocks w.nfcoef must be on the device.
+template <typename R>
+static int real_exponent_tables(Work<R>& w, const nfs_params* p, hipStream_t st) {
+  const Geom& geo = w.geo;
+  const int g = geo.g, N = geo.N, d = geo.d, K0 = w.K0;
+  const long rows = w.ncell / g;
+  AxisArgs<R> ax{};
+  ax.L = g;
+  ax.N = N;
+  ax.d = d;
+  ax.tw = w.tw;
+  ax.mul = Multiplier{nullptr, -1, 0};
+  for (int b = 0; b < w.B; ++b) {
+    R* tab = w.dtab + size_t(b) * w.H;
+    if (!(w.sc[b].eps_t > 0.0)) {
+      NFS_HIP(launch_fill(tab, sizeof(R) * w.H, st));
+      continue;
+    }
+    NFS_HIP(launch_kernel_samples<R>(d, g, w.nfcoef + size_t(b) * kNearStride, w.U, st));
+    RowArgs<R> ra{};
+    ra.mode = ROW_R2C;
+    ra.L = g;
+    ra.N = N;
+    ra.nrows = int(rows);
+    ra.real_io = w.U;
+    ra.gmode = GRID_REAL;
+    ra.grid_plane = w.gplane;
+    ra.spec = d == 1 ? w.spec : w.W;
+    ra.zero_src = 0;
+    ra.tw = w.tw;
+    NFS_HIP(launch_rows(ra, st));
+    if (d >= 2) {
+      const cplx<R>* cur = w.W;
+      if (d == 3) {
+        AxisArgs<R> a1 = ax;
+        a1.mode = AX_FWD;
+        a1.in = w.W;
+        a1.out = w.V;
+        a1.nin = g;
+        a1.nout = N + 1;
+        a1.out_centered = 1;
+        a1.in_stride = a1.out_stride = K0;
+        a1.in_ostride = long(g) * K0;
+        a1.out_ostride = long(N + 1) * K0;
+        a1.inner = K0;
+        a1.npen = long(g) * K0;
+        NFS_HIP(launch_axis(a1, st));
+        cur = w.V;
+      }
+      const long inner = d == 2 ? K0 : long(N + 1) * K0;
+      AxisArgs<R> a0 = ax;
+      a0.mode = AX_FWD;
+      a0.in = cur;
+      a0.out = w.spec;
+      a0.nin = g;
+      a0.nout = N + 1;
+      a0.out_centered = 1;
+      a0.in_stride = a0.out_stride = inner;
+      a0.inner = int(inner);
+      a0.npen = inner;
+      NFS_HIP(launch_axis(a0, st));
+    }
+    NFS_HIP(launch_spec_table<R>(d, N, g, w.spec, w.inv_phi, tab, st));
+  }
+  return NFS_OK;
+}
+
 template <typename R>
 static int upload_tables(Work<R>& w, const nfs_params* p, hipStream_t st) {
   const int g = w.geo.g;
@@ -654,27 +744,38 @@ static int upload_tables(Work<R>& w, const nfs_params* p, hipStream_t st) {
   std::vector<R> t1, t2;
   bool any = false;
   for (int b = 0; b < w.B; ++b) any = any || w.sc[b].eps_t > 0.0;
-  if (any && p->r == 1) {
+  if (any && p->r != 2) {
     const double eI = near_radius(p);
     const int ps = near_smooth(p);
+    const double rho = cost_exponent(p);
+    const bool real_exp = p->r == 0;
     t1.assign(size_t(w.B) * w.H, R(0));
     t2.assign(size_t(w.B) * w.H, R(0));
     std::vector<double> coef(size_t(w.B) * kNearStride, 0.0);
     for (int b = 0; b < w.B; ++b) {
       const double e = w.sc[b].eps_t;
-      const std::vector<double> cf = nearfield_poly(e, eI, ps);
-      const std::vector<double> tb = r1_table(p->d, p->N, e, eI, cf, phi);
-      for (long i = 0; i < w.H; ++i) t1[size_t(b) * w.H + i] = R(tb[i]);
+      const std::vector<double> cf = nearfield_poly(e, eI, ps, rho);
+      if (!real_exp && e > 0.0) {
+        const std::vector<double> tb = r1_table(p->d, p->N, e, eI, cf, phi);
+        for (long i = 0; i < w.H; ++i) t1[size_t(b) * w.H + i] = R(tb[i]);
+      }
       double* c = coef.data() + size_t(b) * kNearStride;
       c[0] = 1.0 / (e * g);
       c[1] = (eI * g) * (eI * g);
       c[2] = 1.0 / c[1];
       c[3] = ps;
       for (int j = 0; j < ps; ++j) c[4 + j] = cf[j];
+      c[kNearRhoHalf] = 0.5 * rho;
+      c[kNearRhoInv] = 1.0 / (e * std::pow(double(g), rho));  // (cells)^rho -> r^rho / eps_t
     }
-    NFS_HIP(hipMemcpyAsync(w.dtab, t1.data(), sizeof(R) * t1.size(), hipMemcpyHostToDevice, st));
     NFS_HIP(hipMemcpyAsync(w.dtab2, t2.data(), sizeof(R) * t2.size(), hipMemcpyHostToDevice, st));
     NFS_HIP(hipMemcpyAsync(w.nfcoef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, st));
+    if (real_exp) {
+      NFS_HIP(hipStreamSynchronize(st));  // t1 is not used
+      NFS_TRY(real_exponent_tables(w, p, st));
+    } else {
+      NFS_HIP(hipMemcpyAsync(w.dtab, t1.data(), sizeof(R) * t1.size(), hipMemcpyHostToDevice, st));
+    }
   } else if (any) {
     // closed form evaluated on the device for all problems at once (the host
     // loop over 512 problems' 129^2 tables took 48 ms of the batch's plan)
@@ -890,6 +991,7 @@ static hipError_t near_field(Work<R>& w, const CloudBuf<R>& src, const CloudBuf<
   a.out = w.nf;
   a.pstate = pstate;
   a.scell = src.cellstart;
+  a.real_exp = w.rho != 1.0;
   return launch_nearfield(a, tgt.nchunks, st);
 }
 
@@ -984,8 +1086,7 @@ static int do_fastsum(const nfs_params* p, const double* src, int64_t ns, const 
   NFS_HIP(hipStreamSynchronize(st));
   for (int i = 0; i < 9; ++i)
     if (!std::isfinite(box[i])) return fail(NFS_EINVAL, "non-finite point coordinates or weights");
-  w.sc = {p->r == 1 ? choose_scaling_r1(p->d, p->eps, p->precision == NFS_FP32 ? 20.0 : 36.0, box, box + 3)
-                     : choose_scaling(p->d, p->r, p->eps, p->N, box, box + 3)};
+  w.sc = {near_scaling(p, p->eps, box, box + 3)};
   NFS_TRY(sort_cloud(w, w.X, src, w.sc, wv, nullptr, st));
   NFS_TRY(sort_cloud(w, w.Y, tgt, w.sc, tscale, nullptr, st));
   NFS_TRY(upload_tables(w, p, st));
@@ -1280,8 +1381,7 @@ static int plan_sinkhorn(Work<R>& w, const nfs_params* p, const double* eps, con
         hi[c] = bx[3 + c];
       }
     }
-    w.sc[b] = p->r == 1 ? choose_scaling_r1(d, eps[b], p->precision == NFS_FP32 ? 20.0 : 36.0, lo, hi)
-                        : choose_scaling(d, p->r, eps[b], p->N, lo, hi);
+    w.sc[b] = near_scaling(p, eps[b], lo, hi);
     for (int c = 0; c < d; ++c) w.sc[b].shift[c] = shift[c];
   }
   NFS_TRY(sort_cloud(w, w.X, x, w.sc, mu, ax, st, -1.0));
@@ -1747,6 +1847,7 @@ struct Solver : SolverBase {
   // mean over the problem.  Outputs in the caller's (packed) point order.
   int grad(double* gx, double* gmu, double* gy, double* gnu, hipStream_t caller) override {
     if (logd || centred) return fail(NFS_EUNSUPPORTED, "the solver gradient needs the scaling form, uncentred");
+    if (p.r == 0) return fail(NFS_EUNSUPPORTED, "no gradient for a real cost exponent (r = 0)");
     NFS_TRY(enter(caller));
     hipStream_t st = gs;
     const int B = w.B, d = p.d;
@@ -1964,6 +2065,7 @@ template <typename R>
 static int do_grad(const nfs_params* p, const double* x, int64_t n, const double* mu, const double* y, int64_t nt,
                    const double* nu, const double* alpha, const double* alpha_t, double* grad_x, double* grad_mu,
                    void* ws, size_t wsb, hipStream_t st) {
+  if (p->r == 0) return fail(NFS_EUNSUPPORTED, "no gradient for a real cost exponent (r = 0)");
   Work<R> w;
   carve(w, p, 1, n, nt, nullptr, 2);
   if (wsb < w.bytes) return fail(NFS_EWORKSPACE, "workspace too small");

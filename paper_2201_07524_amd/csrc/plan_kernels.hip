@@ -789,6 +789,74 @@ template hipError_t launch_gauss_tables<float>(int, int, int, const double*, con
 template hipError_t launch_gauss_tables<double>(int, int, int, const double*, const double*, double*, double*,
                                                 hipStream_t);
 
+// ------------------------------------------------------------------ diagonal tables (real rho)
+template <typename R>
+__global__ __launch_bounds__(kBlock) void kernel_samples_kernel(int d, int g, long ncell, const double* cf, R* out) {
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= ncell) return;
+  long rem = i;
+  double r2 = 0.0;  // squared distance in cells to the nearest image of the origin
+  for (int c = 0; c < d; ++c) {
+    const long l = rem % g;
+    rem /= g;
+    const double x = double(l < g / 2 ? l : l - g);
+    r2 += x * x;
+  }
+  double v;
+  if (r2 < cf[1]) {
+    const int ps = int(cf[3]);
+    const double u2 = r2 * cf[2];
+    v = cf[4 + ps - 1];
+    for (int j = ps - 2; j >= 0; --j) v = v * u2 + cf[4 + j];
+  } else {
+    v = exp(-pow(r2, cf[kNearRhoHalf]) * cf[kNearRhoInv]);
+  }
+  out[i] = R(v);
+}
+
+template <typename R>
+hipError_t launch_kernel_samples(int d, int g, const double* cf, R* out, hipStream_t st) {
+  long ncell = 1;
+  for (int c = 0; c < d; ++c) ncell *= g;
+  hipLaunchKernelGGL(kernel_samples_kernel<R>, dim3(unsigned((ncell + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, d, g,
+                     ncell, cf, out);
+  return hipGetLastError();
+}
+template hipError_t launch_kernel_samples<float>(int, int, const double*, float*, hipStream_t);
+template hipError_t launch_kernel_samples<double>(int, int, const double*, double*, hipStream_t);
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void spec_table_kernel(int d, int N, int g, long H, const cplx<R>* spec,
+                                                            const double* inv_phi, R* tab) {
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= H) return;
+  const int h = N / 2 + 1;
+  long rem = i, o = 0, stride = 1;
+  double f = 1.0;
+  for (int c = d - 1; c >= 0; --c) {
+    const int kc = int(rem % h);
+    rem /= h;
+    // the last axis holds k = 0..N/2, the others the centered k = -N/2..N/2
+    o += stride * (c == d - 1 ? kc : kc + N / 2);
+    stride *= c == d - 1 ? h : N + 1;
+    f *= inv_phi[kc] * inv_phi[kc];
+    if (kc == N / 2) f *= 0.5;
+  }
+  tab[i] = R(double(spec[o].x) * f / pow(double(g), d));
+}
+
+template <typename R>
+hipError_t launch_spec_table(int d, int N, int g, const cplx<R>* spec, const double* inv_phi, R* tab, hipStream_t st) {
+  long H = 1;
+  for (int c = 0; c < d; ++c) H *= N / 2 + 1;
+  hipLaunchKernelGGL(spec_table_kernel<R>, dim3(unsigned((H + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, d, N, g, H,
+                     spec, inv_phi, tab);
+  return hipGetLastError();
+}
+template hipError_t launch_spec_table<float>(int, int, int, const cplx<float>*, const double*, float*, hipStream_t);
+template hipError_t launch_spec_table<double>(int, int, int, const cplx<double>*, const double*, double*,
+                                              hipStream_t);
+
 // ------------------------------------------------------------------ read-out sums
 __global__ __launch_bounds__(kBlock) void readout_kernel(ReadoutArgs a) {
   constexpr int NV = 3;

@@ -40,7 +40,7 @@ class _Params(ctypes.Structure):
                 ("N", ctypes.c_int32), ("m", ctypes.c_int32), ("sigma", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("eps_I", ctypes.c_double), ("p_smooth", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("rexp", ctypes.c_double)]
 
 
 class _Result(ctypes.Structure):
@@ -60,7 +60,7 @@ class Params:
     eps: float
     N: int
     m: int
-    r: int = 2
+    r: float = 2  # cost exponent: 1, 2, or a real value in (1, 4] (rexp of the C params)
     sigma: float = 2.0
     precision: str = "fp64"
     tile: int = 0
@@ -71,8 +71,9 @@ class Params:
 
     def to_c(self):
         prec = {"fp64": NFS_FP64, "fp32": NFS_FP32, "auto": NFS_AUTO}[self.precision]
-        return _Params(self.d, self.r, self.eps, self.N, self.m, self.sigma, prec, self.tile,
-                       self.chunk, self.flags, self.eps_I, self.p_smooth, 0)
+        r, rexp = (int(self.r), 0.0) if float(self.r) in (1.0, 2.0) else (0, float(self.r))
+        return _Params(self.d, r, self.eps, self.N, self.m, self.sigma, prec, self.tile,
+                       self.chunk, self.flags, self.eps_I, self.p_smooth, 0, rexp)
 
 
 _lib = None

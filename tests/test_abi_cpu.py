@@ -35,7 +35,9 @@ def _p(**kw):
 @pytest.mark.parametrize("kw,code", [
     (dict(d=0), nfs.NFS_EINVAL),
     (dict(d=4), nfs.NFS_EINVAL),
-    (dict(r=3), nfs.NFS_EUNSUPPORTED),
+    (dict(r=5), nfs.NFS_EINVAL),           # real exponents lie in (1, 4]
+    (dict(r=0.5), nfs.NFS_EINVAL),
+    (dict(r=1.5, eps_I=17), nfs.NFS_EINVAL),  # near-field radius above N/4
     (dict(eps=0.0), nfs.NFS_EINVAL),
     (dict(eps=-1.0), nfs.NFS_EINVAL),
     (dict(N=63), nfs.NFS_EINVAL),
@@ -58,6 +60,20 @@ def test_validate_sizes_and_accepts():
     assert nfs.validate(_p(), 1, 1) == nfs.NFS_OK
     assert nfs.validate(_p(d=1, N=256, m=8, precision="fp64"), 2048, 2048) == nfs.NFS_OK
     assert nfs.validate(_p(d=3, N=128, m=8), 10**6, 10**6) == nfs.NFS_OK
+    assert nfs.validate(_p(r=1.5), 100, 100) == nfs.NFS_OK
+    assert nfs.validate(_p(r=3), 100, 100) == nfs.NFS_OK
+    assert nfs.validate(_p(r=4), 100, 100) == nfs.NFS_OK
+
+
+def test_real_exponent_maps_to_rexp():
+    for r, want in ((1, (1, 0.0)), (2, (2, 0.0)), (1.5, (0, 1.5)), (3, (0, 3.0))):
+        c = _p(r=r).to_c()
+        assert (c.r, c.rexp) == want
+    raw = _p().to_c()
+    raw.r = 3  # an integer exponent other than 0, 1, 2 is not a code the library knows
+    lib = nfs.load_library()
+    import ctypes
+    assert lib.nfs_validate(ctypes.byref(raw), 100, 100) == nfs.NFS_EUNSUPPORTED
 
 
 def test_error_message_and_workspace_size():

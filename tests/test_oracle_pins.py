@@ -81,6 +81,43 @@ def test_kernel_sum_riemann_closed_form(d, r):
         assert abs(got_dense - exact) <= tol * exact
 
 
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("rho", [1.5, 3.0])
+def test_kernel_integral_real_exponent(d, rho):
+    """A real exponent of the distance (Definition 2.1): the midpoint sum of
+    exp(-|x|^rho/eps) over a fine grid approaches its integral over R^d,
+    vol_d eps^(d/rho) Gamma(1 + d/rho) (radial substitution u = r^rho/eps).
+    Pins the exponent's placement in the C direct sums and the dense kernel."""
+    eps = 0.02
+    h = {1: 1e-3, 2: 2.5e-3, 3: 6e-3}[d]
+    half = int(math.ceil((38 * eps) ** (1.0 / rho) / h))
+    ax = h * np.arange(-half, half + 1)
+    pts = np.stack(np.meshgrid(*([ax] * d), indexing="ij"), axis=-1).reshape(-1, d)
+    w = np.full(pts.shape[0], h ** d)
+    tgt = np.zeros((1, d))
+    vol = {1: 2.0, 2: math.pi, 3: 4.0 * math.pi / 3.0}[d]
+    exact = vol * eps ** (d / rho) * math.gamma(1.0 + d / rho)
+    got_c = direct.kv(tgt, pts, w, rho, eps)[0]
+    assert abs(got_c - exact) <= 3e-3 * exact
+    if pts.shape[0] <= 40000:
+        got_dense = (sd.gibbs_kernel(tgt, pts, rho, eps) @ w)[0]
+        assert abs(got_dense - exact) <= 3e-3 * exact
+
+
+def test_real_exponent_homogeneity():
+    """exp(-|l z|^rho / (l^rho eps)) = exp(-|z|^rho/eps): scaling the clouds by
+    l and eps by l^rho leaves the sums unchanged only with the exponent on the
+    distance itself (not on its square, nor on eps)."""
+    x, y = _cloud(50, 2, 31), _cloud(70, 2, 32)
+    w = np.random.default_rng(33).uniform(0, 1, 70)
+    for rho in (1.5, 2.5):
+        a = direct.kv(x, y, w, rho, 0.05)
+        b = direct.kv(3.0 * x, 3.0 * y, w, rho, 0.05 * 3.0 ** rho)
+        assert np.allclose(a, b, rtol=1e-12, atol=0)
+        K = sd.gibbs_kernel(x, y, rho, 0.05)
+        assert np.allclose(a, K @ w, rtol=1e-13, atol=0)
+
+
 @pytest.mark.parametrize("eps", [0.02, 0.5])
 def test_coincident_support_upper_value_is_zero(eps):
     """Coincident supports: c = 0, so s = -eps (H(p) + H(pt)) and the upper
