@@ -1,6 +1,7 @@
 """Full-size parity on sampled outputs, in the launch configuration the
 benchmark uses (default tile and chunk): the 3-D mixtures with the gradient,
-the 3-D ball/shell with the Euclidean cost, and the 512-problem batch.
+the 3-D ball/shell with the Euclidean cost and with |x - y|^1.5, and the
+512-problem batch.
 
 Each test runs a few iterations at full size and checks the last half-step
 alpha_t = nu / (K^T alpha) on sampled targets against the oracle's FP64
@@ -101,6 +102,18 @@ def test_ball_shell_r1_full_size_sampled_parity():
     rows = np.random.default_rng(14).choice(cfg["y"].shape[0], size=128, replace=False)
     check_last_half_step(cfg["x"], cfg["y"], cfg["pt"], res.alpha.cpu().numpy(), res.alpha_t.cpu().numpy(),
                          1, cfg["eps"], rows)
+
+
+def test_ball_shell_real_exponent_full_size_sampled_parity():
+    """The same clouds with the cost |x - y|^1.5 (a real exponent: sampled-kernel
+    tables and the real-exponent near field), FP32, default near field: 3
+    iterations, checked like the r = 1 case against the oracle's direct sums."""
+    cfg = workloads.ball_shell_3d()
+    prm = nfs.Params(d=3, r=1.5, eps=cfg["eps"], N=cfg["N"], m=cfg["m"], precision="fp32")
+    res = nfs.sinkhorn(prm, T(cfg["x"]), T(cfg["p"]), T(cfg["y"]), T(cfg["pt"]), 3)
+    rows = np.random.default_rng(15).choice(cfg["y"].shape[0], size=128, replace=False)
+    check_last_half_step(cfg["x"], cfg["y"], cfg["pt"], res.alpha.cpu().numpy(), res.alpha_t.cpu().numpy(),
+                         1.5, cfg["eps"], rows)
 
 
 def test_batched_full_size_sampled_parity():
