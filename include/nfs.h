@@ -118,8 +118,9 @@ typedef struct nfs_params {
                          replaced inside |z| < eps_I by the even polynomial matching its first
                          p_smooth - 1 derivatives at eps_I (Section 3.1), the Fourier
                          coefficients of the regularized kernel come from its samples on the
-                         oversampled grid, and the near field adds K - K_R.  No gradient
-                         (NFS_EUNSUPPORTED) and no primal cost.  Ignored unless r = 0 */
+                         oversampled grid, and the near field adds K - K_R.  The gradients
+                         use grad c = rexp |x-y|^(rexp-2) (x-y); no primal cost.  Ignored
+                         unless r = 0 */
 } nfs_params;
 
 typedef struct nfs_result {

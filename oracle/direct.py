@@ -76,7 +76,10 @@ def kv(tgt, src, w, r, eps, rows=None):
 
 
 def grad_rows(tgt, src, w, r, eps, rows=None):
-    """sum_j w_j k_ij grad_x c(tgt_i, src_j) for i in ``rows``; shape (nrows, d)."""
+    """sum_j w_j k_ij grad_x c(tgt_i, src_j) for i in ``rows``; shape (nrows, d)
+    (r = 1 or 2 only)."""
+    if float(r) not in (1.0, 2.0):
+        raise ValueError("grad_rows takes r = 1 or 2")
     lib = load()
     tgt = _pts(tgt)
     src = _pts(src)

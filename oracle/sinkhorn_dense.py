@@ -167,7 +167,8 @@ def envelope_gradient(x, y, K, alpha, alpha_t, r, eps):
       d s / d p_i  = eps log alpha_i, projected onto sum = 0 (the weights live
                      on the probability simplex).
     For r = 2, grad_x c = 2 (x_i - y_j); for r = 1 it is the unit vector
-    (x_i - y_j)/|x_i - y_j| (zero where the points coincide).
+    (x_i - y_j)/|x_i - y_j| (zero where the points coincide); for a real
+    r > 1, r |x_i - y_j|^(r - 2) (x_i - y_j) (zero where they coincide).
     """
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
@@ -182,8 +183,11 @@ def envelope_gradient(x, y, K, alpha, alpha_t, r, eps):
     elif r == 1:
         nrm = np.sqrt(np.sum(diff * diff, axis=-1, keepdims=True))
         g = np.where(nrm > 0, diff / np.where(nrm > 0, nrm, 1.0), 0.0)
+    elif r > 1:
+        nrm = np.sqrt(np.sum(diff * diff, axis=-1, keepdims=True))
+        g = np.where(nrm > 0, r * np.where(nrm > 0, nrm, 1.0) ** (r - 2) * diff, 0.0)
     else:
-        raise ValueError("r must be 1 or 2")
+        raise ValueError("r must be 1, 2 or a real exponent above 1")
     grad_x = np.einsum("ij,ijc->ic", pi, g)
     gmu = eps * np.where(alpha > 0, np.log(np.where(alpha > 0, alpha, 1.0)), 0.0)
     grad_mu = gmu - gmu.mean()
@@ -195,7 +199,8 @@ def envelope_gradient_targets(x, y, K, alpha, alpha_t, r, eps):
     same envelope argument on eq. (14):
       d s / d y_j  = sum_i pi_ij grad_y c(x_i, y_j),
       d s / d pt_j = eps log alpha_t_j, projected onto sum = 0.
-    For r = 2, grad_y c = 2 (y_j - x_i); for r = 1, (y_j - x_i)/|y_j - x_i|.
+    For r = 2, grad_y c = 2 (y_j - x_i); for r = 1, (y_j - x_i)/|y_j - x_i|;
+    for a real r > 1, r |y_j - x_i|^(r - 2) (y_j - x_i).
     """
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
@@ -210,8 +215,11 @@ def envelope_gradient_targets(x, y, K, alpha, alpha_t, r, eps):
     elif r == 1:
         nrm = np.sqrt(np.sum(diff * diff, axis=-1, keepdims=True))
         g = np.where(nrm > 0, diff / np.where(nrm > 0, nrm, 1.0), 0.0)
+    elif r > 1:
+        nrm = np.sqrt(np.sum(diff * diff, axis=-1, keepdims=True))
+        g = np.where(nrm > 0, r * np.where(nrm > 0, nrm, 1.0) ** (r - 2) * diff, 0.0)
     else:
-        raise ValueError("r must be 1 or 2")
+        raise ValueError("r must be 1, 2 or a real exponent above 1")
     grad_y = np.einsum("ij,ijc->jc", pi, g)
     gnu = eps * np.where(alpha_t > 0, np.log(np.where(alpha_t > 0, alpha_t, 1.0)), 0.0)
     grad_nu = gnu - gnu.mean()

@@ -138,14 +138,15 @@ __global__ __launch_bounds__(kBlock) void nearfield_kernel(NearArgs<R> a) {
   }
 }
 
-// Gradient of the near-field sum at the targets (r = 1): for every target,
+// Gradient of the near-field sum at the targets: for every target,
 //   out[c * plane + q] = sum_{sources j within eps_I} w_j wm d/dx'_c (K - K_R)(x'_q - y'_j),
 // the derivative in torus units (x' = g x_cells).  With z the target-source
-// offset in cells, r = |z| and rho = r^2 / eps_I^2 (cells),
-//   grad (K - K_R) = -g [inv_e e^{-r inv_e} / r + 2 inv_ei2 sum_{j>=1} j c_j rho^{j-1}] z,
+// offset in cells, r = |z| and u = r^2 / eps_I^2 (cells),
+//   grad (K - K_R) = -g [k'(r) + 2 inv_ei2 sum_{j>=1} j c_j u^{j-1}] z,
+//   rho = 1:  k'(r) = inv_e e^{-r inv_e} / r,
+//   real rho: k'(r) = rho inv_er r^(rho-2) e^{-r^rho inv_er}  (inv_er = coef[kNearRhoInv]),
 // the first term taken as 0 at r = 0 (the cost's gradient is zero where the
-// points coincide).  Same tiling as nearfield_kernel.  Built for rho = 1 only
-// (REAL is always false: the launch macro names it for every near-field kernel).
+// points coincide; r^(rho-1) -> 0 there for rho > 1).  Same tiling as nearfield_kernel.
 template <typename R, int D, int PS, bool REAL>
 __global__ __launch_bounds__(kBlock) void nearfield_grad_kernel(NearArgs<R> a) {
   __shared__ R su[D][kBlock];
@@ -156,6 +157,7 @@ __global__ __launch_bounds__(kBlock) void nearfield_grad_kernel(NearArgs<R> a) {
   const int nbins = geo.nt[0] * geo.nt[1] * geo.nt[2];
   const double* cf = a.coef + size_t(pb) * kNearStride;
   const R inv_e = R(cf[0]), ei2 = R(cf[1]), inv_ei2 = R(cf[2]);
+  const R hr = R(cf[kNearRhoHalf]), inv_er = R(cf[kNearRhoInv]);
   // derivative coefficients j c_j of the inner polynomial, in rho
   R dc[PS > 1 ? PS - 1 : 1];
 #pragma unroll
@@ -223,8 +225,15 @@ __global__ __launch_bounds__(kBlock) void nearfield_grad_kernel(NearArgs<R> a) {
             R dP = PS > 1 ? dc[PS - 2] : R(0);
 #pragma unroll
             for (int jj = PS - 3; jj >= 0; --jj) dP = dP * rho + dc[jj];
-            const R r = sqrt(r2);
-            const R ek = r > R(0) ? inv_e * exp(-r * inv_e) / r : R(0);
+            R ek;
+            if constexpr (REAL) {
+              // r^rho = r2^(rho/2); k'(r) = rho inv_er (r^rho / r2) e^{-r^rho inv_er}
+              const R rr = r2 > R(0) ? pow(r2, hr) : R(0);
+              ek = r2 > R(0) ? R(2) * hr * inv_er * (rr / r2) * exp(-rr * inv_er) : R(0);
+            } else {
+              const R r = sqrt(r2);
+              ek = r > R(0) ? inv_e * exp(-r * inv_e) / r : R(0);
+            }
             const R h = wj * (ek + R(2) * inv_ei2 * dP);
 #pragma unroll
             for (int cc = 0; cc < D; ++cc) acc[k][cc] += h * z[cc];
@@ -519,9 +528,9 @@ extern template hipError_t launch_nearfield_form<double, false>(const NearArgs<d
 extern template hipError_t launch_nearfield_form<float, true>(const NearArgs<float>&, int, hipStream_t);
 extern template hipError_t launch_nearfield_form<double, true>(const NearArgs<double>&, int, hipStream_t);
 
-template <typename R>
-hipError_t launch_nearfield_grad_impl(const NearArgs<R>& a, int nchunks, hipStream_t st) {
-  constexpr bool REAL = false;
+// Its gradient in one exponent form, instantiated like the sum.
+template <typename R, bool REAL>
+hipError_t launch_nearfield_grad_form(const NearArgs<R>& a, int nchunks, hipStream_t st) {
   if (nchunks <= 0) return hipSuccess;
   if (a.geo.d == 1) {
     NFS_NEAR_P(nearfield_grad_kernel, 1)
@@ -532,5 +541,9 @@ hipError_t launch_nearfield_grad_impl(const NearArgs<R>& a, int nchunks, hipStre
   }
   return hipGetLastError();
 }
+extern template hipError_t launch_nearfield_grad_form<float, false>(const NearArgs<float>&, int, hipStream_t);
+extern template hipError_t launch_nearfield_grad_form<double, false>(const NearArgs<double>&, int, hipStream_t);
+extern template hipError_t launch_nearfield_grad_form<float, true>(const NearArgs<float>&, int, hipStream_t);
+extern template hipError_t launch_nearfield_grad_form<double, true>(const NearArgs<double>&, int, hipStream_t);
 
 }  // namespace nfs

@@ -995,7 +995,7 @@ static hipError_t near_field(Work<R>& w, const CloudBuf<R>& src, const CloudBuf<
   return launch_nearfield(a, tgt.nchunks, st);
 }
 
-// Gradient of the near-field correction (r = 1) of the product with sources
+// Gradient of the near-field correction (r = 1 or a real exponent) of the product with sources
 // `src` at the targets `tgt`: d components in torus units, component c at
 // out + c * tgt.n (sorted target order, normalized like the spread).
 template <typename R>
@@ -1016,6 +1016,7 @@ static hipError_t near_field_grad(Work<R>& w, const CloudBuf<R>& src, const Clou
   a.ps = w.ps;
   a.out = out;
   a.out_plane = tgt.n;
+  a.real_exp = w.rho != 1.0;
   return launch_nearfield_grad(a, tgt.nchunks, st);
 }
 
@@ -1847,7 +1848,6 @@ struct Solver : SolverBase {
   // mean over the problem.  Outputs in the caller's (packed) point order.
   int grad(double* gx, double* gmu, double* gy, double* gnu, hipStream_t caller) override {
     if (logd || centred) return fail(NFS_EUNSUPPORTED, "the solver gradient needs the scaling form, uncentred");
-    if (p.r == 0) return fail(NFS_EUNSUPPORTED, "no gradient for a real cost exponent (r = 0)");
     NFS_TRY(enter(caller));
     hipStream_t st = gs;
     const int B = w.B, d = p.d;
@@ -2065,7 +2065,6 @@ template <typename R>
 static int do_grad(const nfs_params* p, const double* x, int64_t n, const double* mu, const double* y, int64_t nt,
                    const double* nu, const double* alpha, const double* alpha_t, double* grad_x, double* grad_mu,
                    void* ws, size_t wsb, hipStream_t st) {
-  if (p->r == 0) return fail(NFS_EUNSUPPORTED, "no gradient for a real cost exponent (r = 0)");
   Work<R> w;
   carve(w, p, 1, n, nt, nullptr, 2);
   if (wsb < w.bytes) return fail(NFS_EWORKSPACE, "workspace too small");

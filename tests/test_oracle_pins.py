@@ -299,7 +299,7 @@ def test_gradient_sum_identity_r2():
     assert abs(gmu.sum()) <= 1e-14
 
 
-@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 1.5])
 def test_gradient_central_differences(r):
     """Envelope gradient vs central finite differences of the converged cost.
     Positions: h = 1e-4.  Weights: along the simplex directions e_i - e_k with
@@ -334,7 +334,7 @@ def test_gradient_central_differences(r):
         assert abs(fd - (gmu[i] - gmu[k])) <= 1e-6 * max(1.0, abs(fd))
 
 
-@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 1.5])
 def test_target_gradient_central_differences_and_translation(r):
     """Target-side envelope gradient vs central differences of the converged
     cost (positions h = 1e-4, weights along e_j - e_k), and translation
