@@ -608,8 +608,9 @@ __device__ __forceinline__ Red red_combine(Red a, Red b) {
           fmin(a.tmin, b.tmin), fmax(a.tmax, b.tmax), a.cnt + b.cnt};
 }
 
+template <int NT = kBlock>
 __device__ Red block_reduce(Red v, Red* sh) {
-  // wave64 butterfly, then across the 4 waves in fixed order
+  // wave64 butterfly, then across the NT / 64 waves in fixed order
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     Red w;
@@ -626,7 +627,7 @@ __device__ Red block_reduce(Red v, Red* sh) {
   if (lane == 0) sh[wid] = v;
   __syncthreads();
   Red r = sh[0];
-  for (int k = 1; k < kBlock / 64; ++k) r = red_combine(r, sh[k]);
+  for (int k = 1; k < NT / 64; ++k) r = red_combine(r, sh[k]);
   return r;
 }
 
@@ -693,6 +694,12 @@ __global__ __launch_bounds__(kBlock) void reduce_stats_kernel(InterpArgs<R> a) {
 
 // --------------------------------------------------------------------------- interp
 constexpr int kInterpRun = 2;
+// Threads per interpolation workgroup: 512 for FP32 in 3-D (1e6-point 3-D
+// mixture, m = 8: 415 -> 380 us per launch, the iteration 3.09 -> 3.01 ms),
+// 256 otherwise (2-D mixture: 48 us at 256 threads, 52 at 512; FP64 in 3-D
+// needs more registers than 512 threads leave).
+template <typename R, int D>
+constexpr int interp_block() { return sizeof(R) == 4 && D == 3 ? 512 : kBlock; }
 
 // Interpolates GC consecutive sorted points that lie in one cell: each row of
 // taps is read from the LDS tile once and dotted with the GC windows.
@@ -802,10 +809,11 @@ template <typename R, int D, bool LOG>
 constexpr int interp_min_waves() { return sizeof(R) == 4 && D == 3 && !LOG ? 4 : 1; }
 
 template <typename R, int D, int M, bool LOG>
-__global__ __launch_bounds__(kBlock, (interp_min_waves<R, D, LOG>())) void interp_kernel(InterpArgs<R> a) {
+__global__ __launch_bounds__((interp_block<R, D>()), (interp_min_waves<R, D, LOG>())) void interp_kernel(InterpArgs<R> a) {
+  constexpr int IB = interp_block<R, D>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
-  __shared__ Red red_sh[kBlock / 64];
+  __shared__ Red red_sh[IB / 64];
   const Geom geo = a.geo;
   const int E = geo.E;
   const int g = geo.g;
@@ -866,16 +874,16 @@ __global__ __launch_bounds__(kBlock, (interp_min_waves<R, D, LOG>())) void inter
     return gp[lin];
   };
   constexpr int kTileBatch = 8;
-  for (int base = lo + int(threadIdx.x); base < hi; base += kTileBatch * kBlock) {
+  for (int base = lo + int(threadIdx.x); base < hi; base += kTileBatch * IB) {
     R v[kTileBatch];
 #pragma unroll
     for (int u = 0; u < kTileBatch; ++u) {
-      const int i = base + u * kBlock;
+      const int i = base + u * IB;
       if (i < hi) v[u] = grid_at(i);
     }
 #pragma unroll
     for (int u = 0; u < kTileBatch; ++u) {
-      const int i = base + u * kBlock;
+      const int i = base + u * IB;
       if (i < hi) tile[i] = v[u];
     }
   }
@@ -971,8 +979,8 @@ __global__ __launch_bounds__(kBlock, (interp_min_waves<R, D, LOG>())) void inter
     for (int p = 0; p < GC; ++p) epilogue(q0 + p, acc[p], nfq[p], in.p[p], in.al[p]);
   };
   if constexpr (ahead) {
-    for (int rr = threadIdx.x; rr < nit; rr += kBlock) {
-      const int rn = rr + kBlock;
+    for (int rr = threadIdx.x; rr < nit; rr += IB) {
+      const int rn = rr + IB;
       PointIn<R, D, GI> nxt;
       int qn = 0;
       if (rn < nit) {
@@ -989,8 +997,8 @@ __global__ __launch_bounds__(kBlock, (interp_min_waves<R, D, LOG>())) void inter
       q1 = ch.start + runs[nfull + threadIdx.x];
       one.load(a, q1, pa);
     }
-    for (int rr = threadIdx.x; rr < nsingle; rr += kBlock) {
-      const int rn = rr + kBlock;
+    for (int rr = threadIdx.x; rr < nsingle; rr += IB) {
+      const int rn = rr + IB;
       PointIn<R, D, 1> nxt;
       int qn = 0;
       if (rn < nsingle) {
@@ -1002,13 +1010,13 @@ __global__ __launch_bounds__(kBlock, (interp_min_waves<R, D, LOG>())) void inter
       q1 = qn;
     }
   } else {
-    for (int rr = threadIdx.x; rr < nit; rr += kBlock) {
+    for (int rr = threadIdx.x; rr < nit; rr += IB) {
       const int q0 = step_q0(rr);
       PointIn<R, D, GI> in;
       in.load(a, q0, false);
       step(q0, in);
     }
-    for (int rr = threadIdx.x; rr < nsingle; rr += kBlock) {
+    for (int rr = threadIdx.x; rr < nsingle; rr += IB) {
       const int q0 = ch.start + runs[nfull + rr];
       PointIn<R, D, 1> in;
       in.load(a, q0, false);
@@ -1017,7 +1025,7 @@ __global__ __launch_bounds__(kBlock, (interp_min_waves<R, D, LOG>())) void inter
   }
   if (a.epi != EPI_OUT) {
     // this chunk's partial; reduce_stats_kernel combines them per problem
-    const Red r = block_reduce(acc_red, red_sh);
+    const Red r = block_reduce<IB>(acc_red, red_sh);
     if (threadIdx.x == 0) {
       double* pw = a.partials + kRedVals * size_t(cb);
       pw[0] = r.res2;
@@ -1041,13 +1049,13 @@ size_t tile_bytes(const Geom& geo) {
 
 #define NFS_DISPATCH_M_X(D_, R_, KERNEL, X_, ARGS, NBLK, SHM, STREAM)                                        \
   switch (geo.M) {                                                                                          \
-    case 2: hipLaunchKernelGGL((KERNEL<R_, D_, 2, X_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, ARGS); break; \
-    case 3: hipLaunchKernelGGL((KERNEL<R_, D_, 3, X_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, ARGS); break; \
-    case 4: hipLaunchKernelGGL((KERNEL<R_, D_, 4, X_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, ARGS); break; \
-    case 5: hipLaunchKernelGGL((KERNEL<R_, D_, 5, X_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, ARGS); break; \
-    case 6: hipLaunchKernelGGL((KERNEL<R_, D_, 6, X_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, ARGS); break; \
-    case 7: hipLaunchKernelGGL((KERNEL<R_, D_, 7, X_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, ARGS); break; \
-    case 8: hipLaunchKernelGGL((KERNEL<R_, D_, 8, X_>), dim3(NBLK), dim3(kBlock), SHM, STREAM, ARGS); break; \
+    case 2: hipLaunchKernelGGL((KERNEL<R_, D_, 2, X_>), dim3(NBLK), dim3(interp_block<R_, D_>()), SHM, STREAM, ARGS); break; \
+    case 3: hipLaunchKernelGGL((KERNEL<R_, D_, 3, X_>), dim3(NBLK), dim3(interp_block<R_, D_>()), SHM, STREAM, ARGS); break; \
+    case 4: hipLaunchKernelGGL((KERNEL<R_, D_, 4, X_>), dim3(NBLK), dim3(interp_block<R_, D_>()), SHM, STREAM, ARGS); break; \
+    case 5: hipLaunchKernelGGL((KERNEL<R_, D_, 5, X_>), dim3(NBLK), dim3(interp_block<R_, D_>()), SHM, STREAM, ARGS); break; \
+    case 6: hipLaunchKernelGGL((KERNEL<R_, D_, 6, X_>), dim3(NBLK), dim3(interp_block<R_, D_>()), SHM, STREAM, ARGS); break; \
+    case 7: hipLaunchKernelGGL((KERNEL<R_, D_, 7, X_>), dim3(NBLK), dim3(interp_block<R_, D_>()), SHM, STREAM, ARGS); break; \
+    case 8: hipLaunchKernelGGL((KERNEL<R_, D_, 8, X_>), dim3(NBLK), dim3(interp_block<R_, D_>()), SHM, STREAM, ARGS); break; \
     default: return hipErrorInvalidValue;                                                                   \
   }
 
