@@ -322,9 +322,9 @@ int nfs_sinkhorn_divergence(const nfs_params* prm, const double* x, int64_t n, c
  *   grad_mu[i] = eps log alpha_i - mean_k(eps log alpha_k)                               (n)
  * with the kernel gradient summed by fast summation (coefficients 2 pi i k b_k
  * of the regularized kernel); for r = 1 (grad_x c = (x - y)/|x - y|, zero
- * where points coincide) the gradient of the near-field correction K - K_R is
- * added by direct sums over the pairs closer than eps_I.  Either output may
- * be NULL.
+ * where points coincide) and a real exponent rexp (grad_x c = rexp |x - y|^(rexp-2)
+ * (x - y)) the gradient of the near-field correction K - K_R is added by
+ * direct sums over the pairs closer than eps_I.  Either output may be NULL.
  */
 int nfs_sinkhorn_grad(const nfs_params* prm, const double* x, int64_t n, const double* mu,
                       const double* y, int64_t nt, const double* nu,

@@ -137,7 +137,7 @@ static int check_params(const nfs_params* p, int64_t n, int64_t nt) {
 // Per-problem slot of the bounding-box buffer: the x box, then the y box.
 constexpr int kBoxSlot = 2 * kBoxVals;
 
-// Near-field radius on the torus and smoothness for r = 1.
+// Near-field radius on the torus and smoothness (r = 1 and real exponents).
 static double near_radius(const nfs_params* p) { return (p->eps_I > 0.0 ? p->eps_I : default_eps_I(p)) / p->N; }
 static int near_smooth(const nfs_params* p) { return p->p_smooth ? p->p_smooth : default_p_smooth(p); }
 
@@ -244,8 +244,8 @@ struct Work {
   double* tmp = nullptr;
   int r = 2;                  // 2: Gaussian; 1: a kernel with a near field (r = 1 or a real exponent)
   double rho = 2.0;           // the cost exponent
-  double* nf = nullptr;       // near-field sums (r = 1), per sorted target
-  double* nfcoef = nullptr;   // B x kNearStride (r = 1)
+  double* nf = nullptr;       // near-field sums (r != 2), per sorted target
+  double* nfcoef = nullptr;   // B x kNearStride (r != 2)
   int kt = 0;
   int ps = 0;
   std::vector<Scaling> sc;
@@ -970,7 +970,7 @@ static InterpArgs<R> interp_args(Work<R>& w, const CloudBuf<R>& tgt, int epi, co
   return a;
 }
 
-// Near-field correction (r = 1) of the product with sources `src` at the
+// Near-field correction (r = 1 or a real exponent) of the product with sources `src` at the
 // targets `tgt`, into w.nf (sorted target order, normalized like the spread).
 template <typename R>
 static hipError_t near_field(Work<R>& w, const CloudBuf<R>& src, const CloudBuf<R>& tgt, const double* weights,
