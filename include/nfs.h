@@ -64,7 +64,10 @@ extern "C" {
 
 /* flags */
 #define NFS_FLAG_NO_GRAPH 1      /* launch the iteration kernels directly, no hipGraph replay */
-#define NFS_FLAG_PRIMAL_COST 2   /* also evaluate <pi, C> (one extra fast summation) */
+#define NFS_FLAG_PRIMAL_COST 2   /* also evaluate <pi, C> (one extra fast summation with the
+                                    kernel c K; for r = 1 and real exponents its table comes
+                                    from samples of its own regularized form at plan time, and
+                                    the extra sum has its own near field) */
 #define NFS_FLAG_TILE_REDUCE 4   /* spread: store each chunk's LDS tile and sum the tiles per
                                     (tile, neighbour) instead of flushing LDS tiles straight
                                     into the grid with global atomics (the default) */
@@ -98,7 +101,7 @@ extern "C" {
 typedef struct nfs_params {
   int32_t d;          /* dimension, 1..3 */
   int32_t r;          /* cost exponent: 2 -> c = |x-y|^2; 1 -> c = |x-y| (near-field corrected,
-                         Remark 3.2; no primal cost); 0 -> the real exponent rexp */
+                         Remark 3.2); 0 -> the real exponent rexp */
   double eps;         /* temperature > 0; K = exp(-c/eps) (the paper's 1/lambda) */
   int32_t N;          /* bandwidth per dimension: I_N = {-N/2..N/2-1}^d, even, >= 4 */
   int32_t m;          /* window cutoff: 2m+1 grid taps per dimension, 2 <= m <= 8 */
@@ -119,7 +122,7 @@ typedef struct nfs_params {
                          p_smooth - 1 derivatives at eps_I (Section 3.1), the Fourier
                          coefficients of the regularized kernel come from its samples on the
                          oversampled grid, and the near field adds K - K_R.  The gradients
-                         use grad c = rexp |x-y|^(rexp-2) (x-y); no primal cost.  Ignored
+                         use grad c = rexp |x-y|^(rexp-2) (x-y).  Ignored
                          unless r = 0 */
 } nfs_params;
 

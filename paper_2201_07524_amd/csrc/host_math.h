@@ -188,10 +188,12 @@ inline Scaling choose_scaling_rho(int d, double eps, double rho, double L, const
 // With a real exponent rho, K(r) = exp(-r^rho/e): its derivatives in u = r/eI at
 // u = 1 come from the Taylor series of exp(h(t)), h(t) = -(eI^rho/e) (1 + t)^rho
 // = -(eI^rho/e) sum_j binom(rho, j) t^j, truncated at degree p - 1.
-inline std::vector<double> nearfield_poly(double e, double eI, int p, double rho = 1.0) {
+// cost: the same for the cost-weighted kernel r^rho exp(-r^rho/e) (the primal
+// cost's kernel), whose series is that of exp(h(t)) times eI^rho (1 + t)^rho.
+inline std::vector<double> nearfield_poly(double e, double eI, int p, double rho = 1.0, bool cost = false) {
   std::vector<long double> A(size_t(p) * p, 0.0L), b(p);
   std::vector<long double> dk(p);  // d^q/du^q K at u = 1
-  if (rho == 1.0) {
+  if (rho == 1.0 && !cost) {
     for (int q = 0; q < p; ++q) dk[q] = std::pow(-(long double)(eI / e), (long double)q) * std::exp(-(long double)(eI / e));
   } else {
     const long double a = std::pow((long double)eI, (long double)rho) / (long double)e;
@@ -212,6 +214,12 @@ inline std::vector<double> nearfield_poly(double e, double eI, int p, double rho
         term[i] = nt[i] / (long double)k;
         ex[i] += term[i];
       }
+    }
+    if (cost) {  // times eI^rho (1 + t)^rho = -(e) h(t)
+      std::vector<long double> prod(p, 0.0L);
+      for (int i = 0; i < p; ++i)
+        for (int j = 0; i + j < p; ++j) prod[i + j] += ex[i] * (-(long double)e * h[j]);
+      ex = prod;
     }
     long double fact = 1.0L;
     for (int q = 0; q < p; ++q) {

@@ -141,9 +141,18 @@ struct InterpArgs {
 // [1] eps_I^2 in cells^2, [2] 1/eps_I^2 in cells^-2, [3] p, [4 + j] c_j (j < p <= 16),
 // [kNearRhoHalf] rho/2, [kNearRhoInv] 1/(eps_t g^rho) ((cell distance)^rho -> r^rho/eps).
 // NearArgs::real_exp selects K = exp(-(r2 cells)^(rho/2) [kNearRhoInv]); else rho = 1.
+// NearArgs::cost selects the primal cost's kernel c K instead, c = |x - y|^rho in
+// the caller's units: K_c = (r2 cells)^(rho/2) [kNearCostMul] exp(-(r2 cells)^(rho/2)
+// [kNearRhoInv]) with [kNearCostMul] = 1/(g s)^rho (s the torus scale) and the c_j
+// of its own regularizing polynomial (a second coefficient block), any rho.
 constexpr int kNearStride = 24;
 constexpr int kNearRhoHalf = 20;
 constexpr int kNearRhoInv = 21;
+constexpr int kNearCostMul = 22;
+// Exponent forms of the near-field kernels (template parameter FORM).
+constexpr int kNearR1 = 0;    // exp(-r/eps)
+constexpr int kNearReal = 1;  // exp(-r^rho/eps)
+constexpr int kNearCost = 2;  // r^rho exp(-r^rho/eps), scaled to the caller's cost units
 template <typename R>
 struct NearArgs {
   Geom geo;
@@ -164,6 +173,7 @@ struct NearArgs {
   const int* scell;     // nullable: per source tile the cell starts (TileSortArgs::cellstart);
                         // with it only the source cells within eps_I of each wave's targets are read
   int real_exp;         // kernel exp(-|z|^rho/eps) with the real rho of coef (else rho = 1)
+  int cost;             // the primal cost's kernel |z|^rho exp(-|z|^rho/eps) (coef: its own block)
 };
 template <typename R>
 hipError_t launch_nearfield(const NearArgs<R>& a, int nchunks, hipStream_t st);
@@ -411,14 +421,16 @@ hipError_t launch_gauss_tables(int d, int N, int B, const double* pb, const doub
 // (row-major, g per axis, last axis fastest) on the torus, taken at the
 // nearest image of the origin, from a near-field coefficient block cf
 // (NearArgs::coef layout): the even polynomial inside (cf[1] = (eps_I g)^2
-// squared cells) and exp(-r2^(rho/2) cf[kNearRhoInv]) outside; r2 in squared
+// squared cells) and exp(-r2^(rho/2) cf[kNearRhoInv]) outside (cost: the primal
+// cost's kernel r2^(rho/2) cf[kNearCostMul] exp(-r2^(rho/2) cf[kNearRhoInv]), with
+// the polynomial of the cost block inside); r2 in squared
 // cells.  spec_table: from the forward spectrum of those samples (the row
 // transform's k = 0..N/2 on the last axis, centered k = -N/2..N/2 on the
 // others, as the adjoint NFFT leaves it), tab[i] = Re(spec) hw / (g^d prod_c
 // Phi(k_c)^2) over |k_c| = 0..N/2 (extent (N/2+1)^d, row-major), the same
 // table as the Gaussian's.  Evaluated in FP64, stored as R.
 template <typename R>
-hipError_t launch_kernel_samples(int d, int g, const double* cf, R* out, hipStream_t st);
+hipError_t launch_kernel_samples(int d, int g, const double* cf, int cost, R* out, hipStream_t st);
 template <typename R>
 hipError_t launch_spec_table(int d, int N, int g, const cplx<R>* spec, const double* inv_phi, R* tab, hipStream_t st);
 

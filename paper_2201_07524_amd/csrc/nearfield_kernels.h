@@ -3,9 +3,10 @@
 // K_R replaces the kernel inside the near-field radius eps_I, and the sum over
 // close pairs adds K - K_R back), with its gradient for rho = 1.
 //
-// The kernels are templates over the exponent form; the two forms are
-// compiled in two translation units (nearfield_r1.hip, nearfield_real.hip),
-// so the rho = 1 instances carry none of the real form's code.
+// The kernels are templates over the form of the kernel (rho = 1, a real rho,
+// or the primal cost's kernel |z|^rho exp(-|z|^rho/eps)); each form is compiled
+// in its own translation unit (nearfield_r1.hip, nearfield_real.hip,
+// nearfield_cost.hip), so the rho = 1 instances carry none of the others' code.
 #pragma once
 
 #include <type_traits>
@@ -32,7 +33,7 @@ constexpr int kNearTargets = kNearTPT * kBlock;
 //     and square root (about 1 ulp each); FP64: exp(-sqrt(r2)/eps).
 //   real rho: exp(-r^rho/eps) with r^rho = r2^(rho/2) = exp2((rho/2) log2 r2)
 //     (hardware log2 and exp2 in FP32, pow in FP64; r2 = 0 gives K = 1).
-template <typename R, int D, int PS, bool REAL>
+template <typename R, int D, int PS, int FORM>
 __global__ __launch_bounds__(kBlock) void nearfield_kernel(NearArgs<R> a) {
   __shared__ R su[D][kBlock];
   __shared__ R sw[kBlock];
@@ -50,6 +51,7 @@ __global__ __launch_bounds__(kBlock) void nearfield_kernel(NearArgs<R> a) {
   // real exponent rho: exp(-r^rho/eps) = exp2(r2^(rho/2) * (-log2(e)/(eps g^rho)))
   const R hr = R(cf[kNearRhoHalf]), inv_er = R(cf[kNearRhoInv]);
   const float nler = float(-cf[kNearRhoInv] * 1.4426950408889634);
+  const R cmul = R(cf[kNearCostMul]);
   R c[PS];
 #pragma unroll
   for (int j = 0; j < PS; ++j) c[j] = R(cf[4 + j]);
@@ -117,7 +119,15 @@ __global__ __launch_bounds__(kBlock) void nearfield_kernel(NearArgs<R> a) {
             R P = c[PS - 1];
 #pragma unroll
             for (int jj = PS - 2; jj >= 0; --jj) P = P * rho2 + c[jj];
-            if constexpr (REAL) {
+            if constexpr (FORM == kNearCost) {
+              if constexpr (sizeof(R) == 4) {
+                const R rr = __builtin_amdgcn_exp2f(hr * __builtin_amdgcn_logf(r2));
+                acc[k] += wj * (rr * cmul * __builtin_amdgcn_exp2f(rr * nler) - P);
+              } else {
+                const R rr = pow(r2, hr);
+                acc[k] += wj * (rr * cmul * exp(-rr * inv_er) - P);
+              }
+            } else if constexpr (FORM == kNearReal) {
               if constexpr (sizeof(R) == 4)
                 acc[k] += wj * (__builtin_amdgcn_exp2f(__builtin_amdgcn_exp2f(hr * __builtin_amdgcn_logf(r2)) * nler) - P);
               else
@@ -147,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void nearfield_kernel(NearArgs<R> a) {
 //   real rho: k'(r) = rho inv_er r^(rho-2) e^{-r^rho inv_er}  (inv_er = coef[kNearRhoInv]),
 // the first term taken as 0 at r = 0 (the cost's gradient is zero where the
 // points coincide; r^(rho-1) -> 0 there for rho > 1).  Same tiling as nearfield_kernel.
-template <typename R, int D, int PS, bool REAL>
+template <typename R, int D, int PS, int FORM>
 __global__ __launch_bounds__(kBlock) void nearfield_grad_kernel(NearArgs<R> a) {
   __shared__ R su[D][kBlock];
   __shared__ R sw[kBlock];
@@ -226,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void nearfield_grad_kernel(NearArgs<R> a) {
 #pragma unroll
             for (int jj = PS - 3; jj >= 0; --jj) dP = dP * rho + dc[jj];
             R ek;
-            if constexpr (REAL) {
+            if constexpr (FORM == kNearReal) {
               // r^rho = r2^(rho/2); k'(r) = rho inv_er (r^rho / r2) e^{-r^rho inv_er}
               const R rr = r2 > R(0) ? pow(r2, hr) : R(0);
               ek = r2 > R(0) ? R(2) * hr * inv_er * (rr / r2) * exp(-rr * inv_er) : R(0);
@@ -295,7 +305,7 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
   return v;
 }
 
-template <typename R, int D, int PS, bool REAL>
+template <typename R, int D, int PS, int FORM>
 __global__ __launch_bounds__(kBlock) void nearfield_cells_kernel(NearArgs<R> a) {
   __shared__ NearSrc<R> sbuf[kBlock];
   __shared__ int spre[kBlock];  // per wave: inclusive prefix of the round's piece lengths
@@ -316,6 +326,7 @@ __global__ __launch_bounds__(kBlock) void nearfield_cells_kernel(NearArgs<R> a) 
   const float nle = float(-cf[0] * 1.4426950408889634);
   const R hr = R(cf[kNearRhoHalf]), inv_er = R(cf[kNearRhoInv]);
   const float nler = float(-cf[kNearRhoInv] * 1.4426950408889634);
+  const R cmul = R(cf[kNearCostMul]);
   R c[PS];
 #pragma unroll
   for (int j = 0; j < PS; ++j) c[j] = R(cf[4 + j]);
@@ -453,7 +464,15 @@ __global__ __launch_bounds__(kBlock) void nearfield_cells_kernel(NearArgs<R> a) 
 #pragma unroll
             for (int jj2 = PS - 2; jj2 >= 0; --jj2) P = P * rho2 + c[jj2];
             R e;
-            if constexpr (REAL) {
+            if constexpr (FORM == kNearCost) {
+              if constexpr (sizeof(R) == 4) {
+                const R rr = __builtin_amdgcn_exp2f(hr * __builtin_amdgcn_logf(r2));
+                e = rr * cmul * __builtin_amdgcn_exp2f(rr * nler);
+              } else {
+                const R rr = pow(r2, hr);
+                e = rr * cmul * exp(-rr * inv_er);
+              }
+            } else if constexpr (FORM == kNearReal) {
               if constexpr (sizeof(R) == 4)
                 e = __builtin_amdgcn_exp2f(__builtin_amdgcn_exp2f(hr * __builtin_amdgcn_logf(r2)) * nler);
               else
@@ -482,27 +501,27 @@ __global__ __launch_bounds__(kBlock) void nearfield_cells_kernel(NearArgs<R> a) 
 
 #define NFS_NEAR_P(KERNEL, D_)                                                                                       \
   switch (a.ps) {                                                                                          \
-    case 2: hipLaunchKernelGGL((KERNEL<R, D_, 2, REAL>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
-    case 3: hipLaunchKernelGGL((KERNEL<R, D_, 3, REAL>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
-    case 4: hipLaunchKernelGGL((KERNEL<R, D_, 4, REAL>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
-    case 5: hipLaunchKernelGGL((KERNEL<R, D_, 5, REAL>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
-    case 6: hipLaunchKernelGGL((KERNEL<R, D_, 6, REAL>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
-    case 7: hipLaunchKernelGGL((KERNEL<R, D_, 7, REAL>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
-    case 8: hipLaunchKernelGGL((KERNEL<R, D_, 8, REAL>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
-    case 9: hipLaunchKernelGGL((KERNEL<R, D_, 9, REAL>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
-    case 10: hipLaunchKernelGGL((KERNEL<R, D_, 10, REAL>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
-    case 11: hipLaunchKernelGGL((KERNEL<R, D_, 11, REAL>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
-    case 12: hipLaunchKernelGGL((KERNEL<R, D_, 12, REAL>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
-    case 13: hipLaunchKernelGGL((KERNEL<R, D_, 13, REAL>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
-    case 14: hipLaunchKernelGGL((KERNEL<R, D_, 14, REAL>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
-    case 15: hipLaunchKernelGGL((KERNEL<R, D_, 15, REAL>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
-    case 16: hipLaunchKernelGGL((KERNEL<R, D_, 16, REAL>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
+    case 2: hipLaunchKernelGGL((KERNEL<R, D_, 2, FORM>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
+    case 3: hipLaunchKernelGGL((KERNEL<R, D_, 3, FORM>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
+    case 4: hipLaunchKernelGGL((KERNEL<R, D_, 4, FORM>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
+    case 5: hipLaunchKernelGGL((KERNEL<R, D_, 5, FORM>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
+    case 6: hipLaunchKernelGGL((KERNEL<R, D_, 6, FORM>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
+    case 7: hipLaunchKernelGGL((KERNEL<R, D_, 7, FORM>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
+    case 8: hipLaunchKernelGGL((KERNEL<R, D_, 8, FORM>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
+    case 9: hipLaunchKernelGGL((KERNEL<R, D_, 9, FORM>), dim3(nchunks), dim3(kBlock), 0, st, a); break;   \
+    case 10: hipLaunchKernelGGL((KERNEL<R, D_, 10, FORM>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
+    case 11: hipLaunchKernelGGL((KERNEL<R, D_, 11, FORM>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
+    case 12: hipLaunchKernelGGL((KERNEL<R, D_, 12, FORM>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
+    case 13: hipLaunchKernelGGL((KERNEL<R, D_, 13, FORM>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
+    case 14: hipLaunchKernelGGL((KERNEL<R, D_, 14, FORM>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
+    case 15: hipLaunchKernelGGL((KERNEL<R, D_, 15, FORM>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
+    case 16: hipLaunchKernelGGL((KERNEL<R, D_, 16, FORM>), dim3(nchunks), dim3(kBlock), 0, st, a); break; \
     default: return hipErrorInvalidValue;                                                                  \
   }
 
-// The near-field sum in one exponent form (REAL: a real rho, else rho = 1),
+// The near-field sum in one form (FORM: kNearR1, kNearReal or kNearCost),
 // instantiated by nearfield_r1.hip and nearfield_real.hip.
-template <typename R, bool REAL>
+template <typename R, int FORM>
 hipError_t launch_nearfield_form(const NearArgs<R>& a, int nchunks, hipStream_t st) {
   if (nchunks <= 0) return hipSuccess;
   // cell-culled sources when the plan left per-cell starts (sources in cell order)
@@ -523,13 +542,15 @@ hipError_t launch_nearfield_form(const NearArgs<R>& a, int nchunks, hipStream_t 
   }
   return hipGetLastError();
 }
-extern template hipError_t launch_nearfield_form<float, false>(const NearArgs<float>&, int, hipStream_t);
-extern template hipError_t launch_nearfield_form<double, false>(const NearArgs<double>&, int, hipStream_t);
-extern template hipError_t launch_nearfield_form<float, true>(const NearArgs<float>&, int, hipStream_t);
-extern template hipError_t launch_nearfield_form<double, true>(const NearArgs<double>&, int, hipStream_t);
+extern template hipError_t launch_nearfield_form<float, kNearR1>(const NearArgs<float>&, int, hipStream_t);
+extern template hipError_t launch_nearfield_form<double, kNearR1>(const NearArgs<double>&, int, hipStream_t);
+extern template hipError_t launch_nearfield_form<float, kNearReal>(const NearArgs<float>&, int, hipStream_t);
+extern template hipError_t launch_nearfield_form<double, kNearReal>(const NearArgs<double>&, int, hipStream_t);
+extern template hipError_t launch_nearfield_form<float, kNearCost>(const NearArgs<float>&, int, hipStream_t);
+extern template hipError_t launch_nearfield_form<double, kNearCost>(const NearArgs<double>&, int, hipStream_t);
 
 // Its gradient in one exponent form, instantiated like the sum.
-template <typename R, bool REAL>
+template <typename R, int FORM>
 hipError_t launch_nearfield_grad_form(const NearArgs<R>& a, int nchunks, hipStream_t st) {
   if (nchunks <= 0) return hipSuccess;
   if (a.geo.d == 1) {
@@ -541,9 +562,9 @@ hipError_t launch_nearfield_grad_form(const NearArgs<R>& a, int nchunks, hipStre
   }
   return hipGetLastError();
 }
-extern template hipError_t launch_nearfield_grad_form<float, false>(const NearArgs<float>&, int, hipStream_t);
-extern template hipError_t launch_nearfield_grad_form<double, false>(const NearArgs<double>&, int, hipStream_t);
-extern template hipError_t launch_nearfield_grad_form<float, true>(const NearArgs<float>&, int, hipStream_t);
-extern template hipError_t launch_nearfield_grad_form<double, true>(const NearArgs<double>&, int, hipStream_t);
+extern template hipError_t launch_nearfield_grad_form<float, kNearR1>(const NearArgs<float>&, int, hipStream_t);
+extern template hipError_t launch_nearfield_grad_form<double, kNearR1>(const NearArgs<double>&, int, hipStream_t);
+extern template hipError_t launch_nearfield_grad_form<float, kNearReal>(const NearArgs<float>&, int, hipStream_t);
+extern template hipError_t launch_nearfield_grad_form<double, kNearReal>(const NearArgs<double>&, int, hipStream_t);
 
 }  // namespace nfs

@@ -5,9 +5,9 @@
 
 namespace nfs {
 
-template hipError_t launch_nearfield_form<float, true>(const NearArgs<float>&, int, hipStream_t);
-template hipError_t launch_nearfield_form<double, true>(const NearArgs<double>&, int, hipStream_t);
-template hipError_t launch_nearfield_grad_form<float, true>(const NearArgs<float>&, int, hipStream_t);
-template hipError_t launch_nearfield_grad_form<double, true>(const NearArgs<double>&, int, hipStream_t);
+template hipError_t launch_nearfield_form<float, kNearReal>(const NearArgs<float>&, int, hipStream_t);
+template hipError_t launch_nearfield_form<double, kNearReal>(const NearArgs<double>&, int, hipStream_t);
+template hipError_t launch_nearfield_grad_form<float, kNearReal>(const NearArgs<float>&, int, hipStream_t);
+template hipError_t launch_nearfield_grad_form<double, kNearReal>(const NearArgs<double>&, int, hipStream_t);
 
 }  // namespace nfs

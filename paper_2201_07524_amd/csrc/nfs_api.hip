@@ -246,6 +246,7 @@ struct Work {
   double rho = 2.0;           // the cost exponent
   double* nf = nullptr;       // near-field sums (r != 2), per sorted target
   double* nfcoef = nullptr;   // B x kNearStride (r != 2)
+  double* nfcoef_c = nullptr; // B x kNearStride: the primal cost's kernel (r != 2)
   int kt = 0;
   int ps = 0;
   std::vector<Scaling> sc;
@@ -379,6 +380,7 @@ static void carve(Work<R>& w, const nfs_params* p, int B, long nA, long nB, char
   if (p->r != 2) {
     w.nf = cv.take<double>(size_t(std::max(nA, nB)));
     w.nfcoef = cv.take<double>(size_t(B) * kNearStride);
+    w.nfcoef_c = cv.take<double>(size_t(B) * kNearStride);
     w.kt = int(std::ceil(near_radius(p) * g / T - 1e-12));
     w.ps = near_smooth(p);
   }
@@ -632,14 +634,15 @@ static int sort_cloud(Work<R>& w, CloudBuf<R>& cb, const double* pts, const std:
   return NFS_OK;
 }
 
-// Diagonal tables of a real cost exponent: the Fourier coefficients of the
-// regularized kernel K_R on the torus (Section 3.1: the polynomial inside the
-// near-field radius, the kernel outside) as the DFT of its samples on the
-// oversampled grid, truncated to |k_c| <= N/2.  One problem at a time through
-// the adjoint NFFT's forward passes (w.U -> w.W [-> w.V] -> w.spec); the
-// coefficient blocks w.nfcoef must be on the device.
+// Diagonal tables from samples: the Fourier coefficients of a regularized
+// kernel on the torus (Section 3.1: the polynomial inside the near-field
+// radius, the kernel outside) as the DFT of its samples on the oversampled
+// grid, truncated to |k_c| <= N/2.  One problem at a time through the adjoint
+// NFFT's forward passes (w.U -> w.W [-> w.V] -> w.spec).  coef: the device
+// coefficient blocks (B x kNearStride); cost: the primal cost's kernel
+// (blocks of w.nfcoef_c) instead of K; tables: B x H outputs.
 template <typename R>
-static int real_exponent_tables(Work<R>& w, const nfs_params* p, hipStream_t st) {
+static int sampled_tables(Work<R>& w, const double* coef, int cost, R* tables, hipStream_t st) {
   const Geom& geo = w.geo;
   const int g = geo.g, N = geo.N, d = geo.d, K0 = w.K0;
   const long rows = w.ncell / g;
@@ -650,12 +653,12 @@ static int real_exponent_tables(Work<R>& w, const nfs_params* p, hipStream_t st)
   ax.tw = w.tw;
   ax.mul = Multiplier{nullptr, -1, 0};
   for (int b = 0; b < w.B; ++b) {
-    R* tab = w.dtab + size_t(b) * w.H;
+    R* tab = tables + size_t(b) * w.H;
     if (!(w.sc[b].eps_t > 0.0)) {
       NFS_HIP(launch_fill(tab, sizeof(R) * w.H, st));
       continue;
     }
-    NFS_HIP(launch_kernel_samples<R>(d, g, w.nfcoef + size_t(b) * kNearStride, w.U, st));
+    NFS_HIP(launch_kernel_samples<R>(d, g, coef + size_t(b) * kNearStride, cost, w.U, st));
     RowArgs<R> ra{};
     ra.mode = ROW_R2C;
     ra.L = g;
@@ -749,9 +752,11 @@ static int upload_tables(Work<R>& w, const nfs_params* p, hipStream_t st) {
     const int ps = near_smooth(p);
     const double rho = cost_exponent(p);
     const bool real_exp = p->r == 0;
+    // the primal cost <pi, C> needs the cost-weighted kernel's table and near field
+    const bool cost = (p->flags & NFS_FLAG_PRIMAL_COST) != 0;
     t1.assign(size_t(w.B) * w.H, R(0));
     t2.assign(size_t(w.B) * w.H, R(0));
-    std::vector<double> coef(size_t(w.B) * kNearStride, 0.0);
+    std::vector<double> coef(size_t(w.B) * kNearStride, 0.0), coefc(size_t(w.B) * kNearStride, 0.0);
     for (int b = 0; b < w.B; ++b) {
       const double e = w.sc[b].eps_t;
       const std::vector<double> cf = nearfield_poly(e, eI, ps, rho);
@@ -767,15 +772,29 @@ static int upload_tables(Work<R>& w, const nfs_params* p, hipStream_t st) {
       for (int j = 0; j < ps; ++j) c[4 + j] = cf[j];
       c[kNearRhoHalf] = 0.5 * rho;
       c[kNearRhoInv] = 1.0 / (e * std::pow(double(g), rho));  // (cells)^rho -> r^rho / eps_t
+      if (cost) {
+        // the primal cost's kernel |z|^rho exp(-|z|^rho/eps) in the caller's units:
+        // (r_t / s)^rho exp(-r_t^rho / eps_t), regularized by its own polynomial
+        double* cc = coefc.data() + size_t(b) * kNearStride;
+        const double sr = std::pow(w.sc[b].scale, rho);
+        std::copy(c, c + kNearStride, cc);
+        if (e > 0.0) {
+          const std::vector<double> cfc = nearfield_poly(e, eI, ps, rho, true);
+          for (int j = 0; j < ps; ++j) cc[4 + j] = cfc[j] / sr;
+        }
+        cc[kNearCostMul] = 1.0 / (std::pow(double(g), rho) * sr);
+      }
     }
     NFS_HIP(hipMemcpyAsync(w.dtab2, t2.data(), sizeof(R) * t2.size(), hipMemcpyHostToDevice, st));
     NFS_HIP(hipMemcpyAsync(w.nfcoef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, st));
+    NFS_HIP(hipMemcpyAsync(w.nfcoef_c, coefc.data(), sizeof(double) * coefc.size(), hipMemcpyHostToDevice, st));
     if (real_exp) {
       NFS_HIP(hipStreamSynchronize(st));  // t1 is not used
-      NFS_TRY(real_exponent_tables(w, p, st));
+      NFS_TRY(sampled_tables(w, w.nfcoef, 0, w.dtab, st));
     } else {
       NFS_HIP(hipMemcpyAsync(w.dtab, t1.data(), sizeof(R) * t1.size(), hipMemcpyHostToDevice, st));
     }
+    if (cost) NFS_TRY(sampled_tables(w, w.nfcoef_c, 1, w.dtab2, st));
   } else if (any) {
     // closed form evaluated on the device for all problems at once (the host
     // loop over 512 problems' 129^2 tables took 48 ms of the batch's plan)
@@ -974,7 +993,8 @@ static InterpArgs<R> interp_args(Work<R>& w, const CloudBuf<R>& tgt, int epi, co
 // targets `tgt`, into w.nf (sorted target order, normalized like the spread).
 template <typename R>
 static hipError_t near_field(Work<R>& w, const CloudBuf<R>& src, const CloudBuf<R>& tgt, const double* weights,
-                             const double* wmul, double wconst, hipStream_t st, const int* pstate = nullptr) {
+                             const double* wmul, double wconst, hipStream_t st, const int* pstate = nullptr,
+                             bool cost = false) {
   NearArgs<R> a{};
   a.geo = w.geo;
   a.tcoords = tgt.coords;
@@ -985,13 +1005,14 @@ static hipError_t near_field(Work<R>& w, const CloudBuf<R>& src, const CloudBuf<
   a.scounts = src.counts;
   a.wmul = wmul;
   a.wconst = wconst;
-  a.coef = w.nfcoef;
+  a.coef = cost ? w.nfcoef_c : w.nfcoef;
   a.kt = w.kt;
   a.ps = w.ps;
   a.out = w.nf;
   a.pstate = pstate;
   a.scell = src.cellstart;
   a.real_exp = w.rho != 1.0;
+  a.cost = cost;
   return launch_nearfield(a, tgt.nchunks, st);
 }
 
@@ -1938,11 +1959,13 @@ struct Solver : SolverBase {
                      w.st_rdy + 4 * b};
       NFS_HIP(launch_readout(rb, st));
     }
-    const bool primal = (p.flags & NFS_FLAG_PRIMAL_COST) && p.r == 2 && !logd && !centred;
+    const bool primal = (p.flags & NFS_FLAG_PRIMAL_COST) && !logd && !centred;
     if (primal) {
       NFS_HIP(spread(w, w.Y, w.Y.w1s, w.wmul_y, 1.0, st));
       NFS_HIP(fft_chain(w, w.dtab2, -1, st));
+      if (w.r == 1) NFS_HIP(near_field(w, w.Y, w.X, w.Y.w1s, w.wmul_y, 1.0, st, nullptr, true));
       InterpArgs<R> ia = interp_args(w, w.X, EPI_OUT, w.wmul_y);
+      if (w.r == 1) ia.nf = w.nf;
       ia.out = w.tmp;
       ia.scale_vec = w.X.w1s;
       NFS_HIP(launch_interp(ia, w.X.nchunks, st));

@@ -791,7 +791,8 @@ template hipError_t launch_gauss_tables<double>(int, int, int, const double*, co
 
 // ------------------------------------------------------------------ diagonal tables (real rho)
 template <typename R>
-__global__ __launch_bounds__(kBlock) void kernel_samples_kernel(int d, int g, long ncell, const double* cf, R* out) {
+__global__ __launch_bounds__(kBlock) void kernel_samples_kernel(int d, int g, long ncell, const double* cf, int cost,
+                                                                R* out) {
   const long i = long(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= ncell) return;
   long rem = i;
@@ -809,21 +810,23 @@ __global__ __launch_bounds__(kBlock) void kernel_samples_kernel(int d, int g, lo
     v = cf[4 + ps - 1];
     for (int j = ps - 2; j >= 0; --j) v = v * u2 + cf[4 + j];
   } else {
-    v = exp(-pow(r2, cf[kNearRhoHalf]) * cf[kNearRhoInv]);
+    const double rr = pow(r2, cf[kNearRhoHalf]);
+    v = exp(-rr * cf[kNearRhoInv]);
+    if (cost) v *= rr * cf[kNearCostMul];
   }
   out[i] = R(v);
 }
 
 template <typename R>
-hipError_t launch_kernel_samples(int d, int g, const double* cf, R* out, hipStream_t st) {
+hipError_t launch_kernel_samples(int d, int g, const double* cf, int cost, R* out, hipStream_t st) {
   long ncell = 1;
   for (int c = 0; c < d; ++c) ncell *= g;
   hipLaunchKernelGGL(kernel_samples_kernel<R>, dim3(unsigned((ncell + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, d, g,
-                     ncell, cf, out);
+                     ncell, cf, cost, out);
   return hipGetLastError();
 }
-template hipError_t launch_kernel_samples<float>(int, int, const double*, float*, hipStream_t);
-template hipError_t launch_kernel_samples<double>(int, int, const double*, double*, hipStream_t);
+template hipError_t launch_kernel_samples<float>(int, int, const double*, int, float*, hipStream_t);
+template hipError_t launch_kernel_samples<double>(int, int, const double*, int, double*, hipStream_t);
 
 template <typename R>
 __global__ __launch_bounds__(kBlock) void spec_table_kernel(int d, int N, int g, long H, const cplx<R>* spec,

@@ -157,3 +157,23 @@ def test_real_exponent_gradient_matches_oracle(prec, eps_I, p_smooth, tol):
     assert _grad_rel(gm.cpu().numpy(), rm) <= 1e-10 and _grad_rel(gn.cpu().numpy(), rn) <= 1e-10
     ox, _ = nfs.sinkhorn_grad(prm, T(x), T(p), T(y), T(pt), res.alpha, res.alpha_t, want_mu=False)
     assert _grad_rel(gx.cpu().numpy(), ox.cpu().numpy()) <= (1e-12 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("r,prec,tol", [(1, "fp64", 1e-8), (1.5, "fp64", 1e-8), (1.5, "fp32", 2e-6), (3.0, "fp64", 1e-8)])
+def test_primal_cost_matches_oracle(r, prec, tol):
+    """<pi, C> of eq. (15) for r = 1 and real exponents: one more fast summation
+    with the kernel c K = |z|^r exp(-|z|^r/eps), whose table comes from samples
+    of its own regularized form and whose near field adds c K - (c K)_R.  Ball/
+    shell subsample against the dense oracle's primal cost after 30 iterations:
+    measured 9e-10 (r = 1), 4e-10 (1.5), 2e-11 (3) in FP64 and 1e-7 in FP32."""
+    x = workloads.uniform_ball(1100, 2700)
+    y = workloads.noisy_shell(1000, 2701)
+    p, pt = workloads.uniform_weights(1100), workloads.uniform_weights(1000)
+    eps, iters = 0.02, 30
+    ref = sd.solve(x, p, y, pt, r, eps, iters)
+    prm = nfs.Params(d=3, r=r, eps=eps, N=64, m=8 if prec == "fp64" else 6, precision=prec,
+                     eps_I=8 if prec == "fp64" else 0, p_smooth=10 if prec == "fp64" else 0,
+                     flags=nfs.FLAG_PRIMAL_COST)
+    res = nfs.sinkhorn(prm, T(x), T(p), T(y), T(pt), iters)
+    print(f"r={r} {prec}: primal rel {rel(res.cost_primal, ref['cost_primal']):.2e} cost rel {rel(res.cost, ref['cost']):.2e}")
+    assert rel(res.cost_primal, ref["cost_primal"]) <= tol
