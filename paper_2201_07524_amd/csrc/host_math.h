@@ -260,105 +260,6 @@ inline std::vector<double> nearfield_poly(double e, double eI, int p, double rho
   return cf;
 }
 
-// Fourier transform (period-free, Poisson summation) of the radial function
-// K_R at frequency magnitude kappa in d dimensions:
-//   FT[exp(-r/e)] + FT[(K_R - K) 1_{r < eI}],
-// with FT[exp(-r/e)] = 2e/(1+a^2) (d=1), 2 pi e^2/(1+a^2)^{3/2} (d=2),
-// 8 pi e^3/(1+a^2)^2 (d=3), a = 2 pi kappa e, and the correction as a radial
-// integral (cos, J0, sinc kernels) by Gauss-Legendre quadrature on [0, eI];
-// J0 by its integral (1/pi) int_0^pi cos(x sin t) dt (midpoint rule).
-struct RadialQuad {
-  std::vector<double> r, w;
-};
-
-inline RadialQuad gauss_legendre(int n, double a, double b) {
-  RadialQuad q;
-  q.r.resize(n);
-  q.w.resize(n);
-  for (int i = 0; i < n; ++i) {
-    double x = std::cos(kPi * (i + 0.75) / (n + 0.5));
-    for (int it = 0; it < 100; ++it) {
-      double p0 = 1.0, p1 = x;
-      for (int k = 2; k <= n; ++k) {
-        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
-        p0 = p1;
-        p1 = p2;
-      }
-      const double dp = n * (x * p1 - p0) / (x * x - 1.0);
-      const double dx = p1 / dp;
-      x -= dx;
-      if (std::fabs(dx) < 1e-16) break;
-    }
-    double p0 = 1.0, p1 = x;
-    for (int k = 2; k <= n; ++k) {
-      const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
-      p0 = p1;
-      p1 = p2;
-    }
-    const double dp = n * (x * p1 - p0) / (x * x - 1.0);
-    q.r[i] = 0.5 * (b - a) * (x + 1.0) + a;
-    q.w[i] = (b - a) / ((1.0 - x * x) * dp * dp);
-  }
-  return q;
-}
-
-inline double bessel_j0(double x) {
-  const int n = 64;
-  double s = 0.0;
-  for (int i = 0; i < n; ++i) s += std::cos(x * std::sin(kPi * (i + 0.5) / n));
-  return s / n;
-}
-
-inline double r1_coeff(int d, double kappa, double e, double eI, const std::vector<double>& cf, const RadialQuad& q) {
-  const double a2 = std::pow(2.0 * kPi * kappa * e, 2);
-  double full;
-  if (d == 1) full = 2.0 * e / (1.0 + a2);
-  else if (d == 2) full = 2.0 * kPi * e * e / std::pow(1.0 + a2, 1.5);
-  else full = 8.0 * kPi * e * e * e / ((1.0 + a2) * (1.0 + a2));
-  double corr = 0.0;
-  for (size_t i = 0; i < q.r.size(); ++i) {
-    const double r = q.r[i];
-    const double rho2 = (r / eI) * (r / eI);
-    double P = 0.0;
-    for (int j = int(cf.size()) - 1; j >= 0; --j) P = P * rho2 + cf[j];
-    const double diff = P - std::exp(-r / e);
-    const double x = 2.0 * kPi * kappa * r;
-    double ker;
-    if (d == 1) ker = 2.0 * std::cos(x);
-    else if (d == 2) ker = 2.0 * kPi * r * bessel_j0(x);
-    else ker = 4.0 * kPi * r * r * (x > 0.0 ? std::sin(x) / x : 1.0);
-    corr += q.w[i] * diff * ker;
-  }
-  return full + corr;
-}
-
-// Diagonal table for r = 1 over |k_c| = 0..N/2: b(|k|) hw / prod Phi^2 (radial
-// coefficients cached per integer |k|^2).
-inline std::vector<double> r1_table(int d, int N, double e, double eI, const std::vector<double>& cf,
-                                    const std::vector<double>& phi) {
-  const int H = N / 2 + 1;
-  const RadialQuad q = gauss_legendre(96, 0.0, eI);
-  std::vector<double> byk2(size_t(d) * (N / 2) * (N / 2) + 1, std::nan(""));
-  long total = 1;
-  for (int c = 0; c < d; ++c) total *= H;
-  std::vector<double> tab(total);
-  for (long i = 0; i < total; ++i) {
-    long rem = i;
-    long k2 = 0;
-    double f = 1.0;
-    for (int c = d - 1; c >= 0; --c) {
-      const int kc = int(rem % H);
-      rem /= H;
-      k2 += long(kc) * kc;
-      f /= phi[kc] * phi[kc];
-      if (kc == N / 2) f *= 0.5;
-    }
-    if (std::isnan(byk2[k2])) byk2[k2] = r1_coeff(d, std::sqrt(double(k2)), e, eI, cf, q);
-    tab[i] = byk2[k2] * f;
-  }
-  return tab;
-}
-
 inline std::vector<double> window_hat_table(int N, int m, int g, const WindowConst& w) {
   const int H = N / 2 + 1;
   std::vector<double> phi(H);

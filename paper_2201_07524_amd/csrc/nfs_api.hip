@@ -744,26 +744,24 @@ static int upload_tables(Work<R>& w, const nfs_params* p, hipStream_t st) {
     const WindowPoly64 wp = make_window_poly64(p->m, w.win);
     NFS_HIP(hipMemcpyAsync(w.wpoly, &wp, sizeof(WindowPoly64), hipMemcpyHostToDevice, st));
   }
-  std::vector<R> t1, t2;
+  std::vector<R> t2;
   bool any = false;
   for (int b = 0; b < w.B; ++b) any = any || w.sc[b].eps_t > 0.0;
   if (any && p->r != 2) {
     const double eI = near_radius(p);
     const int ps = near_smooth(p);
     const double rho = cost_exponent(p);
-    const bool real_exp = p->r == 0;
-    // the primal cost <pi, C> needs the cost-weighted kernel's table and near field
+    // The diagonal table comes from samples of K_R on the grid (a DFT on the
+    // device, the same for r = 1 and real exponents: a closed-form transform
+    // plus a radial quadrature of K - K_R on the host took 0.5 s per 2-D
+    // problem at N = 256, and the samples are as accurate).  The primal cost
+    // <pi, C> needs the cost-weighted kernel's table and near field as well.
     const bool cost = (p->flags & NFS_FLAG_PRIMAL_COST) != 0;
-    t1.assign(size_t(w.B) * w.H, R(0));
     t2.assign(size_t(w.B) * w.H, R(0));
     std::vector<double> coef(size_t(w.B) * kNearStride, 0.0), coefc(size_t(w.B) * kNearStride, 0.0);
     for (int b = 0; b < w.B; ++b) {
       const double e = w.sc[b].eps_t;
       const std::vector<double> cf = nearfield_poly(e, eI, ps, rho);
-      if (!real_exp && e > 0.0) {
-        const std::vector<double> tb = r1_table(p->d, p->N, e, eI, cf, phi);
-        for (long i = 0; i < w.H; ++i) t1[size_t(b) * w.H + i] = R(tb[i]);
-      }
       double* c = coef.data() + size_t(b) * kNearStride;
       c[0] = 1.0 / (e * g);
       c[1] = (eI * g) * (eI * g);
@@ -788,12 +786,7 @@ static int upload_tables(Work<R>& w, const nfs_params* p, hipStream_t st) {
     NFS_HIP(hipMemcpyAsync(w.dtab2, t2.data(), sizeof(R) * t2.size(), hipMemcpyHostToDevice, st));
     NFS_HIP(hipMemcpyAsync(w.nfcoef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, st));
     NFS_HIP(hipMemcpyAsync(w.nfcoef_c, coefc.data(), sizeof(double) * coefc.size(), hipMemcpyHostToDevice, st));
-    if (real_exp) {
-      NFS_HIP(hipStreamSynchronize(st));  // t1 is not used
-      NFS_TRY(sampled_tables(w, w.nfcoef, 0, w.dtab, st));
-    } else {
-      NFS_HIP(hipMemcpyAsync(w.dtab, t1.data(), sizeof(R) * t1.size(), hipMemcpyHostToDevice, st));
-    }
+    NFS_TRY(sampled_tables(w, w.nfcoef, 0, w.dtab, st));
     if (cost) NFS_TRY(sampled_tables(w, w.nfcoef_c, 1, w.dtab2, st));
   } else if (any) {
     // closed form evaluated on the device for all problems at once (the host
