@@ -110,14 +110,17 @@ def test_sinkhorn_real_exponent_3d_vs_oracle():
 
 def test_batched_real_exponent_matches_single_solves():
     """Every problem of a batch gets its own torus scaling and hence its own
-    table; each matches the single solve of that problem."""
+    tables (the kernel's and the primal cost's); each matches the single solve
+    of that problem."""
     probs = [workloads.subsample(workloads.gmm_2d(8000), n, seed=40 + n) for n in (700, 1300)]
-    prm = nfs.Params(d=2, r=2.5, eps=0.05, N=64, m=8, precision="fp64", eps_I=8, p_smooth=10)
+    prm = nfs.Params(d=2, r=2.5, eps=0.05, N=64, m=8, precision="fp64", eps_I=8, p_smooth=10,
+                     flags=nfs.FLAG_PRIMAL_COST)
     b = nfs.batch_sinkhorn(prm, [T(q["x"]) for q in probs], [T(q["p"]) for q in probs],
                            [T(q["y"]) for q in probs], [T(q["pt"]) for q in probs], [0.05, 0.05], 20)
     for q, rb in zip(probs, b):
         rs = nfs.sinkhorn(prm, T(q["x"]), T(q["p"]), T(q["y"]), T(q["pt"]), 20)
         assert rel(rb.cost, rs.cost) <= 1e-12
+        assert rel(rb.cost_primal, rs.cost_primal) <= 1e-12
         assert relerr(rb.alpha.cpu().numpy(), rs.alpha.cpu().numpy()) <= 1e-10
 
 
