@@ -1378,8 +1378,8 @@ static int plan_sinkhorn(Work<R>& w, const nfs_params* p, const double* eps, con
     const double* bx = box.data() + size_t(kBoxSlot) * b;
     const double* by = bx + kBoxVals;
     for (int i = 0; i < kBoxVals; ++i) {
-      const bool used = centred ? (i < 9 || i < 9 + d) : (i < 9);
-      if (used && (!std::isfinite(bx[i]) || (centred || i >= 6) && !std::isfinite(by[i])))
+      const bool used = centred ? (i < 9 + d) : (i < 9);
+      if (used && (!std::isfinite(bx[i]) || ((centred || i >= 6) && !std::isfinite(by[i]))))
         return fail(NFS_EINVAL, "non-finite point coordinates or weights");
     }
     const long nx = w.X.off[b + 1] - w.X.off[b], ny = w.Y.off[b + 1] - w.Y.off[b];
@@ -1568,8 +1568,8 @@ struct Solver : SolverBase {
         best_chunk = c;
       }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     NFS_TRY(rc);
     w.chunk = best_chunk;
     NFS_TRY(build_chunks(w, w.X, best_chunk, true, st));
@@ -1712,8 +1712,8 @@ struct Solver : SolverBase {
           best_tile = T;
         }
       }
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
       NFS_TRY(rc);
       p.tile = best_tile;
     }
